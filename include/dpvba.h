@@ -1,0 +1,196 @@
+/*
+ * dpvba.h -- C ABI of the patch-graph Gauss-Newton bundle adjustment library
+ * (gfx950 / MI355X).
+ *
+ * The problem is the one stated in the DPV-SLAM paper (Lipson, Teed, Deng,
+ * arXiv 2408.01654), Sec. 3.1: frames i with camera-to-world poses G_i, p x p
+ * patches P_ik owned by frame i with an inverse depth, a directed edge set of
+ * (i, k, j) linking patch k of frame i to frame j, per-edge ideal
+ * reprojections I_ikj ("targets") and confidences w_ikj ("weights").  The
+ * reprojection is eq. (2), P'_ikj = Pi[G_j^-1 G_i Pi^-1(P_ik)], and bundle
+ * adjustment minimises eq. (3), the confidence-weighted sum of squared
+ * differences between reprojections and targets.  The solver eliminates the
+ * per-patch depths by a Schur complement and factors the reduced pose block
+ * by Cholesky (Appendix A), serving both the sliding-window BA of the
+ * odometry (Sec. 3.1) and the global BA after a proximity loop closure
+ * (Sec. 3.2).
+ *
+ * Readings fixed by this library where the paper is silent:
+ *   - one inverse depth per patch; only the patch centre enters the residual
+ *     (the whole patch is available through dpvba_reproject);
+ *   - cost = 1/2 sum_e (w_x r_x^2 + w_y r_y^2): confidences multiply;
+ *   - poses are camera-to-world (tx,ty,tz,qx,qy,qz,qw), unit quaternion,
+ *     updated on the right, G <- G Exp(xi), xi = (rho, phi), full SE(3) Exp;
+ *   - damping H~ = H + lambda (Diag(H) + I) on the full system;
+ *   - an edge is valid iff d_k > 0 and q_z > z_min d_k (q the point in the
+ *     target camera scaled by d_k); invalid edges contribute nothing;
+ *   - poses [0, n_fixed) are held, all depths are free;
+ *   - a fixed number of iterations, no step rejection.
+ *
+ * Memory and ownership.  Unless marked "host", every pointer is a device
+ * pointer owned by the caller, who keeps it alive until the work enqueued on
+ * the given stream has completed.  The library never frees or retains caller
+ * buffers.  A context owns all of its workspace.  dpvba_analyze is the only
+ * call that may allocate device memory; the numeric calls (dpvba_solve,
+ * dpvba_reduced_system, dpvba_reproject) allocate nothing, synchronise
+ * nothing and only enqueue work on the caller's stream (dpvba_solve with a
+ * non-NULL report enqueues one device-to-host copy into it and the caller
+ * reads it after synchronising the stream).  A context is used by one host
+ * thread at a time.
+ *
+ * Errors.  Every call returns a dpvba_status.  Argument errors found on the
+ * host return immediately with nothing enqueued.  Conditions found on the
+ * device (non-positive pivot) are reported through dpvba_report.status once
+ * the stream has completed.  No C++ exception crosses this interface and
+ * nothing aborts.
+ */
+#ifndef DPVBA_H
+#define DPVBA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DPVBA_OK = 0,
+  DPVBA_EINVAL = 1,   /* bad argument, index out of range, inconsistent patch owner */
+  DPVBA_ENOTPD = 2,   /* reduced camera system not positive definite            */
+  DPVBA_ENOMEM = 3,   /* device allocation failed (dpvba_analyze / create)       */
+  DPVBA_EHIP = 4,     /* a HIP runtime call failed                               */
+  DPVBA_ESTATE = 5    /* numeric call without a matching dpvba_analyze           */
+} dpvba_status;
+
+typedef enum {
+  DPVBA_FP32 = 0,       /* float32 assembly, factorisation and solve             */
+  DPVBA_FP64 = 2        /* float64 throughout (parity mode)                      */
+} dpvba_precision;
+
+typedef struct dpvba_ctx dpvba_ctx;
+
+/* One BA problem (paper Sec. 3.1, eq. 1-3).  Host struct holding device
+ * pointers.
+ *   n_frames   N, number of poses.
+ *   n_patches  P, number of patches (patch k has one inverse depth).
+ *   n_edges    E, number of edges (i, k, j).
+ *   patch_size p, odd, >= 1.
+ *   n_fixed    poses [0, n_fixed) are held constant (gauge); 0 <= n_fixed <= N.
+ *   patches    [P, p, p, 2] float32: pixel (x, y) of each patch pixel in its
+ *              source frame; row a, column b; the centre ((p-1)/2, (p-1)/2)
+ *              enters the residual.
+ *   ii, jj, kk [E] int32: source frame, target frame, patch of every edge.
+ *              0 <= ii, jj < N, ii != jj, 0 <= kk < P, and every edge of one
+ *              patch has the same ii (the patch's owner frame).  Any order;
+ *              duplicated edges add up.
+ *   target     [E, 2] float32: ideal reprojection I_ikj in pixels.
+ *   weight     [E, 2] float32: confidence w_ikj (x, y), finite and >= 0.
+ *   fx..cy     pinhole intrinsics shared by every frame.                  */
+typedef struct {
+  int32_t n_frames, n_patches, n_edges, patch_size, n_fixed;
+  const float* patches;
+  const int32_t* ii;
+  const int32_t* jj;
+  const int32_t* kk;
+  const float* target;
+  const float* weight;
+  float fx, fy, cx, cy;
+} dpvba_graph;
+
+/* Solver options (host).
+ *   n_iters    Gauss-Newton iterations, 0 <= n_iters <= DPVBA_MAX_ITERS.
+ *   lambda     damping, finite, >= 0 (rounded to float in DPVBA_FP32).
+ *   z_min      validity threshold, finite, >= 0.
+ *   precision  dpvba_precision.
+ *   flags      reserved, must be 0.                                      */
+#define DPVBA_MAX_ITERS 32
+typedef struct {
+  int32_t n_iters;
+  int32_t precision;
+  double lambda;
+  double z_min;
+  uint32_t flags;
+} dpvba_opts;
+
+/* Per-solve report, written asynchronously into host memory (pinned
+ * memory recommended) and valid after the stream has completed.
+ *   cost[t]         1/2 sum w r^2 over valid edges at iterate t (t <= n_iters),
+ *                   accumulated in float64.
+ *   n_invalid[t]    invalid edges at iterate t (t < n_iters).
+ *   min_pivot[t]    smallest L_ii^2 / S_ii of the Cholesky at iteration t.
+ *   status          DPVBA_OK, or DPVBA_ENOTPD if a pivot was not positive
+ *                   (that iteration's step is then zero).                  */
+typedef struct {
+  int32_t status;
+  int32_t n_iters;
+  double cost[DPVBA_MAX_ITERS + 1];
+  int32_t n_invalid[DPVBA_MAX_ITERS];
+  double min_pivot[DPVBA_MAX_ITERS];
+} dpvba_report;
+
+/* Create a context on HIP device `device`.  Allocates the context's fixed
+ * state.  Returns EINVAL for a bad device, ENOMEM/EHIP on failure.        */
+dpvba_status dpvba_create(dpvba_ctx** out, int32_t device);
+
+/* Release the context and all of its device memory.  NULL is ignored.   */
+void dpvba_destroy(dpvba_ctx* ctx);
+
+/* Symbolic analysis of the edge set (ii, jj, kk) and sizes of `g` (the
+ * structure of the block-sparse normal equations of eq. 3, Appendix A):
+ * groups every patch's edges, splits each source frame's patches into
+ * tiles, and builds the index lists that assemble the reduced camera
+ * system.  Copies ii/jj/kk to the host (synchronising `stream`), validates
+ * them, and (re)allocates the workspace for this graph.  Must be repeated
+ * whenever ii, jj, kk or any size changes; targets, weights, patches,
+ * poses and depths may change freely between numeric calls.
+ * Returns EINVAL on any index or ownership violation, ENOMEM on allocation
+ * failure.                                                                */
+dpvba_status dpvba_analyze(dpvba_ctx* ctx, const dpvba_graph* g, void* stream);
+
+/* Reprojection of every edge's whole patch (eq. 2) with the patch's one
+ * inverse depth.
+ *   poses      [N, 7] float32, inv_depth [P] float32 (read).
+ *   coords     [E, p, p, 2] float32 (written): reprojected pixel (x, y).
+ *   valid      [E] uint8 or NULL (written): the centre validity rule with
+ *              threshold z_min (>= 0).
+ * Needs no analysis.  EINVAL on bad sizes or NULL pointers.               */
+dpvba_status dpvba_reproject(dpvba_ctx* ctx, const dpvba_graph* g, const float* poses,
+                             const float* inv_depth, float z_min, float* coords,
+                             uint8_t* valid, void* stream);
+
+/* Damped reduced camera system at the given iterate (eq. 3 linearised,
+ * Appendix A): S = B~ - E C~^-1 E^T and s = -v + E C~^-1 w over the free
+ * poses, n = 6 (N - n_fixed).
+ *   S          [n, n] (float or double per opts->precision), written in
+ *              full (both triangles), row-major.
+ *   s          [n] same type, written.
+ *   cost       one double (device) or NULL: 1/2 sum w r^2 at this iterate.
+ * Needs dpvba_analyze on this graph.                                      */
+dpvba_status dpvba_reduced_system(dpvba_ctx* ctx, const dpvba_graph* g, const float* poses,
+                                  const float* inv_depth, const dpvba_opts* opts, void* S,
+                                  void* s, double* cost, void* stream);
+
+/* opts->n_iters Gauss-Newton iterations of eq. (3): per iteration assemble
+ * the block-sparse normal equations, eliminate depths, factor and solve
+ * the reduced system, back-substitute the depths, retract the free poses.
+ *   poses      [N, 7] read and overwritten with the result (quaternions
+ *              renormalised): float32, or float64 when opts->precision is
+ *              DPVBA_FP64 (the pointer is then reinterpreted).
+ *   inv_depth  [P] read and overwritten, same element type as poses.
+ *   report     host memory or NULL.
+ * Needs dpvba_analyze on this graph.                                      */
+dpvba_status dpvba_solve(dpvba_ctx* ctx, const dpvba_graph* g, float* poses, float* inv_depth,
+                         const dpvba_opts* opts, dpvba_report* report, void* stream);
+
+/* Text of the last HIP failure seen by a call on this context (the failing
+ * call and HIP's message), "" if none.  Owned by the context.             */
+const char* dpvba_last_error(const dpvba_ctx* ctx);
+
+/* Static text for a status code. */
+const char* dpvba_status_string(dpvba_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPVBA_H */

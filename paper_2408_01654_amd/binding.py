@@ -1,0 +1,212 @@
+"""ctypes binding of libdpvba.so (include/dpvba.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Tensors must already live on the GPU; torch provides the device
+memory and the stream.  There is no CPU fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpvba.so")
+
+DPVBA_OK, DPVBA_EINVAL, DPVBA_ENOTPD, DPVBA_ENOMEM, DPVBA_EHIP, DPVBA_ESTATE = range(6)
+FP32, FP64 = 0, 2
+MAX_ITERS = 32
+
+
+class DpvbaError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [
+        ("n_frames", ctypes.c_int32), ("n_patches", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+        ("patch_size", ctypes.c_int32), ("n_fixed", ctypes.c_int32),
+        ("patches", ctypes.c_void_p), ("ii", ctypes.c_void_p), ("jj", ctypes.c_void_p),
+        ("kk", ctypes.c_void_p), ("target", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+        ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("n_iters", ctypes.c_int32), ("precision", ctypes.c_int32), ("lambda_", ctypes.c_double),
+                ("z_min", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_iters", ctypes.c_int32),
+                ("cost", ctypes.c_double * (MAX_ITERS + 1)),
+                ("n_invalid", ctypes.c_int32 * MAX_ITERS),
+                ("min_pivot", ctypes.c_double * MAX_ITERS)]
+
+    def to_dict(self):
+        n = self.n_iters
+        return {"status": int(self.status), "n_iters": n, "cost": list(self.cost[: n + 1]),
+                "n_invalid": list(self.n_invalid[:n]), "min_pivot": list(self.min_pivot[:n])}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2408_01654_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.dpvba_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32]
+        L.dpvba_create.restype = ctypes.c_int
+        L.dpvba_destroy.argtypes = [vp]
+        L.dpvba_destroy.restype = None
+        L.dpvba_analyze.argtypes = [vp, ctypes.POINTER(Graph), vp]
+        L.dpvba_analyze.restype = ctypes.c_int
+        L.dpvba_reproject.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.c_float, vp, vp, vp]
+        L.dpvba_reproject.restype = ctypes.c_int
+        L.dpvba_reduced_system.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp]
+        L.dpvba_reduced_system.restype = ctypes.c_int
+        L.dpvba_solve.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(Report), vp]
+        L.dpvba_solve.restype = ctypes.c_int
+        L.dpvba_last_error.argtypes = [vp]
+        L.dpvba_last_error.restype = ctypes.c_char_p
+        L.dpvba_status_string.argtypes = [ctypes.c_int]
+        L.dpvba_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().dpvba_status_string(int(s)).decode()
+
+
+def _check(status: int, what: str, ctx=None):
+    if status != DPVBA_OK:
+        if ctx is not None and status == DPVBA_EHIP:
+            what = f"{what} [{lib().dpvba_last_error(ctx).decode()}]"
+        raise DpvbaError(status, what)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class GraphTensors:
+    """Device tensors of one BA problem (see dpvba_graph)."""
+
+    n_frames: int
+    n_fixed: int
+    patches: torch.Tensor   # [P,p,p,2] float32
+    ii: torch.Tensor        # [E] int32
+    jj: torch.Tensor
+    kk: torch.Tensor
+    target: torch.Tensor    # [E,2] float32
+    weight: torch.Tensor    # [E,2] float32
+    intrinsics: tuple       # fx, fy, cx, cy
+
+    @staticmethod
+    def from_arrays(n_frames, n_fixed, patches, ii, jj, kk, target, weight, intrinsics, device="cuda"):
+        f32 = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        i32 = lambda a: torch.as_tensor(a).to(device=device, dtype=torch.int32).contiguous()
+        return GraphTensors(int(n_frames), int(n_fixed), f32(patches), i32(ii), i32(jj), i32(kk),
+                            f32(target).reshape(-1, 2), f32(weight).reshape(-1, 2),
+                            tuple(float(x) for x in intrinsics))
+
+    @staticmethod
+    def from_scene(scene, device="cuda"):
+        return GraphTensors.from_arrays(scene.n_frames, scene.n_fixed, scene.patches, scene.ii, scene.jj,
+                                        scene.kk, scene.target, scene.weight, scene.intrinsics, device)
+
+    def struct(self) -> Graph:
+        fx, fy, cx, cy = self.intrinsics
+        return Graph(self.n_frames, self.patches.shape[0], self.ii.shape[0], self.patches.shape[1],
+                     self.n_fixed, _ptr(self.patches), _ptr(self.ii), _ptr(self.jj), _ptr(self.kk),
+                     _ptr(self.target), _ptr(self.weight), fx, fy, cx, cy)
+
+
+class Context:
+    """One dpvba_ctx on a device."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p(0)
+        _check(lib().dpvba_create(ctypes.byref(self._h), int(device)), "dpvba_create")
+        self.device = device
+        self._graph = None
+
+    def close(self):
+        if self._h:
+            lib().dpvba_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def analyze(self, g: GraphTensors, stream=None):
+        gs = g.struct()
+        _check(lib().dpvba_analyze(self._h, ctypes.byref(gs), _stream(stream)), "dpvba_analyze", self._h)
+        self._graph = g
+
+    def reproject(self, g: GraphTensors, poses, inv_depth, z_min=0.1, stream=None):
+        E, p = g.ii.shape[0], g.patches.shape[1]
+        coords = torch.empty((E, p, p, 2), dtype=torch.float32, device=poses.device)
+        valid = torch.empty((E,), dtype=torch.uint8, device=poses.device)
+        gs = g.struct()
+        _check(lib().dpvba_reproject(self._h, ctypes.byref(gs), _ptr(poses), _ptr(inv_depth), float(z_min),
+                                     _ptr(coords), _ptr(valid), _stream(stream)), "dpvba_reproject", self._h)
+        return coords, valid
+
+    @staticmethod
+    def _opts(n_iters, lam, z_min, precision):
+        return Opts(int(n_iters), int(precision), float(lam), float(z_min), 0)
+
+    def reduced_system(self, g: GraphTensors, poses, inv_depth, lam=1e-4, z_min=0.1, precision=FP32,
+                       stream=None):
+        dt = torch.float64 if precision == FP64 else torch.float32
+        n = 6 * (g.n_frames - g.n_fixed)
+        S = torch.empty((n, n), dtype=dt, device=poses.device)
+        s = torch.empty((n,), dtype=dt, device=poses.device)
+        cost = torch.empty((1,), dtype=torch.float64, device=poses.device)
+        o = self._opts(0, lam, z_min, precision)
+        gs = g.struct()
+        _check(lib().dpvba_reduced_system(self._h, ctypes.byref(gs), _ptr(poses), _ptr(inv_depth),
+                                          ctypes.byref(o), _ptr(S), _ptr(s), _ptr(cost), _stream(stream)),
+               "dpvba_reduced_system", self._h)
+        return S, s, cost
+
+    def solve(self, g: GraphTensors, poses, inv_depth, n_iters=2, lam=1e-4, z_min=0.1, precision=FP32,
+              report=True, stream=None):
+        """In-place solve of poses [N,7] and inv_depth [P] (float32, or float64
+        for precision=FP64).  Returns the report as a dict (after synchronising
+        the stream) or None."""
+        want = torch.float64 if precision == FP64 else torch.float32
+        if poses.dtype != want or inv_depth.dtype != want:
+            raise TypeError(f"poses and inv_depth must be {want}")
+        if not (poses.is_contiguous() and inv_depth.is_contiguous()):
+            raise ValueError("poses and inv_depth must be contiguous")
+        o = self._opts(n_iters, lam, z_min, precision)
+        gs = g.struct()
+        rep = Report() if report else None
+        _check(lib().dpvba_solve(self._h, ctypes.byref(gs), _ptr(poses), _ptr(inv_depth), ctypes.byref(o),
+                                 ctypes.byref(rep) if rep is not None else None, _stream(stream)), "dpvba_solve", self._h)
+        if rep is None:
+            return None
+        (torch.cuda.current_stream() if stream is None else stream).synchronize()
+        return rep.to_dict()

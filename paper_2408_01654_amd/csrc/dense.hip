@@ -1,0 +1,341 @@
+// Damped solve of the reduced camera system S dxi = s (DPV-SLAM Appendix A:
+// the Cholesky factorisation of the pose block of the Schur complement).
+//
+// S is dense row-major n x n; only its lower triangle is read.  Two paths:
+//  * small n: one workgroup factors S in LDS (packed lower triangle) and runs
+//    both triangular solves;
+//  * large n: blocked right-looking Cholesky with 64-wide panels (diagonal
+//    block factor and inverse, panel solve as a product with that inverse,
+//    trailing symmetric update), then blocked triangular solves that reuse the
+//    stored diagonal-block inverses.
+// A pivot that is not positive (or not finite) sets *status and is replaced
+// by 1 so the arithmetic stays finite; the caller then discards the step.
+// min_pivot receives the smallest L_ii^2 / S_ii (as ordered bits of a
+// non-negative float, combined with an integer atomic minimum, which is
+// order-independent).
+#include "common.h"
+
+namespace dpvba {
+
+constexpr int kNB = 64;
+
+__device__ __forceinline__ void pivot_min(unsigned int* min_bits, float ratio) {
+  if (!(ratio >= 0.f)) ratio = 0.f;
+  atomicMin(min_bits, __float_as_uint(ratio));
+}
+
+// ------------------------------------------------------------------ small path
+
+template <typename T>
+__global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const T* rhs, int n, T* dx,
+                                                               int* status, unsigned int* min_bits) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T* A = reinterpret_cast<T*>(dyn_lds);  // packed lower, row i at i(i+1)/2
+  T* b = A + n * (n + 1) / 2;
+  T* d0 = b + n;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) {
+    const T* row = S + (size_t)i * n;
+    T* dst = A + i * (i + 1) / 2;
+    for (int j = 0; j <= i; ++j) dst[j] = row[j];
+    b[i] = rhs[i];
+    d0[i] = row[i];
+  }
+  __syncthreads();
+  __shared__ int bad;
+  __shared__ float minr;
+  if (tid == 0) { bad = 0; minr = 3.0e38f; }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const int jj = j * (j + 1) / 2 + j;
+    if (tid == 0) {
+      T piv = A[jj];
+      const float ratio = (float)(piv / d0[j]);
+      if (ratio < minr || !(ratio == ratio)) minr = ratio == ratio ? ratio : 0.f;
+      if (!(piv > (T)0) || !(piv < (T)3.0e38)) { bad = 1; piv = (T)1; }
+      A[jj] = dsqrt(piv);
+    }
+    __syncthreads();
+    const T ljj = A[jj];
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) A[i * (i + 1) / 2 + j] /= ljj;
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int idx = tid; idx < m * m; idx += blockDim.x) {
+      const int i = j + 1 + idx / m, k = j + 1 + idx % m;
+      if (k <= i) A[i * (i + 1) / 2 + k] -= A[i * (i + 1) / 2 + j] * A[k * (k + 1) / 2 + j];
+    }
+    __syncthreads();
+  }
+  // forward: L y = b
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) b[j] /= A[j * (j + 1) / 2 + j];
+    __syncthreads();
+    const T yj = b[j];
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) b[i] -= A[i * (i + 1) / 2 + j] * yj;
+    __syncthreads();
+  }
+  // backward: L^T x = y
+  for (int j = n - 1; j >= 0; --j) {
+    if (tid == 0) b[j] /= A[j * (j + 1) / 2 + j];
+    __syncthreads();
+    const T xj = b[j];
+    const T* rowj = A + j * (j + 1) / 2;
+    for (int i = tid; i < j; i += blockDim.x) b[i] -= rowj[i] * xj;
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += blockDim.x) dx[i] = bad ? (T)0 : b[i];
+  if (tid == 0) {
+    if (bad) atomicOr(status, 1);
+    pivot_min(min_bits, minr);
+  }
+}
+
+// ------------------------------------------------------------------ large path
+
+// Factor the diagonal block at k0 (kb <= 64) in LDS, write L back, and write
+// inv(L_kk) (lower, kb x kb, stride 64) to Linv.
+template <typename T>
+__global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, int kb, T* Linv, const T* d0,
+                                                         int* status, unsigned int* min_bits) {
+  __shared__ T A[kNB][kNB + 1];
+  __shared__ T X[kNB][kNB + 1];
+  __shared__ int bad;
+  __shared__ float minr;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
+    const int r = idx / kb, c = idx % kb;
+    A[r][c] = c <= r ? S[(size_t)(k0 + r) * n + k0 + c] : (T)0;
+  }
+  if (tid == 0) { bad = 0; minr = 3.0e38f; }
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    if (tid == 0) {
+      T piv = A[j][j];
+      const float ratio = (float)(piv / d0[k0 + j]);
+      if (ratio < minr || !(ratio == ratio)) minr = ratio == ratio ? ratio : 0.f;
+      if (!(piv > (T)0) || !(piv < (T)3.0e38)) { bad = 1; piv = (T)1; }
+      A[j][j] = dsqrt(piv);
+    }
+    __syncthreads();
+    const T ljj = A[j][j];
+    for (int i = j + 1 + tid; i < kb; i += blockDim.x) A[i][j] /= ljj;
+    __syncthreads();
+    const int m = kb - j - 1;
+    for (int idx = tid; idx < m * m; idx += blockDim.x) {
+      const int i = j + 1 + idx / m, k = j + 1 + idx % m;
+      if (k <= i) A[i][k] -= A[i][j] * A[k][j];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower factor, one column per thread: L X = I
+  for (int c = tid; c < kb; c += blockDim.x) {
+    for (int r = 0; r < kb; ++r) {
+      if (r < c) { X[r][c] = (T)0; continue; }
+      T v = r == c ? (T)1 : (T)0;
+      for (int m = c; m < r; ++m) v -= A[r][m] * X[m][c];
+      X[r][c] = v / A[r][r];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
+    const int r = idx / kb, c = idx % kb;
+    if (c <= r) S[(size_t)(k0 + r) * n + k0 + c] = A[r][c];
+    Linv[r * kNB + c] = X[r][c];
+  }
+  if (tid == 0) {
+    if (bad) atomicOr(status, 1);
+    pivot_min(min_bits, minr);
+  }
+}
+
+// Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
+// block per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int k0, int kb, const T* Linv) {
+  __shared__ T Ab[kNB][kNB + 1];
+  __shared__ T Li[kNB][kNB + 1];
+  const int i0 = k0 + kb + blockIdx.x * kNB;
+  const int rows = min(kNB, n - i0);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kNB * kNB; idx += blockDim.x) {
+    const int r = idx / kNB, c = idx % kNB;
+    Ab[r][c] = (r < rows && c < kb) ? S[(size_t)(i0 + r) * n + k0 + c] : (T)0;
+    Li[r][c] = (r < kb && c < kb) ? Linv[r * kNB + c] : (T)0;
+  }
+  __syncthreads();
+  // out[r][c] = sum_m Ab[r][m] * Li[c][m],  m <= c
+  for (int idx = tid; idx < rows * kb; idx += blockDim.x) {
+    const int r = idx / kb, c = idx % kb;
+    T v = (T)0;
+    for (int m = 0; m <= c; ++m) v += Ab[r][m] * Li[c][m];
+    S[(size_t)(i0 + r) * n + k0 + c] = v;
+  }
+}
+
+// Trailing update A_IJ -= L_Ik L_Jk^T for 64x64 blocks I >= J of the trailing
+// matrix; blockIdx.x enumerates the lower block pairs.
+template <typename T>
+__global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, int kb) {
+  __shared__ T Li[kNB][kNB + 1];
+  __shared__ T Lj[kNB][kNB + 1];
+  const int t0 = k0 + kb;
+  const int blk = blockIdx.x;
+  int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > blk) --I;
+  while ((I + 1) * (I + 2) / 2 <= blk) ++I;
+  const int J = blk - I * (I + 1) / 2;
+  const int i0 = t0 + I * kNB, j0 = t0 + J * kNB;
+  const int ri = min(kNB, n - i0), rj = min(kNB, n - j0);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kNB * kNB; idx += blockDim.x) {
+    const int r = idx / kNB, c = idx % kNB;
+    Li[r][c] = (r < ri && c < kb) ? S[(size_t)(i0 + r) * n + k0 + c] : (T)0;
+    Lj[r][c] = (r < rj && c < kb) ? S[(size_t)(j0 + r) * n + k0 + c] : (T)0;
+  }
+  __syncthreads();
+  // each thread: a 4x4 patch of the 64x64 output
+  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+  T acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+  for (int m = 0; m < kb; ++m) {
+    T x[4], y[4];
+    for (int a = 0; a < 4; ++a) { x[a] = Li[tr + a][m]; y[a] = Lj[tc + a][m]; }
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+  }
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const int r = tr + a, c = tc + b;
+      if (r < ri && c < rj && (I != J || c <= r)) S[(size_t)(i0 + r) * n + j0 + c] -= acc[a][b];
+    }
+}
+
+// Forward solve step for block k: y_k = inv(L_kk) b_k (every workgroup computes
+// it; workgroup 0 stores it), then workgroup w >= 1 updates block k + w:
+// b_i -= L_ik y_k.
+template <typename T>
+__global__ void __launch_bounds__(256) trsv_fwd_kernel(const T* S, int n, int k, const T* Linv_all, T* b,
+                                                       T* y) {
+  __shared__ T yk[kNB];
+  const int k0 = k * kNB, kb = min(kNB, n - k0);
+  const T* Li = Linv_all + (size_t)k * kNB * kNB;
+  const int tid = threadIdx.x;
+  if (tid < kb) {
+    T v = (T)0;
+    for (int m = 0; m <= tid; ++m) v += Li[tid * kNB + m] * b[k0 + m];
+    yk[tid] = v;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid < kb) y[k0 + tid] = yk[tid];
+    return;
+  }
+  const int i0 = k0 + blockIdx.x * kNB;
+  const int rows = min(kNB, n - i0);
+  // 4 threads per row, fixed split of the kb columns, combined in order
+  __shared__ T part[kNB][4];
+  const int r = tid / 4, q = tid % 4;
+  T v = (T)0;
+  if (r < rows) {
+    const T* row = S + (size_t)(i0 + r) * n + k0;
+    for (int m = q; m < kb; m += 4) v += row[m] * yk[m];
+  }
+  part[r][q] = v;
+  __syncthreads();
+  if (tid < rows) b[i0 + tid] -= ((part[tid][0] + part[tid][1]) + (part[tid][2] + part[tid][3]));
+}
+
+// Backward solve step for block k: x_k = inv(L_kk)^T y_k (y_k already reduced
+// by all later blocks), then workgroup w >= 1 updates block w - 1 < k:
+// y_j -= L_kj^T x_k.
+template <typename T>
+__global__ void __launch_bounds__(256) trsv_bwd_kernel(const T* S, int n, int k, const T* Linv_all, T* y,
+                                                       T* x) {
+  __shared__ T xk[kNB];
+  const int k0 = k * kNB, kb = min(kNB, n - k0);
+  const T* Li = Linv_all + (size_t)k * kNB * kNB;
+  const int tid = threadIdx.x;
+  if (tid < kb) {
+    T v = (T)0;
+    for (int m = tid; m < kb; ++m) v += Li[m * kNB + tid] * y[k0 + m];
+    xk[tid] = v;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid < kb) x[k0 + tid] = xk[tid];
+    return;
+  }
+  const int j0 = (blockIdx.x - 1) * kNB;
+  const int cols = min(kNB, n - j0);
+  __shared__ T part[4][kNB];
+  const int c = tid % kNB, q = tid / kNB;
+  T v = (T)0;
+  if (c < cols) {
+    for (int m = q; m < kb; m += 4) v += S[(size_t)(k0 + m) * n + j0 + c] * xk[m];
+  }
+  part[q][c] = v;
+  __syncthreads();
+  if (tid < cols) y[j0 + tid] -= ((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]));
+}
+
+template <typename T>
+__global__ void zero_on_status_kernel(T* dx, int n, const int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && *status) dx[i] = (T)0;
+}
+
+template <typename T>
+__global__ void copy_vec_kernel(const T* src, T* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ launchers
+
+int small_solve_max_n(int tsize) { return tsize == 4 ? 240 : 160; }
+
+int small_solve_lds_bytes(int n, int tsize) { return (n * (n + 1) / 2 + 2 * n) * tsize; }
+
+template <typename T>
+hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* work_y, T* Linv_all, const T* d0,
+                             int* status, unsigned int* min_bits, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (n <= small_solve_max_n(sizeof(T))) {
+    {
+      hipError_t e = opt_in_lds((const void*)small_chol_solve_kernel<T>, small_solve_lds_bytes(n, sizeof(T)));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((small_chol_solve_kernel<T>), dim3(1), dim3(256), small_solve_lds_bytes(n, sizeof(T)),
+                       st, S, rhs, n, dx, status, min_bits);
+    return hipGetLastError();
+  }
+  const int nblk = (n + kNB - 1) / kNB;
+  for (int k = 0; k < nblk; ++k) {
+    const int k0 = k * kNB, kb = min(kNB, n - k0);
+    T* Linv = Linv_all + (size_t)k * kNB * kNB;
+    hipLaunchKernelGGL((potrf_diag_kernel<T>), dim3(1), dim3(256), 0, st, S, n, k0, kb, Linv, d0, status,
+                       min_bits);
+    const int rest = nblk - k - 1;
+    if (rest > 0) {
+      hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(rest), dim3(256), 0, st, S, n, k0, kb, Linv);
+      hipLaunchKernelGGL((syrk_update_kernel<T>), dim3(rest * (rest + 1) / 2), dim3(256), 0, st, S, n, k0,
+                         kb);
+    }
+  }
+  hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, rhs, work_b, n);
+  for (int k = 0; k < nblk; ++k)
+    hipLaunchKernelGGL((trsv_fwd_kernel<T>), dim3(nblk - k), dim3(256), 0, st, S, n, k, Linv_all, work_b,
+                       work_y);
+  for (int k = nblk - 1; k >= 0; --k)
+    hipLaunchKernelGGL((trsv_bwd_kernel<T>), dim3(k + 1), dim3(256), 0, st, S, n, k, Linv_all, work_y, dx);
+  hipLaunchKernelGGL((zero_on_status_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, dx, n, status);
+  return hipGetLastError();
+}
+
+template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, float*, float*, float*,
+                                             const float*, int*, unsigned int*, hipStream_t);
+template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, double*,
+                                              const double*, int*, unsigned int*, hipStream_t);
+
+}  // namespace dpvba
