@@ -118,8 +118,11 @@ typedef struct {
  *                   accumulated in float64.
  *   n_invalid[t]    invalid edges at iterate t (t < n_iters).
  *   min_pivot[t]    smallest L_ii^2 / S_ii of the Cholesky at iteration t.
- *   status          DPVBA_OK, or DPVBA_ENOTPD if a pivot was not positive
- *                   (that iteration's step is then zero).                  */
+ *   status          DPVBA_OK, DPVBA_ENOTPD if a pivot was not positive
+ *                   (that iteration's step is then zero), or DPVBA_EHIP if
+ *                   a bounded device-wide wait of the single-launch solver
+ *                   expired (the results are then invalid and the context
+ *                   must be destroyed).                                    */
 typedef struct {
   int32_t status;
   int32_t n_iters;
@@ -146,6 +149,41 @@ void dpvba_destroy(dpvba_ctx* ctx);
  * Returns EINVAL on any index or ownership violation, ENOMEM on allocation
  * failure.                                                                */
 dpvba_status dpvba_analyze(dpvba_ctx* ctx, const dpvba_graph* g, void* stream);
+
+/* Tile-shape choice of the analysis (host).  A tile is a run of at most
+ * tile_patches_* patches of one source frame; 0 selects the default (96 for
+ * the float32 plan, 32 for the float64 plan).  Larger tiles write smaller
+ * partial systems; smaller tiles expose more workgroups.  Both plans are
+ * built by every analysis.                                                */
+typedef struct {
+  int32_t tile_patches_fp32;
+  int32_t tile_patches_fp64;
+} dpvba_tuning;
+
+/* dpvba_analyze with explicit tile shapes (tune may be NULL).  EINVAL for
+ * negative entries.                                                       */
+dpvba_status dpvba_analyze_ex(dpvba_ctx* ctx, const dpvba_graph* g, const dpvba_tuning* tune,
+                              void* stream);
+
+/* Sizes of the plan that the last successful analysis built for one
+ * precision (host struct).
+ *   n_tiles        tiles (runs of one source frame's patches).
+ *   n_free         free poses N - n_fixed; the reduced system is 6 n_free.
+ *   part_S_elems   elements of the tiles' partial reduced systems.
+ *   part_vec_elems elements of the tiles' partial right-hand sides and
+ *                  damping diagonals.
+ *   grid_cells     (patch, target slot) cells of all tiles (>= n_edges).
+ *   u_elems        elements of the stored Schur rows.
+ *   lds_bytes      shared memory of the largest tile.
+ * Returns EINVAL for a bad precision, ESTATE before a successful analysis. */
+typedef struct {
+  int32_t n_tiles, n_free;
+  int64_t part_S_elems, part_vec_elems, grid_cells, u_elems;
+  int32_t lds_bytes, pad;
+} dpvba_analysis_info;
+
+dpvba_status dpvba_get_analysis_info(const dpvba_ctx* ctx, int32_t precision,
+                                     dpvba_analysis_info* info);
 
 /* Reprojection of every edge's whole patch (eq. 2) with the patch's one
  * inverse depth.
@@ -177,10 +215,37 @@ dpvba_status dpvba_reduced_system(dpvba_ctx* ctx, const dpvba_graph* g, const fl
  *              renormalised): float32, or float64 when opts->precision is
  *              DPVBA_FP64 (the pointer is then reinterpreted).
  *   inv_depth  [P] read and overwritten, same element type as poses.
- *   report     host memory or NULL.
+ *   report     host memory or NULL; with NULL the final-iterate cost is
+ *              not computed.
  * Needs dpvba_analyze on this graph.                                      */
 dpvba_status dpvba_solve(dpvba_ctx* ctx, const dpvba_graph* g, float* poses, float* inv_depth,
                          const dpvba_opts* opts, dpvba_report* report, void* stream);
+
+/* Phase timing with HIP events (tracing).  While tracing is on, the
+ * numeric calls record an event pair on their stream around every
+ * `sample_every`-th launch of each phase (sample_every >= 1); the pairs are
+ * resolved by dpvba_trace_end.  Phases: tile assembly of the reduced system;
+ * its gather into the dense damped matrix; the Cholesky factorisation and
+ * triangular solves; depth back-substitution; pose retraction; final cost.
+ * dpvba_trace_begin creates the events (it may allocate host and driver
+ * resources); it returns EINVAL for sample_every < 1 or max_pairs < 1.   */
+typedef enum {
+  DPVBA_PHASE_ASSEMBLE = 0,
+  DPVBA_PHASE_GATHER = 1,
+  DPVBA_PHASE_FACTOR = 2,
+  DPVBA_PHASE_BACKSUB = 3,
+  DPVBA_PHASE_RETRACT = 4,
+  DPVBA_PHASE_COST = 5,
+  DPVBA_N_PHASES = 6
+} dpvba_phase;
+
+dpvba_status dpvba_trace_begin(dpvba_ctx* ctx, int32_t sample_every, int32_t max_pairs);
+
+/* Stop tracing: waits for the recorded events and writes, per phase, the
+ * summed duration of the sampled launches in milliseconds, the number of
+ * sampled launches and the number of launches seen (host arrays of
+ * DPVBA_N_PHASES entries; any may be NULL).                               */
+dpvba_status dpvba_trace_end(dpvba_ctx* ctx, double* ms, int32_t* n_sampled, int64_t* n_launched);
 
 /* Text of the last HIP failure seen by a call on this context (the failing
  * call and HIP's message), "" if none.  Owned by the context.             */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdpvba.so")
 DPVBA_OK, DPVBA_EINVAL, DPVBA_ENOTPD, DPVBA_ENOMEM, DPVBA_EHIP, DPVBA_ESTATE = range(6)
 FP32, FP64 = 0, 2
 MAX_ITERS = 32
+PHASES = ("assemble", "gather", "factor", "backsub", "retract", "cost")
 
 
 class DpvbaError(RuntimeError):
@@ -39,6 +40,16 @@ class Graph(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("n_iters", ctypes.c_int32), ("precision", ctypes.c_int32), ("lambda_", ctypes.c_double),
                 ("z_min", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class AnalysisInfo(ctypes.Structure):
+    _fields_ = [("n_tiles", ctypes.c_int32), ("n_free", ctypes.c_int32), ("part_S_elems", ctypes.c_int64),
+                ("part_vec_elems", ctypes.c_int64), ("grid_cells", ctypes.c_int64), ("u_elems", ctypes.c_int64),
+                ("lds_bytes", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_patches_fp32", ctypes.c_int32), ("tile_patches_fp64", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -77,6 +88,14 @@ def lib():
         L.dpvba_solve.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts),
                                   ctypes.POINTER(Report), vp]
         L.dpvba_solve.restype = ctypes.c_int
+        L.dpvba_trace_begin.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        L.dpvba_trace_begin.restype = ctypes.c_int
+        L.dpvba_trace_end.argtypes = [vp, vp, vp, vp]
+        L.dpvba_trace_end.restype = ctypes.c_int
+        L.dpvba_analyze_ex.argtypes = [vp, ctypes.POINTER(Graph), ctypes.POINTER(Tuning), vp]
+        L.dpvba_analyze_ex.restype = ctypes.c_int
+        L.dpvba_get_analysis_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(AnalysisInfo)]
+        L.dpvba_get_analysis_info.restype = ctypes.c_int
         L.dpvba_last_error.argtypes = [vp]
         L.dpvba_last_error.restype = ctypes.c_char_p
         L.dpvba_status_string.argtypes = [ctypes.c_int]
@@ -159,10 +178,17 @@ class Context:
         except Exception:
             pass
 
-    def analyze(self, g: GraphTensors, stream=None):
+    def analyze(self, g: GraphTensors, stream=None, tile_patches_fp32=0, tile_patches_fp64=0):
         gs = g.struct()
-        _check(lib().dpvba_analyze(self._h, ctypes.byref(gs), _stream(stream)), "dpvba_analyze", self._h)
+        tune = Tuning(int(tile_patches_fp32), int(tile_patches_fp64))
+        _check(lib().dpvba_analyze_ex(self._h, ctypes.byref(gs), ctypes.byref(tune), _stream(stream)),
+               "dpvba_analyze", self._h)
         self._graph = g
+
+    def analysis_info(self, precision=FP32) -> dict:
+        info = AnalysisInfo()
+        _check(lib().dpvba_get_analysis_info(self._h, int(precision), ctypes.byref(info)), "dpvba_get_analysis_info")
+        return {f: getattr(info, f) for f, _ in AnalysisInfo._fields_}
 
     def reproject(self, g: GraphTensors, poses, inv_depth, z_min=0.1, stream=None):
         E, p = g.ii.shape[0], g.patches.shape[1]
@@ -210,3 +236,16 @@ class Context:
             return None
         (torch.cuda.current_stream() if stream is None else stream).synchronize()
         return rep.to_dict()
+
+    def trace_begin(self, sample_every: int = 1, max_pairs: int = 1 << 16):
+        _check(lib().dpvba_trace_begin(self._h, int(sample_every), int(max_pairs)), "dpvba_trace_begin", self._h)
+
+    def trace_end(self):
+        """Per phase: (summed ms of sampled launches, sampled count, launches seen)."""
+        n = len(PHASES)
+        ms = (ctypes.c_double * n)()
+        ns = (ctypes.c_int32 * n)()
+        nl = (ctypes.c_int64 * n)()
+        _check(lib().dpvba_trace_end(self._h, ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(ns, ctypes.c_void_p),
+                                     ctypes.cast(nl, ctypes.c_void_p)), "dpvba_trace_end", self._h)
+        return {PHASES[p]: (ms[p], ns[p], nl[p]) for p in range(n)}

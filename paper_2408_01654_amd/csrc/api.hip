@@ -12,19 +12,28 @@
 #include <new>
 #include <vector>
 
-#include "../../include/dpvba.h"
+#include "dpvba.h"
 #include "layout.h"
+#include "tileargs.h"
 
 namespace dpvba {
 
-// kernels (assemble.hip, dense.hip)
-template <typename T, typename P> struct TileArgs;
-template <typename T, typename P>
-hipError_t launch_tile_assemble(const TileArgs<T, P>& A, int n_tiles, int lds_bytes, hipStream_t st);
-template <typename T, typename P>
-hipError_t launch_tile_backsub(const TileArgs<T, P>& A, int n_tiles, int lds_bytes, hipStream_t st);
-template <typename T, typename P>
-hipError_t launch_retract(P* poses, const T* dx, int n_fixed, int n_free, const int* status, hipStream_t st);
+// kernels (tile.hip, assemble.hip, dense.hip)
+template <typename T>
+hipError_t launch_tile_iterate(const IterArgs<T>& A, int lds_bytes, hipStream_t st);
+template <typename T>
+hipError_t launch_tile_finalize(const TileInfo* tiles, int n_tiles, int lds_bytes, const int* tile_patch,
+                                const int* blk_pose, const T* U_s, const T* pscale_s, const T* depth_s,
+                                const T* dx, const int* status, T* depth_out, const T* poses_final,
+                                T* poses_out, int n_frames, hipStream_t st);
+template <typename T>
+hipError_t launch_retract_copy(const T* poses_cur, T* poses_next, const T* dx, int n_fixed, int n_frames,
+                               const int* status, hipStream_t st);
+template <typename T>
+int small_solve_grid(int lds_bytes);
+template <typename T>
+hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, hipStream_t st);
+int small_solve_max_n(int tsize);
 template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
@@ -43,7 +52,7 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* wor
                              int* status, unsigned int* min_bits, hipStream_t st);
 hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st);
 hipError_t launch_report_finalize(dpvba_report* rep, const int* status, const unsigned int* min_bits,
-                                  int n_iters, hipStream_t st);
+                                  int n_iters, const int* err, hipStream_t st);
 
 }  // namespace dpvba
 
@@ -53,9 +62,11 @@ using namespace dpvba;
 
 namespace {
 
-// Shared-memory budget of one tile in float64 (float32 tiles use half).
-constexpr int kLdsBudget64 = 150 * 1024;
-constexpr int kMaxPatchesPerTile = 32;
+// Shared-memory budget of one tile, and default patches per tile for the
+// float32 and float64 plans.
+constexpr int kLdsBudget = 150 * 1024;
+constexpr int kDefaultTilePatches32 = 96;
+constexpr int kDefaultTilePatches64 = 32;
 
 struct DevBuf {
   void* p = nullptr;
@@ -86,6 +97,15 @@ hipError_t upload(DevBuf& b, const std::vector<X>& v, hipStream_t st) {
   return hipStreamSynchronize(st);
 }
 
+// Device copy of one tiling of the patch graph.
+struct Tiling {
+  int n_tiles = 0, lds_bytes = 0, max_w6 = 0;
+  long long part_S = 0, part_vec = 0, u_elems = 0, grid_cells = 0, n_tp = 0;
+  DevBuf tiles, tile_patch, slot_frame, slot_blk, edge_grid, blk_pose, s_off, s_src, v_off, v_src;
+  DevBuf* bufs[10] = {&tiles, &tile_patch, &slot_frame, &slot_blk, &edge_grid, &blk_pose, &s_off, &s_src, &v_off,
+                      &v_src};
+};
+
 }  // namespace
 
 struct dpvba_ctx {
@@ -94,14 +114,39 @@ struct dpvba_ctx {
   bool analysed = false;
   int N = 0, P = 0, E = 0, p = 0, n_fixed = 0, n_free = 0;
   const int32_t *ii = nullptr, *jj = nullptr, *kk = nullptr;
-  int n_tiles = 0;
-  int lds_f32 = 0, lds_f64 = 0;
-  size_t part_S_elems = 0, part_vec_elems = 0;
-  DevBuf tiles, tile_patch, slot_frame, slot_blk, edge_grid, blk_pose, s_off, s_src, v_off, v_src;
+  Tiling tl[2];  // [0] float32 plan, [1] float64 plan
+  int coop_grid32 = 0, coop_lds32 = -1, coop_grid64 = 0, coop_lds64 = -1;  // co-resident workgroups
   // workspace
-  DevBuf part_S, part_vec, part_cost, part_invalid, S, rhs, dB, d0, dx, wb, wy, Linv, edge_part;
+  DevBuf part_S, part_vec, part_cost, part_invalid, U_s, pscale_s, depth_s, xh_s, poses_a, poses_b;
+  DevBuf S, rhs, dB, d0, dx, wb, wy, Linv, edge_part, ticket, dev_err;
   DevBuf status, min_bits, devrep;
   char err[256] = {0};
+  // tracing
+  bool tracing = false;
+  int trace_every = 1;
+  std::vector<hipEvent_t> ev;       // 2 per pair
+  std::vector<int> ev_phase;        // phase per pair
+  int ev_used = 0;
+  long long seen[DPVBA_N_PHASES] = {0};
+  int open_pair = -1;
+};
+
+// Trace scope: records an event pair around one phase when sampled.
+struct TraceScope {
+  dpvba_ctx* c;
+  hipStream_t st;
+  int pair = -1;
+  TraceScope(dpvba_ctx* c_, int phase, hipStream_t st_) : c(c_), st(st_) {
+    if (!c->tracing) return;
+    const long long n = c->seen[phase]++;
+    if (n % c->trace_every != 0 || c->ev_used * 2 + 2 > (int)c->ev.size()) return;
+    pair = c->ev_used++;
+    c->ev_phase[pair] = phase;
+    (void)hipEventRecord(c->ev[2 * pair], st);
+  }
+  ~TraceScope() {
+    if (pair >= 0) (void)hipEventRecord(c->ev[2 * pair + 1], st);
+  }
 };
 
 static void record_error(dpvba_ctx* c, hipError_t e, const char* where) {
@@ -126,6 +171,56 @@ static dpvba_status hip_status(hipError_t e) {
 extern "C" {
 
 const char* dpvba_last_error(const dpvba_ctx* c) { return c ? c->err : ""; }
+
+dpvba_status dpvba_get_analysis_info(const dpvba_ctx* c, int32_t precision, dpvba_analysis_info* info) {
+  if (!c || !info || (precision != DPVBA_FP32 && precision != DPVBA_FP64)) return DPVBA_EINVAL;
+  if (!c->analysed) return DPVBA_ESTATE;
+  const Tiling& t = c->tl[precision == DPVBA_FP64 ? 1 : 0];
+  info->n_tiles = t.n_tiles;
+  info->n_free = c->n_free;
+  info->part_S_elems = t.part_S;
+  info->part_vec_elems = t.part_vec;
+  info->grid_cells = t.grid_cells;
+  info->u_elems = t.u_elems;
+  info->lds_bytes = t.lds_bytes;
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_trace_begin(dpvba_ctx* c, int32_t sample_every, int32_t max_pairs) {
+  if (!c || sample_every < 1 || max_pairs < 1) return DPVBA_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  if ((int)c->ev.size() < 2 * max_pairs) {
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.assign(2 * (size_t)max_pairs, nullptr);
+    for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+    c->ev_phase.assign(max_pairs, 0);
+  }
+  c->trace_every = sample_every;
+  c->ev_used = 0;
+  for (long long& x : c->seen) x = 0;
+  c->tracing = true;
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_trace_end(dpvba_ctx* c, double* ms, int32_t* n_sampled, int64_t* n_launched) {
+  if (!c || !c->tracing) return DPVBA_EINVAL;
+  c->tracing = false;
+  double tot[DPVBA_N_PHASES] = {0};
+  int cnt[DPVBA_N_PHASES] = {0};
+  for (int q = 0; q < c->ev_used; ++q) {
+    HIP_TRY(hipEventSynchronize(c->ev[2 * q + 1]));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, c->ev[2 * q], c->ev[2 * q + 1]));
+    tot[c->ev_phase[q]] += t;
+    cnt[c->ev_phase[q]]++;
+  }
+  for (int p = 0; p < DPVBA_N_PHASES; ++p) {
+    if (ms) ms[p] = tot[p];
+    if (n_sampled) n_sampled[p] = cnt[p];
+    if (n_launched) n_launched[p] = c->seen[p];
+  }
+  return DPVBA_OK;
+}
 
 const char* dpvba_status_string(dpvba_status s) {
   switch (s) {
@@ -154,12 +249,15 @@ dpvba_status dpvba_create(dpvba_ctx** out, int32_t device) {
 void dpvba_destroy(dpvba_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  DevBuf* bufs[] = {&c->tiles, &c->tile_patch, &c->slot_frame, &c->slot_blk, &c->edge_grid, &c->blk_pose,
-                    &c->s_off, &c->s_src, &c->v_off, &c->v_src, &c->part_S, &c->part_vec, &c->part_cost,
-                    &c->part_invalid, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx, &c->wb, &c->wy, &c->Linv,
-                    &c->edge_part, &c->status, &c->min_bits, &c->devrep};
+  DevBuf* bufs[] = {&c->part_S, &c->part_vec, &c->part_cost, &c->part_invalid, &c->U_s, &c->pscale_s,
+                    &c->depth_s, &c->xh_s, &c->poses_a, &c->poses_b, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx,
+                    &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  for (Tiling& t : c->tl)
+    for (DevBuf* b : t.bufs)
+      if (b->p) (void)hipFree(b->p);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -175,8 +273,179 @@ static bool graph_sizes_ok(const dpvba_graph* g) {
   return true;
 }
 
-dpvba_status dpvba_analyze(dpvba_ctx* c, const dpvba_graph* g, void* stream) {
+// Host copy of one tiling.
+struct HostTiling {
+  std::vector<TileInfo> tiles;
+  std::vector<int32_t> tile_patch, slot_frame, slot_blk, edge_grid, blk_pose, s_off, s_src, v_off;
+  std::vector<int2> v_src;
+  long long part_S = 0, part_vec = 0, u_elems = 0;
+  int lds = 0, max_w6 = 0;
+};
+
+// Split each source frame's patches into tiles of at most `kcap` patches
+// whose shared-memory plan (element size tsize) fits the budget, then build
+// the gather lists.  Returns false if one patch alone does not fit.
+static bool plan_tiling(int N, int nf, const std::vector<int32_t>& jj, const std::vector<int32_t>& pcount,
+                        const std::vector<int32_t>& pedges, const std::vector<std::vector<int32_t>>& frame_patches,
+                        int kcap, int tsize, HostTiling& H) {
+  const int n_free = N - nf;
+  auto patch_mult = [&](int k, std::map<int, int>& m) {
+    for (int q = pcount[k]; q < pcount[k + 1]; ++q) m[jj[pedges[q]]]++;
+  };
+  auto plan_of = [&](const std::map<int, int>& mult, int frame, int& Tn, int& nb, int& mm) {
+    Tn = 0;
+    mm = 1;
+    nb = frame >= nf ? 1 : 0;
+    for (auto& kv : mult) {
+      Tn += kv.second;
+      mm = std::max(mm, kv.second);
+      if (kv.first >= nf) nb++;
+    }
+  };
+  auto emit = [&](int frame, const std::vector<int32_t>& pl, const std::map<int, int>& mult) {
+    TileInfo t{};
+    t.frame = frame;
+    t.n_patch = (int)pl.size();
+    t.patch_begin = (int)H.tile_patch.size();
+    t.slot_begin = (int)H.slot_frame.size();
+    t.grid_begin = (int)H.edge_grid.size();
+    t.blk_begin = (int)H.blk_pose.size();
+    std::vector<int> blocks;
+    if (frame >= nf) blocks.push_back(frame);
+    for (auto& kv : mult)
+      if (kv.first >= nf) blocks.push_back(kv.first);
+    std::sort(blocks.begin(), blocks.end());
+    auto blk_of = [&](int pose) -> int {
+      auto it = std::lower_bound(blocks.begin(), blocks.end(), pose);
+      return (it != blocks.end() && *it == pose) ? (int)(it - blocks.begin()) : -1;
+    };
+    t.src_blk = blk_of(frame);
+    t.n_blk = (int)blocks.size();
+    std::map<int, int> first_slot;
+    int Tn = 0, mm = 1;
+    for (auto& kv : mult) {
+      first_slot[kv.first] = Tn;
+      mm = std::max(mm, kv.second);
+      for (int m = 0; m < kv.second; ++m) {
+        H.slot_frame.push_back(kv.first);
+        H.slot_blk.push_back(blk_of(kv.first));
+      }
+      Tn += kv.second;
+    }
+    t.n_slot = Tn;
+    t.max_mult = mm;
+    for (int b : blocks) H.blk_pose.push_back(b - nf);
+    const size_t g0 = H.edge_grid.size();
+    H.edge_grid.resize(g0 + (size_t)t.n_patch * Tn, -1);
+    for (int lp = 0; lp < t.n_patch; ++lp) {
+      const int k = pl[lp];
+      H.tile_patch.push_back(k);
+      std::map<int, int> used;
+      for (int q = pcount[k]; q < pcount[k + 1]; ++q) {
+        const int e = pedges[q];
+        const int s = first_slot[jj[e]] + used[jj[e]]++;
+        H.edge_grid[g0 + (size_t)lp * Tn + s] = e;
+      }
+    }
+    t.part_begin = (int)H.part_S;
+    t.vec_begin = (int)H.part_vec;
+    t.u_begin = (int)H.u_elems;
+    H.part_S += (long long)t.n_blk * (t.n_blk + 1) / 2 * 36;
+    H.part_vec += 12LL * t.n_blk;
+    H.u_elems += (long long)t.n_patch * 6 * t.n_blk;
+    H.lds = std::max(H.lds, tile_lds_bytes(t.n_patch, Tn, t.n_blk, tsize));
+    H.max_w6 = std::max(H.max_w6, 6 * t.n_blk);
+    H.tiles.push_back(t);
+  };
+  for (int f = 0; f < N; ++f) {
+    std::vector<int32_t> cur;
+    std::map<int, int> cur_mult;
+    for (int k : frame_patches[f]) {
+      std::map<int, int> km;
+      patch_mult(k, km);
+      std::map<int, int> merged = cur_mult;
+      for (auto& kv : km) merged[kv.first] = std::max(merged[kv.first], kv.second);
+      int Tn, nb, mm;
+      plan_of(merged, f, Tn, nb, mm);
+      const bool fits = Tn <= kMaxSlots && (int)cur.size() + 1 <= kcap &&
+                        tile_lds_bytes((int)cur.size() + 1, Tn, nb, tsize) <= kLdsBudget;
+      if (!fits) {
+        if (cur.empty()) return false;
+        emit(f, cur, cur_mult);
+        cur.clear();
+        cur_mult.clear();
+        merged = km;
+        plan_of(merged, f, Tn, nb, mm);
+        if (!(Tn <= kMaxSlots && tile_lds_bytes(1, Tn, nb, tsize) <= kLdsBudget)) return false;
+      }
+      cur.push_back(k);
+      cur_mult = merged;
+    }
+    if (!cur.empty()) emit(f, cur, cur_mult);
+  }
+  if (H.part_S > INT32_MAX || H.part_vec > INT32_MAX || H.u_elems > INT32_MAX) return false;
+  // gather lists: lower block (P >= Q) -> tile partial offsets, in tile order
+  const long long n_lb = (long long)n_free * (n_free + 1) / 2;
+  H.s_off.assign(n_lb + 1, 0);
+  H.v_off.assign(n_free + 1, 0);
+  for (const TileInfo& t : H.tiles) {
+    for (int a = 0; a < t.n_blk; ++a)
+      for (int b = a; b < t.n_blk; ++b) {
+        const long long Pp = H.blk_pose[t.blk_begin + b], Qq = H.blk_pose[t.blk_begin + a];
+        H.s_off[Pp * (Pp + 1) / 2 + Qq + 1]++;
+      }
+    for (int a = 0; a < t.n_blk; ++a) H.v_off[H.blk_pose[t.blk_begin + a] + 1]++;
+  }
+  for (long long q = 0; q < n_lb; ++q) H.s_off[q + 1] += H.s_off[q];
+  for (int q = 0; q < n_free; ++q) H.v_off[q + 1] += H.v_off[q];
+  H.s_src.assign(H.s_off[n_lb], 0);
+  H.v_src.assign(H.v_off[n_free], make_int2(0, 0));
+  std::vector<int32_t> cs(H.s_off.begin(), H.s_off.end() - 1), cv(H.v_off.begin(), H.v_off.end() - 1);
+  for (const TileInfo& t : H.tiles) {
+    for (int a = 0; a < t.n_blk; ++a)
+      for (int b = a; b < t.n_blk; ++b) {
+        const long long Pp = H.blk_pose[t.blk_begin + b], Qq = H.blk_pose[t.blk_begin + a];
+        H.s_src[cs[Pp * (Pp + 1) / 2 + Qq]++] = t.part_begin + upper_pair_index(a, b, t.n_blk) * 36;
+      }
+    for (int a = 0; a < t.n_blk; ++a) {
+      const int Pp = H.blk_pose[t.blk_begin + a];
+      H.v_src[cv[Pp]++] = make_int2(t.vec_begin + 6 * a, t.vec_begin + 6 * t.n_blk + 6 * a);
+    }
+  }
+  return true;
+}
+
+static hipError_t upload_tiling(Tiling& T_, const HostTiling& H, hipStream_t st) {
+  hipError_t e;
+  if ((e = upload(T_.tiles, H.tiles, st)) != hipSuccess) return e;
+  if ((e = upload(T_.tile_patch, H.tile_patch, st)) != hipSuccess) return e;
+  if ((e = upload(T_.slot_frame, H.slot_frame, st)) != hipSuccess) return e;
+  if ((e = upload(T_.slot_blk, H.slot_blk, st)) != hipSuccess) return e;
+  if ((e = upload(T_.edge_grid, H.edge_grid, st)) != hipSuccess) return e;
+  if ((e = upload(T_.blk_pose, H.blk_pose, st)) != hipSuccess) return e;
+  if ((e = upload(T_.s_off, H.s_off, st)) != hipSuccess) return e;
+  if ((e = upload(T_.s_src, H.s_src, st)) != hipSuccess) return e;
+  if ((e = upload(T_.v_off, H.v_off, st)) != hipSuccess) return e;
+  if ((e = upload(T_.v_src, H.v_src, st)) != hipSuccess) return e;
+  T_.n_tiles = (int)H.tiles.size();
+  T_.lds_bytes = H.lds;
+  T_.max_w6 = H.max_w6;
+  T_.part_S = H.part_S;
+  T_.part_vec = H.part_vec;
+  T_.u_elems = H.u_elems;
+  T_.grid_cells = (long long)H.edge_grid.size();
+  T_.n_tp = (long long)H.tile_patch.size();
+  return hipSuccess;
+}
+
+dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tuning* tune, void* stream) {
   if (!c || !graph_sizes_ok(g)) return DPVBA_EINVAL;
+  int kcap32 = kDefaultTilePatches32, kcap64 = kDefaultTilePatches64;
+  if (tune) {
+    if (tune->tile_patches_fp32 < 0 || tune->tile_patches_fp64 < 0) return DPVBA_EINVAL;
+    if (tune->tile_patches_fp32 > 0) kcap32 = tune->tile_patches_fp32;
+    if (tune->tile_patches_fp64 > 0) kcap64 = tune->tile_patches_fp64;
+  }
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(c->device));
   c->analysed = false;
@@ -204,155 +473,28 @@ dpvba_status dpvba_analyze(dpvba_ctx* c, const dpvba_graph* g, void* stream) {
     std::vector<int32_t> cur(pcount.begin(), pcount.end() - 1);
     for (int e = 0; e < E; ++e) pedges[cur[kk[e]]++] = e;  // stable: original order within a patch
   }
-  // patches with edges, grouped by owner frame (ascending patch index)
   std::vector<std::vector<int32_t>> frame_patches(N);
   for (int k = 0; k < P; ++k)
     if (owner[k] >= 0) frame_patches[owner[k]].push_back(k);
-
-  std::vector<TileInfo> tiles;
-  std::vector<int32_t> tile_patch, slot_frame, slot_blk, edge_grid, blk_pose;
-  long long part_S = 0, part_vec = 0;
-  int max_lds64 = 0, max_lds32 = 0;
-
-  auto patch_mult = [&](int k, std::map<int, int>& m) {
-    for (int q = pcount[k]; q < pcount[k + 1]; ++q) m[jj[pedges[q]]]++;
-  };
-  auto plan_of = [&](const std::map<int, int>& mult, int frame, int& Tn, int& nb) {
-    Tn = 0;
-    nb = frame >= nf ? 1 : 0;
-    for (auto& kv : mult) {
-      Tn += kv.second;
-      if (kv.first >= nf) nb++;
-    }
-  };
-  auto emit_tile = [&](int frame, const std::vector<int32_t>& pl, const std::map<int, int>& mult) {
-    TileInfo t{};
-    t.frame = frame;
-    t.n_patch = (int)pl.size();
-    t.patch_begin = (int)tile_patch.size();
-    t.slot_begin = (int)slot_frame.size();
-    t.grid_begin = (int)edge_grid.size();
-    t.blk_begin = (int)blk_pose.size();
-    // blocks: free poses among {frame} U targets, ascending
-    std::vector<int> blocks;
-    if (frame >= nf) blocks.push_back(frame);
-    for (auto& kv : mult)
-      if (kv.first >= nf) blocks.push_back(kv.first);
-    std::sort(blocks.begin(), blocks.end());
-    auto blk_of = [&](int pose) -> int {
-      auto it = std::lower_bound(blocks.begin(), blocks.end(), pose);
-      return (it != blocks.end() && *it == pose) ? (int)(it - blocks.begin()) : -1;
-    };
-    t.src_blk = blk_of(frame);
-    t.n_blk = (int)blocks.size();
-    std::map<int, int> first_slot;
-    int Tn = 0;
-    for (auto& kv : mult) {
-      first_slot[kv.first] = Tn;
-      for (int m = 0; m < kv.second; ++m) {
-        slot_frame.push_back(kv.first);
-        slot_blk.push_back(blk_of(kv.first));
-      }
-      Tn += kv.second;
-    }
-    t.n_slot = Tn;
-    for (int b : blocks) blk_pose.push_back(b - nf);
-    const size_t g0 = edge_grid.size();
-    edge_grid.resize(g0 + (size_t)t.n_patch * Tn, -1);
-    for (int lp = 0; lp < t.n_patch; ++lp) {
-      const int k = pl[lp];
-      tile_patch.push_back(k);
-      std::map<int, int> used;
-      for (int q = pcount[k]; q < pcount[k + 1]; ++q) {
-        const int e = pedges[q];
-        const int s = first_slot[jj[e]] + used[jj[e]]++;
-        edge_grid[g0 + (size_t)lp * Tn + s] = e;
-      }
-    }
-    t.part_begin = (int)part_S;
-    t.vec_begin = (int)part_vec;
-    part_S += (long long)t.n_blk * (t.n_blk + 1) / 2 * 36;
-    part_vec += 12LL * t.n_blk;
-    max_lds64 = std::max(max_lds64, tile_lds_bytes(t.n_patch, Tn, t.n_blk, 8));
-    max_lds32 = std::max(max_lds32, tile_lds_bytes(t.n_patch, Tn, t.n_blk, 4));
-    tiles.push_back(t);
-  };
-
-  for (int f = 0; f < N; ++f) {
-    std::vector<int32_t> cur;
-    std::map<int, int> cur_mult;
-    for (int k : frame_patches[f]) {
-      std::map<int, int> km;
-      patch_mult(k, km);
-      std::map<int, int> merged = cur_mult;
-      for (auto& kv : km) merged[kv.first] = std::max(merged[kv.first], kv.second);
-      int Tn, nb;
-      plan_of(merged, f, Tn, nb);
-      const bool fits = Tn <= kMaxSlots && (int)cur.size() + 1 <= kMaxPatchesPerTile &&
-                        tile_lds_bytes((int)cur.size() + 1, Tn, nb, 8) <= kLdsBudget64;
-      if (!fits) {
-        if (cur.empty()) return DPVBA_EINVAL;  // one patch alone exceeds the tile limits
-        emit_tile(f, cur, cur_mult);
-        cur.clear();
-        cur_mult.clear();
-        merged = km;
-        plan_of(merged, f, Tn, nb);
-        if (!(Tn <= kMaxSlots && tile_lds_bytes(1, Tn, nb, 8) <= kLdsBudget64)) return DPVBA_EINVAL;
-      }
-      cur.push_back(k);
-      cur_mult = merged;
-    }
-    if (!cur.empty()) emit_tile(f, cur, cur_mult);
-  }
-  if (part_S > INT32_MAX || part_vec > INT32_MAX) return DPVBA_EINVAL;
-
-  // gather lists: lower block (P >= Q) -> tile partial offsets, tile order
-  const long long n_lb = (long long)n_free * (n_free + 1) / 2;
-  std::vector<int32_t> s_off(n_lb + 1, 0), v_off(n_free + 1, 0);
-  for (const TileInfo& t : tiles) {
-    for (int a = 0; a < t.n_blk; ++a)
-      for (int b = a; b < t.n_blk; ++b) {
-        const long long Pp = blk_pose[t.blk_begin + b], Qq = blk_pose[t.blk_begin + a];
-        s_off[Pp * (Pp + 1) / 2 + Qq + 1]++;
-      }
-    for (int a = 0; a < t.n_blk; ++a) v_off[blk_pose[t.blk_begin + a] + 1]++;
-  }
-  for (long long q = 0; q < n_lb; ++q) s_off[q + 1] += s_off[q];
-  for (int q = 0; q < n_free; ++q) v_off[q + 1] += v_off[q];
-  std::vector<int32_t> s_src(s_off[n_lb]);
-  std::vector<int2> v_src(v_off[n_free]);
-  {
-    std::vector<int32_t> cs(s_off.begin(), s_off.end() - 1), cv(v_off.begin(), v_off.end() - 1);
-    for (const TileInfo& t : tiles) {
-      for (int a = 0; a < t.n_blk; ++a)
-        for (int b = a; b < t.n_blk; ++b) {
-          const long long Pp = blk_pose[t.blk_begin + b], Qq = blk_pose[t.blk_begin + a];
-          s_src[cs[Pp * (Pp + 1) / 2 + Qq]++] = t.part_begin + upper_pair_index(a, b, t.n_blk) * 36;
-        }
-      for (int a = 0; a < t.n_blk; ++a) {
-        const int Pp = blk_pose[t.blk_begin + a];
-        v_src[cv[Pp]++] = make_int2(t.vec_begin + 6 * a, t.vec_begin + 6 * t.n_blk + 6 * a);
-      }
-    }
-  }
-
-  HIP_TRY(upload(c->tiles, tiles, st));
-  HIP_TRY(upload(c->tile_patch, tile_patch, st));
-  HIP_TRY(upload(c->slot_frame, slot_frame, st));
-  HIP_TRY(upload(c->slot_blk, slot_blk, st));
-  HIP_TRY(upload(c->edge_grid, edge_grid, st));
-  HIP_TRY(upload(c->blk_pose, blk_pose, st));
-  HIP_TRY(upload(c->s_off, s_off, st));
-  HIP_TRY(upload(c->s_src, s_src, st));
-  HIP_TRY(upload(c->v_off, v_off, st));
-  HIP_TRY(upload(c->v_src, v_src, st));
+  HostTiling H32, H64;
+  if (!plan_tiling(N, nf, jj, pcount, pedges, frame_patches, kcap32, 4, H32)) return DPVBA_EINVAL;
+  if (!plan_tiling(N, nf, jj, pcount, pedges, frame_patches, kcap64, 8, H64)) return DPVBA_EINVAL;
+  HIP_TRY(upload_tiling(c->tl[0], H32, st));
+  HIP_TRY(upload_tiling(c->tl[1], H64, st));
 
   const size_t n = 6 * (size_t)n_free;
   const size_t nblk64 = (n + 63) / 64;
-  HIP_TRY(ensure(c->part_S, (size_t)part_S * 8));
-  HIP_TRY(ensure(c->part_vec, (size_t)part_vec * 8));
-  HIP_TRY(ensure(c->part_cost, tiles.size() * 8));
-  HIP_TRY(ensure(c->part_invalid, tiles.size() * 4));
+  auto mx = [&](long long a, long long b) { return (size_t)std::max(a, b); };
+  HIP_TRY(ensure(c->part_S, std::max(H32.part_S * 4, H64.part_S * 8)));
+  HIP_TRY(ensure(c->part_vec, std::max(H32.part_vec * 4, H64.part_vec * 8)));
+  HIP_TRY(ensure(c->part_cost, mx(H32.tiles.size(), H64.tiles.size()) * 8));
+  HIP_TRY(ensure(c->part_invalid, mx(H32.tiles.size(), H64.tiles.size()) * 4));
+  HIP_TRY(ensure(c->U_s, std::max(H32.u_elems * 4, H64.u_elems * 8)));
+  HIP_TRY(ensure(c->pscale_s, (size_t)P * 2 * 8));
+  HIP_TRY(ensure(c->depth_s, (size_t)P * 8));
+  HIP_TRY(ensure(c->xh_s, (size_t)P * 2 * 8));
+  HIP_TRY(ensure(c->poses_a, (size_t)N * 7 * 8));
+  HIP_TRY(ensure(c->poses_b, (size_t)N * 7 * 8));
   HIP_TRY(ensure(c->S, n * n * 8));
   HIP_TRY(ensure(c->rhs, n * 8));
   HIP_TRY(ensure(c->dB, n * 8));
@@ -362,19 +504,25 @@ dpvba_status dpvba_analyze(dpvba_ctx* c, const dpvba_graph* g, void* stream) {
   HIP_TRY(ensure(c->wy, n * 8));
   HIP_TRY(ensure(c->Linv, nblk64 * 64 * 64 * 8));
   HIP_TRY(ensure(c->edge_part, ((size_t)(E + 255) / 256) * 8));
+  if (!c->ticket.p) {
+    HIP_TRY(ensure(c->ticket, 64));
+    HIP_TRY(ensure(c->dev_err, 64));
+    HIP_TRY(hipMemsetAsync(c->ticket.p, 0, 64, st));
+    HIP_TRY(hipMemsetAsync(c->dev_err.p, 0, 64, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
   HIP_TRY(ensure(c->status, DPVBA_MAX_ITERS * 4));
   HIP_TRY(ensure(c->min_bits, DPVBA_MAX_ITERS * 4));
   HIP_TRY(ensure(c->devrep, sizeof(dpvba_report)));
 
   c->N = N; c->P = P; c->E = E; c->p = g->patch_size; c->n_fixed = nf; c->n_free = n_free;
   c->ii = g->ii; c->jj = g->jj; c->kk = g->kk;
-  c->n_tiles = (int)tiles.size();
-  c->lds_f32 = max_lds32;
-  c->lds_f64 = max_lds64;
-  c->part_S_elems = (size_t)part_S;
-  c->part_vec_elems = (size_t)part_vec;
   c->analysed = true;
   return DPVBA_OK;
+}
+
+dpvba_status dpvba_analyze(dpvba_ctx* c, const dpvba_graph* g, void* stream) {
+  return dpvba_analyze_ex(c, g, nullptr, stream);
 }
 
 }  // extern "C"
@@ -398,11 +546,9 @@ static dpvba_status check_opts(const dpvba_opts* o) {
 }
 
 template <typename T>
-static TileArgs<T, T> make_args(dpvba_ctx* c, const dpvba_graph* g, const T* poses, T* depth, T lambda,
-                                T z_min) {
-  TileArgs<T, T> A{};
-  A.poses = poses;
-  A.inv_depth = depth;
+static IterArgs<T> make_iter_args(dpvba_ctx* c, const dpvba_graph* g, const Tiling& tl, const T* poses_cur,
+                                  T* poses_next, const T* depth_in, T lambda, T z_min) {
+  IterArgs<T> A{};
   A.patches = g->patches;
   A.p = g->patch_size;
   A.target = g->target;
@@ -410,82 +556,168 @@ static TileArgs<T, T> make_args(dpvba_ctx* c, const dpvba_graph* g, const T* pos
   A.fx = g->fx; A.fy = g->fy; A.cx = g->cx; A.cy = g->cy;
   A.z_min = z_min;
   A.lambda = lambda;
+  A.n_frames = c->N;
   A.n_fixed = c->n_fixed;
-  A.tiles = (const TileInfo*)c->tiles.p;
-  A.tile_patch = (const int*)c->tile_patch.p;
-  A.slot_frame = (const int*)c->slot_frame.p;
-  A.slot_blk = (const int*)c->slot_blk.p;
-  A.edge_grid = (const int*)c->edge_grid.p;
-  A.blk_pose = (const int*)c->blk_pose.p;
+  A.n_free = c->n_free;
+  A.n_tiles = tl.n_tiles;
+  A.poses_cur = poses_cur;
+  A.poses_next = poses_next;
+  A.depth_in = depth_in;
+  A.depth_s = (T*)c->depth_s.p;
+  A.xh_s = (T*)c->xh_s.p;
+  A.U_s = (T*)c->U_s.p;
+  A.pscale_s = (T*)c->pscale_s.p;
+  A.tiles = (const TileInfo*)tl.tiles.p;
+  A.tile_patch = (const int*)tl.tile_patch.p;
+  A.slot_frame = (const int*)tl.slot_frame.p;
+  A.slot_blk = (const int*)tl.slot_blk.p;
+  A.edge_grid = (const int*)tl.edge_grid.p;
+  A.blk_pose = (const int*)tl.blk_pose.p;
   A.part_S = (T*)c->part_S.p;
   A.part_vec = (T*)c->part_vec.p;
   A.part_cost = (double*)c->part_cost.p;
   A.part_invalid = (int*)c->part_invalid.p;
+  A.s_off = (const int*)tl.s_off.p;
+  A.s_src = (const int*)tl.s_src.p;
+  A.v_off = (const int*)tl.v_off.p;
+  A.v_src = (const int2*)tl.v_src.p;
+  A.dx = (T*)c->dx.p;
+  A.first = 1;
   return A;
 }
 
 template <typename T>
-static hipError_t assemble_and_gather(dpvba_ctx* c, const dpvba_graph* g, const T* poses, T* depth, T lambda,
-                                      T z_min, T* S, T* rhs, int mirror, double* cost_out, int* invalid_out,
-                                      hipStream_t st) {
-  TileArgs<T, T> A = make_args<T>(c, g, poses, depth, lambda, z_min);
-  const int lds = sizeof(T) == 8 ? c->lds_f64 : c->lds_f32;
-  hipError_t e = launch_tile_assemble<T, T>(A, c->n_tiles, lds, st);
+static bool use_small_path(const dpvba_ctx* c) {
+  const int n = 6 * c->n_free;
+  return n + 1 <= kSmallRows && small_solve_lds_bytes(n, (int)sizeof(T)) <= 160 * 1024;
+}
+
+template <typename T>
+static hipError_t reduced_impl(dpvba_ctx* c, const dpvba_graph* g, const T* poses, const T* depth, T lambda,
+                               T z_min, T* S, T* rhs, double* cost_out, hipStream_t st) {
+  const Tiling& tl = c->tl[sizeof(T) == 8 ? 1 : 0];
+  IterArgs<T> A = make_iter_args<T>(c, g, tl, poses, nullptr, depth, lambda, z_min);
+  hipError_t e;
+  {
+    TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
+    e = launch_tile_iterate<T>(A, tl.lds_bytes, st);
+  }
   if (e != hipSuccess) return e;
+  TraceScope ts(c, DPVBA_PHASE_GATHER, st);
   if (cost_out) {
-    if (c->n_tiles) {
-      e = launch_report_reduce((const double*)c->part_cost.p, (const int*)c->part_invalid.p, c->n_tiles,
-                               cost_out, invalid_out, st);
-    } else {
-      e = launch_report_reduce((const double*)c->part_cost.p, nullptr, 0, cost_out, invalid_out, st);
-    }
+    e = launch_report_reduce((const double*)c->part_cost.p, (const int*)c->part_invalid.p, tl.n_tiles, cost_out,
+                             nullptr, st);
     if (e != hipSuccess) return e;
   }
-  return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)c->s_off.p,
-                          (const int*)c->s_src.p, (const int*)c->v_off.p, (const int2*)c->v_src.p, c->n_free,
-                          S, rhs, (T*)c->dB.p, lambda, mirror, (T*)c->d0.p, st);
+  return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
+                          (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free, S,
+                          rhs, (T*)c->dB.p, lambda, 1, (T*)c->d0.p, st);
 }
 
 template <typename T>
 static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* depth, const dpvba_opts* o,
                              dpvba_report* report, hipStream_t st) {
   const T lambda = (T)o->lambda, z_min = (T)o->z_min;
+  const Tiling& tl = c->tl[sizeof(T) == 8 ? 1 : 0];
   const int n = 6 * c->n_free;
+  const int nit = o->n_iters;
+  const bool small = use_small_path<T>(c);
   dpvba_report* dev = (dpvba_report*)c->devrep.p;
   int* status = (int*)c->status.p;
   unsigned int* mb = (unsigned int*)c->min_bits.p;
-  hipError_t e = launch_report_init(status, mb, DPVBA_MAX_ITERS, st);
-  if (e != hipSuccess) return e;
-  const int lds = sizeof(T) == 8 ? c->lds_f64 : c->lds_f32;
-  for (int it = 0; it < o->n_iters; ++it) {
-    e = assemble_and_gather<T>(c, g, poses, depth, lambda, z_min, (T*)c->S.p, (T*)c->rhs.p, 0,
+  T* pbuf[2] = {(T*)c->poses_a.p, (T*)c->poses_b.p};
+  T* dx = (T*)c->dx.p;
+  hipError_t e;
+  if (small && nit > 0) {
+    SmallArgs<T> S{};
+    S.it = make_iter_args<T>(c, g, tl, poses, pbuf[0], depth, lambda, z_min);
+    S.poses_io = poses;
+    S.depth_io = depth;
+    S.pbuf0 = pbuf[0];
+    S.pbuf1 = pbuf[1];
+    S.Sp = (T*)c->S.p;
+    S.rhs = (T*)c->rhs.p;
+    S.d0 = (T*)c->d0.p;
+    S.status = status;
+    S.min_bits = mb;
+    S.cost = dev->cost;
+    S.invalid = dev->n_invalid;
+    S.n_iters = nit;
+    S.bar = (unsigned int*)c->ticket.p;
+    S.err = (int*)c->dev_err.p;
+    const int lds_small = std::max(tl.lds_bytes, small_solve_lds_bytes(n, (int)sizeof(T)));
+    int& cap = sizeof(T) == 8 ? c->coop_grid64 : c->coop_grid32;
+    int& cap_lds = sizeof(T) == 8 ? c->coop_lds64 : c->coop_lds32;
+    if (cap_lds != lds_small) {
+      cap = small_solve_grid<T>(lds_small);
+      cap_lds = lds_small;
+    }
+    const int grid = std::min(tl.n_tiles, cap);
+    if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
+    TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
+    e = launch_small_solve<T>(S, grid, lds_small, st);
+    if (e != hipSuccess) return e;
+  }
+  if (!small) {
+    e = launch_report_init(status, mb, DPVBA_MAX_ITERS, st);
+    if (e != hipSuccess) return e;
+  }
+  for (int it = 0; it < nit && !small; ++it) {
+    const T* cur = it == 0 ? poses : pbuf[(it - 1) & 1];
+    T* next = pbuf[it & 1];
+    IterArgs<T> A = make_iter_args<T>(c, g, tl, cur, next, depth, lambda, z_min);
+    A.first = it == 0;
+    A.dx_prev = it ? dx : nullptr;
+    A.status_prev = it ? status + it - 1 : nullptr;
+    {
+      TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
+      e = launch_tile_iterate<T>(A, tl.lds_bytes, st);
+    }
+    if (e != hipSuccess) return e;
+    {
+      TraceScope ts(c, DPVBA_PHASE_GATHER, st);
+      e = launch_report_reduce((const double*)c->part_cost.p, (const int*)c->part_invalid.p, tl.n_tiles,
                                &dev->cost[it], &dev->n_invalid[it], st);
+      if (e == hipSuccess)
+        e = launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
+                             (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
+                             (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, 0, (T*)c->d0.p, st);
+    }
     if (e != hipSuccess) return e;
-    e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, (T*)c->dx.p, (T*)c->wb.p, (T*)c->wy.p,
-                             (T*)c->Linv.p, (const T*)c->d0.p, status + it, mb + it, st);
+    {
+      TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
+      e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, dx, (T*)c->wb.p, (T*)c->wy.p, (T*)c->Linv.p,
+                               (const T*)c->d0.p, status + it, mb + it, st);
+    }
     if (e != hipSuccess) return e;
-    TileArgs<T, T> A = make_args<T>(c, g, poses, depth, lambda, z_min);
-    A.dx = (const T*)c->dx.p;
-    A.step_status = status + it;
-    e = launch_tile_backsub<T, T>(A, c->n_tiles, lds, st);
-    if (e != hipSuccess) return e;
-    e = launch_retract<T, T>(poses, (const T*)c->dx.p, c->n_fixed, c->n_free, status + it, st);
-    if (e != hipSuccess) return e;
-  }
-  e = launch_edge_cost<T, T>(poses, depth, g->patches, g->patch_size, g->ii, g->jj, g->kk, g->target, g->weight,
-                             g->n_edges, (T)g->fx, (T)g->fy, (T)g->cx, (T)g->cy, z_min, (double*)c->edge_part.p,
-                             st);
-  if (e != hipSuccess) return e;
-  e = launch_report_reduce((const double*)c->edge_part.p, nullptr, (g->n_edges + 255) / 256,
-                           &dev->cost[o->n_iters], nullptr, st);
-  if (e != hipSuccess) return e;
-  e = launch_report_finalize(dev, status, mb, o->n_iters, st);
-  if (e != hipSuccess) return e;
-  if (report) {
-    e = hipMemcpyAsync(report, dev, sizeof(dpvba_report), hipMemcpyDeviceToHost, st);
+    {
+      TraceScope ts(c, DPVBA_PHASE_RETRACT, st);
+      e = launch_retract_copy<T>(cur, next, dx, c->n_fixed, c->N, status + it, st);
+    }
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  if (nit > 0 && !small) {
+    TraceScope ts(c, DPVBA_PHASE_BACKSUB, st);
+    e = launch_tile_finalize<T>((const TileInfo*)tl.tiles.p, tl.n_tiles, tl.lds_bytes, (const int*)tl.tile_patch.p,
+                                (const int*)tl.blk_pose.p, (const T*)c->U_s.p, (const T*)c->pscale_s.p,
+                                (const T*)c->depth_s.p, dx, status + nit - 1, depth, pbuf[(nit - 1) & 1], poses,
+                                c->N, st);
+    if (e != hipSuccess) return e;
+  }
+  if (!report) return hipSuccess;
+  {
+    TraceScope ts_cost(c, DPVBA_PHASE_COST, st);
+    e = launch_edge_cost<T, T>(poses, depth, g->patches, g->patch_size, g->ii, g->jj, g->kk, g->target, g->weight,
+                               g->n_edges, (T)g->fx, (T)g->fy, (T)g->cx, (T)g->cy, z_min,
+                               (double*)c->edge_part.p, st);
+  }
+  if (e != hipSuccess) return e;
+  e = launch_report_reduce((const double*)c->edge_part.p, nullptr, (g->n_edges + 255) / 256, &dev->cost[nit],
+                           nullptr, st);
+  if (e != hipSuccess) return e;
+  e = launch_report_finalize(dev, status, mb, nit, (const int*)c->dev_err.p, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(report, dev, sizeof(dpvba_report), hipMemcpyDeviceToHost, st);
 }
 
 extern "C" {
@@ -512,12 +744,11 @@ dpvba_status dpvba_reduced_system(dpvba_ctx* c, const dpvba_graph* g, const floa
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   if (o->precision == DPVBA_FP64) {
-    HIP_TRY(assemble_and_gather<double>(c, g, (const double*)(const void*)poses, (double*)(void*)inv_depth,
-                                        (double)o->lambda, (double)o->z_min, (double*)S, (double*)s, 1, cost,
-                                        nullptr, st));
+    HIP_TRY(reduced_impl<double>(c, g, (const double*)(const void*)poses, (const double*)(const void*)inv_depth,
+                                 (double)o->lambda, (double)o->z_min, (double*)S, (double*)s, cost, st));
   } else {
-    HIP_TRY(assemble_and_gather<float>(c, g, poses, (float*)inv_depth, (float)o->lambda, (float)o->z_min, (float*)S,
-                                       (float*)s, 1, cost, nullptr, st));
+    HIP_TRY(reduced_impl<float>(c, g, poses, inv_depth, (float)o->lambda, (float)o->z_min, (float*)S, (float*)s,
+                                cost, st));
   }
   return DPVBA_OK;
 }

@@ -295,8 +295,6 @@ __global__ void copy_vec_kernel(const T* src, T* dst, int n) {
 
 int small_solve_max_n(int tsize) { return tsize == 4 ? 240 : 160; }
 
-int small_solve_lds_bytes(int n, int tsize) { return (n * (n + 1) / 2 + 2 * n) * tsize; }
-
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* work_y, T* Linv_all, const T* d0,
                              int* status, unsigned int* min_bits, hipStream_t st) {

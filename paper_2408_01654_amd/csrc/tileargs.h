@@ -1,20 +1,30 @@
-// Arguments of the tile kernels (assembly and depth back-substitution).
+// Arguments of the tile kernels and of the single-launch small-problem solver.
 #pragma once
+
+#include <hip/hip_runtime.h>
 
 #include "layout.h"
 
 namespace dpvba {
 
-template <typename T, typename P>
-struct TileArgs {
-  const P* poses;          // [N,7]
-  P* inv_depth;            // [P] (back-substitution writes it)
-  const float* patches;    // [P,p,p,2]
+template <typename T>
+struct IterArgs {
+  const float* patches;
   int p;
-  const float* target;     // [E,2]
-  const float* weight;     // [E,2]
+  const float* target;
+  const float* weight;
   T fx, fy, cx, cy, z_min, lambda;
-  int n_fixed;
+  int n_frames, n_fixed, n_free, n_tiles;
+  const T* poses_cur;      // [N,7] x_t
+  T* poses_next;           // [N,7] x_{t+1} (written by the last workgroup)
+  const T* depth_in;       // caller's inverse depths (read when first)
+  T* depth_s;              // tile-ordered inverse depths
+  T* xh_s;                 // tile-ordered patch rays [.,2]
+  T* U_s;                  // stored Schur rows
+  T* pscale_s;             // per patch: 1/sqrt(C~), w/sqrt(C~)
+  const T* dx_prev;        // previous pose step (applied unless first)
+  const int* status_prev;  // nonzero: previous step discarded
+  int first;
   const TileInfo* tiles;
   const int* tile_patch;
   const int* slot_frame;
@@ -25,8 +35,36 @@ struct TileArgs {
   T* part_vec;
   double* part_cost;
   int* part_invalid;
-  const T* dx;             // [6 N'] pose step (back-substitution)
-  const int* step_status;  // nonzero: discard this iteration's step
+  // gather lists and per-iteration outputs of the small-problem solver
+  const int* s_off;
+  const int* s_src;
+  const int* v_off;
+  const int2* v_src;
+  T* dx;
+  int* status;
+  unsigned int* min_bits;
+  double* cost_out;
+  int* invalid_out;
+};
+
+// Arguments of the single-launch solver of small problems.
+template <typename T>
+struct SmallArgs {
+  IterArgs<T> it;       // shared fields; per-iteration fields set in the kernel
+  T* poses_io;          // caller's poses (read at t = 0, written at the end)
+  T* depth_io;          // caller's inverse depths
+  T* pbuf0;
+  T* pbuf1;
+  T* Sp;                // packed reduced system
+  T* rhs;
+  T* d0;
+  int* status;          // per iteration
+  unsigned int* min_bits;
+  double* cost;         // per iteration, or null
+  int* invalid;
+  int n_iters;
+  unsigned int* bar;
+  int* err;
 };
 
 }  // namespace dpvba

@@ -312,7 +312,9 @@ def make_window(call: int, n_calls: int = N_CALLS, noise_px: float = 0.5) -> Sce
     seq = window_sequence(n_calls, noise_px)
     K = seq["K"]
     f0, f1 = call, call + WINDOW
-    sel = (seq["ii"] >= f0) & (seq["ii"] < f1) & (seq["jj"] >= f0) & (seq["jj"] < f1)
+    # the global edge list is sorted by source frame: slice that range first
+    e0, e1 = np.searchsorted(seq["ii"], [f0, f1])
+    sel = e0 + np.nonzero((seq["jj"][e0:e1] >= f0) & (seq["jj"][e0:e1] < f1))[0]
     R = seq["R"][f0:f1]; c = seq["c"][f0:f1]
     p0, p1 = f0 * K, f1 * K
     u = seq["u"][p0:p1]; v = seq["v"][p0:p1]; d = seq["d"][p0:p1]
