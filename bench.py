@@ -68,6 +68,56 @@ def cpu_baseline(windows, budget_s=12.0, max_windows=80):
             "seconds": dt}
 
 
+def bench_global(steps):
+    """Global BA after loop closure: 1000 keyframes x 96 patches, 1,505,568
+    edges, 5 GN iterations (float32).  Returns throughput, per-phase average
+    launch durations and the edge-assembly roofline."""
+    import torch
+    import paper_2408_01654_amd as dp
+    from scenes import make_config
+    s = make_config(2)
+    g = dp.GraphTensors.from_scene(s)
+    ctx = dp.Context(0)
+    t0 = time.perf_counter()
+    ctx.analyze(g)
+    t_an = time.perf_counter() - t0
+    info = ctx.analysis_info()
+    poses0 = torch.as_tensor(s.poses).cuda().contiguous()
+    depth0 = torch.as_tensor(s.inv_depth).cuda().contiguous()
+    poses, depth = poses0.clone(), depth0.clone()
+    ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, report=False)
+    torch.cuda.synchronize()
+    ctx.trace_begin(sample_every=1, max_pairs=1 << 16)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        poses.copy_(poses0)
+        depth.copy_(depth0)
+        ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, report=False)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ph = ctx.trace_end()
+    rep = ctx.solve(g, poses.copy_(poses0), depth.copy_(depth0), n_iters=s.n_iters, lam=s.lam, z_min=s.z_min)
+    ctx.close()
+    avg = {k: (v[0] / v[1] * 1e3 if v[1] else 0.0) for k, v in ph.items()}
+    E, P, N = s.n_edges, s.n_patches, s.n_frames
+    # per launch of the assembly: edge records (grid cell 4 B + target 8 B + weight 8 B), patch centre and
+    # inverse depth, poses, and the outputs: tile shares of S and s, stored Schur rows (4 B per element)
+    alg = (info["grid_cells"] * 4 + E * 16 + P * 12 + N * 28
+           + 4 * (info["part_S_elems"] + info["part_vec_elems"] + info["u_elems"]) + P * 8)
+    ach = alg / (avg["assemble"] * 1e-6) / 1e9 if avg["assemble"] else 0.0
+    out = {"workload": "global BA after loop closure: 1000 keyframes x 96 patches, 1,505,568 edges, "
+                       "5 GN iterations, float32",
+           "edges_per_s": E * s.n_iters * steps / sec, "gn_iters_per_s": s.n_iters * steps / sec,
+           "ms_per_solve": 1e3 * sec / steps, "analysis_s": t_an, "phases_avg_us": avg,
+           "phases_launches": {k: v[2] for k, v in ph.items()},
+           "assembly_roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": ach / HBM_PEAK_GBS, "alg_bytes_per_launch": alg},
+           "cost": rep["cost"], "status": rep["status"]}
+    log(f"[bench] global BA: {out['ms_per_solve']:.2f} ms/solve, {out['edges_per_s']:.4g} edge-iters/s, "
+        f"assembly {avg['assemble']:.1f} us ({ach:.0f} GB/s), analysis {t_an:.2f}s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +127,8 @@ def main():
     ap.add_argument("--trace-every", type=int, default=7)
     ap.add_argument("--check", type=int, default=4, help="windows checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--global-steps", type=int, default=3,
+                    help="timed solves of the 1000-keyframe global BA reported beside the main line (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the BA path here is "
@@ -189,6 +241,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
                 "avg_launch_us": avg[dom] * 1e3, "alg_bytes_per_launch": alg_bytes[dom]}
 
+    global_ba = bench_global(args.global_steps) if args.global_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(windows)
@@ -210,6 +264,7 @@ def main():
         "phases_launches": {k: v[2] for k, v in phases.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "global_ba": global_ba,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

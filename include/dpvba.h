@@ -31,8 +31,9 @@
  * pointer owned by the caller, who keeps it alive until the work enqueued on
  * the given stream has completed.  The library never frees or retains caller
  * buffers.  A context owns all of its workspace.  dpvba_analyze is the only
- * call that may allocate device memory; the numeric calls (dpvba_solve,
- * dpvba_reduced_system, dpvba_reproject) allocate nothing, synchronise
+ * call that may allocate device memory (besides the first dpvba_solve_backward
+ * of a given size, which sizes its own workspace); the numeric calls
+ * (dpvba_solve, dpvba_reduced_system, dpvba_reproject) allocate nothing, synchronise
  * nothing and only enqueue work on the caller's stream (dpvba_solve with a
  * non-NULL report enqueues one device-to-host copy into it and the caller
  * reads it after synchronising the stream).  A context is used by one host
@@ -64,6 +65,9 @@ typedef enum {
 
 typedef enum {
   DPVBA_FP32 = 0,       /* float32 assembly, factorisation and solve             */
+  DPVBA_MIXED = 1,      /* float32 assembly and state; shares gathered in float64;
+                           float32 Cholesky refined against the float64 residual,
+                           float64 Cholesky when that does not converge          */
   DPVBA_FP64 = 2        /* float64 throughout (parity mode)                      */
 } dpvba_precision;
 
@@ -122,13 +126,20 @@ typedef struct {
  *                   (that iteration's step is then zero), or DPVBA_EHIP if
  *                   a bounded device-wide wait of the single-launch solver
  *                   expired (the results are then invalid and the context
- *                   must be destroyed).                                    */
+ *                   must be destroyed).
+ *   refine_resid[t] DPVBA_MIXED: max |s - S dxi| / max |s| in float64 after
+ *                   the refinement steps of iteration t (before any float64
+ *                   fallback); 0 in the other modes.
+ *   fp64_fallback[t] DPVBA_MIXED: 1 if iteration t was re-solved with the
+ *                   float64 Cholesky.                                      */
 typedef struct {
   int32_t status;
   int32_t n_iters;
   double cost[DPVBA_MAX_ITERS + 1];
   int32_t n_invalid[DPVBA_MAX_ITERS];
   double min_pivot[DPVBA_MAX_ITERS];
+  double refine_resid[DPVBA_MAX_ITERS];
+  int32_t fp64_fallback[DPVBA_MAX_ITERS];
 } dpvba_report;
 
 /* Create a context on HIP device `device`.  Allocates the context's fixed
@@ -220,6 +231,92 @@ dpvba_status dpvba_reduced_system(dpvba_ctx* ctx, const dpvba_graph* g, const fl
  * Needs dpvba_analyze on this graph.                                      */
 dpvba_status dpvba_solve(dpvba_ctx* ctx, const dpvba_graph* g, float* poses, float* inv_depth,
                          const dpvba_opts* opts, dpvba_report* report, void* stream);
+
+/* Adjoint of dpvba_solve, for training through the BA layer (Sec. 2: the
+ * network is supervised on the camera poses that bundle adjustment
+ * produces; objective eq. 3).  Given the gradient of a loss with respect to
+ * the poses and inverse depths that opts->n_iters iterations produce from
+ * (poses0, inv_depth0), writes the gradient of that loss with respect to
+ * every edge's target and weight.  The iterations are replayed from the
+ * start, keeping the iterates; each iteration's Schur system is recomputed
+ * at its iterate when walking back.  The derivative is that of the
+ * iteration as computed: fixed iteration count, validity decided at each
+ * iterate (an invalid edge contributes nothing), the damping's dependence
+ * on Diag(H) included, and the Jacobians' dependence on the iterate
+ * included (second derivatives of the projection).  An iteration whose
+ * factorisation failed (its pose step was skipped) passes the gradient
+ * through unchanged.
+ *   poses0, inv_depth0  [N, 7], [P]: the starting point given to dpvba_solve
+ *              (read only).
+ *   grad_poses [N, 7] or NULL (zero): dL/d(final poses) in the stored
+ *              (t, q) coordinates; components along q are projected out by
+ *              the quaternion normalisation.
+ *   grad_inv_depth [P] or NULL (zero): dL/d(final inverse depths).
+ *   grad_target, grad_weight [E, 2] (written): dL/d target, dL/d weight.
+ * All six arrays are float32, or float64 when opts->precision is DPVBA_FP64
+ * (the pointers are then reinterpreted).  The first call for a given
+ * (n_iters, size) allocates its workspace in the context, about
+ * (n_iters + 1) 7 N + n_iters (P + 6 N) + 15 E elements.
+ * Needs dpvba_analyze on this graph.  EINVAL on bad arguments.             */
+dpvba_status dpvba_solve_backward(dpvba_ctx* ctx, const dpvba_graph* g, const float* poses0,
+                                  const float* inv_depth0, const dpvba_opts* opts,
+                                  const float* grad_poses, const float* grad_inv_depth,
+                                  float* grad_target, float* grad_weight, void* stream);
+
+/* A batch of independent problems packed back to back (many uneven
+ * sliding windows, Sec. 3.1, solved together).  Host struct; the offset and
+ * n_fixed arrays are host memory, the data arrays device memory.
+ *   n_problems B >= 1.
+ *   frame_off, patch_off, edge_off  [B + 1] prefix offsets: problem b owns
+ *              poses [frame_off[b], frame_off[b+1]) of the packed [sum N, 7]
+ *              pose array, inverse depths and patches
+ *              [patch_off[b], patch_off[b+1]) and edges
+ *              [edge_off[b], edge_off[b+1]).
+ *   n_fixed    [B] held poses of each problem (its first n_fixed[b]).
+ *   ii, jj, kk [sum E] indices LOCAL to the edge's problem.
+ *   patches, target, weight, patch_size, fx..cy as in dpvba_graph (one
+ *              camera for the whole batch).                               */
+typedef struct {
+  int32_t n_problems, patch_size;
+  const int32_t* frame_off;
+  const int32_t* patch_off;
+  const int32_t* edge_off;
+  const int32_t* n_fixed;
+  const float* patches;
+  const int32_t* ii;
+  const int32_t* jj;
+  const int32_t* kk;
+  const float* target;
+  const float* weight;
+  float fx, fy, cx, cy;
+} dpvba_batch;
+
+/* Symbolic analysis of a batch (replaces any previous batch analysis; the
+ * single-problem analysis is kept).  tile_patches: host [B] patches per
+ * tile for each problem in float32 and mixed modes (<= 0: default), e.g.
+ * from an autotuner, or NULL; float64 uses the default.  The same checks as
+ * dpvba_analyze, per problem, plus the offsets being non-decreasing.       */
+dpvba_status dpvba_analyze_batch(dpvba_ctx* ctx, const dpvba_batch* b, const int32_t* tile_patches,
+                                 void* stream);
+
+/* Flag of dpvba_opts for dpvba_solve_batch: record the call's launches in a
+ * HIP graph on first use and replay that graph on later calls with the same
+ * arguments (pointers, options and stream); any change re-records.  The
+ * report, if requested, is produced outside the graph.  Needs a stream other
+ * than the null stream (EINVAL otherwise); ignored while tracing.        */
+#define DPVBA_FLAG_GRAPH 1u
+
+/* opts->n_iters iterations of every problem of the analysed batch: the
+ * tiles of all problems are assembled by one launch per iteration, then one
+ * workgroup per problem gathers, factors and solves its reduced system and
+ * retracts its poses (see dpvba_solve for the iteration).
+ *   poses      [sum N, 7], inv_depth [sum P]: read and overwritten; float32
+ *              (DPVBA_FP32, DPVBA_MIXED) or float64 (DPVBA_FP64).
+ *   reports    host [B] or NULL: one report per problem.
+ *   opts->flags  0 or DPVBA_FLAG_GRAPH.
+ * Needs dpvba_analyze_batch on this batch (same index arrays).            */
+dpvba_status dpvba_solve_batch(dpvba_ctx* ctx, const dpvba_batch* b, float* poses, float* inv_depth,
+                               const dpvba_opts* opts, dpvba_report* reports, void* stream);
 
 /* Phase timing with HIP events (tracing).  While tracing is on, the
  * numeric calls record an event pair on their stream around every

@@ -12,8 +12,9 @@ every step, including the Jacobians' dependence on the iterate and the
 factorisation.  It is written independently of `ba64` (torch tensors,
 dense block assembly by index_add) so that the two cross-check each other.
 
-Loss (pose L2 error): L = sum over free poses of |t_i - t_i^gt|^2 +
-|Log(R_i^gt^T R_i)|^2.
+The iterate is carried in the stored coordinates (t, q) of the poses, so
+the gradients with respect to the final poses are the ones a caller
+computes on the returned [N,7] array.
 """
 from __future__ import annotations
 
@@ -51,29 +52,39 @@ def _exp_coeffs(phi):
     return A, B, C
 
 
-def retract_right(R, t, xi):
-    """G Exp(xi): R Exp(phi), t + R V(phi) rho."""
+def quat_mul(a, b):
+    """Hamilton product of (x, y, z, w) quaternions."""
+    ax, ay, az, aw = a.unbind(-1)
+    bx, by, bz, bw = b.unbind(-1)
+    return torch.stack([aw * bx + ax * bw + ay * bz - az * by,
+                        aw * by - ax * bz + ay * bw + az * bx,
+                        aw * bz + ax * by - ay * bx + az * bw,
+                        aw * bw - ax * bx - ay * by - az * bz], -1)
+
+
+def retract_right(t, q, xi):
+    """G Exp(xi) on the stored coordinates: t + R V(phi) rho and the
+    normalised q (x) (sin(theta/2) phi / theta, cos(theta/2))."""
     rho, phi = xi[..., :3], xi[..., 3:]
     A, B, C = _exp_coeffs(phi)
+    th2 = (phi * phi).sum(-1)
+    small = th2 < 1e-4
+    th = torch.where(small, torch.ones_like(th2), th2).sqrt()
+    h = torch.where(small, 0.5 - th2 / 48 + th2 * th2 / 3840, torch.sin(th / 2) / th)
+    ch = torch.where(small, 1 - th2 / 8 + th2 * th2 / 384, torch.cos(th / 2))
     K = _hat(phi)
     I = torch.eye(3, dtype=DT).expand(K.shape)
-    K2 = K @ K
-    dR = I + A[..., None, None] * K + B[..., None, None] * K2
-    V = I + B[..., None, None] * K + C[..., None, None] * K2
-    return R @ dR, t + (R @ (V @ rho[..., None]))[..., 0]
+    V = I + B[..., None, None] * K + C[..., None, None] * (K @ K)
+    R = quat_to_rot(q)
+    tn = t + (R @ (V @ rho[..., None]))[..., 0]
+    qn = quat_mul(q, torch.cat([h[..., None] * phi, ch[..., None]], -1))
+    return tn, qn / qn.norm(dim=-1, keepdim=True)
 
 
-def rot_log_sq(R):
-    """|Log(R)|^2 via the rotation angle theta = atan2(|v|, (tr R - 1) / 2)."""
-    v = torch.stack([R[..., 2, 1] - R[..., 1, 2], R[..., 0, 2] - R[..., 2, 0], R[..., 1, 0] - R[..., 0, 1]], -1) / 2
-    c = (R[..., 0, 0] + R[..., 1, 1] + R[..., 2, 2] - 1) / 2
-    s = v.norm(dim=-1)
-    return torch.atan2(s, c) ** 2
-
-
-def gn_iteration(R, t, d, centres, ii, jj, kk, target, weight, intr, n_fixed, lam, z_min):
-    """One damped GN step; returns the updated (R, t, d)."""
+def gn_iteration(t, q, d, centres, ii, jj, kk, target, weight, intr, n_fixed, lam, z_min):
+    """One damped GN step on the stored coordinates; returns (t, q, d)."""
     fx, fy, cx, cy = intr
+    R = quat_to_rot(q)
     N, P = R.shape[0], d.shape[0]
     Rj_T = R[jj].transpose(-1, -2)
     Rji = Rj_T @ R[ii]
@@ -81,16 +92,16 @@ def gn_iteration(R, t, d, centres, ii, jj, kk, target, weight, intr, n_fixed, la
     xh = torch.stack([(centres[kk, 0] - cx) / fx, (centres[kk, 1] - cy) / fy,
                       torch.ones(kk.shape[0], dtype=DT)], -1)
     dk = d[kk]
-    q = (Rji @ xh[..., None])[..., 0] + tji * dk[:, None]
-    valid = ((dk > 0) & (q[:, 2] > z_min * dk)).to(DT)
-    z = torch.where(valid > 0, q[:, 2], torch.ones_like(q[:, 2]))
-    r = torch.stack([fx * q[:, 0] / z + cx, fy * q[:, 1] / z + cy], -1) - target
-    E = q.shape[0]
+    pt = (Rji @ xh[..., None])[..., 0] + tji * dk[:, None]
+    valid = ((dk > 0) & (pt[:, 2] > z_min * dk)).to(DT)
+    z = torch.where(valid > 0, pt[:, 2], torch.ones_like(pt[:, 2]))
+    r = torch.stack([fx * pt[:, 0] / z + cx, fy * pt[:, 1] / z + cy], -1) - target
+    E = pt.shape[0]
     zero = torch.zeros(E, dtype=DT)
-    Jpi = torch.stack([torch.stack([fx / z, zero, -fx * q[:, 0] / (z * z)], -1),
-                       torch.stack([zero, fy / z, -fy * q[:, 1] / (z * z)], -1)], -2)
+    Jpi = torch.stack([torch.stack([fx / z, zero, -fx * pt[:, 0] / (z * z)], -1),
+                       torch.stack([zero, fy / z, -fy * pt[:, 1] / (z * z)], -1)], -2)
     eye = torch.eye(3, dtype=DT).expand(E, 3, 3)
-    Jj = Jpi @ torch.cat([-dk[:, None, None] * eye, _hat(q)], -1)
+    Jj = Jpi @ torch.cat([-dk[:, None, None] * eye, _hat(pt)], -1)
     Ji = Jpi @ Rji @ torch.cat([dk[:, None, None] * eye, -_hat(xh)], -1)
     Jd = (Jpi @ tji[..., None])[..., 0]
     W = weight * valid[:, None]
@@ -132,22 +143,32 @@ def gn_iteration(R, t, d, centres, ii, jj, kk, target, weight, intr, n_fixed, la
     else:
         dxi = torch.zeros(0, dtype=DT)
     dd = (-gd - Em.T @ dxi) / Ct
-    Rn, tn = retract_right(R[nf:], t[nf:], dxi.reshape(Nf, 6))
-    return torch.cat([R[:nf], Rn], 0), torch.cat([t[:nf], tn], 0), d + dd
+    tn, qn = retract_right(t[nf:], q[nf:], dxi.reshape(Nf, 6))
+    return torch.cat([t[:nf], tn], 0), torch.cat([q[:nf], qn], 0), d + dd
 
 
 def unrolled(poses0, d0, centres, ii, jj, kk, target, weight, intr, n_fixed, n_iters, lam, z_min):
-    R, t = quat_to_rot(poses0[:, 3:]), poses0[:, :3]
-    d = d0
+    """poses [N,7] (t, q) and depths [P] after n_iters iterations."""
+    t, q, d = poses0[:, :3], poses0[:, 3:], d0
     for _ in range(n_iters):
-        R, t, d = gn_iteration(R, t, d, centres, ii, jj, kk, target, weight, intr, n_fixed, lam, z_min)
-    return R, t, d
+        t, q, d = gn_iteration(t, q, d, centres, ii, jj, kk, target, weight, intr, n_fixed, lam, z_min)
+    return torch.cat([t, q], -1), d
 
 
-def pose_loss(R, t, poses_gt, n_fixed):
-    Rg, tg = quat_to_rot(poses_gt[:, 3:]), poses_gt[:, :3]
-    Rr = Rg[n_fixed:].transpose(-1, -2) @ R[n_fixed:]
-    return ((t[n_fixed:] - tg[n_fixed:]) ** 2).sum() + rot_log_sq(Rr).sum()
+def pose_depth_loss(poses, d, poses_ref, d_ref, n_fixed):
+    """A test loss touching every output: squared translation error,
+    1 - <q, q_ref>^2 per free pose (sign invariant), and the mean squared
+    inverse-depth error."""
+    t, q = poses[n_fixed:, :3], poses[n_fixed:, 3:]
+    tr, qr = poses_ref[n_fixed:, :3], poses_ref[n_fixed:, 3:]
+    return ((t - tr) ** 2).sum() + (1 - (q * qr).sum(-1) ** 2).sum() + ((d - d_ref) ** 2).mean()
+
+
+def scene_loss(scene):
+    """pose_depth_loss against the scene's ground truth, as a callable."""
+    ref = torch.as_tensor(scene.poses_gt, dtype=DT)
+    dref = torch.as_tensor(scene.inv_depth_gt, dtype=DT)
+    return lambda poses, d: pose_depth_loss(poses, d, ref, dref, int(scene.n_fixed))
 
 
 def _tensors(scene):
@@ -157,40 +178,46 @@ def _tensors(scene):
         centres=torch.as_tensor(scene.patches[:, c, c, :], dtype=DT),
         ii=torch.as_tensor(scene.ii, dtype=torch.long), jj=torch.as_tensor(scene.jj, dtype=torch.long),
         kk=torch.as_tensor(scene.kk, dtype=torch.long), intr=[float(x) for x in scene.intrinsics],
-        n_fixed=int(scene.n_fixed), poses_gt=torch.as_tensor(scene.poses_gt, dtype=DT))
+        n_fixed=int(scene.n_fixed))
 
 
-def loss_and_grads(scene, n_iters=None, lam=None, z_min=None):
-    """Loss after the unrolled iterations and its gradients with respect to
-    the targets [E,2] and weights [E,2] (numpy float64)."""
+def _run(scene, target, weight, n_iters, lam, z_min, track=False):
     T = _tensors(scene)
+    if track:  # keep the outputs in the graph even without iterations
+        T["poses0"].requires_grad_(True)
+        T["d0"].requires_grad_(True)
+    return unrolled(T["poses0"], T["d0"], T["centres"], T["ii"], T["jj"], T["kk"], target, weight, T["intr"],
+                    T["n_fixed"], scene.n_iters if n_iters is None else n_iters,
+                    scene.lam if lam is None else lam, scene.z_min if z_min is None else z_min)
+
+
+def loss_and_grads(scene, loss_fn=None, n_iters=None, lam=None, z_min=None):
+    """L = loss_fn(poses_T, d_T) after the unrolled iterations, and (numpy
+    float64) dL/d target [E,2], dL/d weight [E,2], dL/d poses_T [N,7],
+    dL/d d_T [P].  loss_fn defaults to scene_loss(scene)."""
+    loss_fn = scene_loss(scene) if loss_fn is None else loss_fn
     target = torch.as_tensor(scene.target, dtype=DT).clone().requires_grad_(True)
     weight = torch.as_tensor(scene.weight, dtype=DT).clone().requires_grad_(True)
-    R, t, d = unrolled(T["poses0"], T["d0"], T["centres"], T["ii"], T["jj"], T["kk"], target, weight, T["intr"],
-                       T["n_fixed"], scene.n_iters if n_iters is None else n_iters,
-                       scene.lam if lam is None else lam, scene.z_min if z_min is None else z_min)
-    L = pose_loss(R, t, T["poses_gt"], T["n_fixed"])
-    gt, gw = torch.autograd.grad(L, (target, weight))
-    return float(L.detach()), gt.numpy(), gw.numpy()
+    poses, d = _run(scene, target, weight, n_iters, lam, z_min, track=True)
+    L = loss_fn(poses, d)
+    ins = (target, weight, poses, d)
+    gr = torch.autograd.grad(L, ins, allow_unused=True)
+    gt, gw, gp, gd = (torch.zeros_like(x) if g is None else g for g, x in zip(gr, ins))
+    return float(L.detach()), gt.numpy(), gw.numpy(), gp.detach().numpy(), gd.detach().numpy()
 
 
-def loss_value(scene, target, weight, n_iters=None, lam=None, z_min=None):
+def loss_value(scene, target, weight, loss_fn=None, n_iters=None, lam=None, z_min=None):
     """The loss alone, for given float64 targets / weights (numpy)."""
-    T = _tensors(scene)
+    loss_fn = scene_loss(scene) if loss_fn is None else loss_fn
     with torch.no_grad():
-        R, t, d = unrolled(T["poses0"], T["d0"], T["centres"], T["ii"], T["jj"], T["kk"],
-                           torch.as_tensor(target, dtype=DT), torch.as_tensor(weight, dtype=DT), T["intr"],
-                           T["n_fixed"], scene.n_iters if n_iters is None else n_iters,
-                           scene.lam if lam is None else lam, scene.z_min if z_min is None else z_min)
-        return float(pose_loss(R, t, T["poses_gt"], T["n_fixed"]))
+        poses, d = _run(scene, torch.as_tensor(target, dtype=DT), torch.as_tensor(weight, dtype=DT), n_iters,
+                        lam, z_min)
+        return float(loss_fn(poses, d))
 
 
 def forward_state(scene, n_iters=None):
-    """(R [N,3,3], t [N,3], d [P]) after the unrolled iterations, numpy float64."""
-    T = _tensors(scene)
+    """(poses [N,7], d [P]) after the unrolled iterations, numpy float64."""
     with torch.no_grad():
-        R, t, d = unrolled(T["poses0"], T["d0"], T["centres"], T["ii"], T["jj"], T["kk"],
-                           torch.as_tensor(scene.target, dtype=DT), torch.as_tensor(scene.weight, dtype=DT),
-                           T["intr"], T["n_fixed"], scene.n_iters if n_iters is None else n_iters, scene.lam,
-                           scene.z_min)
-    return R.numpy(), t.numpy(), d.numpy()
+        poses, d = _run(scene, torch.as_tensor(scene.target, dtype=DT), torch.as_tensor(scene.weight, dtype=DT),
+                        n_iters, None, None)
+    return poses.numpy(), d.numpy()

@@ -4,5 +4,5 @@ The numeric work runs in the HIP library libdpvba.so (C ABI in
 include/dpvba.h); ``binding`` marshals torch device tensors into it.
 """
 from .binding import (  # noqa: F401
-    FP32, FP64, Context, DpvbaError, GraphTensors, LIB_PATH, lib, status_string,
+    FP32, FP64, MIXED, BatchTensors, Context, DpvbaError, GraphTensors, LIB_PATH, bundle_adjust, lib, status_string,
 )

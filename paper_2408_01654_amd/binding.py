@@ -10,13 +10,15 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdpvba.so")
 
 DPVBA_OK, DPVBA_EINVAL, DPVBA_ENOTPD, DPVBA_ENOMEM, DPVBA_EHIP, DPVBA_ESTATE = range(6)
-FP32, FP64 = 0, 2
+FP32, MIXED, FP64 = 0, 1, 2
+FLAG_GRAPH = 1
 MAX_ITERS = 32
 PHASES = ("assemble", "gather", "factor", "backsub", "retract", "cost")
 
@@ -56,12 +58,15 @@ class Report(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_iters", ctypes.c_int32),
                 ("cost", ctypes.c_double * (MAX_ITERS + 1)),
                 ("n_invalid", ctypes.c_int32 * MAX_ITERS),
-                ("min_pivot", ctypes.c_double * MAX_ITERS)]
+                ("min_pivot", ctypes.c_double * MAX_ITERS),
+                ("refine_resid", ctypes.c_double * MAX_ITERS),
+                ("fp64_fallback", ctypes.c_int32 * MAX_ITERS)]
 
     def to_dict(self):
         n = self.n_iters
         return {"status": int(self.status), "n_iters": n, "cost": list(self.cost[: n + 1]),
-                "n_invalid": list(self.n_invalid[:n]), "min_pivot": list(self.min_pivot[:n])}
+                "n_invalid": list(self.n_invalid[:n]), "min_pivot": list(self.min_pivot[:n]),
+                "refine_resid": list(self.refine_resid[:n]), "fp64_fallback": list(self.fp64_fallback[:n])}
 
 
 _lib = None
@@ -88,6 +93,13 @@ def lib():
         L.dpvba_solve.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts),
                                   ctypes.POINTER(Report), vp]
         L.dpvba_solve.restype = ctypes.c_int
+        L.dpvba_solve_backward.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp,
+                                           vp]
+        L.dpvba_solve_backward.restype = ctypes.c_int
+        L.dpvba_analyze_batch.argtypes = [vp, ctypes.POINTER(Batch), vp, vp]
+        L.dpvba_analyze_batch.restype = ctypes.c_int
+        L.dpvba_solve_batch.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, ctypes.POINTER(Opts), vp, vp]
+        L.dpvba_solve_batch.restype = ctypes.c_int
         L.dpvba_trace_begin.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         L.dpvba_trace_begin.restype = ctypes.c_int
         L.dpvba_trace_end.argtypes = [vp, vp, vp, vp]
@@ -158,6 +170,66 @@ class GraphTensors:
                      _ptr(self.target), _ptr(self.weight), fx, fy, cx, cy)
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("n_problems", ctypes.c_int32), ("patch_size", ctypes.c_int32),
+        ("frame_off", ctypes.c_void_p), ("patch_off", ctypes.c_void_p), ("edge_off", ctypes.c_void_p),
+        ("n_fixed", ctypes.c_void_p), ("patches", ctypes.c_void_p), ("ii", ctypes.c_void_p),
+        ("jj", ctypes.c_void_p), ("kk", ctypes.c_void_p), ("target", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+        ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+    ]
+
+
+@dataclass
+class BatchTensors:
+    """Device tensors of a batch of problems packed back to back (see
+    dpvba_batch); indices are local to each problem."""
+
+    frame_off: np.ndarray   # host int32 [B+1]
+    patch_off: np.ndarray
+    edge_off: np.ndarray
+    n_fixed: np.ndarray     # host int32 [B]
+    patches: torch.Tensor   # [sum P,p,p,2] float32
+    ii: torch.Tensor        # [sum E] int32
+    jj: torch.Tensor
+    kk: torch.Tensor
+    target: torch.Tensor    # [sum E,2] float32
+    weight: torch.Tensor
+    intrinsics: tuple
+    poses: torch.Tensor     # [sum N,7] float32 starting poses
+    inv_depth: torch.Tensor  # [sum P] float32 starting inverse depths
+
+    @property
+    def n_problems(self) -> int:
+        return len(self.n_fixed)
+
+    @staticmethod
+    def from_scenes(scenes, device="cuda"):
+        """Pack scenes (one camera) into one batch."""
+        intr = tuple(float(x) for x in scenes[0].intrinsics)
+        for s in scenes:
+            if tuple(float(x) for x in s.intrinsics) != intr:
+                raise ValueError("a batch has one camera")
+        cat = lambda name: np.concatenate([getattr(s, name) for s in scenes], 0)
+        off = lambda xs: np.concatenate([[0], np.cumsum(xs)]).astype(np.int32)
+        f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).to(device)
+        i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int32).to(device)
+        return BatchTensors(
+            off([s.n_frames for s in scenes]), off([s.n_patches for s in scenes]), off([s.n_edges for s in scenes]),
+            np.array([s.n_fixed for s in scenes], dtype=np.int32), f32(cat("patches")), i32(cat("ii")),
+            i32(cat("jj")), i32(cat("kk")), f32(cat("target")).reshape(-1, 2), f32(cat("weight")).reshape(-1, 2),
+            intr, f32(cat("poses")), f32(cat("inv_depth")))
+
+    def struct(self) -> Batch:
+        fx, fy, cx, cy = self.intrinsics
+        self._host = [np.ascontiguousarray(a, dtype=np.int32) for a in
+                      (self.frame_off, self.patch_off, self.edge_off, self.n_fixed)]
+        hp = [a.ctypes.data_as(ctypes.c_void_p) for a in self._host]
+        return Batch(self.n_problems, self.patches.shape[1], hp[0], hp[1], hp[2], hp[3], _ptr(self.patches),
+                     _ptr(self.ii), _ptr(self.jj), _ptr(self.kk), _ptr(self.target), _ptr(self.weight),
+                     fx, fy, cx, cy)
+
+
 class Context:
     """One dpvba_ctx on a device."""
 
@@ -205,7 +277,9 @@ class Context:
 
     def reduced_system(self, g: GraphTensors, poses, inv_depth, lam=1e-4, z_min=0.1, precision=FP32,
                        stream=None):
-        dt = torch.float64 if precision == FP64 else torch.float32
+        """S [n,n] and s [n] at (poses, inv_depth); float64 for FP64 and
+        MIXED (float32 assembly gathered in float64), else float32."""
+        dt = torch.float64 if precision in (FP64, MIXED) else torch.float32
         n = 6 * (g.n_frames - g.n_fixed)
         S = torch.empty((n, n), dtype=dt, device=poses.device)
         s = torch.empty((n,), dtype=dt, device=poses.device)
@@ -219,9 +293,9 @@ class Context:
 
     def solve(self, g: GraphTensors, poses, inv_depth, n_iters=2, lam=1e-4, z_min=0.1, precision=FP32,
               report=True, stream=None):
-        """In-place solve of poses [N,7] and inv_depth [P] (float32, or float64
-        for precision=FP64).  Returns the report as a dict (after synchronising
-        the stream) or None."""
+        """In-place solve of poses [N,7] and inv_depth [P] (float32 for FP32 and
+        MIXED, float64 for FP64).  Returns the report as a dict (after
+        synchronising the stream) or None."""
         want = torch.float64 if precision == FP64 else torch.float32
         if poses.dtype != want or inv_depth.dtype != want:
             raise TypeError(f"poses and inv_depth must be {want}")
@@ -237,6 +311,63 @@ class Context:
         (torch.cuda.current_stream() if stream is None else stream).synchronize()
         return rep.to_dict()
 
+    def solve_backward(self, g: GraphTensors, poses0, inv_depth0, grad_poses=None, grad_inv_depth=None, n_iters=2,
+                       lam=1e-4, z_min=0.1, precision=FP32, stream=None):
+        """Gradients (target [E,2], weight [E,2]) of a loss whose gradients
+        with respect to the poses and inverse depths that `solve` returns
+        from (poses0, inv_depth0) are grad_poses [N,7] and grad_inv_depth [P]
+        (either may be None for zero).  All float32, or float64 for FP64."""
+        want = torch.float64 if precision == FP64 else torch.float32
+        for name, t in (("poses0", poses0), ("inv_depth0", inv_depth0), ("grad_poses", grad_poses),
+                        ("grad_inv_depth", grad_inv_depth)):
+            if t is not None and (t.dtype != want or not t.is_contiguous()):
+                raise TypeError(f"{name} must be a contiguous {want} tensor")
+        E = g.ii.shape[0]
+        gt = torch.empty((E, 2), dtype=want, device=poses0.device)
+        gw = torch.empty((E, 2), dtype=want, device=poses0.device)
+        o = self._opts(n_iters, lam, z_min, precision)
+        gs = g.struct()
+        _check(lib().dpvba_solve_backward(self._h, ctypes.byref(gs), _ptr(poses0), _ptr(inv_depth0), ctypes.byref(o),
+                                          _ptr(grad_poses), _ptr(grad_inv_depth), _ptr(gt), _ptr(gw),
+                                          _stream(stream)), "dpvba_solve_backward", self._h)
+        return gt, gw
+
+    def analyze_batch(self, b: "BatchTensors", tile_patches=None, stream=None):
+        """Symbolic analysis of a packed batch; tile_patches: per-problem
+        patches per tile (float32 / mixed) or None for the default."""
+        bs = b.struct()
+        tp = None
+        if tile_patches is not None:
+            self._tp = np.ascontiguousarray(tile_patches, dtype=np.int32)
+            if self._tp.shape != (b.n_problems,):
+                raise ValueError("tile_patches must have one entry per problem")
+            tp = self._tp.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().dpvba_analyze_batch(self._h, ctypes.byref(bs), tp, _stream(stream)), "dpvba_analyze_batch",
+               self._h)
+
+    def solve_batch(self, b: "BatchTensors", poses, inv_depth, n_iters=2, lam=1e-4, z_min=0.1, precision=FP32,
+                    report=True, graph=False, stream=None):
+        """In-place solve of every problem of an analysed batch: poses
+        [sum N,7], inv_depth [sum P] (float32 for FP32 / MIXED, float64 for
+        FP64).  graph=True records the launches in a HIP graph on first use
+        and replays it.  Returns the per-problem reports (after synchronising
+        the stream) or None."""
+        want = torch.float64 if precision == FP64 else torch.float32
+        if poses.dtype != want or inv_depth.dtype != want:
+            raise TypeError(f"poses and inv_depth must be {want}")
+        if not (poses.is_contiguous() and inv_depth.is_contiguous()):
+            raise ValueError("poses and inv_depth must be contiguous")
+        bs = b.struct()
+        o = Opts(int(n_iters), int(precision), float(lam), float(z_min), FLAG_GRAPH if graph else 0)
+        reps = (Report * b.n_problems)() if report else None
+        _check(lib().dpvba_solve_batch(self._h, ctypes.byref(bs), _ptr(poses), _ptr(inv_depth), ctypes.byref(o),
+                                       ctypes.cast(reps, ctypes.c_void_p) if reps is not None else None,
+                                       _stream(stream)), "dpvba_solve_batch", self._h)
+        if reps is None:
+            return None
+        (torch.cuda.current_stream() if stream is None else stream).synchronize()
+        return [r.to_dict() for r in reps]
+
     def trace_begin(self, sample_every: int = 1, max_pairs: int = 1 << 16):
         _check(lib().dpvba_trace_begin(self._h, int(sample_every), int(max_pairs)), "dpvba_trace_begin", self._h)
 
@@ -249,3 +380,43 @@ class Context:
         _check(lib().dpvba_trace_end(self._h, ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(ns, ctypes.c_void_p),
                                      ctypes.cast(nl, ctypes.c_void_p)), "dpvba_trace_end", self._h)
         return {PHASES[p]: (ms[p], ns[p], nl[p]) for p in range(n)}
+
+
+class _BundleAdjust(torch.autograd.Function):
+    """(target, weight) -> (poses, inv_depth) after n_iters iterations, with
+    the adjoint of the unrolled iterations as its backward."""
+
+    @staticmethod
+    def forward(ctx, target, weight, poses0, inv_depth0, context, graph, n_iters, lam, z_min, precision):
+        dt = torch.float64 if precision == FP64 else torch.float32
+        g = GraphTensors(graph.n_frames, graph.n_fixed, graph.patches, graph.ii, graph.jj, graph.kk,
+                         target.detach().to(torch.float32).contiguous(),
+                         weight.detach().to(torch.float32).contiguous(), graph.intrinsics)
+        p0 = poses0.detach().to(dt).contiguous()
+        d0 = inv_depth0.detach().to(dt).contiguous()
+        poses, d = p0.clone(), d0.clone()
+        context.solve(g, poses, d, n_iters, lam, z_min, precision, report=False)
+        ctx.save_for_backward(p0, d0)
+        ctx.g, ctx.context = g, context
+        ctx.args = (n_iters, lam, z_min, precision)
+        ctx.dtypes = (target.dtype, weight.dtype)
+        return poses, d
+
+    @staticmethod
+    def backward(ctx, grad_poses, grad_d):
+        p0, d0 = ctx.saved_tensors
+        n_iters, lam, z_min, precision = ctx.args
+        gp = None if grad_poses is None else grad_poses.to(p0.dtype).contiguous()
+        gd = None if grad_d is None else grad_d.to(d0.dtype).contiguous()
+        gt, gw = ctx.context.solve_backward(ctx.g, p0, d0, gp, gd, n_iters, lam, z_min, precision)
+        return gt.to(ctx.dtypes[0]), gw.to(ctx.dtypes[1]), None, None, None, None, None, None, None, None
+
+
+def bundle_adjust(context: Context, graph: GraphTensors, poses0, inv_depth0, target, weight, n_iters=2, lam=1e-4,
+                  z_min=0.1, precision=FP32):
+    """Differentiable BA layer: the poses [N,7] and inverse depths [P] after
+    n_iters Gauss-Newton iterations from (poses0, inv_depth0), differentiable
+    with respect to target [E,2] and weight [E,2].  `context` must have
+    analysed `graph` (its index arrays); the graph's own target and weight
+    are not used.  Forward and backward run in libdpvba.so."""
+    return _BundleAdjust.apply(target, weight, poses0, inv_depth0, context, graph, n_iters, lam, z_min, precision)

@@ -24,8 +24,8 @@ hipError_t launch_tile_iterate(const IterArgs<T>& A, int lds_bytes, hipStream_t 
 template <typename T>
 hipError_t launch_tile_finalize(const TileInfo* tiles, int n_tiles, int lds_bytes, const int* tile_patch,
                                 const int* blk_pose, const T* U_s, const T* pscale_s, const T* depth_s,
-                                const T* dx, const int* status, T* depth_out, const T* poses_final,
-                                T* poses_out, int n_frames, hipStream_t st);
+                                const T* dx, const int* status, int status_stride, T* depth_out,
+                                const T* poses_final, T* poses_out, int n_frames, hipStream_t st);
 template <typename T>
 hipError_t launch_retract_copy(const T* poses_cur, T* poses_next, const T* dx, int n_fixed, int n_frames,
                                const int* status, hipStream_t st);
@@ -51,8 +51,93 @@ template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* work_y, T* Linv_all, const T* d0,
                              int* status, unsigned int* min_bits, hipStream_t st);
 hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st);
+template <typename TP, typename T>
+hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
+                            const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
+                            int mirror, T* diag_out, hipStream_t st);
+template <typename T>
+hipError_t launch_chol_factor(T* S, int n, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_b, T* work_y,
+                             hipStream_t st);
+// mixed-precision helpers (mixed.hip)
+template <typename Ti, typename To>
+hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st);
+hipError_t launch_lower_to_f32(const double* S64, float* S32, int n, hipStream_t st);
+hipError_t launch_residual64(const double* S, const double* s, const double* x, int n, double* r,
+                             unsigned long long* maxes, hipStream_t st);
+hipError_t launch_accumulate(double* x, const float* c, int n, hipStream_t st);
+hipError_t launch_refine_decide(const unsigned long long* maxes, const int* status32, double tol, double* resid_out,
+                                int* fallback_out, int* host_flag, hipStream_t st);
+hipError_t launch_step_to_f32(const double* x, float* dx, int n, const int* fallback, const int* status64,
+                              int* status, hipStream_t st);
+// batch kernels (batch.hip)
+template <typename TS>
+struct BatchArgs {
+  const BatchInst* inst;
+  const TS* part_S;
+  const TS* part_vec;
+  const int* s_off;
+  const int* s_src;
+  const int* v_off;
+  const int2* v_src;
+  double lambda;
+  const TS* poses_cur;
+  TS* poses_next;
+  TS* dx;
+  int* status;
+  unsigned int* min_bits;
+  double* refine_resid;
+  int* fallback;
+  int stride, it;
+  double* scratch;
+  int lds_factor;
+};
+template <typename T>
+int batch_solve_lds(int n_max, bool mixed, bool* lds_factor);
+template <typename T>
+hipError_t launch_batch_solve(const BatchArgs<T>& a, int n_inst, int lds_bytes, hipStream_t st);
+hipError_t launch_batch_solve_mixed(const BatchArgs<float>& a, int n_inst, int lds_bytes, hipStream_t st);
+hipError_t launch_batch_cost(const BatchInst* inst, int n_inst, const double* part_cost, const int* part_invalid,
+                             dpvba_report* rep, int it, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_report(const BatchInst* inst, int n_inst, const T* poses, const T* inv_depth,
+                               const float* patches, int p, const int* ii, const int* jj, const int* kk,
+                               const float* target, const float* weight, T fx, T fy, T cx, T cy, T z_min,
+                               const int* status, const unsigned int* min_bits, const double* refine,
+                               const int* fallback, int stride, int n_iters, dpvba_report* rep, hipStream_t st);
+// adjoint kernels (adjoint.hip)
+template <typename T>
+hipError_t launch_edge_adjoint(const T* poses, const T* depth_t, const int* patch_pos, const float* patches, int p,
+                               const int* ii, const int* jj, const int* kk, const float* target,
+                               const float* weight, int n_edges, int n_fixed, T fx, T fy, T cx, T cy, T z_min,
+                               T lambda, const T* u_pose, const T* u_depth, const T* dxi, const T* dd,
+                               const int* status, T* grad_target, T* grad_weight, T* edge_xbar, hipStream_t st);
+template <typename T>
+hipError_t launch_retract_adjoint(const T* poses_t, const T* dxi, const int* status, int n_fixed, int n_frames,
+                                  T* pbar, T* dxi_bar, hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_rhs(const TileInfo* tiles, int n_tiles, const T* U_s, const T* pscale_s, const T* dbar,
+                              T* part_vec, const int* v_off, const int2* v_src, int n_free, const T* dxi_bar,
+                              const int* status, T* rhs, hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_backsub(const TileInfo* tiles, int n_tiles, int max_w6, const int* blk_pose,
+                                  const T* U_s, const T* pscale_s, const T* dbar, const T* u_pose, const T* dxi,
+                                  const int* status, T* u_depth, T* dd, hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_reduce(const T* edge_xbar, const int* pose_off, const int* pose_src, int n_fixed,
+                                 int n_frames, T* pbar, const int* tile_patch, const int* pcount, const int* pedges,
+                                 int n_tp, T* dbar, hipStream_t st);
+template <typename T>
+hipError_t launch_depth_to_tile(const T* src, const int* tile_patch, int n_tp, T* dst, hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T* x, long long n, T v, hipStream_t st);
+template <typename T>
+hipError_t launch_copy(const T* src, T* dst, long long n, hipStream_t st);
 hipError_t launch_report_finalize(dpvba_report* rep, const int* status, const unsigned int* min_bits,
-                                  int n_iters, const int* err, hipStream_t st);
+                                  int n_iters, const int* err, hipStream_t st, const double* refine = nullptr,
+                                  const int* fallback = nullptr);
 
 }  // namespace dpvba
 
@@ -120,6 +205,28 @@ struct dpvba_ctx {
   DevBuf part_S, part_vec, part_cost, part_invalid, U_s, pscale_s, depth_s, xh_s, poses_a, poses_b;
   DevBuf S, rhs, dB, d0, dx, wb, wy, Linv, edge_part, ticket, dev_err;
   DevBuf status, min_bits, devrep;
+  // edge lists of the adjoint: per patch (pcount / pedges, edge order), per
+  // pose (pose_off / pose_src = 2 e + side), tile-order position of a patch
+  DevBuf pcount, pedges, pose_off, pose_src, patch_pos;
+  // mixed precision: float32 factor, float64 iterate and residual, decision state
+  DevBuf S32, x64, r64, rhs32, c32, d0_32, mx_max, mx_resid, mx_fb, mx_flag;
+  int* host_flag = nullptr;  // pinned
+  // batch analysis
+  struct Batch {
+    bool analysed = false;
+    int B = 0, p = 0, N = 0, P = 0, E = 0, n_max = 0;
+    long long n_free = 0, scratch = 0;
+    const int32_t *ii = nullptr, *jj = nullptr, *kk = nullptr;
+    std::vector<int32_t> frame_off, patch_off, edge_off, n_fixed;
+    Tiling tl[2];
+    DevBuf inst[2];
+    DevBuf status, min_bits, refine, fallback, reps, scratch_buf;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;
+  } bt;
+  // adjoint workspace
+  DevBuf bw_poses, bw_depth, bw_dx, bw_pbar, bw_dbar, bw_dxbar, bw_rhs, bw_up, bw_ud, bw_dd, bw_edge, bw_status,
+      bw_minbits;
   char err[256] = {0};
   // tracing
   bool tracing = false;
@@ -251,13 +358,28 @@ void dpvba_destroy(dpvba_ctx* c) {
   (void)hipSetDevice(c->device);
   DevBuf* bufs[] = {&c->part_S, &c->part_vec, &c->part_cost, &c->part_invalid, &c->U_s, &c->pscale_s,
                     &c->depth_s, &c->xh_s, &c->poses_a, &c->poses_b, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx,
-                    &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep};
+                    &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
+                    &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
+                    &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
+                    &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
+                    &c->d0_32, &c->mx_max, &c->mx_resid, &c->mx_fb, &c->mx_flag};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (Tiling& t : c->tl)
     for (DevBuf* b : t.bufs)
       if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->host_flag) (void)hipHostFree(c->host_flag);
+  {
+    DevBuf* bb[] = {&c->bt.inst[0], &c->bt.inst[1], &c->bt.status, &c->bt.min_bits, &c->bt.refine, &c->bt.fallback,
+                    &c->bt.reps, &c->bt.scratch_buf};
+    for (DevBuf* b : bb)
+      if (b->p) (void)hipFree(b->p);
+    for (Tiling& t : c->bt.tl)
+      for (DevBuf* b : t.bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->bt.exec) (void)hipGraphExecDestroy(c->bt.exec);
+  }
   delete c;
 }
 
@@ -281,6 +403,36 @@ struct HostTiling {
   long long part_S = 0, part_vec = 0, u_elems = 0;
   int lds = 0, max_w6 = 0;
 };
+
+// Edge structure of one problem from host copies of its indices: edges
+// grouped by patch (pcount / pedges, original order within a patch) and each
+// frame's patches.  False on an index out of range, a self edge or a patch
+// whose edges leave different frames.
+struct ProblemIndex {
+  std::vector<int32_t> pcount, pedges;
+  std::vector<std::vector<int32_t>> frame_patches;
+};
+
+static bool index_problem(int N, int P, int E, const int32_t* ii, const int32_t* jj, const int32_t* kk,
+                          ProblemIndex& X) {
+  std::vector<int32_t> owner(P, -1);
+  X.pcount.assign(P + 1, 0);
+  for (int e = 0; e < E; ++e) {
+    const int i = ii[e], j = jj[e], k = kk[e];
+    if (i < 0 || i >= N || j < 0 || j >= N || k < 0 || k >= P || i == j) return false;
+    if (owner[k] < 0) owner[k] = i;
+    else if (owner[k] != i) return false;
+    X.pcount[k + 1]++;
+  }
+  for (int k = 0; k < P; ++k) X.pcount[k + 1] += X.pcount[k];
+  X.pedges.assign(E, 0);
+  std::vector<int32_t> cur(X.pcount.begin(), X.pcount.end() - 1);
+  for (int e = 0; e < E; ++e) X.pedges[cur[kk[e]]++] = e;
+  X.frame_patches.assign(N, {});
+  for (int k = 0; k < P; ++k)
+    if (owner[k] >= 0) X.frame_patches[owner[k]].push_back(k);
+  return true;
+}
 
 // Split each source frame's patches into tiles of at most `kcap` patches
 // whose shared-memory plan (element size tsize) fits the budget, then build
@@ -459,28 +611,37 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
     HIP_TRY(hipMemcpyAsync(kk.data(), g->kk, E * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
-  std::vector<int32_t> owner(P, -1), pcount(P + 1, 0);
-  for (int e = 0; e < E; ++e) {
-    const int i = ii[e], j = jj[e], k = kk[e];
-    if (i < 0 || i >= N || j < 0 || j >= N || k < 0 || k >= P || i == j) return DPVBA_EINVAL;
-    if (owner[k] < 0) owner[k] = i;
-    else if (owner[k] != i) return DPVBA_EINVAL;
-    pcount[k + 1]++;
-  }
-  for (int k = 0; k < P; ++k) pcount[k + 1] += pcount[k];
-  std::vector<int32_t> pedges(E);
-  {
-    std::vector<int32_t> cur(pcount.begin(), pcount.end() - 1);
-    for (int e = 0; e < E; ++e) pedges[cur[kk[e]]++] = e;  // stable: original order within a patch
-  }
-  std::vector<std::vector<int32_t>> frame_patches(N);
-  for (int k = 0; k < P; ++k)
-    if (owner[k] >= 0) frame_patches[owner[k]].push_back(k);
+  ProblemIndex X;
+  if (!index_problem(N, P, E, ii.data(), jj.data(), kk.data(), X)) return DPVBA_EINVAL;
+  const std::vector<int32_t>& pcount = X.pcount;
+  const std::vector<int32_t>& pedges = X.pedges;
+  const std::vector<std::vector<int32_t>>& frame_patches = X.frame_patches;
   HostTiling H32, H64;
   if (!plan_tiling(N, nf, jj, pcount, pedges, frame_patches, kcap32, 4, H32)) return DPVBA_EINVAL;
   if (!plan_tiling(N, nf, jj, pcount, pedges, frame_patches, kcap64, 8, H64)) return DPVBA_EINVAL;
   HIP_TRY(upload_tiling(c->tl[0], H32, st));
   HIP_TRY(upload_tiling(c->tl[1], H64, st));
+  {
+    // both plans list the patches in the same order (frame, then patch id)
+    if (H32.tile_patch != H64.tile_patch) return DPVBA_EINVAL;
+    std::vector<int32_t> pos(P, -1), pose_off(N + 1, 0), pose_src(2 * (size_t)E);
+    for (size_t q = 0; q < H32.tile_patch.size(); ++q) pos[H32.tile_patch[q]] = (int32_t)q;
+    for (int e = 0; e < E; ++e) {
+      pose_off[ii[e] + 1]++;
+      pose_off[jj[e] + 1]++;
+    }
+    for (int f = 0; f < N; ++f) pose_off[f + 1] += pose_off[f];
+    std::vector<int32_t> cur(pose_off.begin(), pose_off.end() - 1);
+    for (int e = 0; e < E; ++e) {
+      pose_src[cur[ii[e]]++] = 2 * e;
+      pose_src[cur[jj[e]]++] = 2 * e + 1;
+    }
+    HIP_TRY(upload(c->pcount, pcount, st));
+    HIP_TRY(upload(c->pedges, pedges, st));
+    HIP_TRY(upload(c->pose_off, pose_off, st));
+    HIP_TRY(upload(c->pose_src, pose_src, st));
+    HIP_TRY(upload(c->patch_pos, pos, st));
+  }
 
   const size_t n = 6 * (size_t)n_free;
   const size_t nblk64 = (n + 63) / 64;
@@ -511,8 +672,19 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
     HIP_TRY(hipMemsetAsync(c->dev_err.p, 0, 64, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
-  HIP_TRY(ensure(c->status, DPVBA_MAX_ITERS * 4));
-  HIP_TRY(ensure(c->min_bits, DPVBA_MAX_ITERS * 4));
+  HIP_TRY(ensure(c->status, 2 * DPVBA_MAX_ITERS * 4));  // [MAX, 2 MAX): float64 fallback solves
+  HIP_TRY(ensure(c->min_bits, 2 * DPVBA_MAX_ITERS * 4));
+  HIP_TRY(ensure(c->S32, n * n * 4));
+  HIP_TRY(ensure(c->x64, n * 8));
+  HIP_TRY(ensure(c->r64, n * 8));
+  HIP_TRY(ensure(c->rhs32, n * 4));
+  HIP_TRY(ensure(c->c32, n * 4));
+  HIP_TRY(ensure(c->d0_32, n * 4));
+  HIP_TRY(ensure(c->mx_max, 16));
+  HIP_TRY(ensure(c->mx_resid, DPVBA_MAX_ITERS * 8));
+  HIP_TRY(ensure(c->mx_fb, DPVBA_MAX_ITERS * 4));
+  HIP_TRY(ensure(c->mx_flag, 16));
+  if (!c->host_flag) HIP_TRY(hipHostMalloc((void**)&c->host_flag, sizeof(int), hipHostMallocDefault));
   HIP_TRY(ensure(c->devrep, sizeof(dpvba_report)));
 
   c->N = N; c->P = P; c->E = E; c->p = g->patch_size; c->n_fixed = nf; c->n_free = n_free;
@@ -540,7 +712,7 @@ static dpvba_status check_opts(const dpvba_opts* o) {
   if (o->n_iters < 0 || o->n_iters > DPVBA_MAX_ITERS) return DPVBA_EINVAL;
   if (!(o->lambda >= 0.0) || !(o->lambda < (double)FLT_MAX)) return DPVBA_EINVAL;
   if (!(o->z_min >= 0.0) || !(o->z_min < (double)FLT_MAX)) return DPVBA_EINVAL;
-  if (o->precision != DPVBA_FP32 && o->precision != DPVBA_FP64) return DPVBA_EINVAL;
+  if (o->precision != DPVBA_FP32 && o->precision != DPVBA_MIXED && o->precision != DPVBA_FP64) return DPVBA_EINVAL;
   if (o->flags != 0) return DPVBA_EINVAL;
   return DPVBA_OK;
 }
@@ -612,6 +784,30 @@ static hipError_t reduced_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pose
   return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
                           (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free, S,
                           rhs, (T*)c->dB.p, lambda, 1, (T*)c->d0.p, st);
+}
+
+// Float32 tile assembly gathered in float64 (the DPVBA_MIXED system).
+static hipError_t reduced_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, const float* poses, const float* depth,
+                                     float lambda, float z_min, double* S, double* rhs, double* cost_out,
+                                     hipStream_t st) {
+  const Tiling& tl = c->tl[0];
+  IterArgs<float> A = make_iter_args<float>(c, g, tl, poses, nullptr, depth, lambda, z_min);
+  hipError_t e;
+  {
+    TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
+    e = launch_tile_iterate<float>(A, tl.lds_bytes, st);
+  }
+  if (e != hipSuccess) return e;
+  TraceScope ts(c, DPVBA_PHASE_GATHER, st);
+  if (cost_out) {
+    e = launch_report_reduce((const double*)c->part_cost.p, (const int*)c->part_invalid.p, tl.n_tiles, cost_out,
+                             nullptr, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
+                                         (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
+                                         (const int2*)tl.v_src.p, c->n_free, S, rhs, (double*)c->dB.p,
+                                         (double)lambda, 1, (double*)c->d0.p, st);
 }
 
 template <typename T>
@@ -700,7 +896,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     TraceScope ts(c, DPVBA_PHASE_BACKSUB, st);
     e = launch_tile_finalize<T>((const TileInfo*)tl.tiles.p, tl.n_tiles, tl.lds_bytes, (const int*)tl.tile_patch.p,
                                 (const int*)tl.blk_pose.p, (const T*)c->U_s.p, (const T*)c->pscale_s.p,
-                                (const T*)c->depth_s.p, dx, status + nit - 1, depth, pbuf[(nit - 1) & 1], poses,
+                                (const T*)c->depth_s.p, dx, status + nit - 1, 0, depth, pbuf[(nit - 1) & 1], poses,
                                 c->N, st);
     if (e != hipSuccess) return e;
   }
@@ -718,6 +914,301 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
   e = launch_report_finalize(dev, status, mb, nit, (const int*)c->dev_err.p, st);
   if (e != hipSuccess) return e;
   return hipMemcpyAsync(report, dev, sizeof(dpvba_report), hipMemcpyDeviceToHost, st);
+}
+
+// Refinement of the float32 Cholesky solve against the float64 residual:
+// fixed number of steps, and the largest accepted relative residual.
+constexpr int kRefineSteps = 2;
+constexpr double kRefineTol = 1e-8;
+
+// DPVBA_MIXED: float32 state and tile assembly, float64 gather of the
+// shares, float32 Cholesky with float64 iterative refinement, float64
+// Cholesky when refinement does not reach kRefineTol (decided on the host
+// after one stream synchronisation per iteration).
+static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* poses, float* depth,
+                                   const dpvba_opts* o, dpvba_report* report, hipStream_t st) {
+  const float lambda = (float)o->lambda, z_min = (float)o->z_min;
+  const Tiling& tl = c->tl[0];
+  const int n = 6 * c->n_free;
+  const int nit = o->n_iters;
+  dpvba_report* dev = (dpvba_report*)c->devrep.p;
+  int* status = (int*)c->status.p;
+  int* status64 = status + DPVBA_MAX_ITERS;
+  unsigned int* mb = (unsigned int*)c->min_bits.p;
+  unsigned int* mb64 = mb + DPVBA_MAX_ITERS;
+  float* pbuf[2] = {(float*)c->poses_a.p, (float*)c->poses_b.p};
+  float* dx = (float*)c->dx.p;
+  double* S64 = (double*)c->S.p;
+  double* s64 = (double*)c->rhs.p;
+  double* d064 = (double*)c->d0.p;
+  float* S32 = (float*)c->S32.p;
+  float* Linv32 = (float*)c->Linv.p;
+  double* x64 = (double*)c->x64.p;
+  double* r64 = (double*)c->r64.p;
+  float* rhs32 = (float*)c->rhs32.p;
+  float* c32 = (float*)c->c32.p;
+  float* d032 = (float*)c->d0_32.p;
+  unsigned long long* maxes = (unsigned long long*)c->mx_max.p;
+  double* resid = (double*)c->mx_resid.p;
+  int* fb = (int*)c->mx_fb.p;
+  hipError_t e;
+  if ((e = launch_report_init(status, mb, 2 * DPVBA_MAX_ITERS, st)) != hipSuccess) return e;
+  if ((e = launch_fill<double>(resid, DPVBA_MAX_ITERS, 0.0, st)) != hipSuccess) return e;
+  if ((e = launch_fill<int>(fb, DPVBA_MAX_ITERS, 0, st)) != hipSuccess) return e;
+  for (int it = 0; it < nit; ++it) {
+    const float* cur = it == 0 ? poses : pbuf[(it - 1) & 1];
+    float* next = pbuf[it & 1];
+    IterArgs<float> A = make_iter_args<float>(c, g, tl, cur, next, depth, lambda, z_min);
+    A.first = it == 0;
+    A.dx_prev = it ? dx : nullptr;
+    A.status_prev = it ? status + it - 1 : nullptr;
+    {
+      TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
+      if ((e = launch_tile_iterate<float>(A, tl.lds_bytes, st)) != hipSuccess) return e;
+    }
+    {
+      TraceScope ts(c, DPVBA_PHASE_GATHER, st);
+      e = launch_report_reduce((const double*)c->part_cost.p, (const int*)c->part_invalid.p, tl.n_tiles,
+                               &dev->cost[it], &dev->n_invalid[it], st);
+      if (e == hipSuccess)
+        e = launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
+                                            (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
+                                            (const int2*)tl.v_src.p, c->n_free, S64, s64, (double*)c->dB.p,
+                                            (double)lambda, 1, d064, st);
+      if (e != hipSuccess) return e;
+    }
+    if (n > 0) {
+      TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
+      if ((e = launch_lower_to_f32(S64, S32, n, st)) != hipSuccess) return e;
+      if ((e = launch_convert<double, float>(d064, d032, n, st)) != hipSuccess) return e;
+      if ((e = launch_convert<double, float>(s64, rhs32, n, st)) != hipSuccess) return e;
+      if ((e = launch_chol_factor<float>(S32, n, Linv32, d032, status + it, mb + it, st)) != hipSuccess) return e;
+      if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wb.p, (float*)c->wy.p, st)) !=
+          hipSuccess)
+        return e;
+      if ((e = launch_convert<float, double>(c32, x64, n, st)) != hipSuccess) return e;
+      for (int k = 0; k < kRefineSteps; ++k) {
+        if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
+        if ((e = launch_convert<double, float>(r64, rhs32, n, st)) != hipSuccess) return e;
+        if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wb.p, (float*)c->wy.p, st)) !=
+            hipSuccess)
+          return e;
+        if ((e = launch_accumulate(x64, c32, n, st)) != hipSuccess) return e;
+      }
+      if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
+      if ((e = launch_refine_decide(maxes, status + it, kRefineTol, resid + it, fb + it, (int*)c->mx_flag.p, st)) !=
+          hipSuccess)
+        return e;
+      if ((e = hipMemcpyAsync(c->host_flag, c->mx_flag.p, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+      if (*c->host_flag) {
+        if ((e = launch_chol_solve<double>(S64, s64, n, x64, (double*)c->wb.p, (double*)c->wy.p, (double*)c->Linv.p,
+                                           d064, status64 + it, mb64 + it, st)) != hipSuccess)
+          return e;
+      }
+      if ((e = launch_step_to_f32(x64, dx, n, fb + it, status64 + it, status + it, st)) != hipSuccess) return e;
+    }
+    {
+      TraceScope ts(c, DPVBA_PHASE_RETRACT, st);
+      if ((e = launch_retract_copy<float>(cur, next, dx, c->n_fixed, c->N, status + it, st)) != hipSuccess) return e;
+    }
+  }
+  if (nit > 0) {
+    TraceScope ts(c, DPVBA_PHASE_BACKSUB, st);
+    e = launch_tile_finalize<float>((const TileInfo*)tl.tiles.p, tl.n_tiles, tl.lds_bytes,
+                                    (const int*)tl.tile_patch.p, (const int*)tl.blk_pose.p, (const float*)c->U_s.p,
+                                    (const float*)c->pscale_s.p, (const float*)c->depth_s.p, dx, status + nit - 1,
+                                    0, depth, pbuf[(nit - 1) & 1], poses, c->N, st);
+    if (e != hipSuccess) return e;
+  }
+  if (!report) return hipSuccess;
+  {
+    TraceScope ts_cost(c, DPVBA_PHASE_COST, st);
+    e = launch_edge_cost<float, float>(poses, depth, g->patches, g->patch_size, g->ii, g->jj, g->kk, g->target,
+                                       g->weight, g->n_edges, g->fx, g->fy, g->cx, g->cy, z_min,
+                                       (double*)c->edge_part.p, st);
+  }
+  if (e != hipSuccess) return e;
+  e = launch_report_reduce((const double*)c->edge_part.p, nullptr, (g->n_edges + 255) / 256, &dev->cost[nit], nullptr,
+                           st);
+  if (e != hipSuccess) return e;
+  e = launch_report_finalize(dev, status, mb, nit, (const int*)c->dev_err.p, st, resid, fb);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(report, dev, sizeof(dpvba_report), hipMemcpyDeviceToHost, st);
+}
+
+// Append one problem's tiling to the batch tiling, rebasing its indices
+// into the packed arrays (frames, patches, edges, free poses) and into the
+// concatenated share buffers and gather lists.
+static bool append_tiling(HostTiling& H, const HostTiling& Hb, int b, int frame_begin, int patch_begin,
+                          int edge_begin, int free_begin, BatchInst& I) {
+  I.tile_begin = (int)H.tiles.size();
+  I.n_tiles = (int)Hb.tiles.size();
+  I.s_base = (int)H.s_off.size();
+  I.v_base = (int)H.v_off.size();
+  const long long tp0 = (long long)H.tile_patch.size(), sl0 = (long long)H.slot_frame.size();
+  const long long g0 = (long long)H.edge_grid.size(), bp0 = (long long)H.blk_pose.size();
+  const long long ps0 = H.part_S, pv0 = H.part_vec, u0 = H.u_elems;
+  const long long ss0 = (long long)H.s_src.size(), vs0 = (long long)H.v_src.size();
+  if (g0 + (long long)Hb.edge_grid.size() > INT32_MAX || ps0 + Hb.part_S > INT32_MAX ||
+      pv0 + Hb.part_vec > INT32_MAX || u0 + Hb.u_elems > INT32_MAX)
+    return false;
+  for (TileInfo t : Hb.tiles) {
+    t.frame += frame_begin;
+    t.patch_begin += (int)tp0;
+    t.slot_begin += (int)sl0;
+    t.grid_begin += (int)g0;
+    t.blk_begin += (int)bp0;
+    t.part_begin += (int)ps0;
+    t.vec_begin += (int)pv0;
+    t.u_begin += (int)u0;
+    t.inst = b;
+    H.tiles.push_back(t);
+  }
+  for (int32_t k : Hb.tile_patch) H.tile_patch.push_back(k + patch_begin);
+  for (int32_t f : Hb.slot_frame) H.slot_frame.push_back(f + frame_begin);
+  for (int32_t x : Hb.slot_blk) H.slot_blk.push_back(x);
+  for (int32_t e : Hb.edge_grid) H.edge_grid.push_back(e >= 0 ? e + edge_begin : -1);
+  for (int32_t f : Hb.blk_pose) H.blk_pose.push_back(f + free_begin);
+  for (int32_t o : Hb.s_off) H.s_off.push_back(o + (int)ss0);
+  for (int32_t o : Hb.s_src) H.s_src.push_back(o + (int)ps0);
+  for (int32_t o : Hb.v_off) H.v_off.push_back(o + (int)vs0);
+  for (int2 o : Hb.v_src) H.v_src.push_back(make_int2(o.x + (int)pv0, o.y + (int)pv0));
+  H.part_S += Hb.part_S;
+  H.part_vec += Hb.part_vec;
+  H.u_elems += Hb.u_elems;
+  H.lds = std::max(H.lds, Hb.lds);
+  H.max_w6 = std::max(H.max_w6, Hb.max_w6);
+  return true;
+}
+
+static bool batch_sizes_ok(const dpvba_batch* b) {
+  if (!b || b->n_problems < 1 || b->patch_size < 1 || (b->patch_size % 2) == 0) return false;
+  if (!b->frame_off || !b->patch_off || !b->edge_off || !b->n_fixed) return false;
+  if (!(b->fx != 0.f) || !(b->fy != 0.f)) return false;
+  const int B = b->n_problems;
+  if (b->frame_off[0] != 0 || b->patch_off[0] != 0 || b->edge_off[0] != 0) return false;
+  for (int q = 0; q < B; ++q) {
+    if (b->frame_off[q + 1] <= b->frame_off[q] || b->patch_off[q + 1] < b->patch_off[q] ||
+        b->edge_off[q + 1] < b->edge_off[q])
+      return false;
+    const int N = b->frame_off[q + 1] - b->frame_off[q];
+    if (b->n_fixed[q] < 0 || b->n_fixed[q] > N) return false;
+  }
+  if (b->frame_off[B] > (1 << 24) || b->patch_off[B] > (1 << 28) || b->edge_off[B] > (1 << 29)) return false;
+  if (b->edge_off[B] > 0 && (!b->ii || !b->jj || !b->kk || !b->target || !b->weight)) return false;
+  if (b->patch_off[B] > 0 && !b->patches) return false;
+  return true;
+}
+
+// Adjoint of `n_iters` iterations started from (poses0, depth0): replays
+// the iterations storing x_t and the pose steps, then walks them backwards
+// (see adjoint.hip), recomputing each iteration's Schur system at x_t.
+template <typename T>
+static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* poses0, const T* depth0,
+                                const dpvba_opts* o, const T* grad_poses, const T* grad_depth, T* grad_target,
+                                T* grad_weight, hipStream_t st) {
+  const T lambda = (T)o->lambda, z_min = (T)o->z_min;
+  const Tiling& tl = c->tl[sizeof(T) == 8 ? 1 : 0];
+  const int N = c->N, nf = c->n_fixed, n = 6 * c->n_free, nit = o->n_iters, E = c->E;
+  const long long ntp = tl.n_tp, np7 = 7LL * N;
+  const size_t ts = sizeof(T);
+  hipError_t e;
+  if ((e = launch_fill<T>(grad_target, 2LL * E, (T)0, st)) != hipSuccess) return e;
+  if ((e = launch_fill<T>(grad_weight, 2LL * E, (T)0, st)) != hipSuccess) return e;
+  if (nit == 0) return hipSuccess;
+  if ((e = ensure(c->bw_poses, (size_t)(nit + 1) * np7 * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_depth, (size_t)nit * ntp * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_dx, (size_t)nit * n * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_pbar, (size_t)np7 * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_dbar, (size_t)ntp * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_dxbar, (size_t)n * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_rhs, (size_t)n * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_up, (size_t)n * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_ud, (size_t)ntp * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_dd, (size_t)ntp * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_edge, (size_t)E * 15 * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_status, 2 * DPVBA_MAX_ITERS * 4)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_minbits, 2 * DPVBA_MAX_ITERS * 4)) != hipSuccess) return e;
+  T* Xp = (T*)c->bw_poses.p;
+  T* Xd = (T*)c->bw_depth.p;
+  T* DX = (T*)c->bw_dx.p;
+  T* pbar = (T*)c->bw_pbar.p;
+  T* dbar = (T*)c->bw_dbar.p;
+  T* dxbar = (T*)c->bw_dxbar.p;
+  T* urhs = (T*)c->bw_rhs.p;
+  T* up = (T*)c->bw_up.p;
+  T* ud = (T*)c->bw_ud.p;
+  T* dd = (T*)c->bw_dd.p;
+  T* exb = (T*)c->bw_edge.p;
+  int* status = (int*)c->bw_status.p;  // [0, MAX): replayed steps, [MAX, 2 MAX): adjoint solves
+  unsigned int* mb = (unsigned int*)c->bw_minbits.p;
+  const TileInfo* tiles = (const TileInfo*)tl.tiles.p;
+  if ((e = launch_report_init(status, mb, 2 * DPVBA_MAX_ITERS, st)) != hipSuccess) return e;
+  if ((e = launch_copy<T>(poses0, Xp, np7, st)) != hipSuccess) return e;
+  auto gather = [&]() {
+    return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
+                            (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
+                            (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, 0, (T*)c->d0.p, st);
+  };
+  // replay: x_0 .. x_T, depths d_0 .. d_{T-1} in tile order, steps of the poses
+  for (int it = 0; it < nit; ++it) {
+    T* xt = Xp + it * np7;
+    IterArgs<T> A = make_iter_args<T>(c, g, tl, xt, nullptr, depth0, lambda, z_min);
+    A.first = it == 0;
+    A.dx_prev = it ? DX + (size_t)(it - 1) * n : nullptr;
+    A.status_prev = it ? status + it - 1 : nullptr;
+    if ((e = launch_tile_iterate<T>(A, tl.lds_bytes, st)) != hipSuccess) return e;
+    if ((e = launch_copy<T>((const T*)c->depth_s.p, Xd + it * ntp, ntp, st)) != hipSuccess) return e;
+    if ((e = gather()) != hipSuccess) return e;
+    if ((e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, DX + (size_t)it * n, (T*)c->wb.p,
+                                  (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p, status + it, mb + it, st)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_retract_copy<T>(xt, xt + np7, DX + (size_t)it * n, nf, N, status + it, st)) != hipSuccess)
+      return e;
+  }
+  // adjoint of x_T
+  if (grad_poses) e = launch_copy<T>(grad_poses, pbar, np7, st);
+  else e = launch_fill<T>(pbar, np7, (T)0, st);
+  if (e != hipSuccess) return e;
+  if ((e = launch_depth_to_tile<T>(grad_depth, (const int*)tl.tile_patch.p, (int)ntp, dbar, st)) != hipSuccess)
+    return e;
+  for (int it = nit - 1; it >= 0; --it) {
+    const T* xt = Xp + it * np7;
+    const T* dx_t = DX + (size_t)it * n;
+    const int* stt = status + it;
+    if ((e = launch_retract_adjoint<T>(xt, dx_t, stt, nf, N, pbar, dxbar, st)) != hipSuccess) return e;
+    IterArgs<T> A = make_iter_args<T>(c, g, tl, xt, nullptr, depth0, lambda, z_min);
+    A.first = 0;
+    A.dx_prev = nullptr;
+    A.depth_s = Xd + it * ntp;
+    if ((e = launch_tile_iterate<T>(A, tl.lds_bytes, st)) != hipSuccess) return e;
+    if ((e = gather()) != hipSuccess) return e;
+    if ((e = launch_adjoint_rhs<T>(tiles, tl.n_tiles, (const T*)c->U_s.p, (const T*)c->pscale_s.p, dbar,
+                                   (T*)c->part_vec.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
+                                   dxbar, stt, urhs, st)) != hipSuccess)
+      return e;
+    if ((e = launch_chol_solve<T>((T*)c->S.p, urhs, n, up, (T*)c->wb.p, (T*)c->wy.p, (T*)c->Linv.p,
+                                  (const T*)c->d0.p, status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it,
+                                  st)) != hipSuccess)
+      return e;
+    if ((e = launch_adjoint_backsub<T>(tiles, tl.n_tiles, tl.max_w6, (const int*)tl.blk_pose.p,
+                                       (const T*)c->U_s.p, (const T*)c->pscale_s.p, dbar, up, dx_t, stt, ud, dd,
+                                       st)) != hipSuccess)
+      return e;
+    if ((e = launch_edge_adjoint<T>(xt, Xd + it * ntp, (const int*)c->patch_pos.p, g->patches, g->patch_size, g->ii,
+                                    g->jj, g->kk, g->target, g->weight, E, nf, (T)g->fx, (T)g->fy, (T)g->cx,
+                                    (T)g->cy, z_min, lambda, up, ud, dx_t, dd, stt, grad_target, grad_weight, exb,
+                                    st)) != hipSuccess)
+      return e;
+    if ((e = launch_adjoint_reduce<T>(exb, (const int*)c->pose_off.p, (const int*)c->pose_src.p, nf, N, pbar,
+                                      (const int*)tl.tile_patch.p, (const int*)c->pcount.p,
+                                      (const int*)c->pedges.p, (int)ntp, dbar, st)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
 }
 
 extern "C" {
@@ -746,6 +1237,9 @@ dpvba_status dpvba_reduced_system(dpvba_ctx* c, const dpvba_graph* g, const floa
   if (o->precision == DPVBA_FP64) {
     HIP_TRY(reduced_impl<double>(c, g, (const double*)(const void*)poses, (const double*)(const void*)inv_depth,
                                  (double)o->lambda, (double)o->z_min, (double*)S, (double*)s, cost, st));
+  } else if (o->precision == DPVBA_MIXED) {
+    HIP_TRY(reduced_mixed_impl(c, g, poses, inv_depth, (float)o->lambda, (float)o->z_min, (double*)S, (double*)s,
+                               cost, st));
   } else {
     HIP_TRY(reduced_impl<float>(c, g, poses, inv_depth, (float)o->lambda, (float)o->z_min, (float*)S, (float*)s,
                                 cost, st));
@@ -765,8 +1259,323 @@ dpvba_status dpvba_solve(dpvba_ctx* c, const dpvba_graph* g, float* poses, float
   hipStream_t st = (hipStream_t)stream;
   if (o->precision == DPVBA_FP64) {
     HIP_TRY(solve_impl<double>(c, g, (double*)(void*)poses, (double*)(void*)inv_depth, o, report, st));
+  } else if (o->precision == DPVBA_MIXED) {
+    HIP_TRY(solve_mixed_impl(c, g, poses, inv_depth, o, report, st));
   } else {
     HIP_TRY(solve_impl<float>(c, g, poses, inv_depth, o, report, st));
+  }
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_solve_backward(dpvba_ctx* c, const dpvba_graph* g, const float* poses0,
+                                  const float* inv_depth0, const dpvba_opts* o, const float* grad_poses,
+                                  const float* grad_inv_depth, float* grad_target, float* grad_weight,
+                                  void* stream) {
+  if (!c || !graph_sizes_ok(g)) return DPVBA_EINVAL;
+  dpvba_status rc = check_opts(o);
+  if (rc != DPVBA_OK) return rc;
+  rc = check_analysed(c, g);
+  if (rc != DPVBA_OK) return rc;
+  if (!poses0 || (!inv_depth0 && c->P > 0)) return DPVBA_EINVAL;
+  if (c->E > 0 && (!grad_target || !grad_weight)) return DPVBA_EINVAL;
+  if (o->precision == DPVBA_MIXED) return DPVBA_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (o->precision == DPVBA_FP64) {
+    HIP_TRY(backward_impl<double>(c, g, (const double*)(const void*)poses0, (const double*)(const void*)inv_depth0,
+                                  o, (const double*)(const void*)grad_poses,
+                                  (const double*)(const void*)grad_inv_depth, (double*)(void*)grad_target,
+                                  (double*)(void*)grad_weight, st));
+  } else {
+    HIP_TRY(backward_impl<float>(c, g, poses0, inv_depth0, o, grad_poses, grad_inv_depth, grad_target, grad_weight,
+                                 st));
+  }
+  return DPVBA_OK;
+}
+
+}  // extern "C"
+
+// Iterations of an analysed batch (one precision; see dpvba_solve_batch).
+template <typename T>
+static hipError_t batch_impl(dpvba_ctx* c, const dpvba_batch* b, T* poses, T* depth, const dpvba_opts* o,
+                             bool mixed, hipStream_t st) {
+  auto& B = c->bt;
+  const int ti = sizeof(T) == 8 ? 1 : 0;
+  const Tiling& tl = B.tl[ti];
+  const T lambda = (T)o->lambda, z_min = (T)o->z_min;
+  const int nit = o->n_iters;
+  const int stride = DPVBA_MAX_ITERS;
+  int* status = (int*)B.status.p;
+  unsigned int* mb = (unsigned int*)B.min_bits.p;
+  T* pbuf[2] = {(T*)c->poses_a.p, (T*)c->poses_b.p};
+  hipError_t e;
+  if ((e = launch_report_init(status, mb, B.B * stride, st)) != hipSuccess) return e;
+  bool lds_factor = false;
+  const int lds_solve = batch_solve_lds<T>(B.n_max, mixed, &lds_factor);
+  for (int it = 0; it < nit; ++it) {
+    const T* cur = it == 0 ? poses : pbuf[(it - 1) & 1];
+    T* next = pbuf[it & 1];
+    IterArgs<T> A{};
+    A.patches = b->patches;
+    A.p = b->patch_size;
+    A.target = b->target;
+    A.weight = b->weight;
+    A.fx = b->fx; A.fy = b->fy; A.cx = b->cx; A.cy = b->cy;
+    A.z_min = z_min;
+    A.lambda = lambda;
+    A.n_tiles = tl.n_tiles;
+    A.poses_cur = cur;
+    A.depth_in = depth;
+    A.depth_s = (T*)c->depth_s.p;
+    A.xh_s = (T*)c->xh_s.p;
+    A.U_s = (T*)c->U_s.p;
+    A.pscale_s = (T*)c->pscale_s.p;
+    A.tiles = (const TileInfo*)tl.tiles.p;
+    A.tile_patch = (const int*)tl.tile_patch.p;
+    A.slot_frame = (const int*)tl.slot_frame.p;
+    A.slot_blk = (const int*)tl.slot_blk.p;
+    A.edge_grid = (const int*)tl.edge_grid.p;
+    A.blk_pose = (const int*)tl.blk_pose.p;
+    A.part_S = (T*)c->part_S.p;
+    A.part_vec = (T*)c->part_vec.p;
+    A.part_cost = (double*)c->part_cost.p;
+    A.part_invalid = (int*)c->part_invalid.p;
+    A.first = it == 0;
+    A.dx_prev = it ? (const T*)c->dx.p : nullptr;
+    A.status_prev = it ? status + it - 1 : nullptr;
+    A.status_stride = stride;
+    {
+      TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
+      if ((e = launch_tile_iterate<T>(A, tl.lds_bytes, st)) != hipSuccess) return e;
+    }
+    if ((e = launch_batch_cost((const BatchInst*)B.inst[ti].p, B.B, (const double*)c->part_cost.p,
+                               (const int*)c->part_invalid.p, (dpvba_report*)B.reps.p, it, st)) != hipSuccess)
+      return e;
+    BatchArgs<T> a{};
+    a.inst = (const BatchInst*)B.inst[ti].p;
+    a.part_S = (const T*)c->part_S.p;
+    a.part_vec = (const T*)c->part_vec.p;
+    a.s_off = (const int*)tl.s_off.p;
+    a.s_src = (const int*)tl.s_src.p;
+    a.v_off = (const int*)tl.v_off.p;
+    a.v_src = (const int2*)tl.v_src.p;
+    a.lambda = (double)lambda;
+    a.poses_cur = cur;
+    a.poses_next = next;
+    a.dx = (T*)c->dx.p;
+    a.status = status;
+    a.min_bits = mb;
+    a.refine_resid = (double*)B.refine.p;
+    a.fallback = (int*)B.fallback.p;
+    a.stride = stride;
+    a.it = it;
+    a.scratch = (double*)B.scratch_buf.p;
+    a.lds_factor = lds_factor ? 1 : 0;
+    TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
+    if constexpr (sizeof(T) == 4) {
+      if (mixed) e = launch_batch_solve_mixed(a, B.B, lds_solve, st);
+      else e = launch_batch_solve<T>(a, B.B, lds_solve, st);
+    } else {
+      e = launch_batch_solve<T>(a, B.B, lds_solve, st);
+    }
+    if (e != hipSuccess) return e;
+  }
+  if (nit > 0) {
+    TraceScope ts(c, DPVBA_PHASE_BACKSUB, st);
+    e = launch_tile_finalize<T>((const TileInfo*)tl.tiles.p, tl.n_tiles, tl.lds_bytes, (const int*)tl.tile_patch.p,
+                                (const int*)tl.blk_pose.p, (const T*)c->U_s.p, (const T*)c->pscale_s.p,
+                                (const T*)c->depth_s.p, (const T*)c->dx.p, status + nit - 1, stride, depth,
+                                pbuf[(nit - 1) & 1], poses, B.N, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+static hipError_t batch_report(dpvba_ctx* c, const dpvba_batch* b, const T* poses, const T* depth,
+                               const dpvba_opts* o, bool mixed, dpvba_report* reports, hipStream_t st) {
+  auto& B = c->bt;
+  const int ti = sizeof(T) == 8 ? 1 : 0;
+  hipError_t e = launch_batch_report<T>((const BatchInst*)B.inst[ti].p, B.B, poses, depth, b->patches, b->patch_size,
+                                        b->ii, b->jj, b->kk, b->target, b->weight, (T)b->fx, (T)b->fy, (T)b->cx,
+                                        (T)b->cy, (T)o->z_min, (const int*)B.status.p,
+                                        (const unsigned int*)B.min_bits.p, mixed ? (const double*)B.refine.p : nullptr,
+                                        mixed ? (const int*)B.fallback.p : nullptr, DPVBA_MAX_ITERS, o->n_iters,
+                                        (dpvba_report*)B.reps.p, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(reports, B.reps.p, sizeof(dpvba_report) * (size_t)B.B, hipMemcpyDeviceToHost, st);
+}
+
+extern "C" {
+
+dpvba_status dpvba_analyze_batch(dpvba_ctx* c, const dpvba_batch* b, const int32_t* tile_patches, void* stream) {
+  if (!c || !batch_sizes_ok(b)) return DPVBA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(c->device));
+  auto& Bt = c->bt;
+  Bt.analysed = false;
+  if (Bt.exec) {
+    HIP_TRY(hipGraphExecDestroy(Bt.exec));
+    Bt.exec = nullptr;
+  }
+  const int NB = b->n_problems;
+  const int N = b->frame_off[NB], P = b->patch_off[NB], E = b->edge_off[NB];
+  std::vector<int32_t> ii(E), jj(E), kk(E);
+  if (E) {
+    HIP_TRY(hipMemcpyAsync(ii.data(), b->ii, (size_t)E * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(jj.data(), b->jj, (size_t)E * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(kk.data(), b->kk, (size_t)E * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  HostTiling H[2];
+  std::vector<BatchInst> inst[2];
+  inst[0].resize(NB);
+  inst[1].resize(NB);
+  long long free_begin = 0, scratch = 0;
+  int n_max = 0;
+  for (int q = 0; q < NB; ++q) {
+    const int f0 = b->frame_off[q], Nq = b->frame_off[q + 1] - f0;
+    const int p0 = b->patch_off[q], Pq = b->patch_off[q + 1] - p0;
+    const int e0 = b->edge_off[q], Eq = b->edge_off[q + 1] - e0;
+    const int nf = b->n_fixed[q];
+    ProblemIndex X;
+    if (!index_problem(Nq, Pq, Eq, ii.data() + e0, jj.data() + e0, kk.data() + e0, X)) return DPVBA_EINVAL;
+    std::vector<int32_t> jq(jj.begin() + e0, jj.begin() + e0 + Eq);
+    const int kcap32 = (tile_patches && tile_patches[q] > 0) ? tile_patches[q] : kDefaultTilePatches32;
+    for (int t = 0; t < 2; ++t) {
+      HostTiling Hq;
+      if (!plan_tiling(Nq, nf, jq, X.pcount, X.pedges, X.frame_patches, t ? kDefaultTilePatches64 : kcap32,
+                       t ? 8 : 4, Hq))
+        return DPVBA_EINVAL;
+      BatchInst& I = inst[t][q];
+      I.frame_begin = f0;
+      I.n_frames = Nq;
+      I.n_fixed = nf;
+      I.free_begin = (int)free_begin;
+      I.n_free = Nq - nf;
+      I.patch_begin = p0;
+      I.n_patches = Pq;
+      I.edge_begin = e0;
+      I.n_edges = Eq;
+      I.scratch_off = scratch;
+      if (!append_tiling(H[t], Hq, q, f0, p0, e0, (int)free_begin, I)) return DPVBA_EINVAL;
+    }
+    const long long n = 6LL * (Nq - nf);
+    if (n > 46000) return DPVBA_EINVAL;
+    n_max = std::max(n_max, (int)n);
+    scratch += n * (n + 1) / 2 + 2 * n;
+    free_begin += Nq - nf;
+  }
+  // the per-problem solve keeps a float32 factor of the widest problem in shared memory
+  if (n_max > 0) {
+    bool lf = false;
+    if (batch_solve_lds<float>(n_max, true, &lf) > 150 * 1024) return DPVBA_EINVAL;
+  }
+  HIP_TRY(upload_tiling(Bt.tl[0], H[0], st));
+  HIP_TRY(upload_tiling(Bt.tl[1], H[1], st));
+  HIP_TRY(upload(Bt.inst[0], inst[0], st));
+  HIP_TRY(upload(Bt.inst[1], inst[1], st));
+  const size_t nfree6 = 6 * (size_t)free_begin;
+  HIP_TRY(ensure(c->part_S, std::max(H[0].part_S * 4, H[1].part_S * 8)));
+  HIP_TRY(ensure(c->part_vec, std::max(H[0].part_vec * 4, H[1].part_vec * 8)));
+  HIP_TRY(ensure(c->part_cost, std::max(H[0].tiles.size(), H[1].tiles.size()) * 8));
+  HIP_TRY(ensure(c->part_invalid, std::max(H[0].tiles.size(), H[1].tiles.size()) * 4));
+  HIP_TRY(ensure(c->U_s, std::max(H[0].u_elems * 4, H[1].u_elems * 8)));
+  HIP_TRY(ensure(c->pscale_s, (size_t)P * 2 * 8));
+  HIP_TRY(ensure(c->depth_s, (size_t)P * 8));
+  HIP_TRY(ensure(c->xh_s, (size_t)P * 2 * 8));
+  HIP_TRY(ensure(c->poses_a, (size_t)N * 7 * 8));
+  HIP_TRY(ensure(c->poses_b, (size_t)N * 7 * 8));
+  HIP_TRY(ensure(c->dx, nfree6 * 8));
+  HIP_TRY(ensure(Bt.status, (size_t)NB * DPVBA_MAX_ITERS * 4));
+  HIP_TRY(ensure(Bt.min_bits, (size_t)NB * DPVBA_MAX_ITERS * 4));
+  HIP_TRY(ensure(Bt.refine, (size_t)NB * DPVBA_MAX_ITERS * 8));
+  HIP_TRY(ensure(Bt.fallback, (size_t)NB * DPVBA_MAX_ITERS * 4));
+  HIP_TRY(ensure(Bt.reps, (size_t)NB * sizeof(dpvba_report)));
+  HIP_TRY(ensure(Bt.scratch_buf, (size_t)scratch * 8));
+  Bt.B = NB;
+  Bt.p = b->patch_size;
+  Bt.N = N;
+  Bt.P = P;
+  Bt.E = E;
+  Bt.n_max = n_max;
+  Bt.n_free = free_begin;
+  Bt.scratch = scratch;
+  Bt.ii = b->ii;
+  Bt.jj = b->jj;
+  Bt.kk = b->kk;
+  Bt.frame_off.assign(b->frame_off, b->frame_off + NB + 1);
+  Bt.patch_off.assign(b->patch_off, b->patch_off + NB + 1);
+  Bt.edge_off.assign(b->edge_off, b->edge_off + NB + 1);
+  Bt.n_fixed.assign(b->n_fixed, b->n_fixed + NB);
+  Bt.key.clear();
+  Bt.analysed = true;
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_solve_batch(dpvba_ctx* c, const dpvba_batch* b, float* poses, float* inv_depth,
+                               const dpvba_opts* o, dpvba_report* reports, void* stream) {
+  if (!c || !batch_sizes_ok(b) || !o) return DPVBA_EINVAL;
+  auto& Bt = c->bt;
+  if (!Bt.analysed) return DPVBA_ESTATE;
+  const int NB = b->n_problems;
+  if (NB != Bt.B || b->patch_size != Bt.p || b->ii != Bt.ii || b->jj != Bt.jj || b->kk != Bt.kk ||
+      !std::equal(Bt.frame_off.begin(), Bt.frame_off.end(), b->frame_off) ||
+      !std::equal(Bt.patch_off.begin(), Bt.patch_off.end(), b->patch_off) ||
+      !std::equal(Bt.edge_off.begin(), Bt.edge_off.end(), b->edge_off) ||
+      !std::equal(Bt.n_fixed.begin(), Bt.n_fixed.end(), b->n_fixed))
+    return DPVBA_ESTATE;
+  dpvba_opts oo = *o;
+  const bool graph = (o->flags & DPVBA_FLAG_GRAPH) != 0;
+  oo.flags = 0;
+  dpvba_status rc = check_opts(&oo);
+  if (rc != DPVBA_OK) return rc;
+  if (o->flags & ~DPVBA_FLAG_GRAPH) return DPVBA_EINVAL;
+  if (!poses || (!inv_depth && Bt.P > 0)) return DPVBA_EINVAL;
+  if (graph && !stream) return DPVBA_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const bool mixed = o->precision == DPVBA_MIXED;
+  const bool f64 = o->precision == DPVBA_FP64;
+  auto enqueue = [&]() -> hipError_t {
+    if (f64) return batch_impl<double>(c, b, (double*)(void*)poses, (double*)(void*)inv_depth, o, false, st);
+    return batch_impl<float>(c, b, poses, inv_depth, o, mixed, st);
+  };
+  if (graph && !c->tracing) {
+    double lam = o->lambda, zm = o->z_min;
+    uint64_t lb, zb;
+    std::memcpy(&lb, &lam, 8);
+    std::memcpy(&zb, &zm, 8);
+    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)poses, (uint64_t)(uintptr_t)inv_depth,
+                                 (uint64_t)(uintptr_t)b->patches, (uint64_t)(uintptr_t)b->target,
+                                 (uint64_t)(uintptr_t)b->weight, (uint64_t)o->n_iters, (uint64_t)o->precision, lb,
+                                 zb, (uint64_t)(uintptr_t)st};
+    if (!Bt.exec || key != Bt.key) {
+      if (Bt.exec) {
+        HIP_TRY(hipGraphExecDestroy(Bt.exec));
+        Bt.exec = nullptr;
+      }
+      HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+      hipError_t e = enqueue();
+      hipGraph_t gr = nullptr;
+      hipError_t e2 = hipStreamEndCapture(st, &gr);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        HIP_TRY(e != hipSuccess ? e : e2);
+      }
+      hipError_t e3 = hipGraphInstantiate(&Bt.exec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      HIP_TRY(e3);
+      Bt.key = key;
+    }
+    HIP_TRY(hipGraphLaunch(Bt.exec, st));
+  } else {
+    HIP_TRY(enqueue());
+  }
+  if (reports) {
+    if (f64) HIP_TRY(batch_report<double>(c, b, (const double*)(const void*)poses, (const double*)(const void*)inv_depth,
+                                          o, false, reports, st));
+    else HIP_TRY(batch_report<float>(c, b, poses, inv_depth, o, mixed, reports, st));
   }
   return DPVBA_OK;
 }

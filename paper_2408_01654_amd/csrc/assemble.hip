@@ -8,16 +8,18 @@
 namespace dpvba {
 
 // Gather of the per-tile vectors into the right-hand side s and Diag(B).
-template <typename T>
-__global__ void gather_vec_kernel(const T* part_vec, const int* off, const int2* src, int n, T* rhs,
+// The shares (type TP) are summed in the output type T, so float shares
+// gathered into double are combined without further rounding error.
+template <typename TP, typename T>
+__global__ void gather_vec_kernel(const TP* part_vec, const int* off, const int2* src, int n, T* rhs,
                                   T* dB) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
   const int P_ = x / 6, m = x % 6;
   T v = (T)0, d = (T)0;
   for (int q = off[P_]; q < off[P_ + 1]; ++q) {
-    v += part_vec[src[q].x + m];
-    d += part_vec[src[q].y + m];
+    v += (T)part_vec[src[q].x + m];
+    d += (T)part_vec[src[q].y + m];
   }
   rhs[x] = v;
   dB[x] = d;
@@ -26,8 +28,8 @@ __global__ void gather_vec_kernel(const T* part_vec, const int* off, const int2*
 // Gather of every lower 6x6 block (P >= Q) of the damped reduced system from
 // the tile partials (zero where no tile contributes), with the Marquardt
 // diagonal lam (Diag(B) + 1) added.  `mirror` also writes the upper triangle.
-template <typename T>
-__global__ void gather_S_kernel(const T* part_S, const int* off, const int* src, int n_free, T* S,
+template <typename TP, typename T>
+__global__ void gather_S_kernel(const TP* part_S, const int* off, const int* src, int n_free, T* S,
                                 const T* dB, T lambda, int mirror, T* diag_out) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nblk = (long long)n_free * (n_free + 1) / 2;
@@ -41,11 +43,11 @@ __global__ void gather_S_kernel(const T* part_S, const int* off, const int* src,
   const int eo = c * 6 + r;  // the tiles store upper entries of their block pairs
   int q = lo;
   for (; q + 4 <= hi; q += 4) {
-    const T v0 = part_S[src[q] + eo], v1 = part_S[src[q + 1] + eo];
-    const T v2 = part_S[src[q + 2] + eo], v3 = part_S[src[q + 3] + eo];
+    const T v0 = (T)part_S[src[q] + eo], v1 = (T)part_S[src[q + 1] + eo];
+    const T v2 = (T)part_S[src[q + 2] + eo], v3 = (T)part_S[src[q + 3] + eo];
     v += v0; v += v1; v += v2; v += v3;
   }
-  for (; q < hi; ++q) v += part_S[src[q] + eo];
+  for (; q < hi; ++q) v += (T)part_S[src[q] + eo];
   const int n = 6 * n_free;
   const int row = 6 * Pb + r, col = 6 * Qb + c;
   if (row == col) {
@@ -164,12 +166,14 @@ __global__ void report_init_kernel(int* status, unsigned int* min_bits, int n) {
 }
 
 __global__ void report_finalize_kernel(dpvba_report* rep, const int* status, const unsigned int* min_bits,
-                                       int n_iters, const int* err) {
+                                       int n_iters, const int* err, const double* refine, const int* fallback) {
   if (threadIdx.x != 0) return;
   int st = DPVBA_OK;
   for (int t = 0; t < n_iters; ++t) {
     if (status[t]) st = DPVBA_ENOTPD;
     rep->min_pivot[t] = (double)__uint_as_float(min_bits[t]);
+    rep->refine_resid[t] = refine ? refine[t] : 0.0;
+    rep->fp64_fallback[t] = fallback ? fallback[t] : 0;
   }
   if (err && *err) st = DPVBA_EHIP;
   rep->status = st;
@@ -182,25 +186,35 @@ hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStr
 }
 
 hipError_t launch_report_finalize(dpvba_report* rep, const int* status, const unsigned int* min_bits,
-                                  int n_iters, const int* err, hipStream_t st) {
-  hipLaunchKernelGGL(report_finalize_kernel, dim3(1), dim3(64), 0, st, rep, status, min_bits, n_iters, err);
+                                  int n_iters, const int* err, hipStream_t st, const double* refine,
+                                  const int* fallback) {
+  hipLaunchKernelGGL(report_finalize_kernel, dim3(1), dim3(64), 0, st, rep, status, min_bits, n_iters, err, refine,
+                     fallback);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- launchers
 
+template <typename TP, typename T>
+hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
+                            const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
+                            int mirror, T* diag_out, hipStream_t st) {
+  if (n_free == 0) return hipSuccess;
+  const int n = 6 * n_free;
+  hipLaunchKernelGGL((gather_vec_kernel<TP, T>), dim3((n + 255) / 256), dim3(256), 0, st, part_vec, v_off,
+                     v_src, n, rhs, dB);
+  const long long tot = (long long)n_free * (n_free + 1) / 2 * 36;
+  hipLaunchKernelGGL((gather_S_kernel<TP, T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,
+                     s_off, s_src, n_free, S, dB, lambda, mirror, diag_out);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
                          int mirror, T* diag_out, hipStream_t st) {
-  if (n_free == 0) return hipSuccess;
-  const int n = 6 * n_free;
-  hipLaunchKernelGGL((gather_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, part_vec, v_off,
-                     v_src, n, rhs, dB);
-  const long long tot = (long long)n_free * (n_free + 1) / 2 * 36;
-  hipLaunchKernelGGL((gather_S_kernel<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,
-                     s_off, s_src, n_free, S, dB, lambda, mirror, diag_out);
-  return hipGetLastError();
+  return launch_gather_as<T, T>(part_S, part_vec, s_off, s_src, v_off, v_src, n_free, S, rhs, dB, lambda, mirror,
+                                diag_out, st);
 }
 
 template <typename T, typename P>
@@ -243,5 +257,8 @@ template hipError_t launch_gather<float>(const float*, const float*, const int*,
 template hipError_t launch_gather<double>(const double*, const double*, const int*, const int*, const int*,
                                           const int2*, int, double*, double*, double*, double, int, double*,
                                           hipStream_t);
+template hipError_t launch_gather_as<float, double>(const float*, const float*, const int*, const int*,
+                                                    const int*, const int2*, int, double*, double*, double*,
+                                                    double, int, double*, hipStream_t);
 
 }  // namespace dpvba

@@ -1,0 +1,372 @@
+// Batched solve: many independent BA problems (uneven sliding windows) in
+// the same launches.  The tiles of every problem form one grid, so the
+// assembly of all problems is load-balanced by the hardware dispatcher (the
+// tile kernel is unchanged; a tile knows its problem).  Then one workgroup
+// per problem gathers its damped reduced camera system (DPV-SLAM Appendix A)
+// from the tiles' shares, factors it, solves it and retracts its poses.
+//
+// Precision modes of the per-problem solve:
+//   float32  shares, packed factor and solve in float32 (shared memory);
+//   float64  all float64, packed factor in shared memory when it fits, else
+//            in the problem's slice of the global scratch;
+//   mixed    float32 shares gathered in float64 into the scratch, float32
+//            factor in shared memory, kRefine steps of iterative refinement
+//            against the float64 residual, and a float64 factorisation of the
+//            scratch copy when the refined residual stays above the tolerance
+//            or a float32 pivot failed.
+#include "edge.h"
+#include "packed.h"
+#include "dpvba.h"
+
+namespace dpvba {
+
+constexpr int kBatchThreads = 256;
+constexpr int kBatchRefine = 2;
+constexpr double kBatchRefineTol = 1e-8;
+
+template <typename TS>
+struct BatchArgs {
+  const BatchInst* inst;
+  const TS* part_S;
+  const TS* part_vec;
+  const int* s_off;
+  const int* s_src;
+  const int* v_off;
+  const int2* v_src;
+  double lambda;
+  const TS* poses_cur;
+  TS* poses_next;
+  TS* dx;
+  int* status;            // [problem * stride + iteration]
+  unsigned int* min_bits;
+  double* refine_resid;
+  int* fallback;
+  int stride, it;
+  double* scratch;        // packed float64 systems
+  int lds_factor;         // packed factor in shared memory
+};
+
+// Damped system of one problem: packed lower A, right-hand side b and the
+// damped diagonal d0, summed from the shares in tile order in type TA.
+template <typename TS, typename TA>
+__device__ void batch_gather(const BatchArgs<TS>& a, const BatchInst& I, TA* A, TA* b, TA* d0) {
+  const int n = 6 * I.n_free;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) {
+    const int P = i / 6, m = i % 6;
+    TA vb = (TA)0, db = (TA)0;
+    for (int q = a.v_off[I.v_base + P]; q < a.v_off[I.v_base + P + 1]; ++q) {
+      const int2 o = a.v_src[q];
+      vb += (TA)a.part_vec[o.x + m];
+      db += (TA)a.part_vec[o.y + m];
+    }
+    b[i] = vb;
+    d0[i] = db;  // Diag(B) for now
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - (idx / n) * n;
+    if (j > i) continue;
+    const int P = i / 6, Q = j / 6, r = i % 6, c = j % 6;
+    const int blk = P * (P + 1) / 2 + Q;
+    const int eo = c * 6 + r;  // shares hold the upper entries of their block pairs
+    TA v = (TA)0;
+    for (int q = a.s_off[I.s_base + blk]; q < a.s_off[I.s_base + blk + 1]; ++q) v += (TA)a.part_S[a.s_src[q] + eo];
+    if (i == j) v += (TA)a.lambda * (d0[i] + (TA)1);
+    A[packed_index(i, j)] = v;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) d0[i] = A[packed_index(i, i)];
+  __syncthreads();
+}
+
+// Write the step and retract the problem's free poses.
+template <typename TS, typename TX>
+__device__ void batch_apply(const BatchArgs<TS>& a, const BatchInst& I, const TX* x, bool bad) {
+  const int n = 6 * I.n_free;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) a.dx[6 * (size_t)I.free_begin + q] = bad ? (TS)0 : (TS)x[q];
+  for (int f = threadIdx.x; f < I.n_frames; f += blockDim.x) {
+    const size_t g = (size_t)(I.frame_begin + f);
+    TS* pn = a.poses_next + 7 * g;
+    for (int m = 0; m < 7; ++m) pn[m] = a.poses_cur[7 * g + m];
+    if (f >= I.n_fixed && !bad) {
+      TS xi[6];
+      for (int m = 0; m < 6; ++m) xi[m] = (TS)x[6 * (f - I.n_fixed) + m];
+      retract_pose<TS, TS>(pn, xi);
+    }
+  }
+}
+
+__device__ __forceinline__ void batch_pivot_min(unsigned int* min_bits, float ratio) {
+  if (!(ratio >= 0.f)) ratio = 0.f;
+  atomicMin(min_bits, __float_as_uint(ratio));
+}
+
+// float32 or float64: one precision throughout.
+template <typename T>
+__global__ void __launch_bounds__(kBatchThreads) batch_solve_kernel(BatchArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ int bad;
+  __shared__ float minr;
+  const BatchInst I = a.inst[blockIdx.x];
+  const int n = 6 * I.n_free;
+  T* vb = reinterpret_cast<T*>(lds);
+  T* d0 = vb + n;
+  T* A = a.lds_factor ? d0 + n : reinterpret_cast<T*>(a.scratch + I.scratch_off);
+  int* st = a.status + blockIdx.x * a.stride + a.it;
+  if (n == 0) {
+    batch_apply<T, T>(a, I, vb, false);
+    return;
+  }
+  batch_gather<T, T>(a, I, A, vb, d0);
+  packed_cholesky<T>(A, n, d0, &bad, &minr);
+  packed_solve<T, T>(A, vb, n);
+  const bool failed = bad != 0;
+  batch_apply<T, T>(a, I, vb, failed);
+  if (threadIdx.x == 0) {
+    *st = failed;
+    batch_pivot_min(a.min_bits + blockIdx.x * a.stride + a.it, minr);
+  }
+}
+
+// r = s - S x for the packed symmetric S (float64), one row per thread;
+// returns max |r| (all threads), reduced in a fixed order through `red`.
+__device__ double batch_residual(const double* S, const double* s, const double* x, double* r, int n, double* red) {
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = 0.0;
+    const double* row = S + packed_index(i, 0);
+    for (int j = 0; j <= i; ++j) v += row[j] * x[j];
+    for (int j = i + 1; j < n; ++j) v += S[packed_index(j, i)] * x[j];
+    const double ri = s[i] - v;
+    r[i] = ri;
+    if (ri != ri) mx = ri;  // a NaN sticks
+    else if (mx == mx) mx = fmax(mx, fabs(ri));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o = red[threadIdx.x + w];
+      red[threadIdx.x] = (o != o || o > red[threadIdx.x]) ? o : red[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// Mixed precision: float32 state and shares, float64 system in the scratch.
+__global__ void __launch_bounds__(kBatchThreads) batch_solve_mixed_kernel(BatchArgs<float> a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ int bad;
+  __shared__ float minr;
+  __shared__ double red[kBatchThreads];
+  const BatchInst I = a.inst[blockIdx.x];
+  const int n = 6 * I.n_free;
+  double* x64 = reinterpret_cast<double*>(lds);  // [n]
+  double* r64 = x64 + n;                          // [n]
+  double* b64 = r64 + n;                          // [n] copy of s for the float64 fallback
+  float* c32 = reinterpret_cast<float*>(b64 + n); // [n]
+  float* d32 = c32 + n;                           // [n]
+  float* A32 = d32 + n;                           // packed
+  double* S64 = a.scratch + I.scratch_off;        // packed, then s [n], then d0 [n]
+  double* s64 = S64 + (size_t)n * (n + 1) / 2;
+  double* d064 = s64 + n;
+  const int idx_st = blockIdx.x * a.stride + a.it;
+  if (n == 0) {
+    batch_apply<float, float>(a, I, c32, false);
+    if (threadIdx.x == 0) {
+      a.refine_resid[idx_st] = 0.0;
+      a.fallback[idx_st] = 0;
+    }
+    return;
+  }
+  batch_gather<float, double>(a, I, S64, s64, d064);
+  const int np = n * (n + 1) / 2;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) A32[q] = (float)S64[q];
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    c32[q] = (float)s64[q];
+    d32[q] = (float)d064[q];
+  }
+  __syncthreads();
+  packed_cholesky<float>(A32, n, d32, &bad, &minr);
+  const int bad32 = bad;
+  const float minr32 = minr;
+  packed_solve<float, float>(A32, c32, n);
+  for (int q = threadIdx.x; q < n; q += blockDim.x) x64[q] = (double)c32[q];
+  __syncthreads();
+  double smax = 0.0;
+  {
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(s64[i]));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+      __syncthreads();
+    }
+    smax = red[0];
+    __syncthreads();
+  }
+  for (int k = 0; k < kBatchRefine; ++k) {
+    batch_residual(S64, s64, x64, r64, n, red);
+    for (int q = threadIdx.x; q < n; q += blockDim.x) c32[q] = (float)r64[q];
+    __syncthreads();
+    packed_solve<float, float>(A32, c32, n);
+    for (int q = threadIdx.x; q < n; q += blockDim.x) x64[q] += (double)c32[q];
+    __syncthreads();
+  }
+  const double rmax = batch_residual(S64, s64, x64, r64, n, red);
+  const double rel = smax > 0.0 ? rmax / smax : rmax;
+  const bool fb = bad32 != 0 || !(rel <= kBatchRefineTol);
+  bool failed = false;
+  if (fb) {  // float64 factorisation of the scratch copy
+    for (int q = threadIdx.x; q < n; q += blockDim.x) b64[q] = s64[q];
+    __syncthreads();
+    packed_cholesky<double>(S64, n, d064, &bad, &minr);
+    failed = bad != 0;
+    packed_solve<double, double>(S64, b64, n);
+    for (int q = threadIdx.x; q < n; q += blockDim.x) x64[q] = b64[q];
+    __syncthreads();
+  }
+  batch_apply<float, double>(a, I, x64, failed);
+  if (threadIdx.x == 0) {
+    a.status[idx_st] = failed;
+    a.refine_resid[idx_st] = rel;
+    a.fallback[idx_st] = fb;
+    batch_pivot_min(a.min_bits + idx_st, minr32);
+  }
+}
+
+// Per problem: sum its tiles' costs and invalid counts of one iteration.
+__global__ void batch_cost_kernel(const BatchInst* inst, int n_inst, const double* part_cost,
+                                  const int* part_invalid, dpvba_report* rep, int it) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_inst) return;
+  const BatchInst I = inst[b];
+  double c = 0.0;
+  int v = 0;
+  for (int t = I.tile_begin; t < I.tile_begin + I.n_tiles; ++t) {
+    c += part_cost[t];
+    v += part_invalid[t];
+  }
+  rep[b].cost[it] = c;
+  rep[b].n_invalid[it] = v;
+}
+
+// Per problem (one workgroup): cost at the final iterate and the report.
+template <typename T>
+__global__ void __launch_bounds__(256) batch_report_kernel(
+    const BatchInst* inst, const T* poses, const T* inv_depth, const float* patches, int p, const int* ii,
+    const int* jj, const int* kk, const float* target, const float* weight, T fx, T fy, T cx, T cy, T z_min,
+    const int* status, const unsigned int* min_bits, const double* refine, const int* fallback, int stride,
+    int n_iters, dpvba_report* rep) {
+  __shared__ double sred[256];
+  const BatchInst I = inst[blockIdx.x];
+  double cst = 0.0;
+  for (int q = threadIdx.x; q < I.n_edges; q += blockDim.x) {
+    const int e = I.edge_begin + q;
+    T Ri[9], Rj[9], ti_[3], tj[3], Rt[12];
+    const T* pi = poses + 7 * (size_t)(I.frame_begin + ii[e]);
+    const T* pj = poses + 7 * (size_t)(I.frame_begin + jj[e]);
+    quat_to_rot<T, T>(pi + 3, Ri);
+    quat_to_rot<T, T>(pj + 3, Rj);
+    for (int m = 0; m < 3; ++m) { ti_[m] = pi[m]; tj[m] = pj[m]; }
+    relative_pose<T>(Ri, ti_, Rj, tj, Rt, Rt + 9);
+    const int k = I.patch_begin + kk[e], c = (p - 1) / 2;
+    const float* cen = patches + ((size_t)k * p * p + (size_t)c * p + c) * 2;
+    EdgeTerms<T> o;
+    const float2 tg = reinterpret_cast<const float2*>(target)[e];
+    const float2 wt = reinterpret_cast<const float2*>(weight)[e];
+    if (edge_eval<T>(Rt, ((T)cen[0] - cx) / fx, ((T)cen[1] - cy) / fy, inv_depth[k], fx, fy, cx, cy, z_min, tg.x,
+                     tg.y, wt.x, wt.y, o))
+      cst += 0.5 * ((double)o.w[0] * o.r[0] * o.r[0] + (double)o.w[1] * o.r[1] * o.r[1]);
+  }
+  sred[threadIdx.x] = cst;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  dpvba_report* R = rep + blockIdx.x;
+  R->cost[n_iters] = sred[0];
+  int s = DPVBA_OK;
+  for (int t = 0; t < n_iters; ++t) {
+    const int q = blockIdx.x * stride + t;
+    if (status[q]) s = DPVBA_ENOTPD;
+    R->min_pivot[t] = (double)__uint_as_float(min_bits[q]);
+    R->refine_resid[t] = refine ? refine[q] : 0.0;
+    R->fp64_fallback[t] = fallback ? fallback[q] : 0;
+  }
+  R->status = s;
+  R->n_iters = n_iters;
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T>
+int batch_solve_lds(int n_max, bool mixed, bool* lds_factor) {
+  const int np = n_max * (n_max + 1) / 2;
+  if (mixed) {
+    *lds_factor = true;
+    return 3 * n_max * 8 + 2 * n_max * 4 + np * 4;
+  }
+  const int vec = 2 * n_max * (int)sizeof(T);
+  const int full = vec + np * (int)sizeof(T);
+  *lds_factor = full <= 150 * 1024;
+  return *lds_factor ? full : vec;
+}
+
+template <typename T>
+hipError_t launch_batch_solve(const BatchArgs<T>& a, int n_inst, int lds_bytes, hipStream_t st) {
+  if (n_inst == 0) return hipSuccess;
+  hipError_t e = opt_in_lds((const void*)batch_solve_kernel<T>, lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((batch_solve_kernel<T>), dim3(n_inst), dim3(kBatchThreads), lds_bytes, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_solve_mixed(const BatchArgs<float>& a, int n_inst, int lds_bytes, hipStream_t st) {
+  if (n_inst == 0) return hipSuccess;
+  hipError_t e = opt_in_lds((const void*)batch_solve_mixed_kernel, lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_solve_mixed_kernel, dim3(n_inst), dim3(kBatchThreads), lds_bytes, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_cost(const BatchInst* inst, int n_inst, const double* part_cost, const int* part_invalid,
+                             dpvba_report* rep, int it, hipStream_t st) {
+  if (n_inst == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_cost_kernel, dim3((n_inst + 63) / 64), dim3(64), 0, st, inst, n_inst, part_cost,
+                     part_invalid, rep, it);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_report(const BatchInst* inst, int n_inst, const T* poses, const T* inv_depth,
+                               const float* patches, int p, const int* ii, const int* jj, const int* kk,
+                               const float* target, const float* weight, T fx, T fy, T cx, T cy, T z_min,
+                               const int* status, const unsigned int* min_bits, const double* refine,
+                               const int* fallback, int stride, int n_iters, dpvba_report* rep, hipStream_t st) {
+  if (n_inst == 0) return hipSuccess;
+  hipLaunchKernelGGL((batch_report_kernel<T>), dim3(n_inst), dim3(256), 0, st, inst, poses, inv_depth, patches, p,
+                     ii, jj, kk, target, weight, fx, fy, cx, cy, z_min, status, min_bits, refine, fallback, stride,
+                     n_iters, rep);
+  return hipGetLastError();
+}
+
+#define DPVBA_BATCH_INST(T)                                                                                       \
+  template int batch_solve_lds<T>(int, bool, bool*);                                                             \
+  template hipError_t launch_batch_solve<T>(const BatchArgs<T>&, int, int, hipStream_t);                         \
+  template hipError_t launch_batch_report<T>(const BatchInst*, int, const T*, const T*, const float*, int,       \
+                                             const int*, const int*, const int*, const float*, const float*, T, \
+                                             T, T, T, T, const int*, const unsigned int*, const double*,         \
+                                             const int*, int, int, dpvba_report*, hipStream_t);
+DPVBA_BATCH_INST(float)
+DPVBA_BATCH_INST(double)
+#undef DPVBA_BATCH_INST
+
+}  // namespace dpvba

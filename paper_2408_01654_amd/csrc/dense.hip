@@ -14,6 +14,7 @@
 // non-negative float, combined with an integer atomic minimum, which is
 // order-independent).
 #include "common.h"
+#include "mfma.h"
 
 namespace dpvba {
 
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, in
 }
 
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
-// block per workgroup.
+// block per workgroup, on the matrix cores.
 template <typename T>
 __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int k0, int kb, const T* Linv) {
   __shared__ T Ab[kNB][kNB + 1];
@@ -163,17 +164,22 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int k0, in
     Li[r][c] = (r < kb && c < kb) ? Linv[r * kNB + c] : (T)0;
   }
   __syncthreads();
-  // out[r][c] = sum_m Ab[r][m] * Li[c][m],  m <= c
-  for (int idx = tid; idx < rows * kb; idx += blockDim.x) {
-    const int r = idx / kb, c = idx % kb;
-    T v = (T)0;
-    for (int m = 0; m <= c; ++m) v += Ab[r][m] * Li[c][m];
-    S[(size_t)(i0 + r) * n + k0 + c] = v;
-  }
+  typename Mfma<T>::acc_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  gemm_nt_64<T>(&Ab[0][0], &Li[0][0], kNB + 1, kNB, acc);
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + Mfma<T>::row(lane, v), c = 16 * t + (lane & 15);
+      if (r < rows && c < kb) S[(size_t)(i0 + r) * n + k0 + c] = acc[t][v];
+    }
 }
 
 // Trailing update A_IJ -= L_Ik L_Jk^T for 64x64 blocks I >= J of the trailing
-// matrix; blockIdx.x enumerates the lower block pairs.
+// matrix, on the matrix cores; blockIdx.x enumerates the lower block pairs.
 template <typename T>
 __global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, int kb) {
   __shared__ T Li[kNB][kNB + 1];
@@ -193,21 +199,17 @@ __global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, i
     Lj[r][c] = (r < rj && c < kb) ? S[(size_t)(j0 + r) * n + k0 + c] : (T)0;
   }
   __syncthreads();
-  // each thread: a 4x4 patch of the 64x64 output
-  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-  T acc[4][4];
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-  for (int m = 0; m < kb; ++m) {
-    T x[4], y[4];
-    for (int a = 0; a < 4; ++a) { x[a] = Li[tr + a][m]; y[a] = Lj[tc + a][m]; }
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
-  }
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) {
-      const int r = tr + a, c = tc + b;
-      if (r < ri && c < rj && (I != J || c <= r)) S[(size_t)(i0 + r) * n + j0 + c] -= acc[a][b];
+  typename Mfma<T>::acc_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  gemm_nt_64<T>(&Li[0][0], &Lj[0][0], kNB + 1, kNB, acc);
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + Mfma<T>::row(lane, v), c = 16 * t + (lane & 15);
+      if (r < ri && c < rj && (I != J || c <= r)) S[(size_t)(i0 + r) * n + j0 + c] -= acc[t][v];
     }
 }
 
@@ -295,19 +297,11 @@ __global__ void copy_vec_kernel(const T* src, T* dst, int n) {
 
 int small_solve_max_n(int tsize) { return tsize == 4 ? 240 : 160; }
 
+// Blocked factorisation in place (lower triangle of S becomes L) with the
+// diagonal-block inverses in Linv_all.
 template <typename T>
-hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* work_y, T* Linv_all, const T* d0,
-                             int* status, unsigned int* min_bits, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  if (n <= small_solve_max_n(sizeof(T))) {
-    {
-      hipError_t e = opt_in_lds((const void*)small_chol_solve_kernel<T>, small_solve_lds_bytes(n, sizeof(T)));
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((small_chol_solve_kernel<T>), dim3(1), dim3(256), small_solve_lds_bytes(n, sizeof(T)),
-                       st, S, rhs, n, dx, status, min_bits);
-    return hipGetLastError();
-  }
+hipError_t launch_chol_factor(T* S, int n, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
+                              hipStream_t st) {
   const int nblk = (n + kNB - 1) / kNB;
   for (int k = 0; k < nblk; ++k) {
     const int k0 = k * kNB, kb = min(kNB, n - k0);
@@ -321,12 +315,40 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* wor
                          kb);
     }
   }
+  return hipGetLastError();
+}
+
+// x = (L L^T)^-1 rhs with a factor from launch_chol_factor.
+template <typename T>
+hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_b, T* work_y,
+                             hipStream_t st) {
+  const int nblk = (n + kNB - 1) / kNB;
   hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, rhs, work_b, n);
   for (int k = 0; k < nblk; ++k)
-    hipLaunchKernelGGL((trsv_fwd_kernel<T>), dim3(nblk - k), dim3(256), 0, st, S, n, k, Linv_all, work_b,
+    hipLaunchKernelGGL((trsv_fwd_kernel<T>), dim3(nblk - k), dim3(256), 0, st, L, n, k, Linv_all, work_b,
                        work_y);
   for (int k = nblk - 1; k >= 0; --k)
-    hipLaunchKernelGGL((trsv_bwd_kernel<T>), dim3(k + 1), dim3(256), 0, st, S, n, k, Linv_all, work_y, dx);
+    hipLaunchKernelGGL((trsv_bwd_kernel<T>), dim3(k + 1), dim3(256), 0, st, L, n, k, Linv_all, work_y, x);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* work_y, T* Linv_all, const T* d0,
+                             int* status, unsigned int* min_bits, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (n <= small_solve_max_n(sizeof(T))) {
+    {
+      hipError_t e = opt_in_lds((const void*)small_chol_solve_kernel<T>, small_solve_lds_bytes(n, sizeof(T)));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((small_chol_solve_kernel<T>), dim3(1), dim3(256), small_solve_lds_bytes(n, sizeof(T)),
+                       st, S, rhs, n, dx, status, min_bits);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_chol_factor<T>(S, n, Linv_all, d0, status, min_bits, st);
+  if (e != hipSuccess) return e;
+  e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_b, work_y, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((zero_on_status_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, dx, n, status);
   return hipGetLastError();
 }
@@ -335,5 +357,8 @@ template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, 
                                              const float*, int*, unsigned int*, hipStream_t);
 template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, double*,
                                               const double*, int*, unsigned int*, hipStream_t);
+template hipError_t launch_chol_factor<float>(float*, int, float*, const float*, int*, unsigned int*, hipStream_t);
+template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, float*,
+                                             hipStream_t);
 
 }  // namespace dpvba

@@ -33,7 +33,8 @@ struct TileInfo {
   int32_t part_begin;  // element offset of the partial block pairs (36 each)
   int32_t vec_begin;   // element offset of the partial vectors (rhs then diag, 6 * n_blk each)
   int32_t u_begin;     // element offset of the stored Schur rows (n_patch * 6 n_blk)
-  int32_t pad[3];
+  int32_t inst;        // problem of a batch the tile belongs to (0 for one problem)
+  int32_t pad[2];
 };
 
 // Upper block pair (a <= b) of nb blocks, row-major over the upper triangle.
@@ -44,14 +45,15 @@ __host__ __device__ inline int upper_pair_index(int a, int b, int nb) {
 __host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 
 // Shared-memory plan of the tile kernel.  Compute-type (T) arrays: slot
-// relative poses, patch rays, per-slot sums, and the Schur-row matrix U
+// relative poses, patch rays, per-patch sums, per-slot sums, and the
+// Schur-row matrix U
 // (K_pad x W_pad, rows = patches, columns = 6 n_blk block columns plus one
 // column for w / sqrt(C~), padded for 16x16x4 matrix-core tiles), which
 // first holds the per-thread partial sums.  Then a byte region of per-cell
 // records (target, weight) that each lane overwrites with its edge's
 // results, later reused for per-slot source blocks.  Then byte tables.
 struct TileLds {
-  int slot, patch, m, u, total_T;           // T offsets
+  int slot, patch, psum, m, u, total_T;     // T offsets
   int K_pad, W_pad;
   int cell_bytes, rec_bytes;                // per cell, region
   int pair_a, pair_b, blk_s0, blk_s1, slot_blk, tables;  // byte offsets in the table region
@@ -66,7 +68,8 @@ __host__ __device__ inline TileLds tile_lds_plan(int K, int Tn, int nb, int tsiz
   L.W_pad = round_up(6 * nb + 1, 16);
   L.slot = 0;
   L.patch = L.slot + Tn * 18;
-  L.m = L.patch + K * 4;
+  L.psum = L.patch + K * 4;
+  L.m = L.psum + K * 8;
   L.u = L.m + Tn * kRedWidth;
   L.total_T = L.u + imax(L.K_pad * L.W_pad, kTileThreads * kRedWidth);
   L.cell_bytes = imax(16, 8 * tsize);
@@ -87,6 +90,21 @@ __host__ __device__ inline int tile_lds_bytes(int K, int Tn, int nb, int tsize) 
   return align16(L.total_T * tsize) + align16(L.rec_bytes) + align16(L.tables);
 }
 
+// One problem of a batch: its ranges in the packed arrays and in the
+// concatenated analysis (tiles, gather lists, solver scratch).
+struct BatchInst {
+  int32_t frame_begin, n_frames, n_fixed;
+  int32_t free_begin;   // first free pose in the packed step vector (units of poses)
+  int32_t n_free;
+  int32_t patch_begin, n_patches;
+  int32_t edge_begin, n_edges;
+  int32_t tile_begin, n_tiles;
+  int32_t s_base;       // its lower-block share lists start at s_off[s_base]
+  int32_t v_base;       // its pose share lists start at v_off[v_base]
+  int32_t pad;
+  int64_t scratch_off;  // element offset of its packed float64 system in the scratch
+};
+
 // Largest augmented system (n + 1 rows) of the single-launch solver: the
 // factor lives in registers, 16 x 16 threads x (kSmallRows / 16)^2 entries.
 constexpr int kSmallRows = 96;
@@ -94,7 +112,7 @@ constexpr int kSmallRows = 96;
 // Shared memory of the one-workgroup dense solve: packed lower triangle of
 // the factor, the solution, two column buffers and the factor's diagonal.
 __host__ __device__ inline int small_solve_lds_bytes(int n, int tsize) {
-  return ((n + 1) * (n + 2) / 2 + 6 * (n + 1)) * tsize;
+  return ((n + 1) * (n + 2) / 2 + 7 * (n + 1)) * tsize;
 }
 
 }  // namespace dpvba

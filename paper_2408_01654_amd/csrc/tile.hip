@@ -20,33 +20,11 @@
 // All sums run in a fixed order, so results are reproducible bit for bit; no
 // floating-point atomics are used.
 #include "edge.h"
+#include "mfma.h"
 #include "tileargs.h"
 #include "dpvba.h"
 
 namespace dpvba {
-
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
-typedef double doublex4_t __attribute__((ext_vector_type(4)));
-
-// 16x16x4 matrix-core step D = A B + C: lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16]; its v-th accumulator (v = 0..3) holds
-// D[row(l, v)][l % 16], with row = 4 (l / 16) + v for float32 and
-// row = l / 16 + 4 v for float64 (checked on gfx950).
-template <typename T> struct Mfma;
-template <> struct Mfma<float> {
-  typedef floatx4_t acc_t;
-  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-template <> struct Mfma<double> {
-  typedef doublex4_t acc_t;
-  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-};
 
 // Phases 0-3 for one tile; the caller synchronises before reusing `lds`.
 template <typename T>
@@ -59,6 +37,7 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
   T* base = reinterpret_cast<T*>(lds);
   T* sSlot = base + L.slot;   // [Tn][18]: R_ji (9), t_ji (3)
   T* sPatch = base + L.patch; // [K][4]: x^0, x^1, d, w / sqrt(C~)
+  T* sPs = base + L.psum;     // [K][8]: C (then 1 / sqrt(C~)), w, -sum_j Ad^T E_j
   T* sM = base + L.m;         // [Tn][28]
   T* sU = base + L.u;         // [Kp][Wp]; first the per-thread partial sums
   T* sWork = sU;
@@ -97,7 +76,8 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
     for (int m = 0; m < 3; ++m) { tiv[m] = pi[m]; tj[m] = pj[m]; }
     relative_pose<T>(Ri, tiv, Rj, tj, sSlot + 18 * s, sSlot + 18 * s + 9);
   }
-  const bool apply_prev = !A.first && A.dx_prev && !(A.status_prev && *A.status_prev);
+  const bool apply_prev =
+      !A.first && A.dx_prev && !(A.status_prev && A.status_prev[ti.inst * A.status_stride]);
   if (apply_prev) {
     for (int x = tid; x < W6; x += blockDim.x) sDx[x] = A.dx_prev[6 * A.blk_pose[ti.blk_begin + x / 6] + x % 6];
     const T* src_u = A.U_s + ti.u_begin;
@@ -228,40 +208,63 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
   }
   __syncthreads();
 
-  // ---- phase 2b: Schur rows u_k = E_k / sqrt(C~_k), appended w_k / sqrt(C~_k)
+  // ---- phase 2b: Schur rows u_k = E_k / sqrt(C~_k), appended w_k / sqrt(C~_k).
+  // (i) thread (k, m) sums component m of (C, w, -sum_j Ad^T E_j) over the
+  //     patch's slots in slot order; (ii) thread (k, x) writes row entry x.
   const int src = ti.src_blk;
-  for (int k = tid; k < Kp; k += blockDim.x) {
-    T* row = sU + k * Wp;
-    for (int x = 0; x < Wp; ++x) row[x] = (T)0;
-    if (k >= K) continue;
-    T C = (T)0, w = (T)0;
-    T Ei[6] = {0, 0, 0, 0, 0, 0};
+  for (int idx = tid; idx < K * 8; idx += blockDim.x) {
+    const int k = idx >> 3, m = idx & 7;
+    T v = (T)0;
     for (int ss = 0; ss < Tn; ++ss) {
       const T* cell = sCell + (size_t)(k * Tn + ss) * cellT;
-      C += cell[6];
-      w += cell[7];
-      T tmp[6];
-      adjoint_transpose_apply<T>(sSlot + 18 * ss, sSlot + 18 * ss + 9, cell, tmp);
-#pragma unroll
-      for (int m = 0; m < 6; ++m) Ei[m] -= tmp[m];
-      const int b = sSlotBlk[ss];
-      if (b >= 0) {
-#pragma unroll
-        for (int m = 0; m < 6; ++m) row[6 * b + m] += cell[m];
+      if (m < 2) {
+        v += cell[6 + m];
+      } else if (m < 5) {  // rotation part R^T a of Ad^T (a; b)
+        const T* R = sSlot + 18 * ss;
+        const int q = m - 2;
+        v -= R[q] * cell[0] + R[3 + q] * cell[1] + R[6 + q] * cell[2];
+      } else {             // R^T (b - t x a)
+        const T* R = sSlot + 18 * ss;
+        const T* tt = R + 9;
+        const int q = m - 5;
+        const T b0 = cell[3] - (tt[1] * cell[2] - tt[2] * cell[1]);
+        const T b1 = cell[4] - (tt[2] * cell[0] - tt[0] * cell[2]);
+        const T b2 = cell[5] - (tt[0] * cell[1] - tt[1] * cell[0]);
+        v -= R[q] * b0 + R[3 + q] * b1 + R[6 + q] * b2;
       }
     }
-    const T Ct = C * ((T)1 + A.lambda) + A.lambda;
+    sPs[idx] = v;
+  }
+  __syncthreads();
+  for (int k = tid; k < K; k += blockDim.x) {
+    const T Ct = sPs[8 * k] * ((T)1 + A.lambda) + A.lambda;
     const T is = (T)1 / dsqrt(Ct);
-    for (int x = 0; x < W6; ++x) row[x] *= is;
-    if (src >= 0) {
-#pragma unroll
-      for (int m = 0; m < 6; ++m) row[6 * src + m] = Ei[m] * is;
-    }
-    const T rs = w * is;
-    row[W6] = rs;
+    const T rs = sPs[8 * k + 1] * is;
+    sPs[8 * k] = is;
     sPatch[4 * k + 3] = rs;
     A.pscale_s[2 * (pb + k)] = is;
     A.pscale_s[2 * (pb + k) + 1] = rs;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < Kp * Wp; idx += blockDim.x) {
+    const int k = idx / Wp, x = idx - (idx / Wp) * Wp;
+    T v = (T)0;
+    if (k < K && x <= W6) {
+      const T rs = sPatch[4 * k + 3];
+      if (x == W6) {
+        v = rs;
+      } else {
+        const int b = x / 6, m = x - (x / 6) * 6;
+        const T is = sPs[8 * k];
+        if (b == src) {
+          v = sPs[8 * k + 2 + m] * is;
+        } else {
+          for (int ss = sBlkS0[b]; ss < sBlkS1[b]; ++ss) v += sCell[(size_t)(k * Tn + ss) * cellT + m];
+          v *= is;
+        }
+      }
+    }
+    sU[idx] = v;
   }
   __syncthreads();
 
@@ -375,24 +378,45 @@ __device__ void gather_slice(const IterArgs<T>& A, T* Sp, T* rhs, T* d0, int wav
     for (int b0 = lo; b0 < hi; b0 += 64) {
       const int o_l = b0 + lane < hi ? A.s_src[b0 + lane] : 0;
       const int nq = min(64, hi - b0);
-      for (int q = 0; q < nq; ++q) {
-        const int o = __shfl(o_l, q);
-        if (lower) v += A.part_S[o + eo];
+      for (int q0 = 0; q0 < nq; q0 += 8) {  // 8 independent loads in flight, summed in order
+        T part[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int o = __shfl(o_l, (q0 + u) & 63);
+          part[u] = (lower && q0 + u < nq) ? A.part_S[o + eo] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += part[u];
       }
     }
     const int row = 6 * P + r, col = 6 * Q + c;
-    if (P == Q && lane < 42) {
+    if (P == Q) {
+      // Diag(B) (lanes on the diagonal) and s (lanes 36..41) of pose P
       const int m = lane < 36 ? r : lane - 36;
+      const bool want_d = lane < 36 && r == c, want_s = lane >= 36 && lane < 42;
       const int vlo = A.v_off[P], vhi = A.v_off[P + 1];
       T db = (T)0, sv = (T)0;
-      for (int q = vlo; q < vhi; ++q) {
-        const int2 o = A.v_src[q];
-        if (lane < 36) db += A.part_vec[o.y + m];
-        else sv += A.part_vec[o.x + m];
+      for (int b0 = vlo; b0 < vhi; b0 += 64) {
+        const int2 o_l = b0 + lane < vhi ? A.v_src[b0 + lane] : make_int2(0, 0);
+        const int nq = min(64, vhi - b0);
+        for (int q0 = 0; q0 < nq; q0 += 8) {
+          T pd[8], ps[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int ox = __shfl(o_l.x, (q0 + u) & 63), oy = __shfl(o_l.y, (q0 + u) & 63);
+            const bool in = q0 + u < nq;
+            pd[u] = (want_d && in) ? A.part_vec[oy + m] : (T)0;
+            ps[u] = (want_s && in) ? A.part_vec[ox + m] : (T)0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            db += pd[u];
+            sv += ps[u];
+          }
+        }
       }
-      if (lane >= 36) {
-        rhs[6 * P + m] = sv;
-      } else if (r == c) {
+      if (want_s) rhs[6 * P + m] = sv;
+      if (want_d) {
         v += A.lambda * (db + (T)1);
         d0[row] = v;
       }
@@ -420,6 +444,7 @@ __device__ void factor_solve_retract_reg(const IterArgs<T>& A, const T* Sp_g, co
   T* x = Lp + (n + 1) * (n + 2) / 2;       // [n + 1]
   T* colb = x + (n + 1);                   // [2][n + 1]
   T* dd = colb + 2 * (n + 1);              // [n + 1] damped diagonal of S
+  T* invd = dd + (n + 1);                  // [n + 1] 1 / L_jj
   __shared__ int bad;
   __shared__ float minr;
   if (tid == 0) { bad = 0; minr = 3.0e38f; }
@@ -453,6 +478,7 @@ __device__ void factor_solve_retract_reg(const IterArgs<T>& A, const T* Sp_g, co
         d = (T)1;
       }
       const T rs = (T)1 / dsqrt(d);
+      if (ty == jm) invd[j] = rs;
 #pragma unroll
       for (int bi = 0; bi < MB; ++bi) {
         const int i = 16 * bi + ty;
@@ -491,34 +517,32 @@ __device__ void factor_solve_retract_reg(const IterArgs<T>& A, const T* Sp_g, co
       if (bk <= bi && k < n && k <= i && i <= n) Lp[i * (i + 1) / 2 + k] = a[bi][bk];
     }
   __syncthreads();
-  // backward substitution L^T dxi = y in wavefront 0 (lane owns rows lane + 64 q)
+  // backward substitution L^T dxi = y in wavefront 0; lane l owns rows l and
+  // l + 64 (n < 128), held in two named registers
   if (tid < 64) {
     const T* yrow = Lp + n * (n + 1) / 2;
     T r0 = tid < n ? yrow[tid] : (T)0;
     T r1 = tid + 64 < n ? yrow[tid + 64] : (T)0;
-    T r2 = tid + 128 < n ? yrow[tid + 128] : (T)0;
-    T r3 = tid + 192 < n ? yrow[tid + 192] : (T)0;
-    auto pick = [&](int q) { return q == 0 ? r0 : q == 1 ? r1 : q == 2 ? r2 : r3; };
-    auto upd = [&](int q, T v) { if (q == 0) r0 = v; else if (q == 1) r1 = v; else if (q == 2) r2 = v; else r3 = v; };
     for (int j = n - 1; j >= 0; --j) {
-      const int own = j & 63, q = j >> 6;
+      const bool hi = j >= 64;
       const int jr = j * (j + 1) / 2;
-      const T xj = __shfl(pick(q), own) / Lp[jr + j];
-      if (tid == own) upd(q, xj);
-#pragma unroll
-      for (int q2 = 0; q2 < 4; ++q2) {
-        const int i = tid + 64 * q2;
-        if (i < j) upd(q2, pick(q2) - Lp[jr + i] * xj);
+      const T xj = __shfl(hi ? r1 : r0, j & 63) * invd[j];
+      if (tid == (j & 63)) {
+        if (hi) r1 = xj;
+        else r0 = xj;
       }
+      if (tid < j) r0 -= Lp[jr + tid] * xj;
+      if (tid + 64 < j) r1 -= Lp[jr + tid + 64] * xj;
     }
-#pragma unroll
-    for (int q2 = 0; q2 < 4; ++q2) {
-      const int i = tid + 64 * q2;
-      if (i < n) {
-        const T v = bad ? (T)0 : pick(q2);
-        x[i] = v;
-        A.dx[i] = v;
-      }
+    if (tid < n) {
+      const T v = bad ? (T)0 : r0;
+      x[tid] = v;
+      A.dx[tid] = v;
+    }
+    if (tid + 64 < n) {
+      const T v = bad ? (T)0 : r1;
+      x[tid + 64] = v;
+      A.dx[tid + 64] = v;
     }
   }
   __syncthreads();
@@ -662,11 +686,12 @@ __global__ void __launch_bounds__(kTileThreads) small_solve_kernel(SmallArgs<T> 
 template <typename T>
 __global__ void __launch_bounds__(kTileThreads) tile_finalize_kernel(
     const TileInfo* tiles, const int* tile_patch, const int* blk_pose, const T* U_s, const T* pscale_s,
-    const T* depth_s, const T* dx, const int* status, T* depth_out, const T* poses_final, T* poses_out,
-    int n_frames) {
+    const T* depth_s, const T* dx, const int* status, int status_stride, T* depth_out, const T* poses_final,
+    T* poses_out, int n_frames) {
   extern __shared__ __align__(16) unsigned char lds[];
-  tile_writeback<T>(tiles[blockIdx.x], tile_patch, blk_pose, U_s, pscale_s, depth_s, dx, !(status && *status),
-                    depth_out, reinterpret_cast<T*>(lds));
+  const TileInfo ti = tiles[blockIdx.x];
+  tile_writeback<T>(ti, tile_patch, blk_pose, U_s, pscale_s, depth_s, dx,
+                    !(status && status[ti.inst * status_stride]), depth_out, reinterpret_cast<T*>(lds));
   if (blockIdx.x == 0 && poses_final != poses_out)
     for (int x = threadIdx.x; x < 7 * n_frames; x += blockDim.x) poses_out[x] = poses_final[x];
 }
@@ -701,8 +726,8 @@ hipError_t launch_tile_iterate(const IterArgs<T>& A, int lds_bytes, hipStream_t 
 template <typename T>
 hipError_t launch_tile_finalize(const TileInfo* tiles, int n_tiles, int lds_bytes, const int* tile_patch,
                                 const int* blk_pose, const T* U_s, const T* pscale_s, const T* depth_s,
-                                const T* dx, const int* status, T* depth_out, const T* poses_final,
-                                T* poses_out, int n_frames, hipStream_t st) {
+                                const T* dx, const int* status, int status_stride, T* depth_out,
+                                const T* poses_final, T* poses_out, int n_frames, hipStream_t st) {
   if (n_tiles == 0) {
     if (poses_final != poses_out)
       return hipMemcpyAsync(poses_out, poses_final, sizeof(T) * 7 * (size_t)n_frames, hipMemcpyDeviceToDevice, st);
@@ -711,8 +736,8 @@ hipError_t launch_tile_finalize(const TileInfo* tiles, int n_tiles, int lds_byte
   hipError_t e = opt_in_lds((const void*)tile_finalize_kernel<T>, lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((tile_finalize_kernel<T>), dim3(n_tiles), dim3(kTileThreads), lds_bytes, st, tiles,
-                     tile_patch, blk_pose, U_s, pscale_s, depth_s, dx, status, depth_out, poses_final, poses_out,
-                     n_frames);
+                     tile_patch, blk_pose, U_s, pscale_s, depth_s, dx, status, status_stride, depth_out, poses_final,
+                     poses_out, n_frames);
   return hipGetLastError();
 }
 
@@ -749,8 +774,8 @@ hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, hi
 #define DPVBA_TILE_INSTANTIATE(T)                                                                          \
   template hipError_t launch_tile_iterate<T>(const IterArgs<T>&, int, hipStream_t);                       \
   template hipError_t launch_tile_finalize<T>(const TileInfo*, int, int, const int*, const int*, const T*, \
-                                              const T*, const T*, const T*, const int*, T*, const T*, T*,  \
-                                              int, hipStream_t);                                           \
+                                              const T*, const T*, const T*, const int*, int, T*, const T*, \
+                                              T*, int, hipStream_t);                                       \
   template hipError_t launch_retract_copy<T>(const T*, T*, const T*, int, int, const int*, hipStream_t);  \
   template int small_solve_grid<T>(int);                                                                  \
   template hipError_t launch_small_solve<T>(const SmallArgs<T>&, int, int, hipStream_t);

@@ -23,7 +23,8 @@ struct IterArgs {
   T* U_s;                  // stored Schur rows
   T* pscale_s;             // per patch: 1/sqrt(C~), w/sqrt(C~)
   const T* dx_prev;        // previous pose step (applied unless first)
-  const int* status_prev;  // nonzero: previous step discarded
+  const int* status_prev;  // nonzero: previous step discarded (entry inst * status_stride)
+  int status_stride;       // distance between the problems' status words (0: one problem)
   int first;
   const TileInfo* tiles;
   const int* tile_patch;

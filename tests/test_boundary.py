@@ -46,6 +46,11 @@ def test_null_arguments_rejected_on_host():
     assert L.dpvba_solve(None, ctypes.byref(g), None, None, ctypes.byref(o), ctypes.byref(rep), None) \
         == binding.DPVBA_EINVAL
     assert L.dpvba_reduced_system(None, None, None, None, None, None, None, None, None) == binding.DPVBA_EINVAL
+    assert L.dpvba_solve_backward(None, ctypes.byref(g), None, None, ctypes.byref(o), None, None, None, None,
+                                  None) == binding.DPVBA_EINVAL
+    b = binding.Batch()
+    assert L.dpvba_analyze_batch(None, ctypes.byref(b), None, None) == binding.DPVBA_EINVAL
+    assert L.dpvba_solve_batch(None, ctypes.byref(b), None, None, ctypes.byref(o), None, None) == binding.DPVBA_EINVAL
     L.dpvba_destroy(None)
 
 
@@ -56,4 +61,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(binding.Opts) == 32
     assert binding.Opts.lambda_.offset == 8
     assert binding.Report.cost.offset == 8
-    assert ctypes.sizeof(binding.Report) == 8 + 33 * 8 + 32 * 4 + 32 * 8
+    assert ctypes.sizeof(binding.Report) == 8 + 33 * 8 + 32 * 4 + 32 * 8 + 32 * 8 + 32 * 4
+    assert binding.Report.refine_resid.offset == 8 + 33 * 8 + 32 * 4 + 32 * 8
+    assert ctypes.sizeof(binding.Batch) == 2 * 4 + 10 * 8 + 4 * 4
+    assert binding.Batch.frame_off.offset == 8 and binding.Batch.patches.offset == 40
+    assert binding.Batch.fx.offset == 88

@@ -15,7 +15,8 @@ from scenes.patchgraph import Scene
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-9, "fp32": 1e-4}
+TOL = {"fp64": 1e-9, "fp32": 1e-4, "mixed": 1e-4}
+PREC = {"fp64": 2, "mixed": 1, "fp32": 0}
 
 
 @pytest.fixture(scope="module")
@@ -41,6 +42,7 @@ def _gpu_solve(dp, ctx, s: Scene, precision, n_iters=None, lam=None):
     dt = torch.float64 if precision == dp.FP64 else torch.float32
     poses = torch.as_tensor(s.poses, dtype=dt).cuda().contiguous()
     depth = torch.as_tensor(s.inv_depth, dtype=dt).cuda().contiguous()
+    _log(f"  gpu solve {s.name} precision={precision}")
     rep = ctx.solve(g, poses, depth, n_iters=s.n_iters if n_iters is None else n_iters,
                     lam=s.lam if lam is None else lam, z_min=s.z_min, precision=precision)
     return poses.double().cpu().numpy(), depth.double().cpu().numpy(), rep
@@ -63,7 +65,7 @@ SMALL_SCENES = [
 
 
 @pytest.mark.parametrize("mk", SMALL_SCENES)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_reduced_system_matches_oracle(dp, ctx, mk, prec):
     s = mk()
     _log(f"reduced system {s.name} {prec}")
@@ -72,13 +74,15 @@ def test_reduced_system_matches_oracle(dp, ctx, mk, prec):
     rs = ba64.reduce(ne, s.lam)
     g = dp.GraphTensors.from_scene(s)
     ctx.analyze(g)
-    precision = dp.FP64 if prec == "fp64" else dp.FP32
+    precision = PREC[prec]
     dt = torch.float64 if prec == "fp64" else torch.float32
     poses = torch.as_tensor(s.poses, dtype=dt).cuda()
     depth = torch.as_tensor(s.inv_depth, dtype=dt).cuda()
     S, sv, cost = ctx.reduced_system(g, poses, depth, lam=s.lam, z_min=s.z_min, precision=precision)
+    assert S.dtype == (torch.float32 if prec == "fp32" else torch.float64)
     S = S.double().cpu().numpy(); sv = sv.double().cpu().numpy()
-    # float64: rounding of sums with cancellation (terms up to ~1e3 x |S|)
+    # float64: rounding of sums with cancellation (terms up to ~1e3 x |S|);
+    # mixed: float32 per-tile shares, so the float32 bound applies
     tol = 1e-11 if prec == "fp64" else 2e-5
     errS = np.abs(S - rs.S).max() / np.abs(rs.S).max()
     errs = np.abs(sv - rs.s).max() / np.abs(rs.s).max()
@@ -89,13 +93,18 @@ def test_reduced_system_matches_oracle(dp, ctx, mk, prec):
 
 
 @pytest.mark.parametrize("mk", SMALL_SCENES)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_solve_matches_oracle(dp, ctx, mk, prec):
     s = mk()
     _log(f"solve {s.name} {prec}")
     Po, Do, rep_o = ba64.solve_scene(s)
-    P, D, rep = _gpu_solve(dp, ctx, s, dp.FP64 if prec == "fp64" else dp.FP32)
+    P, D, rep = _gpu_solve(dp, ctx, s, PREC[prec])
     assert rep["status"] == 0
+    if prec == "mixed":
+        _log(f"  refine resid {rep['refine_resid']} fallback {rep['fp64_fallback']}")
+        assert all(r <= 1e-8 or f == 1 for r, f in zip(rep["refine_resid"], rep["fp64_fallback"]))
+    else:
+        assert rep["refine_resid"] == [0.0] * s.n_iters and rep["fp64_fallback"] == [0] * s.n_iters
     assert rep["n_invalid"] == rep_o.n_invalid
     np.testing.assert_allclose(rep["cost"], rep_o.cost, rtol=1e-9 if prec == "fp64" else 1e-3)
     _compare(s, P, D, Po, Do, TOL[prec], f"{s.name} {prec}")
@@ -105,9 +114,9 @@ def test_large_reduced_system_uses_blocked_factorisation(dp, ctx):
     # 60 frames, 58 free: n = 348 > the single-workgroup limit
     s = tiny_scene(60, 12, seed=4, radius=5, trajectory="forward")
     _log(f"blocked path {s.name} E={s.n_edges}")
-    for prec in ("fp64", "fp32"):
-        Po, Do, _ = ba64.solve_scene(s)
-        P, D, rep = _gpu_solve(dp, ctx, s, dp.FP64 if prec == "fp64" else dp.FP32)
+    Po, Do, _ = ba64.solve_scene(s)
+    for prec in ("fp64", "mixed", "fp32"):
+        P, D, rep = _gpu_solve(dp, ctx, s, PREC[prec])
         assert rep["status"] == 0
         _compare(s, P, D, Po, Do, TOL[prec], f"blocked {prec}")
 
@@ -190,3 +199,34 @@ def test_rejects_bad_graph(dp, ctx):
     ii[0] = ii[0] if ii[0] != s.jj[0] else (ii[0] + 1) % s.n_frames
     with pytest.raises(dp.DpvbaError):
         ctx.analyze(dp.GraphTensors.from_scene(_edit(s, ii=ii)))
+
+
+def _align_scale(P, Po):
+    """Least-squares scale about pose 0 mapping P's camera centres onto Po's."""
+    a = P[:, :3] - P[0, :3]
+    b = Po[:, :3] - Po[0, :3]
+    return float(np.sum(a * b) / np.sum(a * a))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
+def test_global_ba_matches_oracle_golden(dp, ctx, prec):
+    # 1000 keyframes, 1,505,568 edges, 5 iterations, n = 5994 (blocked path);
+    # expected values written by tests/golden/make_global_ba_golden.py
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "global_ba_oracle.npz"))
+    s = make_config(2)
+    _log(f"global BA {prec}: E={s.n_edges}")
+    P, D, rep = _gpu_solve(dp, ctx, s, PREC[prec])
+    _log(f"  status {rep['status']} cost {rep['cost']} vs {list(gold['cost'])}")
+    _log(f"  min pivot {rep['min_pivot']} refine {rep['refine_resid']} fallback {rep['fp64_fallback']}")
+    assert rep["status"] == 0
+    assert rep["n_invalid"] == list(gold["n_invalid"])
+    dt, dr = ba64.pose_errors(P, gold["poses"])
+    rel = np.abs(D - gold["inv_depth"]) / np.abs(gold["inv_depth"])
+    sc = _align_scale(P, gold["poses"])
+    Ps = P.copy(); Ps[:, :3] = P[0, :3] + sc * (P[:, :3] - P[0, :3])
+    dts, _ = ba64.pose_errors(Ps, gold["poses"])
+    _log(f"  raw: dt {dt.max():.3e} dr {dr.max():.3e} depth rel {rel.max():.3e}; "
+         f"scale-aligned dt {dts.max():.3e} (scale {sc - 1:+.2e})")
+    tol = TOL[prec]
+    assert dr.max() < tol and dt.max() < tol and rel.max() < tol

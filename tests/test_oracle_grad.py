@@ -3,36 +3,64 @@ the independent numpy oracle, and its reverse-mode gradients with respect to
 targets and weights agree with central finite differences of the loss."""
 import numpy as np
 import pytest
+import torch
 
 from oracle import ba64, grad64, lie64
 from scenes import tiny_scene, make_config
+
+
+def _same_rotation(pa, pb, atol):
+    Ra, _ = lie64.pose_to_rt(pa)
+    Rb, _ = lie64.pose_to_rt(pb)
+    np.testing.assert_allclose(Ra, Rb, atol=atol)
 
 
 @pytest.mark.parametrize("mk", [lambda: tiny_scene(5, 6, seed=31), lambda: tiny_scene(6, 5, seed=32, radius=2)])
 def test_forward_matches_numpy_oracle(mk):
     s = mk()
     P, D, _ = ba64.solve_scene(s)
-    R, t, d = grad64.forward_state(s)
-    Ro, to = lie64.pose_to_rt(P)
-    np.testing.assert_allclose(R, Ro, atol=1e-12)
-    np.testing.assert_allclose(t, to, atol=1e-12)
+    poses, d = grad64.forward_state(s)
+    np.testing.assert_allclose(poses[:, :3], P[:, :3], atol=1e-12)
+    _same_rotation(poses, P, 1e-12)
+    np.testing.assert_allclose(np.linalg.norm(poses[:, 3:], axis=1), 1.0, atol=1e-14)
     np.testing.assert_allclose(d, D, rtol=1e-11)
 
 
 def test_forward_matches_on_a_window():
     s = make_config(3, 0)
     P, D, _ = ba64.solve_scene(s)
-    R, t, d = grad64.forward_state(s)
-    Ro, to = lie64.pose_to_rt(P)
-    np.testing.assert_allclose(R, Ro, atol=1e-11)
-    np.testing.assert_allclose(t, to, atol=1e-11)
+    poses, d = grad64.forward_state(s)
+    np.testing.assert_allclose(poses[:, :3], P[:, :3], atol=1e-11)
+    _same_rotation(poses, P, 1e-11)
     np.testing.assert_allclose(d, D, rtol=1e-10)
+
+
+def test_retraction_matches_se3_exp():
+    """The (t, q) retraction equals G Exp(xi) with the closed-form SE(3) Exp."""
+    rng = np.random.default_rng(5)
+    for scale in (1e-4, 0.3, 2.0):
+        t = rng.normal(size=(4, 3))
+        q = rng.normal(size=(4, 4))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        xi = rng.normal(size=(4, 6)) * scale
+        tn, qn = grad64.retract_right(torch.as_tensor(t), torch.as_tensor(q), torch.as_tensor(xi))
+        for a in range(4):
+            G = np.eye(4)
+            G[:3, :3] = lie64.quat_to_rot(q[a])
+            G[:3, 3] = t[a]
+            Re, te = lie64.se3_exp(xi[a])
+            X = np.eye(4)
+            X[:3, :3] = Re
+            X[:3, 3] = te
+            Gn = G @ X
+            np.testing.assert_allclose(tn[a].numpy(), Gn[:3, 3], atol=1e-13)
+            np.testing.assert_allclose(lie64.quat_to_rot(qn[a].numpy()), Gn[:3, :3], atol=1e-13)
 
 
 @pytest.mark.parametrize("seed", [41, 42])
 def test_gradients_match_central_differences(seed):
     s = tiny_scene(5, 5, seed=seed)
-    L, gt, gw = grad64.loss_and_grads(s)
+    L, gt, gw, _, _ = grad64.loss_and_grads(s)
     rng = np.random.default_rng(seed)
     h = 1e-6
     tgt = s.target.astype(np.float64)
@@ -52,3 +80,28 @@ def test_gradients_match_central_differences(seed):
     dirs = rng.normal(size=tgt.shape)
     fd = (grad64.loss_value(s, tgt + h * dirs, wgt) - grad64.loss_value(s, tgt - h * dirs, wgt)) / (2 * h)
     assert abs(fd - np.sum(gt * dirs)) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_gradients_with_held_poses_and_three_iterations():
+    s = tiny_scene(6, 4, seed=43, n_fixed=2)
+    L, gt, gw, _, _ = grad64.loss_and_grads(s, n_iters=3)
+    rng = np.random.default_rng(43)
+    h = 1e-6
+    tgt = s.target.astype(np.float64)
+    wgt = s.weight.astype(np.float64)
+    for arr, g, which in ((tgt, gt, 0), (wgt, gw, 1)):
+        dirs = rng.normal(size=arr.shape)
+        if which == 0:
+            fd = (grad64.loss_value(s, tgt + h * dirs, wgt, n_iters=3) -
+                  grad64.loss_value(s, tgt - h * dirs, wgt, n_iters=3)) / (2 * h)
+        else:
+            fd = (grad64.loss_value(s, tgt, wgt + h * dirs, n_iters=3) -
+                  grad64.loss_value(s, tgt, wgt - h * dirs, n_iters=3)) / (2 * h)
+        assert abs(fd - np.sum(g * dirs)) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_zero_iterations_give_zero_gradients():
+    s = tiny_scene(4, 4, seed=44)
+    L, gt, gw, gp, gd = grad64.loss_and_grads(s, n_iters=0)
+    assert np.all(gt == 0) and np.all(gw == 0)
+    assert np.abs(gp).max() > 0 and np.abs(gd).max() > 0
