@@ -295,7 +295,8 @@ typedef struct {
  * single-problem analysis is kept).  tile_patches: host [B] patches per
  * tile for each problem in float32 and mixed modes (<= 0: default), e.g.
  * from an autotuner, or NULL; float64 uses the default.  The same checks as
- * dpvba_analyze, per problem, plus the offsets being non-decreasing.       */
+ * dpvba_analyze, per problem, plus: offsets non-decreasing with at least one
+ * frame per problem, and at most 42 free poses per problem (EINVAL).      */
 dpvba_status dpvba_analyze_batch(dpvba_ctx* ctx, const dpvba_batch* b, const int32_t* tile_patches,
                                  void* stream);
 

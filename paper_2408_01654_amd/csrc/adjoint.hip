@@ -231,20 +231,32 @@ __global__ void __launch_bounds__(256) tile_adjoint_backsub_kernel(
   }
 }
 
-// Step 5 sums.  Poses: xbar_t of every free pose gets its edges' shares in
-// edge order (pose_src holds 2 e + side, side 0 = source, 1 = target).
+// Step 5 sums.  Poses: xbar_t of every free pose gets its edges' shares
+// (pose_src holds 2 e + side, side 0 = source, 1 = target); one workgroup
+// per pose, thread t takes list entries t, t + 256, ... and the partial
+// sums are combined by a fixed tree, so the result does not depend on timing.
 template <typename T>
-__global__ void pose_reduce_kernel(const T* edge_xbar, const int* pose_off, const int* pose_src, int n_fixed,
-                                   int n_frames, T* pbar) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int f = n_fixed + x / 7, m = x % 7;
-  if (f >= n_frames) return;
-  T v = (T)0;
-  for (int q = pose_off[f]; q < pose_off[f + 1]; ++q) {
+__global__ void __launch_bounds__(256) pose_reduce_kernel(const T* edge_xbar, const int* pose_off,
+                                                          const int* pose_src, int n_fixed, T* pbar) {
+  __shared__ T red[7][256];
+  const int f = n_fixed + blockIdx.x;
+  T v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int q = pose_off[f] + threadIdx.x; q < pose_off[f + 1]; q += blockDim.x) {
     const int s = pose_src[q];
-    v += edge_xbar[(size_t)kEdgeAdj * (s >> 1) + 7 * (s & 1) + m];
+    const T* x = edge_xbar + (size_t)kEdgeAdj * (s >> 1) + 7 * (s & 1);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) v[m] += x[m];
   }
-  pbar[7 * (size_t)f + m] += v;
+#pragma unroll
+  for (int m = 0; m < 7; ++m) red[m][threadIdx.x] = v[m];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int m = 0; m < 7; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 7) pbar[7 * (size_t)f + threadIdx.x] += red[threadIdx.x][0];
 }
 
 // Depths: per tile-order patch position, its edges in edge order.
@@ -335,10 +347,10 @@ template <typename T>
 hipError_t launch_adjoint_reduce(const T* edge_xbar, const int* pose_off, const int* pose_src, int n_fixed,
                                  int n_frames, T* pbar, const int* tile_patch, const int* pcount, const int* pedges,
                                  int n_tp, T* dbar, hipStream_t st) {
-  const int np = 7 * (n_frames - n_fixed);
-  if (np > 0)
-    hipLaunchKernelGGL((pose_reduce_kernel<T>), dim3(blocks_for(np, 128)), dim3(128), 0, st, edge_xbar, pose_off,
-                       pose_src, n_fixed, n_frames, pbar);
+  const int nfree = n_frames - n_fixed;
+  if (nfree > 0)
+    hipLaunchKernelGGL((pose_reduce_kernel<T>), dim3(nfree), dim3(256), 0, st, edge_xbar, pose_off, pose_src,
+                       n_fixed, pbar);
   if (n_tp > 0)
     hipLaunchKernelGGL((patch_reduce_kernel<T>), dim3(blocks_for(n_tp, 128)), dim3(128), 0, st, edge_xbar,
                        tile_patch, pcount, pedges, n_tp, dbar);

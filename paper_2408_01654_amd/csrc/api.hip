@@ -152,6 +152,9 @@ namespace {
 constexpr int kLdsBudget = 150 * 1024;
 constexpr int kDefaultTilePatches32 = 96;
 constexpr int kDefaultTilePatches64 = 32;
+// Largest reduced system of one problem of a batch (its workgroup keeps the
+// right-hand side on one wavefront, at most 4 entries per lane).
+constexpr int kBatchMaxUnknowns = 252;
 
 struct DevBuf {
   void* p = nullptr;
@@ -1461,7 +1464,7 @@ dpvba_status dpvba_analyze_batch(dpvba_ctx* c, const dpvba_batch* b, const int32
       if (!append_tiling(H[t], Hq, q, f0, p0, e0, (int)free_begin, I)) return DPVBA_EINVAL;
     }
     const long long n = 6LL * (Nq - nf);
-    if (n > 46000) return DPVBA_EINVAL;
+    if (n > kBatchMaxUnknowns) return DPVBA_EINVAL;
     n_max = std::max(n_max, (int)n);
     scratch += n * (n + 1) / 2 + 2 * n;
     free_begin += Nq - nf;

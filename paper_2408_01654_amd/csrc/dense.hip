@@ -15,6 +15,7 @@
 // order-independent).
 #include "common.h"
 #include "mfma.h"
+#include "packed.h"
 
 namespace dpvba {
 
@@ -45,45 +46,8 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
   __syncthreads();
   __shared__ int bad;
   __shared__ float minr;
-  if (tid == 0) { bad = 0; minr = 3.0e38f; }
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const int jj = j * (j + 1) / 2 + j;
-    if (tid == 0) {
-      T piv = A[jj];
-      const float ratio = (float)(piv / d0[j]);
-      if (ratio < minr || !(ratio == ratio)) minr = ratio == ratio ? ratio : 0.f;
-      if (!(piv > (T)0) || !(piv < (T)3.0e38)) { bad = 1; piv = (T)1; }
-      A[jj] = dsqrt(piv);
-    }
-    __syncthreads();
-    const T ljj = A[jj];
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) A[i * (i + 1) / 2 + j] /= ljj;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int idx = tid; idx < m * m; idx += blockDim.x) {
-      const int i = j + 1 + idx / m, k = j + 1 + idx % m;
-      if (k <= i) A[i * (i + 1) / 2 + k] -= A[i * (i + 1) / 2 + j] * A[k * (k + 1) / 2 + j];
-    }
-    __syncthreads();
-  }
-  // forward: L y = b
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) b[j] /= A[j * (j + 1) / 2 + j];
-    __syncthreads();
-    const T yj = b[j];
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) b[i] -= A[i * (i + 1) / 2 + j] * yj;
-    __syncthreads();
-  }
-  // backward: L^T x = y
-  for (int j = n - 1; j >= 0; --j) {
-    if (tid == 0) b[j] /= A[j * (j + 1) / 2 + j];
-    __syncthreads();
-    const T xj = b[j];
-    const T* rowj = A + j * (j + 1) / 2;
-    for (int i = tid; i < j; i += blockDim.x) b[i] -= rowj[i] * xj;
-    __syncthreads();
-  }
+  packed_cholesky<T>(A, n, d0, &bad, &minr);
+  packed_solve<T, T>(A, b, n);
   for (int i = tid; i < n; i += blockDim.x) dx[i] = bad ? (T)0 : b[i];
   if (tid == 0) {
     if (bad) atomicOr(status, 1);
@@ -93,55 +57,70 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
 
 // ------------------------------------------------------------------ large path
 
-// Factor the diagonal block at k0 (kb <= 64) in LDS, write L back, and write
-// inv(L_kk) (lower, kb x kb, stride 64) to Linv.
+// Factor the diagonal block at k0 (kb <= 64), write L back, and write
+// inv(L_kk) (lower, kb x kb, stride 64, zeros above the diagonal) to Linv.
+// The block is factored together with an identity appended below it: the
+// Cholesky factor of [[A, I], [I, .]] has L^-T in its lower-left block, so
+// one elimination gives both L and its inverse.  The 128 x 64 working matrix
+// sits in LDS; column j is eliminated with its scaling deferred (step j
+// subtracts W_ij W_kj / d_j from the trailing entries, d_j = W_jj), so one
+// barrier per column suffices; the trailing entries are spread over a
+// 16 x 16 thread grid with loops that start at the first live block.
 template <typename T>
 __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, int kb, T* Linv, const T* d0,
                                                          int* status, unsigned int* min_bits) {
-  __shared__ T A[kNB][kNB + 1];
-  __shared__ T X[kNB][kNB + 1];
+  constexpr int R = 2 * kNB, C = kNB, LD = kNB + 1;
+  __shared__ T W[R * LD];
   __shared__ int bad;
   __shared__ float minr;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
-    const int r = idx / kb, c = idx % kb;
-    A[r][c] = c <= r ? S[(size_t)(k0 + r) * n + k0 + c] : (T)0;
+  const int ty = tid & 15, tx = tid >> 4;
+  for (int idx = tid; idx < R * C; idx += blockDim.x) {
+    const int i = idx / C, k = idx - (idx / C) * C;
+    T v = (T)0;
+    if (i < kNB) {
+      if (i < kb && k <= i) v = S[(size_t)(k0 + i) * n + k0 + k];
+    } else if (i - kNB == k && k < kb) {
+      v = (T)1;
+    }
+    W[i * LD + k] = v;
   }
   if (tid == 0) { bad = 0; minr = 3.0e38f; }
   __syncthreads();
   for (int j = 0; j < kb; ++j) {
+    const T dj = W[j * LD + j];
     if (tid == 0) {
-      T piv = A[j][j];
-      const float ratio = (float)(piv / d0[k0 + j]);
+      const float ratio = (float)(dj / d0[k0 + j]);
       if (ratio < minr || !(ratio == ratio)) minr = ratio == ratio ? ratio : 0.f;
-      if (!(piv > (T)0) || !(piv < (T)3.0e38)) { bad = 1; piv = (T)1; }
-      A[j][j] = dsqrt(piv);
+      if (!(dj > (T)0) || !(dj < (T)3.0e38)) bad = 1;
     }
-    __syncthreads();
-    const T ljj = A[j][j];
-    for (int i = j + 1 + tid; i < kb; i += blockDim.x) A[i][j] /= ljj;
-    __syncthreads();
-    const int m = kb - j - 1;
-    for (int idx = tid; idx < m * m; idx += blockDim.x) {
-      const int i = j + 1 + idx / m, k = j + 1 + idx % m;
-      if (k <= i) A[i][k] -= A[i][j] * A[k][j];
+    const T inv = (T)1 / ((dj > (T)0 && dj < (T)3.0e38) ? dj : (T)1);
+    const int b0 = (j + 1) >> 4;
+    for (int bi = b0; bi < R / 16; ++bi) {
+      const int i = 16 * bi + ty;
+      if (i <= j) continue;
+      const T wij = W[i * LD + j] * inv;
+      const int bk_end = bi < kNB / 16 ? bi : C / 16 - 1;
+      for (int bk = b0; bk <= bk_end; ++bk) {
+        const int k = 16 * bk + tx;
+        if (k > j && (i >= kNB || k <= i)) W[i * LD + k] -= wij * W[k * LD + j];
+      }
     }
     __syncthreads();
   }
-  // inverse of the lower factor, one column per thread: L X = I
-  for (int c = tid; c < kb; c += blockDim.x) {
-    for (int r = 0; r < kb; ++r) {
-      if (r < c) { X[r][c] = (T)0; continue; }
-      T v = r == c ? (T)1 : (T)0;
-      for (int m = c; m < r; ++m) v -= A[r][m] * X[m][c];
-      X[r][c] = v / A[r][r];
+  // scale column j by 1 / sqrt(d_j); L_jj = sqrt(d_j)
+  for (int idx = tid; idx < R * C; idx += blockDim.x) {
+    const int i = idx / C, k = idx - (idx / C) * C;
+    if (k >= kb || (i < kNB && k > i)) continue;
+    const T dk = W[k * LD + k];
+    const T sd = dsqrt((dk > (T)0 && dk < (T)3.0e38) ? dk : (T)1);
+    const T v = (i == k) ? sd : W[i * LD + k] / sd;
+    if (i < kNB) {
+      if (i < kb) S[(size_t)(k0 + i) * n + k0 + k] = v;
+    } else {
+      const int r = i - kNB;  // row r of L^-T = column r of L^-1
+      if (r < kb) Linv[k * kNB + r] = v;
     }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
-    const int r = idx / kb, c = idx % kb;
-    if (c <= r) S[(size_t)(k0 + r) * n + k0 + c] = A[r][c];
-    Linv[r * kNB + c] = X[r][c];
   }
   if (tid == 0) {
     if (bad) atomicOr(status, 1);
@@ -295,6 +274,7 @@ __global__ void copy_vec_kernel(const T* src, T* dst, int n) {
 
 // ------------------------------------------------------------------ launchers
 
+// packed factor in LDS; the solves keep the vector on one wavefront (n <= 256)
 int small_solve_max_n(int tsize) { return tsize == 4 ? 240 : 160; }
 
 // Blocked factorisation in place (lower triangle of S becomes L) with the

@@ -105,14 +105,27 @@ struct BatchInst {
   int64_t scratch_off;  // element offset of its packed float64 system in the scratch
 };
 
-// Largest augmented system (n + 1 rows) of the single-launch solver: the
-// factor lives in registers, 16 x 16 threads x (kSmallRows / 16)^2 entries.
+// Largest system (n + 1 <= kSmallRows) handled by the single-launch solver,
+// whose workgroup 0 factors it as a packed triangle in LDS; larger systems
+// take the blocked multi-launch path.
 constexpr int kSmallRows = 96;
 
-// Shared memory of the one-workgroup dense solve: packed lower triangle of
-// the factor, the solution, two column buffers and the factor's diagonal.
+// Row capacity 16 MB of the register-blocked dense solve of n unknowns
+// (augmented with the right-hand side: n + 1 rows).
+__host__ __device__ inline int small_solve_rows(int n) {
+  const int n1 = n + 1;
+  return n1 <= 32 ? 32 : (n1 <= 64 ? 64 : (n1 <= 80 ? 80 : 96));
+}
+
+// Shared memory of the one-workgroup dense solve: for the register-blocked
+// solver two column buffers, the reciprocal and damped diagonals, the
+// factor's rows (NR x NR) and the step; for the packed solver the packed
+// triangle and two vectors.
 __host__ __device__ inline int small_solve_lds_bytes(int n, int tsize) {
-  return ((n + 1) * (n + 2) / 2 + 7 * (n + 1)) * tsize;
+  const int nr = small_solve_rows(n);
+  const int blocked = (5 * nr + nr * nr) * tsize;
+  const int packed = (n * (n + 1) / 2 + 2 * n) * tsize;
+  return blocked > packed ? blocked : packed;
 }
 
 }  // namespace dpvba

@@ -10,55 +10,348 @@ namespace dpvba {
 
 __device__ __forceinline__ int packed_index(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// In-place A = L L^T (right-looking, one column at a time).  A pivot that is
-// not positive or not finite is replaced by 1 and counted in *bad; *minr
-// receives the smallest pivot / d0 ratio.  bad and minr live in shared memory.
+// In-place A = L L^T, right-looking with the column scaling deferred: step j
+// subtracts A_ij A_kj / d_j from the trailing entries (j < k <= i), where
+// d_j = A_jj after the earlier steps, so one barrier per column suffices;
+// a final pass scales column j by 1 / sqrt(d_j).  The trailing entries are
+// spread over a 16 x 16 thread grid (entry (i, k) on the thread with
+// i = ty, k = tx mod 16), which needs blockDim.x >= 256 (threads beyond 256
+// idle).  A pivot that is not positive or not finite is replaced by 1 and
+// counted in *bad; *minr receives the smallest pivot / d0 ratio.  bad and
+// minr live in shared memory.
+template <typename TA>
+__device__ __forceinline__ TA packed_pivot(TA d) {
+  return (d > (TA)0 && d < (TA)3.0e38) ? d : (TA)1;
+}
+
 template <typename TA>
 __device__ void packed_cholesky(TA* A, int n, const TA* d0, int* bad, float* minr) {
   const int tid = threadIdx.x;
+  const int ty = tid & 15, tx = (tid >> 4) & 15;
+  const bool worker = tid < 256;
   if (tid == 0) { *bad = 0; *minr = 3.0e38f; }
   __syncthreads();
+  const int nb = (n + 15) >> 4;
   for (int j = 0; j < n; ++j) {
-    const int jj = packed_index(j, j);
+    const TA dj = A[packed_index(j, j)];
     if (tid == 0) {
-      TA piv = A[jj];
-      const float ratio = (float)(piv / d0[j]);
+      const float ratio = (float)(dj / d0[j]);
       if (ratio < *minr || !(ratio == ratio)) *minr = ratio == ratio ? ratio : 0.f;
-      if (!(piv > (TA)0) || !(piv < (TA)3.0e38)) { *bad = 1; piv = (TA)1; }
-      A[jj] = dsqrt(piv);
+      if (!(dj > (TA)0) || !(dj < (TA)3.0e38)) *bad = 1;
+    }
+    const TA inv = (TA)1 / packed_pivot(dj);
+    if (worker) {
+      for (int bi = (j + 1) >> 4; bi < nb; ++bi) {
+        const int i = 16 * bi + ty;
+        if (i <= j || i >= n) continue;
+        const TA aij = A[packed_index(i, j)] * inv;
+        TA* row = A + packed_index(i, 0);
+        for (int bk = (j + 1) >> 4; bk <= bi; ++bk) {
+          const int k = 16 * bk + tx;
+          if (k > j && k <= i) row[k] -= aij * A[packed_index(k, j)];
+        }
+      }
     }
     __syncthreads();
-    const TA ljj = A[jj];
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) A[packed_index(i, j)] /= ljj;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int idx = tid; idx < m * m; idx += blockDim.x) {
-      const int i = j + 1 + idx / m, k = j + 1 + idx % m;
-      if (k <= i) A[packed_index(i, k)] -= A[packed_index(i, j)] * A[packed_index(k, j)];
+  }
+  // L_ij = A_ij / sqrt(d_j) (i > j), L_jj = sqrt(d_j)
+  for (int i = tid; i < n; i += blockDim.x) {
+    TA* row = A + packed_index(i, 0);
+    for (int j = 0; j < i; ++j) row[j] /= dsqrt(packed_pivot(A[packed_index(j, j)]));
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += blockDim.x) A[packed_index(j, j)] = dsqrt(packed_pivot(A[packed_index(j, j)]));
+  __syncthreads();
+}
+
+// b <- (L L^T)^-1 b in place (n <= 256): both substitutions run in the
+// first wavefront with b held in registers (row i on lane i mod 64) and
+// each solved entry broadcast by a lane shuffle; no workgroup barrier inside.
+template <typename TA, typename TB>
+__device__ void packed_solve(const TA* L, TB* b, int n) {
+  const int lane = threadIdx.x;
+  if (lane < 64) {
+    TB r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = (lane + 64 * q < n) ? b[lane + 64 * q] : (TB)0;
+    // forward: L y = b
+    for (int j = 0; j < n; ++j) {
+      const int qj = j >> 6;
+      TB bj = (TB)0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q == qj) bj = r[q];
+      const TB yj = __shfl(bj, j & 63) / (TB)L[packed_index(j, j)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        if (i == j) r[q] = yj;
+        else if (i > j && i < n) r[q] -= (TB)L[packed_index(i, j)] * yj;
+      }
     }
-    __syncthreads();
+    // backward: L^T x = y
+    for (int j = n - 1; j >= 0; --j) {
+      const int qj = j >> 6;
+      TB yj = (TB)0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q == qj) yj = r[q];
+      const TB xj = __shfl(yj, j & 63) / (TB)L[packed_index(j, j)];
+      const TA* rowj = L + packed_index(j, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        if (i == j) r[q] = xj;
+        else if (i < j) r[q] -= (TB)rowj[i] * xj;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lane + 64 * q < n) b[lane + 64 * q] = r[q];
+  }
+  __syncthreads();
+}
+
+// Cholesky of the augmented matrix [[S, .], [s^T, .]] (n + 1 <= NMAX rows)
+// by the first wavefront alone, with no workgroup barrier: lane l keeps rows
+// l and l + 64 in registers (entry k of a row in register k, so every index
+// is a compile-time constant).  Column j: the pivot is read from its lane
+// (v_readlane), every lane scales its column-j entries, then subtracts
+// l_ij l_kj from its entries k > j, taking each l_kj from lane k mod 64 by
+// v_readlane (no LDS round trip on the elimination's critical path).  Entries above a row's diagonal receive the
+// same arithmetic and are never read, so no lane needs a predicate.  The
+// last row ends as y = L^-1 s.  Then L^T dxi = y on the same wavefront with
+// one pivot broadcast per row.  Returns the step in x[0..n) (LDS, zero if a
+// pivot was not positive).
+template <int NMAX>
+__device__ __forceinline__ void wave_chol_solve(int n_in, const float* Sp_g, const float* rhs_g, const float* d0_g, float* cb,
+                                float* Lrow, float* x, float* invd, int* bad_out, float* minr_out) {
+  constexpr int N1 = NMAX < 64 ? NMAX : 64;  // columns held for rows < 64
+  constexpr int N2 = NMAX > 64 ? NMAX : 1;   // columns held for rows >= 64
+  const int n = __builtin_amdgcn_readfirstlane(n_in);  // uniform: loop guards stay scalar
+  const int lane = threadIdx.x;
+  const int r0 = lane, r1 = lane + 64;
+  float a0[N1], a1[N2];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    float v = 0.f;
+    if (k <= r0 && r0 < n) v = Sp_g[r0 * (r0 + 1) / 2 + k];
+    else if (r0 == n && k < n) v = rhs_g[k];
+    a0[k] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < N2; ++k) {
+    float v = 0.f;
+    if (NMAX > 64) {
+      if (k <= r1 && r1 < n) v = Sp_g[r1 * (r1 + 1) / 2 + k];
+      else if (r1 == n && k < n) v = rhs_g[k];
+    }
+    a1[k] = v;
+  }
+  const float dd0 = r0 < n ? d0_g[r0] : 1.f;
+  const float dd1 = r1 < n ? d0_g[r1] : 1.f;
+  int bad = 0;
+  float minr = 3.0e38f;
+#pragma unroll
+  for (int j = 0; j < NMAX - 1; ++j) {
+    if (j >= n) continue;  // uniform; keeps the loop fully unrolled
+    float d, d0j;
+    if (j < 64) {
+      d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a0[j < N1 ? j : 0]), j & 63));
+      d0j = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dd0), j & 63));
+    } else {
+      d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a1[j < N2 ? j : 0]), j & 63));
+      d0j = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dd1), j & 63));
+    }
+    const float ratio = d / d0j;
+    if (!(ratio >= minr)) minr = ratio == ratio ? fmaxf(ratio, 0.f) : 0.f;
+    if (!(d > 0.f) || !(d < 3.0e38f)) {
+      bad = 1;
+      d = 1.f;
+    }
+    const float rs = 1.f / sqrtf(d);
+    if (lane == 0) invd[j] = rs;
+    // scale column j (row j's diagonal becomes L_jj = sqrt(d)) and publish it
+    float l0 = 0.f, l1 = 0.f;
+    if (j < N1) {
+      l0 = a0[j < N1 ? j : 0] * rs;
+      a0[j < N1 ? j : 0] = l0;
+    }
+    if (NMAX > 64) {
+      l1 = a1[j < N2 ? j : 0] * rs;
+      a1[j < N2 ? j : 0] = l1;
+    }
+    // trailing update of entries k > j; l_kj comes from lane k mod 64 by
+    // v_readlane (rows above k receive arithmetic on entries above their
+    // diagonal, which are never read; columns k > n touch unused entries)
+#pragma unroll
+    for (int k = j + 1; k < NMAX; ++k) {
+      const float lk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(k < 64 ? l0 : l1), k & 63));
+      if (k < N1) a0[k < N1 ? k : 0] -= l0 * lk;
+      if (NMAX > 64) a1[k < N2 ? k : 0] -= l1 * lk;
+    }
+  }
+  // rows of L (and y in row n) to LDS, row-major with stride NMAX
+#pragma unroll
+  for (int k = 0; k < N1; ++k)
+    if (r0 < NMAX) Lrow[r0 * NMAX + k] = a0[k];
+  if (NMAX > 64) {
+#pragma unroll
+    for (int k = 0; k < N2; ++k)
+      if (r1 < NMAX) Lrow[r1 * NMAX + k] = a1[k];
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  // backward substitution L^T x = y; lane l holds entries l and l + 64
+  float y0 = r0 < n ? Lrow[n * NMAX + r0] : 0.f;
+  float y1 = (NMAX > 64 && r1 < n) ? Lrow[n * NMAX + r1] : 0.f;
+  for (int i = n - 1; i >= 0; --i) {
+    const float yv = i >= 64 ? y1 : y0;
+    const float xi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), i & 63)) * invd[i];
+    const float* Li = Lrow + i * NMAX;
+    if (r0 < i) y0 -= Li[r0] * xi;
+    if (r1 < i) y1 -= Li[r1] * xi;
+    if (r0 == i) y0 = xi;
+    if (r1 == i) y1 = xi;
+  }
+  if (r0 < n) x[r0] = bad ? 0.f : y0;
+  if (r1 < n) x[r1] = bad ? 0.f : y1;
+  if (lane == 0) {
+    *bad_out = bad;
+    *minr_out = minr;
   }
 }
 
-// b <- (L L^T)^-1 b in place (forward then backward substitution).
-template <typename TA, typename TB>
-__device__ void packed_solve(const TA* L, TB* b, int n) {
+
+// Cholesky of the augmented matrix [[S, .], [s^T, .]] (n + 1 <= 16 MB rows)
+// by a 256-thread workgroup with the matrix in registers: thread
+// (ty, tx) = (tid mod 16, tid / 16) holds entries (16 bi + ty, 16 bk + tx)
+// for all bi, bk < MB, so every register index is a compile-time constant.
+// Column j (loop fully unrolled): the 16 owners of column j (one wavefront)
+// take the pivot by v_readlane, scale their column-j entries and publish the
+// scaled column in a double-buffered LDS vector with zeros at rows <= j;
+// after one barrier every thread subtracts cb_i cb_k from all of its
+// entries.  The zeros make the update a no-op wherever it must not act
+// (finished columns and rows), so no thread needs a predicate, and entries
+// above the diagonal receive arithmetic that is never read.  The last row
+// ends as y = L^-1 s; then L^T x = y on one wavefront.  Returns the step in
+// x[0..n) (LDS; zero if a pivot was not positive).
+template <typename T, int MB>
+__device__ __forceinline__ void block_chol_solve(int n_in, const T* Sp_g, const T* rhs_g, const T* d0_g,
+                                                 unsigned char* lds, T* x, int* bad_out, float* minr_out) {
+  constexpr int NR = 16 * MB;
+  const int n = __builtin_amdgcn_readfirstlane(n_in);
   const int tid = threadIdx.x;
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) b[j] /= (TB)L[packed_index(j, j)];
+  const int ty = tid & 15, tx = tid >> 4;
+  T* cb = reinterpret_cast<T*>(lds);  // [2][NR]
+  T* invd = cb + 2 * NR;             // [NR]
+  T* dd = invd + NR;                 // [NR] damped diagonal (pivot monitor)
+  T* Lrow = dd + NR;                 // [NR][NR] rows of L, then y
+  for (int i = tid; i < n; i += blockDim.x) dd[i] = d0_g[i];
+  T a[MB][MB];
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+    for (int bk = 0; bk < MB; ++bk) {
+      const int i = 16 * bi + ty, k = 16 * bk + tx;
+      T v = (T)0;
+      if (k <= i && i < n) v = Sp_g[i * (i + 1) / 2 + k];
+      else if (i == n && k < n) v = rhs_g[k];
+      a[bi][bk] = v;
+    }
+  int bad = 0;
+  float minr = 3.0e38f;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NR - 1; ++j) {
+    if (j >= n) continue;  // uniform
+    const int bj = j >> 4, jm = j & 15;
+    T* cbj = cb + (j & 1) * NR;
+    if (tx == jm) {  // one wavefront: threads 16 jm .. 16 jm + 15
+      // pivot a_jj lives on the owner with ty == jm: lane (16 jm + jm) mod 64
+      T d;
+      if constexpr (sizeof(T) == 4) {
+        d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[bj][bj]), (16 * jm + jm) & 63));
+      } else {
+        const long long bits = __double_as_longlong(a[bj][bj]);
+        const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), (16 * jm + jm) & 63);
+        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), (16 * jm + jm) & 63);
+        d = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+      }
+      if (ty == jm) {
+        const float ratio = (float)(d / dd[j]);
+        if (!(ratio >= minr)) minr = ratio == ratio ? fmaxf(ratio, 0.f) : 0.f;
+        if (!(d > (T)0) || !(d < (T)3.0e38)) bad = 1;
+      }
+      if (!(d > (T)0) || !(d < (T)3.0e38)) d = (T)1;
+      const T rs = (T)1 / dsqrt(d);
+      if (ty == jm) invd[j] = rs;
+#pragma unroll
+      for (int bi = 0; bi < MB; ++bi) {
+        const int i = 16 * bi + ty;
+        const T l = a[bi][bj] * rs;
+        if (i >= j) a[bi][bj] = l;
+        cbj[i] = i > j ? l : (T)0;
+      }
+    }
     __syncthreads();
-    const TB yj = b[j];
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) b[i] -= (TB)L[packed_index(i, j)] * yj;
-    __syncthreads();
+    T ci[MB], ck[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      ci[b] = cbj[16 * b + ty];
+      ck[b] = cbj[16 * b + tx];
+    }
+#pragma unroll
+    for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+      for (int bk = 0; bk < MB; ++bk) a[bi][bk] -= ci[bi] * ck[bk];
   }
-  for (int j = n - 1; j >= 0; --j) {
-    if (tid == 0) b[j] /= (TB)L[packed_index(j, j)];
-    __syncthreads();
-    const TB xj = b[j];
-    const TA* rowj = L + packed_index(j, 0);
-    for (int i = tid; i < j; i += blockDim.x) b[i] -= (TB)rowj[i] * xj;
-    __syncthreads();
+  // rows of L (and y in row n) to LDS
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+    for (int bk = 0; bk < MB; ++bk) Lrow[(16 * bi + ty) * NR + 16 * bk + tx] = a[bi][bk];
+  __syncthreads();
+  if (tid < 64) {  // backward substitution L^T x = y; lane l holds entries l, l + 64
+    const int r0 = tid, r1 = tid + 64;
+    T y0 = r0 < n ? Lrow[n * NR + r0] : (T)0;
+    T y1 = r1 < n ? Lrow[n * NR + r1] : (T)0;
+    for (int i = n - 1; i >= 0; --i) {
+      const T yv = i >= 64 ? y1 : y0;
+      T yi;
+      if constexpr (sizeof(T) == 4) {
+        yi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), i & 63));
+      } else {
+        const long long bits = __double_as_longlong(yv);
+        const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), i & 63);
+        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), i & 63);
+        yi = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+      }
+      const T xi = yi * invd[i];
+      const T* Li = Lrow + i * NR;
+      if (r0 < i) y0 -= Li[r0] * xi;
+      if (r1 < i) y1 -= Li[r1] * xi;
+      if (r0 == i) y0 = xi;
+      if (r1 == i) y1 = xi;
+    }
+    if (r0 < n) x[r0] = y0;
+    if (r1 < n) x[r1] = y1;
   }
+  // bad and minr are known to the owners' threads: combine through LDS
+  __shared__ int bad_s;
+  __shared__ float minr_s;
+  if (tid == 0) { bad_s = 0; minr_s = 3.0e38f; }
+  __syncthreads();
+  if (bad) atomicOr(&bad_s, 1);
+  if (minr < 3.0e38f) atomicMin(reinterpret_cast<unsigned int*>(&minr_s), __float_as_uint(minr));
+  __syncthreads();
+  if (tid < n && bad_s) x[tid] = (T)0;
+  if (tid + 256 < n && bad_s) x[tid + 256] = (T)0;
+  if (tid == 0) {
+    *bad_out = bad_s;
+    *minr_out = minr_s;
+  }
+  __syncthreads();
 }
 
 }  // namespace dpvba

@@ -21,6 +21,7 @@
 // floating-point atomics are used.
 #include "edge.h"
 #include "mfma.h"
+#include "packed.h"
 #include "tileargs.h"
 #include "dpvba.h"
 
@@ -209,31 +210,31 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
   __syncthreads();
 
   // ---- phase 2b: Schur rows u_k = E_k / sqrt(C~_k), appended w_k / sqrt(C~_k).
-  // (i) thread (k, m) sums component m of (C, w, -sum_j Ad^T E_j) over the
-  //     patch's slots in slot order; (ii) thread (k, x) writes row entry x.
+  // (i) thread k sums (C, w, -sum_j Ad(T_ji)^T E_j) of patch k over its slots
+  //     in slot order (the slot poses are read by every lane at once);
+  //     (ii) thread (k, x) writes row entry x.
   const int src = ti.src_blk;
-  for (int idx = tid; idx < K * 8; idx += blockDim.x) {
-    const int k = idx >> 3, m = idx & 7;
-    T v = (T)0;
+  for (int k = tid; k < K; k += blockDim.x) {
+    T v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int ss = 0; ss < Tn; ++ss) {
       const T* cell = sCell + (size_t)(k * Tn + ss) * cellT;
-      if (m < 2) {
-        v += cell[6 + m];
-      } else if (m < 5) {  // rotation part R^T a of Ad^T (a; b)
-        const T* R = sSlot + 18 * ss;
-        const int q = m - 2;
-        v -= R[q] * cell[0] + R[3 + q] * cell[1] + R[6 + q] * cell[2];
-      } else {             // R^T (b - t x a)
-        const T* R = sSlot + 18 * ss;
-        const T* tt = R + 9;
-        const int q = m - 5;
-        const T b0 = cell[3] - (tt[1] * cell[2] - tt[2] * cell[1]);
-        const T b1 = cell[4] - (tt[2] * cell[0] - tt[0] * cell[2]);
-        const T b2 = cell[5] - (tt[0] * cell[1] - tt[1] * cell[0]);
-        v -= R[q] * b0 + R[3 + q] * b1 + R[6 + q] * b2;
-      }
+      T c[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) c[m] = cell[m];
+      const T* R = sSlot + 18 * ss;
+      const T* tt = R + 9;
+      v[0] += c[6];
+      v[1] += c[7];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v[2 + q] -= R[q] * c[0] + R[3 + q] * c[1] + R[6 + q] * c[2];
+      const T b0 = c[3] - (tt[1] * c[2] - tt[2] * c[1]);
+      const T b1 = c[4] - (tt[2] * c[0] - tt[0] * c[2]);
+      const T b2 = c[5] - (tt[0] * c[1] - tt[1] * c[0]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v[5 + q] -= R[q] * b0 + R[3 + q] * b1 + R[6 + q] * b2;
     }
-    sPs[idx] = v;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) sPs[8 * k + m] = v[m];
   }
   __syncthreads();
   for (int k = tid; k < K; k += blockDim.x) {
@@ -425,127 +426,44 @@ __device__ void gather_slice(const IterArgs<T>& A, T* Sp, T* rhs, T* d0, int wav
   }
 }
 
-// One workgroup: Cholesky of the augmented matrix [[S, .], [s^T, .]] (its
-// last row carries the right-hand side, so the factor's last row becomes
-// y = L^-1 s) held in registers on a 16x16 thread grid: element (i, k) lives
-// on the thread with i mod 16 = tid mod 16 and k mod 16 = tid / 16, so the
-// 16 owners of a column share one wavefront and take the pivot by a lane
-// shuffle.  One barrier per column; the scaled column is broadcast through
-// a double-buffered LDS vector.  Then the backward substitution
-// L^T dxi = y in one wavefront and the retraction of the free poses.  A
-// non-positive pivot discards the step (dxi = 0, *A.status = 1).
-template <typename T, int MB>
-__device__ void factor_solve_retract_reg(const IterArgs<T>& A, const T* Sp_g, const T* rhs_g, const T* d0_g,
-                                         unsigned char* lds) {
+// Factor and solve the gathered system in workgroup 0 and retract the free
+// poses.  float32 systems of up to 79 unknowns: block_chol_solve (matrix in
+// registers, one barrier per column).  Otherwise the packed lower triangle
+// is factored in LDS (packed_cholesky, one barrier per column) and solved on
+// one wavefront.  A non-positive pivot discards the step (dxi = 0,
+// *A.status = 1).
+template <typename T>
+__device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const T* Sp_g, const T* rhs_g,
+                                                     const T* d0_g, unsigned char* lds) {
   const int tid = threadIdx.x;
   const int n = 6 * A.n_free;
-  const int ty = tid & 15, tx = tid >> 4;  // rows i = 16 bi + ty, columns k = 16 bk + tx
-  T* Lp = reinterpret_cast<T*>(lds);       // packed lower factor, rows 0..n
-  T* x = Lp + (n + 1) * (n + 2) / 2;       // [n + 1]
-  T* colb = x + (n + 1);                   // [2][n + 1]
-  T* dd = colb + 2 * (n + 1);              // [n + 1] damped diagonal of S
-  T* invd = dd + (n + 1);                  // [n + 1] 1 / L_jj
   __shared__ int bad;
   __shared__ float minr;
-  if (tid == 0) { bad = 0; minr = 3.0e38f; }
-  T a[MB][MB];
-#pragma unroll
-  for (int bi = 0; bi < MB; ++bi)
-#pragma unroll
-    for (int bk = 0; bk < MB; ++bk) {
-      const int i = 16 * bi + ty, k = 16 * bk + tx;
-      T v = (T)0;
-      if (bk <= bi && k < n && k <= i && i <= n) v = i < n ? Sp_g[i * (i + 1) / 2 + k] : rhs_g[k];
-      a[bi][bk] = v;
-    }
-  for (int i = tid; i < n; i += blockDim.x) dd[i] = d0_g[i];
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const int bj = j >> 4, jm = j & 15;
-    T* cb = colb + (j & 1) * (n + 1);
-    if (tx == jm) {  // the 16 owners of column j (one wavefront)
-      T mine = (T)0;
-#pragma unroll
-      for (int bi = 0; bi < MB; ++bi)
-        if (bi == bj) mine = a[bi][bi];
-      T d = __shfl(mine, ((jm << 4) | jm) & 63);
-      if (ty == jm) {
-        const float ratio = (float)(d / dd[j]);
-        if (!(ratio >= minr)) minr = ratio == ratio ? fmaxf(ratio, 0.f) : 0.f;
-      }
-      if (!(d > (T)0) || !(d < (T)3.0e38)) {
-        if (ty == jm) bad = 1;
-        d = (T)1;
-      }
-      const T rs = (T)1 / dsqrt(d);
-      if (ty == jm) invd[j] = rs;
-#pragma unroll
-      for (int bi = 0; bi < MB; ++bi) {
-        const int i = 16 * bi + ty;
-        if (i >= j && i <= n) {
-#pragma unroll
-          for (int bk = 0; bk < MB; ++bk)
-            if (bk == bj) {
-              const T l = a[bi][bk] * rs;
-              a[bi][bk] = l;
-              cb[i] = l;
-            }
-        }
-      }
+  const int nr = small_solve_rows(n);
+  T* x;
+  if (sizeof(T) == 4 && nr <= 80) {
+    x = reinterpret_cast<T*>(lds) + 4 * nr + nr * nr;  // after the solver's own arrays
+    if (nr == 32) block_chol_solve<T, 2>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
+    else if (nr == 64) block_chol_solve<T, 4>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
+    else block_chol_solve<T, 5>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
+  } else {
+    const int np = n * (n + 1) / 2;
+    T* Ap = reinterpret_cast<T*>(lds);  // packed lower factor
+    x = Ap + np;                        // [n] right-hand side, then the step
+    T* dd = x + n;                      // [n] damped diagonal
+    for (int q = tid; q < np; q += blockDim.x) Ap[q] = Sp_g[q];
+    for (int i = tid; i < n; i += blockDim.x) {
+      x[i] = rhs_g[i];
+      dd[i] = d0_g[i];
     }
     __syncthreads();
-    // trailing update a_ik -= l_ij l_kj for j < k <= i
-#pragma unroll
-    for (int bi = 0; bi < MB; ++bi) {
-      const int i = 16 * bi + ty;
-      if (i <= j || i > n) continue;
-      const T li = cb[i];
-#pragma unroll
-      for (int bk = 0; bk < MB; ++bk) {
-        if (bk > bi) continue;
-        const int k = 16 * bk + tx;
-        if (k > j && k <= i && k < n) a[bi][bk] -= li * cb[k];
-      }
-    }
+    packed_cholesky<T>(Ap, n, dd, &bad, &minr);
+    packed_solve<T, T>(Ap, x, n);
+    for (int i = tid; i < n; i += blockDim.x)
+      if (bad) x[i] = (T)0;
+    __syncthreads();
   }
-  // factor (and y in row n) to LDS
-#pragma unroll
-  for (int bi = 0; bi < MB; ++bi)
-#pragma unroll
-    for (int bk = 0; bk < MB; ++bk) {
-      const int i = 16 * bi + ty, k = 16 * bk + tx;
-      if (bk <= bi && k < n && k <= i && i <= n) Lp[i * (i + 1) / 2 + k] = a[bi][bk];
-    }
-  __syncthreads();
-  // backward substitution L^T dxi = y in wavefront 0; lane l owns rows l and
-  // l + 64 (n < 128), held in two named registers
-  if (tid < 64) {
-    const T* yrow = Lp + n * (n + 1) / 2;
-    T r0 = tid < n ? yrow[tid] : (T)0;
-    T r1 = tid + 64 < n ? yrow[tid + 64] : (T)0;
-    for (int j = n - 1; j >= 0; --j) {
-      const bool hi = j >= 64;
-      const int jr = j * (j + 1) / 2;
-      const T xj = __shfl(hi ? r1 : r0, j & 63) * invd[j];
-      if (tid == (j & 63)) {
-        if (hi) r1 = xj;
-        else r0 = xj;
-      }
-      if (tid < j) r0 -= Lp[jr + tid] * xj;
-      if (tid + 64 < j) r1 -= Lp[jr + tid + 64] * xj;
-    }
-    if (tid < n) {
-      const T v = bad ? (T)0 : r0;
-      x[tid] = v;
-      A.dx[tid] = v;
-    }
-    if (tid + 64 < n) {
-      const T v = bad ? (T)0 : r1;
-      x[tid + 64] = v;
-      A.dx[tid + 64] = v;
-    }
-  }
-  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) A.dx[i] = x[i];
   for (int i = tid; i < A.n_frames; i += blockDim.x) {
     const T* pc = A.poses_cur + 7 * (size_t)i;
     T* pn = A.poses_next + 7 * (size_t)i;
@@ -554,7 +472,7 @@ __device__ void factor_solve_retract_reg(const IterArgs<T>& A, const T* Sp_g, co
   }
   if (tid == 0) {
     *A.status = bad;
-    *A.min_bits = __float_as_uint(minr);
+    *A.min_bits = __float_as_uint(minr >= 0.f ? minr : 0.f);
     if (A.cost_out) {
       double cc = 0.0;
       int inv = 0;
@@ -567,16 +485,6 @@ __device__ void factor_solve_retract_reg(const IterArgs<T>& A, const T* Sp_g, co
     }
   }
   __syncthreads();
-}
-
-template <typename T>
-__device__ void factor_solve_retract(const IterArgs<T>& A, const T* Sp, const T* rhs, const T* d0,
-                                     unsigned char* lds) {
-  // n + 1 <= kSmallRows (the host routes larger systems to the blocked path)
-  const int n1 = 6 * A.n_free + 1;
-  if (n1 <= 32) factor_solve_retract_reg<T, 2>(A, Sp, rhs, d0, lds);
-  else if (n1 <= 64) factor_solve_retract_reg<T, 4>(A, Sp, rhs, d0, lds);
-  else factor_solve_retract_reg<T, 6>(A, Sp, rhs, d0, lds);
 }
 
 // Grid-wide barrier of a cooperative launch: bar[0] counts arrivals,
@@ -645,7 +553,8 @@ __device__ void tile_writeback(const TileInfo& ti, const int* tile_patch, const 
 // reduced system, workgroup 0 factors, solves and retracts; finally the
 // depths are written back.  Poses ping-pong between two buffers.
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads) small_solve_kernel(SmallArgs<T> S) {
+__global__ void __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+small_solve_kernel(SmallArgs<T> S) {
   extern __shared__ __align__(16) unsigned char lds[];
   IterArgs<T> A = S.it;
   const unsigned int nb = gridDim.x;
