@@ -62,69 +62,104 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
 // The block is factored together with an identity appended below it: the
 // Cholesky factor of [[A, I], [I, .]] has L^-T in its lower-left block, so
 // one elimination gives both L and its inverse.  The 128 x 64 working matrix
-// sits in LDS; column j is eliminated with its scaling deferred (step j
-// subtracts W_ij W_kj / d_j from the trailing entries, d_j = W_jj), so one
-// barrier per column suffices; the trailing entries are spread over a
-// 16 x 16 thread grid with loops that start at the first live block.
+// lives in registers on a 16 x 16 thread grid (entry (i, k) on the thread
+// with i = ty, k = tx mod 16; every register index is a compile-time
+// constant because the column loop is unrolled).  Column j: its 16 owners
+// (one wavefront) take the pivot by v_readlane, scale their entries and
+// publish the column in a double-buffered LDS vector with zeros at the rows
+// <= j of the block; after one barrier every thread subtracts c_i c_k from
+// all of its entries, which is a no-op wherever it must not act.
 template <typename T>
-__global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, int kb, T* Linv, const T* d0,
+__global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, int kb_in, T* Linv, const T* d0,
                                                          int* status, unsigned int* min_bits) {
-  constexpr int R = 2 * kNB, C = kNB, LD = kNB + 1;
-  __shared__ T W[R * LD];
-  __shared__ int bad;
-  __shared__ float minr;
+  constexpr int RB = 8, CB = 4;  // 128 rows, 64 columns
+  constexpr int R = 16 * RB;
+  __shared__ T colb[2][R];
+  __shared__ T dd[kNB];
+  __shared__ int bad_s;
+  __shared__ unsigned int minr_s;
+  const int kb = __builtin_amdgcn_readfirstlane(kb_in);
   const int tid = threadIdx.x;
   const int ty = tid & 15, tx = tid >> 4;
-  for (int idx = tid; idx < R * C; idx += blockDim.x) {
-    const int i = idx / C, k = idx - (idx / C) * C;
-    T v = (T)0;
-    if (i < kNB) {
-      if (i < kb && k <= i) v = S[(size_t)(k0 + i) * n + k0 + k];
-    } else if (i - kNB == k && k < kb) {
-      v = (T)1;
+  if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }
+  if (tid < kb) dd[tid] = d0[k0 + tid];
+  T a[RB][CB];
+#pragma unroll
+  for (int bi = 0; bi < RB; ++bi)
+#pragma unroll
+    for (int bk = 0; bk < CB; ++bk) {
+      const int i = 16 * bi + ty, k = 16 * bk + tx;
+      T v = (T)0;
+      if (i < kNB) {
+        if (i < kb && k <= i) v = S[(size_t)(k0 + i) * n + k0 + k];
+      } else if (i - kNB == k && k < kb) {
+        v = (T)1;
+      }
+      a[bi][bk] = v;
     }
-    W[i * LD + k] = v;
-  }
-  if (tid == 0) { bad = 0; minr = 3.0e38f; }
   __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    const T dj = W[j * LD + j];
-    if (tid == 0) {
-      const float ratio = (float)(dj / d0[k0 + j]);
-      if (ratio < minr || !(ratio == ratio)) minr = ratio == ratio ? ratio : 0.f;
-      if (!(dj > (T)0) || !(dj < (T)3.0e38)) bad = 1;
-    }
-    const T inv = (T)1 / ((dj > (T)0 && dj < (T)3.0e38) ? dj : (T)1);
-    const int b0 = (j + 1) >> 4;
-    for (int bi = b0; bi < R / 16; ++bi) {
-      const int i = 16 * bi + ty;
-      if (i <= j) continue;
-      const T wij = W[i * LD + j] * inv;
-      const int bk_end = bi < kNB / 16 ? bi : C / 16 - 1;
-      for (int bk = b0; bk <= bk_end; ++bk) {
-        const int k = 16 * bk + tx;
-        if (k > j && (i >= kNB || k <= i)) W[i * LD + k] -= wij * W[k * LD + j];
+  int bad = 0;
+  float minr = 3.0e38f;
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) {
+    if (j >= kb) continue;  // uniform
+    const int bj = j >> 4, jm = j & 15;
+    T* cb = colb[j & 1];
+    if (tx == jm) {
+      T d;
+      const int src = (16 * jm + jm) & 63;
+      if constexpr (sizeof(T) == 4) {
+        d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[bj][bj]), src));
+      } else {
+        const long long bits = __double_as_longlong(a[bj][bj]);
+        const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), src);
+        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+        d = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+      }
+      if (ty == jm) {
+        const float ratio = (float)(d / dd[j]);
+        if (!(ratio >= minr)) minr = ratio == ratio ? fmaxf(ratio, 0.f) : 0.f;
+        if (!(d > (T)0) || !(d < (T)3.0e38)) bad = 1;
+      }
+      if (!(d > (T)0) || !(d < (T)3.0e38)) d = (T)1;
+      const T rs = (T)1 / dsqrt(d);
+#pragma unroll
+      for (int bi = 0; bi < RB; ++bi) {
+        const int i = 16 * bi + ty;
+        const T l = a[bi][bj] * rs;
+        if (i >= j) a[bi][bj] = l;
+        cb[i] = i > j ? l : (T)0;
       }
     }
     __syncthreads();
+    T ci[RB], ck[CB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) ci[b] = cb[16 * b + ty];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) ck[b] = cb[16 * b + tx];
+#pragma unroll
+    for (int bi = 0; bi < RB; ++bi)
+#pragma unroll
+      for (int bk = 0; bk < CB; ++bk) a[bi][bk] -= ci[bi] * ck[bk];
   }
-  // scale column j by 1 / sqrt(d_j); L_jj = sqrt(d_j)
-  for (int idx = tid; idx < R * C; idx += blockDim.x) {
-    const int i = idx / C, k = idx - (idx / C) * C;
-    if (k >= kb || (i < kNB && k > i)) continue;
-    const T dk = W[k * LD + k];
-    const T sd = dsqrt((dk > (T)0 && dk < (T)3.0e38) ? dk : (T)1);
-    const T v = (i == k) ? sd : W[i * LD + k] / sd;
-    if (i < kNB) {
-      if (i < kb) S[(size_t)(k0 + i) * n + k0 + k] = v;
-    } else {
-      const int r = i - kNB;  // row r of L^-T = column r of L^-1
-      if (r < kb) Linv[k * kNB + r] = v;
+#pragma unroll
+  for (int bi = 0; bi < RB; ++bi)
+#pragma unroll
+    for (int bk = 0; bk < CB; ++bk) {
+      const int i = 16 * bi + ty, k = 16 * bk + tx;
+      if (i < kNB) {
+        if (i < kb && k <= i) S[(size_t)(k0 + i) * n + k0 + k] = a[bi][bk];
+      } else {
+        const int r = i - kNB;  // row r of L^-T = column r of L^-1
+        if (r < kb && k < kb) Linv[k * kNB + r] = (k >= r) ? a[bi][bk] : (T)0;
+      }
     }
-  }
+  if (bad) atomicOr(&bad_s, 1);
+  if (minr < 3.0e38f) atomicMin(&minr_s, __float_as_uint(minr));
+  __syncthreads();
   if (tid == 0) {
-    if (bad) atomicOr(status, 1);
-    pivot_min(min_bits, minr);
+    if (bad_s) atomicOr(status, 1);
+    pivot_min(min_bits, __uint_as_float(minr_s));
   }
 }
 
