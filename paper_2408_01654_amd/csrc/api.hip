@@ -48,8 +48,8 @@ hipError_t launch_reproject(const float* poses, const float* inv_depth, const fl
                             const int* ii, const int* jj, const int* kk, int n_edges, float fx, float fy,
                             float cx, float cy, float z_min, float* coords, uint8_t* valid, hipStream_t st);
 template <typename T>
-hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* work_y, T* Linv_all, const T* d0,
-                             int* status, unsigned int* min_bits, hipStream_t st);
+hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
+                             unsigned int* min_bits, int* flags, int epoch, int* err, hipStream_t st);
 hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st);
 template <typename TP, typename T>
 hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
@@ -59,8 +59,8 @@ template <typename T>
 hipError_t launch_chol_factor(T* S, int n, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
                               hipStream_t st);
 template <typename T>
-hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_b, T* work_y,
-                             hipStream_t st);
+hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
+                             int epoch, int* err, hipStream_t st);
 // mixed-precision helpers (mixed.hip)
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st);
@@ -207,6 +207,8 @@ struct dpvba_ctx {
   // workspace
   DevBuf part_S, part_vec, part_cost, part_invalid, U_s, pscale_s, depth_s, xh_s, poses_a, poses_b;
   DevBuf S, rhs, dB, d0, dx, wb, wy, Linv, edge_part, ticket, dev_err;
+  DevBuf chain_flags;  // per 64-row block: forward and backward publication epochs
+  int chain_epoch = 0;
   DevBuf status, min_bits, devrep;
   // edge lists of the adjoint: per patch (pcount / pedges, edge order), per
   // pose (pose_off / pose_src = 2 e + side), tile-order position of a patch
@@ -258,6 +260,12 @@ struct TraceScope {
     if (pair >= 0) (void)hipEventRecord(c->ev[2 * pair + 1], st);
   }
 };
+
+// Epoch of the next chained triangular solve (never 0, the flags' initial value).
+static int next_epoch(dpvba_ctx* c) {
+  c->chain_epoch = c->chain_epoch >= 0x3fffffff ? 1 : c->chain_epoch + 1;
+  return c->chain_epoch;
+}
 
 static void record_error(dpvba_ctx* c, hipError_t e, const char* where) {
   if (!c) return;
@@ -362,6 +370,7 @@ void dpvba_destroy(dpvba_ctx* c) {
   DevBuf* bufs[] = {&c->part_S, &c->part_vec, &c->part_cost, &c->part_invalid, &c->U_s, &c->pscale_s,
                     &c->depth_s, &c->xh_s, &c->poses_a, &c->poses_b, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx,
                     &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
+                    &c->chain_flags,
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
                     &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
                     &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
@@ -667,6 +676,12 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(ensure(c->wb, n * 8));
   HIP_TRY(ensure(c->wy, n * 8));
   HIP_TRY(ensure(c->Linv, nblk64 * 64 * 64 * 8));
+  if (c->chain_flags.bytes < 2 * nblk64 * 4 + 16) {
+    HIP_TRY(ensure(c->chain_flags, 2 * nblk64 * 4 + 16));
+    HIP_TRY(hipMemsetAsync(c->chain_flags.p, 0, c->chain_flags.bytes, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    c->chain_epoch = 0;
+  }
   HIP_TRY(ensure(c->edge_part, ((size_t)(E + 255) / 256) * 8));
   if (!c->ticket.p) {
     HIP_TRY(ensure(c->ticket, 64));
@@ -885,8 +900,8 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     if (e != hipSuccess) return e;
     {
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
-      e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, dx, (T*)c->wb.p, (T*)c->wy.p, (T*)c->Linv.p,
-                               (const T*)c->d0.p, status + it, mb + it, st);
+      e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, dx, (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p,
+                               status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), (int*)c->dev_err.p, st);
     }
     if (e != hipSuccess) return e;
     {
@@ -986,15 +1001,15 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       if ((e = launch_convert<double, float>(d064, d032, n, st)) != hipSuccess) return e;
       if ((e = launch_convert<double, float>(s64, rhs32, n, st)) != hipSuccess) return e;
       if ((e = launch_chol_factor<float>(S32, n, Linv32, d032, status + it, mb + it, st)) != hipSuccess) return e;
-      if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wb.p, (float*)c->wy.p, st)) !=
-          hipSuccess)
+      if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
+                                    next_epoch(c), (int*)c->dev_err.p, st)) != hipSuccess)
         return e;
       if ((e = launch_convert<float, double>(c32, x64, n, st)) != hipSuccess) return e;
       for (int k = 0; k < kRefineSteps; ++k) {
         if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
         if ((e = launch_convert<double, float>(r64, rhs32, n, st)) != hipSuccess) return e;
-        if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wb.p, (float*)c->wy.p, st)) !=
-            hipSuccess)
+        if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
+                                      next_epoch(c), (int*)c->dev_err.p, st)) != hipSuccess)
           return e;
         if ((e = launch_accumulate(x64, c32, n, st)) != hipSuccess) return e;
       }
@@ -1006,8 +1021,9 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
         return e;
       if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
       if (*c->host_flag) {
-        if ((e = launch_chol_solve<double>(S64, s64, n, x64, (double*)c->wb.p, (double*)c->wy.p, (double*)c->Linv.p,
-                                           d064, status64 + it, mb64 + it, st)) != hipSuccess)
+        if ((e = launch_chol_solve<double>(S64, s64, n, x64, (double*)c->wy.p, (double*)c->Linv.p, d064, status64 + it,
+                                           mb64 + it, (int*)c->chain_flags.p, next_epoch(c), (int*)c->dev_err.p,
+                                           st)) != hipSuccess)
           return e;
       }
       if ((e = launch_step_to_f32(x64, dx, n, fb + it, status64 + it, status + it, st)) != hipSuccess) return e;
@@ -1165,9 +1181,9 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
     if ((e = launch_tile_iterate<T>(A, tl.lds_bytes, st)) != hipSuccess) return e;
     if ((e = launch_copy<T>((const T*)c->depth_s.p, Xd + it * ntp, ntp, st)) != hipSuccess) return e;
     if ((e = gather()) != hipSuccess) return e;
-    if ((e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, DX + (size_t)it * n, (T*)c->wb.p,
-                                  (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p, status + it, mb + it, st)) !=
-        hipSuccess)
+    if ((e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, DX + (size_t)it * n, (T*)c->wy.p,
+                                  (T*)c->Linv.p, (const T*)c->d0.p, status + it, mb + it, (int*)c->chain_flags.p,
+                                  next_epoch(c), (int*)c->dev_err.p, st)) != hipSuccess)
       return e;
     if ((e = launch_retract_copy<T>(xt, xt + np7, DX + (size_t)it * n, nf, N, status + it, st)) != hipSuccess)
       return e;
@@ -1193,9 +1209,9 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
                                    (T*)c->part_vec.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
                                    dxbar, stt, urhs, st)) != hipSuccess)
       return e;
-    if ((e = launch_chol_solve<T>((T*)c->S.p, urhs, n, up, (T*)c->wb.p, (T*)c->wy.p, (T*)c->Linv.p,
-                                  (const T*)c->d0.p, status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it,
-                                  st)) != hipSuccess)
+    if ((e = launch_chol_solve<T>((T*)c->S.p, urhs, n, up, (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p,
+                                  status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it, (int*)c->chain_flags.p,
+                                  next_epoch(c), (int*)c->dev_err.p, st)) != hipSuccess)
       return e;
     if ((e = launch_adjoint_backsub<T>(tiles, tl.n_tiles, tl.max_w6, (const int*)tl.blk_pose.p,
                                        (const T*)c->U_s.p, (const T*)c->pscale_s.p, dbar, up, dx_t, stt, ud, dd,

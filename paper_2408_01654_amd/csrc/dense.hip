@@ -13,6 +13,8 @@
 // min_pivot receives the smallest L_ii^2 / S_ii (as ordered bits of a
 // non-negative float, combined with an integer atomic minimum, which is
 // order-independent).
+#include <algorithm>
+
 #include "common.h"
 #include "mfma.h"
 #include "packed.h"
@@ -227,72 +229,121 @@ __global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, i
     }
 }
 
-// Forward solve step for block k: y_k = inv(L_kk) b_k (every workgroup computes
-// it; workgroup 0 stores it), then workgroup w >= 1 updates block k + w:
-// b_i -= L_ik y_k.
-template <typename T>
-__global__ void __launch_bounds__(256) trsv_fwd_kernel(const T* S, int n, int k, const T* Linv_all, T* b,
-                                                       T* y) {
-  __shared__ T yk[kNB];
-  const int k0 = k * kNB, kb = min(kNB, n - k0);
-  const T* Li = Linv_all + (size_t)k * kNB * kNB;
-  const int tid = threadIdx.x;
-  if (tid < kb) {
-    T v = (T)0;
-    for (int m = 0; m <= tid; ++m) v += Li[tid * kNB + m] * b[k0 + m];
-    yk[tid] = v;
+// Both triangular solves of a blocked factor in one cooperative launch.
+// Workgroup g owns the 64-row blocks I = g, g + G, ...  Forward (L y = b):
+// block I subtracts L_IK y_K for K < I as each y_K is published, then
+// y_I = inv(L_II) acc and publishes it; backward (L^T x = y) runs the same
+// chain from the last block down with L_KI^T and inv(L_II)^T.  A block is
+// published by storing the call's epoch into its flag (agent-scope release
+// after the data); a consumer reads the flag with an agent-scope acquire.
+// Every wait is bounded: on timeout *err is set and the workgroup returns,
+// so every workgroup exits.  The L blocks are loaded before the wait for
+// the vector they multiply, so the chain only carries the dependent part.
+constexpr long long kChainSpin = 1LL << 22;
+
+__device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err) {
+  __shared__ int ok_s;
+  if (threadIdx.x == 0) {
+    long long spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kChainSpin || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        atomicOr(err, 2);
+        ok = 0;
+        break;
+      }
+    }
+    ok_s = ok;
   }
   __syncthreads();
-  if (blockIdx.x == 0) {
-    if (tid < kb) y[k0 + tid] = yk[tid];
-    return;
-  }
-  const int i0 = k0 + blockIdx.x * kNB;
-  const int rows = min(kNB, n - i0);
-  // 4 threads per row, fixed split of the kb columns, combined in order
-  __shared__ T part[kNB][4];
-  const int r = tid / 4, q = tid % 4;
-  T v = (T)0;
-  if (r < rows) {
-    const T* row = S + (size_t)(i0 + r) * n + k0;
-    for (int m = q; m < kb; m += 4) v += row[m] * yk[m];
-  }
-  part[r][q] = v;
-  __syncthreads();
-  if (tid < rows) b[i0 + tid] -= ((part[tid][0] + part[tid][1]) + (part[tid][2] + part[tid][3]));
+  return ok_s != 0;
 }
 
-// Backward solve step for block k: x_k = inv(L_kk)^T y_k (y_k already reduced
-// by all later blocks), then workgroup w >= 1 updates block w - 1 < k:
-// y_j -= L_kj^T x_k.
+__device__ __forceinline__ void chain_publish(int* flag, int epoch) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) trsv_bwd_kernel(const T* S, int n, int k, const T* Linv_all, T* y,
-                                                       T* x) {
-  __shared__ T xk[kNB];
-  const int k0 = k * kNB, kb = min(kNB, n - k0);
-  const T* Li = Linv_all + (size_t)k * kNB * kNB;
+__global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, const T* Linv_all, const T* b, T* y,
+                                                         T* x, int* flags, int epoch, int* err) {
+  __shared__ T Li[kNB][kNB + 1];
+  __shared__ T acc[kNB];
+  __shared__ T vk[kNB];
+  __shared__ T part[4][kNB + 1];
+  const int nblk = (n + kNB - 1) / kNB;
   const int tid = threadIdx.x;
-  if (tid < kb) {
-    T v = (T)0;
-    for (int m = tid; m < kb; ++m) v += Li[m * kNB + tid] * y[k0 + m];
-    xk[tid] = v;
+  const int G = gridDim.x;
+  int* fwd = flags;
+  int* bwd = flags + nblk;
+  // ---- forward
+  for (int I = blockIdx.x; I < nblk; I += G) {
+    const int i0 = I * kNB, ib = min(kNB, n - i0);
+    if (tid < ib) acc[tid] = b[i0 + tid];
+    for (int idx = tid; idx < kNB * kNB; idx += blockDim.x)
+      Li[idx / kNB][idx % kNB] = Linv_all[(size_t)I * kNB * kNB + idx];
+    const int r = tid >> 2, q = tid & 3;  // 4 threads per row, 16 columns each
+    for (int K = 0; K < I; ++K) {
+      T lrow[16];
+      const T* src = L + (size_t)(i0 + r) * n + K * kNB + 16 * q;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) lrow[m] = r < ib ? src[m] : (T)0;
+      if (!chain_wait(fwd + K, epoch, err)) return;
+      if (tid < kNB) vk[tid] = y[K * kNB + tid];
+      __syncthreads();
+      T v = (T)0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v += lrow[m] * vk[16 * q + m];
+      part[q][r] = v;
+      __syncthreads();
+      if (tid < ib) acc[tid] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+      __syncthreads();
+    }
+    __syncthreads();
+    if (tid < ib) {
+      T v = (T)0;
+      for (int m = 0; m <= tid; ++m) v += Li[tid][m] * acc[m];
+      y[i0 + tid] = v;
+    }
+    chain_publish(fwd + I, epoch);
   }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    if (tid < kb) x[k0 + tid] = xk[tid];
-    return;
+  // ---- backward, blocks in decreasing order
+  const int last = blockIdx.x + ((nblk - 1 - blockIdx.x) / G) * G;
+  for (int I = last; I >= 0 && blockIdx.x < nblk; I -= G) {
+    const int i0 = I * kNB, ib = min(kNB, n - i0);
+    if (tid < ib) acc[tid] = y[i0 + tid];
+    for (int idx = tid; idx < kNB * kNB; idx += blockDim.x)
+      Li[idx / kNB][idx % kNB] = Linv_all[(size_t)I * kNB * kNB + idx];
+    const int c = tid & 63, q = tid >> 6;  // thread per column, 4 groups of 16 rows
+    for (int K = nblk - 1; K > I; --K) {
+      const int k0 = K * kNB, kb = min(kNB, n - k0);
+      T lcol[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int rr = 16 * q + m;
+        lcol[m] = (rr < kb && c < ib) ? L[(size_t)(k0 + rr) * n + i0 + c] : (T)0;
+      }
+      if (!chain_wait(bwd + K, epoch, err)) return;
+      if (tid < kNB) vk[tid] = tid < kb ? x[k0 + tid] : (T)0;
+      __syncthreads();
+      T v = (T)0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v += lcol[m] * vk[16 * q + m];
+      part[q][c] = v;
+      __syncthreads();
+      if (tid < ib) acc[tid] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+      __syncthreads();
+    }
+    __syncthreads();
+    if (tid < ib) {
+      T v = (T)0;
+      for (int m = tid; m < ib; ++m) v += Li[m][tid] * acc[m];
+      x[i0 + tid] = v;
+    }
+    chain_publish(bwd + I, epoch);
   }
-  const int j0 = (blockIdx.x - 1) * kNB;
-  const int cols = min(kNB, n - j0);
-  __shared__ T part[4][kNB];
-  const int c = tid % kNB, q = tid / kNB;
-  T v = (T)0;
-  if (c < cols) {
-    for (int m = q; m < kb; m += 4) v += S[(size_t)(k0 + m) * n + j0 + c] * xk[m];
-  }
-  part[q][c] = v;
-  __syncthreads();
-  if (tid < cols) y[j0 + tid] -= ((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]));
 }
 
 template <typename T>
@@ -301,11 +352,6 @@ __global__ void zero_on_status_kernel(T* dx, int n, const int* status) {
   if (i < n && *status) dx[i] = (T)0;
 }
 
-template <typename T>
-__global__ void copy_vec_kernel(const T* src, T* dst, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
-}
 
 // ------------------------------------------------------------------ launchers
 
@@ -335,21 +381,33 @@ hipError_t launch_chol_factor(T* S, int n, T* Linv_all, const T* d0, int* status
 
 // x = (L L^T)^-1 rhs with a factor from launch_chol_factor.
 template <typename T>
-hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_b, T* work_y,
-                             hipStream_t st) {
+int trsv_chain_grid(int nblk) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)trsv_chain_kernel<T>, 256, 0) !=
+      hipSuccess)
+    return 0;
+  return std::min(nblk, per_cu * cus);
+}
+
+// x = (L L^T)^-1 rhs with a factor from launch_chol_factor: one cooperative
+// launch (trsv_chain_kernel).  flags holds 2 ceil(n / 64) ints that the
+// library never resets: each call passes a fresh epoch.
+template <typename T>
+hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
+                             int epoch, int* err, hipStream_t st) {
   const int nblk = (n + kNB - 1) / kNB;
-  hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, rhs, work_b, n);
-  for (int k = 0; k < nblk; ++k)
-    hipLaunchKernelGGL((trsv_fwd_kernel<T>), dim3(nblk - k), dim3(256), 0, st, L, n, k, Linv_all, work_b,
-                       work_y);
-  for (int k = nblk - 1; k >= 0; --k)
-    hipLaunchKernelGGL((trsv_bwd_kernel<T>), dim3(k + 1), dim3(256), 0, st, L, n, k, Linv_all, work_y, x);
-  return hipGetLastError();
+  const int grid = trsv_chain_grid<T>(nblk);
+  if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
+  void* args[] = {(void*)&L, (void*)&n, (void*)&Linv_all, (void*)&rhs, (void*)&work_y, (void*)&x, (void*)&flags,
+                  (void*)&epoch, (void*)&err};
+  return hipLaunchCooperativeKernel((const void*)trsv_chain_kernel<T>, dim3(grid), dim3(256), args, 0, st);
 }
 
 template <typename T>
-hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* work_y, T* Linv_all, const T* d0,
-                             int* status, unsigned int* min_bits, hipStream_t st) {
+hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
+                             unsigned int* min_bits, int* flags, int epoch, int* err, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (n <= small_solve_max_n(sizeof(T))) {
     {
@@ -362,18 +420,18 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_b, T* wor
   }
   hipError_t e = launch_chol_factor<T>(S, n, Linv_all, d0, status, min_bits, st);
   if (e != hipSuccess) return e;
-  e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_b, work_y, st);
+  e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((zero_on_status_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, dx, n, status);
   return hipGetLastError();
 }
 
-template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, float*, float*, float*,
-                                             const float*, int*, unsigned int*, hipStream_t);
-template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, double*,
-                                              const double*, int*, unsigned int*, hipStream_t);
+template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, float*, float*, const float*, int*,
+                                             unsigned int*, int*, int, int*, hipStream_t);
+template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, const double*,
+                                              int*, unsigned int*, int*, int, int*, hipStream_t);
 template hipError_t launch_chol_factor<float>(float*, int, float*, const float*, int*, unsigned int*, hipStream_t);
-template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, float*,
-                                             hipStream_t);
+template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, int*, int,
+                                             int*, hipStream_t);
 
 }  // namespace dpvba
