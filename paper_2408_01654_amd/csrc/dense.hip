@@ -72,8 +72,8 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
 // <= j of the block; after one barrier every thread subtracts c_i c_k from
 // all of its entries, which is a no-op wherever it must not act.
 template <typename T>
-__global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, int kb_in, T* Linv, const T* d0,
-                                                         int* status, unsigned int* min_bits) {
+__device__ __forceinline__ void diag_factor(T* S, int n, int k0, int kb_in, T* Linv, const T* d0, int* status,
+                                            unsigned int* min_bits) {
   constexpr int RB = 8, CB = 4;  // 128 rows, 64 columns
   constexpr int R = 16 * RB;
   __shared__ T colb[2][R];
@@ -165,6 +165,12 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, in
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, int kb, T* Linv, const T* d0,
+                                                         int* status, unsigned int* min_bits) {
+  diag_factor<T>(S, n, k0, kb, Linv, d0, status, min_bits);
+}
+
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
 // block per workgroup, on the matrix cores.
 template <typename T>
@@ -197,7 +203,8 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int k0, in
 // Trailing update A_IJ -= L_Ik L_Jk^T for 64x64 blocks I >= J of the trailing
 // matrix, on the matrix cores; blockIdx.x enumerates the lower block pairs.
 template <typename T>
-__global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, int kb) {
+__global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0,
+                                                          int* status, unsigned int* min_bits) {
   __shared__ T Li[kNB][kNB + 1];
   __shared__ T Lj[kNB][kNB + 1];
   const int t0 = k0 + kb;
@@ -227,6 +234,13 @@ __global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, i
       const int r = 16 * w + Mfma<T>::row(lane, v), c = 16 * t + (lane & 15);
       if (r < ri && c < rj && (I != J || c <= r)) S[(size_t)(i0 + r) * n + j0 + c] -= acc[t][v];
     }
+  // workgroup 0 holds the next diagonal block, now final: factor it while the
+  // other workgroups finish the trailing update (look-ahead of one panel)
+  if (blk == 0 && Linv_next) {
+    __threadfence_block();
+    __syncthreads();
+    diag_factor<T>(S, n, t0, ri, Linv_next, d0, status, min_bits);
+  }
 }
 
 // Both triangular solves of a blocked factor in one cooperative launch.
@@ -364,17 +378,17 @@ template <typename T>
 hipError_t launch_chol_factor(T* S, int n, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
                               hipStream_t st) {
   const int nblk = (n + kNB - 1) / kNB;
-  for (int k = 0; k < nblk; ++k) {
+  if (nblk == 0) return hipSuccess;
+  hipLaunchKernelGGL((potrf_diag_kernel<T>), dim3(1), dim3(256), 0, st, S, n, 0, min(kNB, n), Linv_all, d0, status,
+                     min_bits);
+  for (int k = 0; k + 1 < nblk; ++k) {
     const int k0 = k * kNB, kb = min(kNB, n - k0);
     T* Linv = Linv_all + (size_t)k * kNB * kNB;
-    hipLaunchKernelGGL((potrf_diag_kernel<T>), dim3(1), dim3(256), 0, st, S, n, k0, kb, Linv, d0, status,
-                       min_bits);
     const int rest = nblk - k - 1;
-    if (rest > 0) {
-      hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(rest), dim3(256), 0, st, S, n, k0, kb, Linv);
-      hipLaunchKernelGGL((syrk_update_kernel<T>), dim3(rest * (rest + 1) / 2), dim3(256), 0, st, S, n, k0,
-                         kb);
-    }
+    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(rest), dim3(256), 0, st, S, n, k0, kb, Linv);
+    // the trailing update also factors diagonal block k + 1 (its workgroup 0)
+    hipLaunchKernelGGL((syrk_update_kernel<T>), dim3(rest * (rest + 1) / 2), dim3(256), 0, st, S, n, k0, kb,
+                       Linv + kNB * kNB, d0, status, min_bits);
   }
   return hipGetLastError();
 }
