@@ -425,10 +425,10 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
   if (n == 0) return hipSuccess;
   if (n <= small_solve_max_n(sizeof(T))) {
     {
-      hipError_t e = opt_in_lds((const void*)small_chol_solve_kernel<T>, small_solve_lds_bytes(n, sizeof(T)));
+      hipError_t e = opt_in_lds((const void*)small_chol_solve_kernel<T>, packed_solve_lds_bytes(n, sizeof(T)));
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((small_chol_solve_kernel<T>), dim3(1), dim3(256), small_solve_lds_bytes(n, sizeof(T)),
+    hipLaunchKernelGGL((small_chol_solve_kernel<T>), dim3(1), dim3(256), packed_solve_lds_bytes(n, sizeof(T)),
                        st, S, rhs, n, dx, status, min_bits);
     return hipGetLastError();
   }

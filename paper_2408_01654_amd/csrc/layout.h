@@ -106,8 +106,8 @@ struct BatchInst {
 };
 
 // Largest system (n + 1 <= kSmallRows) handled by the single-launch solver,
-// whose workgroup 0 factors it as a packed triangle in LDS; larger systems
-// take the blocked multi-launch path.
+// whose workgroup 0 factors it in registers (panel_chol_solve); larger
+// systems take the separate dense solve.
 constexpr int kSmallRows = 96;
 
 // Row capacity 16 MB of the register-blocked dense solve of n unknowns
@@ -117,15 +117,18 @@ __host__ __device__ inline int small_solve_rows(int n) {
   return n1 <= 32 ? 32 : (n1 <= 64 ? 64 : (n1 <= 80 ? 80 : 96));
 }
 
-// Shared memory of the one-workgroup dense solve: for the register-blocked
-// solver two column buffers, the reciprocal and damped diagonals, the
-// factor's rows (NR x NR) and the step; for the packed solver the packed
-// triangle and two vectors.
+// Shared memory of the one-workgroup dense solve (register-blocked panels):
+// two published panels (2 x NR x 17), the reciprocal and damped diagonals,
+// the factor's rows (NR x NR) and the step.
 __host__ __device__ inline int small_solve_lds_bytes(int n, int tsize) {
   const int nr = small_solve_rows(n);
-  const int blocked = (5 * nr + nr * nr) * tsize;
-  const int packed = (n * (n + 1) / 2 + 2 * n) * tsize;
-  return blocked > packed ? blocked : packed;
+  return (37 * nr + nr * nr) * tsize;
+}
+
+// Shared memory of the one-workgroup packed solve (small_chol_solve_kernel):
+// the packed lower triangle, the right-hand side and the step.
+__host__ __device__ inline int packed_solve_lds_bytes(int n, int tsize) {
+  return (n * (n + 1) / 2 + 2 * n) * tsize;
 }
 
 }  // namespace dpvba

@@ -354,4 +354,167 @@ __device__ __forceinline__ void block_chol_solve(int n_in, const T* Sp_g, const 
   __syncthreads();
 }
 
+
+// Cholesky of the augmented matrix [[S, .], [s^T, .]] (n + 1 <= 16 MB rows)
+// in panels of 16 columns, by a 256-thread workgroup with the matrix in
+// registers: thread (ty, tx) = (tid mod 16, tid / 16) holds entries
+// (16 bi + ty, 16 bk + tx), bi, bk < MB (the panel loop is unrolled, so every
+// register index is a compile-time constant).  Panel p: the threads publish
+// its column block in LDS; one wavefront factors the 16 columns on its own
+// (rows on lanes, pivots and column entries broadcast by v_readlane, no
+// barrier inside); after one barrier every thread takes back its factored
+// entries and applies the rank-16 update to its blocks right of and below
+// the panel.  Two barriers per panel instead of one per column.  The last
+// row ends as y = L^-1 s; then L^T x = y on one wavefront.  Returns the step
+// in x[0..n) (LDS; zero if a pivot was not positive).
+template <typename T, int MB>
+__device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const T* rhs_g, const T* d0_g,
+                                                 unsigned char* lds, T* x, int* bad_out, float* minr_out) {
+  constexpr int NR = 16 * MB;
+  const int n = __builtin_amdgcn_readfirstlane(n_in);
+  const int tid = threadIdx.x;
+  const int ty = tid & 15, tx = tid >> 4;
+  const int lane = tid & 63, wave = tid >> 6;
+  T* PB = reinterpret_cast<T*>(lds);  // [2][NR][17] published panel
+  T* invd = PB + 2 * NR * 17;         // [NR]
+  T* dd = invd + NR;                  // [NR]
+  T* Lrow = dd + NR;                  // [NR][NR]
+  for (int i = tid; i < n; i += blockDim.x) dd[i] = d0_g[i];
+  T a[MB][MB];
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+    for (int bk = 0; bk < MB; ++bk) {
+      const int i = 16 * bi + ty, k = 16 * bk + tx;
+      T v = (T)0;
+      if (k <= i && i < n) v = Sp_g[i * (i + 1) / 2 + k];
+      else if (i == n && k < n) v = rhs_g[k];
+      a[bi][bk] = v;
+    }
+  int bad = 0;
+  float minr = 3.0e38f;
+#pragma unroll
+  for (int p = 0; p < MB; ++p) {
+    if (16 * p >= n) continue;  // uniform: no pivot left
+    T* P = PB + (p & 1) * NR * 17;
+    // publish the panel's column block (rows >= 16 p)
+#pragma unroll
+    for (int bi = p; bi < MB; ++bi) P[(16 * bi + ty) * 17 + tx] = a[bi][p];
+    __syncthreads();
+    if (wave == (p & 3)) {
+      // lane l holds rows 16 p + l and 16 p + l + 64 of the panel
+      const int rA = 16 * p + lane, rB = rA + 64;
+      T ra[16], rb[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        ra[c] = rA < NR ? P[rA * 17 + c] : (T)0;
+        rb[c] = rB < NR ? P[rB * 17 + c] : (T)0;
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int j = 16 * p + c;
+        if (j >= n) continue;  // uniform
+        T d;
+        if constexpr (sizeof(T) == 4) {
+          d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ra[c]), c));
+        } else {
+          const long long bits = __double_as_longlong(ra[c]);
+          const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), c);
+          const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), c);
+          d = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        }
+        const float ratio = (float)(d / dd[j]);
+        if (!(ratio >= minr)) minr = ratio == ratio ? fmaxf(ratio, 0.f) : 0.f;
+        if (!(d > (T)0) || !(d < (T)3.0e38)) {
+          bad = 1;
+          d = (T)1;
+        }
+        const T rs = (T)1 / dsqrt(d);
+        if (lane == 0) invd[j] = rs;
+        ra[c] *= rs;  // row j's own entry becomes L_jj = sqrt(d)
+        rb[c] *= rs;
+#pragma unroll
+        for (int c2 = c + 1; c2 < 16; ++c2) {
+          T lk;  // l_{16p + c2, j}: lane c2's entry of column c
+          if constexpr (sizeof(T) == 4) {
+            lk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ra[c]), c2));
+          } else {
+            const long long bits = __double_as_longlong(ra[c]);
+            const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), c2);
+            const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), c2);
+            lk = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+          }
+          ra[c2] -= ra[c] * lk;
+          rb[c2] -= rb[c] * lk;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        if (rA < NR) P[rA * 17 + c] = ra[c];
+        if (rB < NR) P[rB * 17 + c] = rb[c];
+      }
+    }
+    __syncthreads();
+    // factored entries back, then the rank-16 update right of and below the panel
+#pragma unroll
+    for (int bi = p; bi < MB; ++bi) a[bi][p] = P[(16 * bi + ty) * 17 + tx];
+#pragma unroll
+    for (int bi = p + 1; bi < MB; ++bi) {
+      T li[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) li[c] = P[(16 * bi + ty) * 17 + c];
+#pragma unroll
+      for (int bk = p + 1; bk <= bi; ++bk) {
+        T acc = (T)0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc += li[c] * P[(16 * bk + tx) * 17 + c];
+        a[bi][bk] -= acc;
+      }
+    }
+  }
+  // rows of L (and y in row n) to LDS
+#pragma unroll
+  for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+    for (int bk = 0; bk < MB; ++bk) Lrow[(16 * bi + ty) * NR + 16 * bk + tx] = a[bi][bk];
+  __shared__ int bad_s;
+  __shared__ unsigned int minr_s;
+  if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }
+  __syncthreads();
+  if (bad) atomicOr(&bad_s, 1);
+  if (minr < 3.0e38f) atomicMin(&minr_s, __float_as_uint(minr));
+  if (tid < 64) {  // backward substitution L^T x = y; lane l holds entries l, l + 64
+    const int r0 = tid, r1 = tid + 64;
+    T y0 = r0 < n ? Lrow[n * NR + r0] : (T)0;
+    T y1 = r1 < n ? Lrow[n * NR + r1] : (T)0;
+    for (int i = n - 1; i >= 0; --i) {
+      const T yv = i >= 64 ? y1 : y0;
+      T yi;
+      if constexpr (sizeof(T) == 4) {
+        yi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), i & 63));
+      } else {
+        const long long bits = __double_as_longlong(yv);
+        const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), i & 63);
+        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), i & 63);
+        yi = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+      }
+      const T xi = yi * invd[i];
+      const T* Li = Lrow + i * NR;
+      if (r0 < i) y0 -= Li[r0] * xi;
+      if (r1 < i) y1 -= Li[r1] * xi;
+      if (r0 == i) y0 = xi;
+      if (r1 == i) y1 = xi;
+    }
+    if (r0 < n) x[r0] = y0;
+    if (r1 < n) x[r1] = y1;
+  }
+  __syncthreads();
+  if (tid < n && bad_s) x[tid] = (T)0;
+  if (tid == 0) {
+    *bad_out = bad_s;
+    *minr_out = __uint_as_float(minr_s);
+  }
+  __syncthreads();
+}
+
 }  // namespace dpvba

@@ -427,11 +427,9 @@ __device__ void gather_slice(const IterArgs<T>& A, T* Sp, T* rhs, T* d0, int wav
 }
 
 // Factor and solve the gathered system in workgroup 0 and retract the free
-// poses.  float32 systems of up to 79 unknowns: block_chol_solve (matrix in
-// registers, one barrier per column).  Otherwise the packed lower triangle
-// is factored in LDS (packed_cholesky, one barrier per column) and solved on
-// one wavefront.  A non-positive pivot discards the step (dxi = 0,
-// *A.status = 1).
+// poses (panel_chol_solve: matrix in registers, 16-column panels factored by
+// one wavefront, two barriers per panel; n + 1 <= 96).  A non-positive
+// pivot discards the step (dxi = 0, *A.status = 1).
 template <typename T>
 __device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const T* Sp_g, const T* rhs_g,
                                                      const T* d0_g, unsigned char* lds) {
@@ -440,29 +438,11 @@ __device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const
   __shared__ int bad;
   __shared__ float minr;
   const int nr = small_solve_rows(n);
-  T* x;
-  if (sizeof(T) == 4 && nr <= 80) {
-    x = reinterpret_cast<T*>(lds) + 4 * nr + nr * nr;  // after the solver's own arrays
-    if (nr == 32) block_chol_solve<T, 2>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
-    else if (nr == 64) block_chol_solve<T, 4>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
-    else block_chol_solve<T, 5>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
-  } else {
-    const int np = n * (n + 1) / 2;
-    T* Ap = reinterpret_cast<T*>(lds);  // packed lower factor
-    x = Ap + np;                        // [n] right-hand side, then the step
-    T* dd = x + n;                      // [n] damped diagonal
-    for (int q = tid; q < np; q += blockDim.x) Ap[q] = Sp_g[q];
-    for (int i = tid; i < n; i += blockDim.x) {
-      x[i] = rhs_g[i];
-      dd[i] = d0_g[i];
-    }
-    __syncthreads();
-    packed_cholesky<T>(Ap, n, dd, &bad, &minr);
-    packed_solve<T, T>(Ap, x, n);
-    for (int i = tid; i < n; i += blockDim.x)
-      if (bad) x[i] = (T)0;
-    __syncthreads();
-  }
+  T* x = reinterpret_cast<T*>(lds) + 36 * nr + nr * nr;  // after the solver's own arrays
+  if (nr == 32) panel_chol_solve<T, 2>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
+  else if (nr == 64) panel_chol_solve<T, 4>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
+  else if (nr == 80) panel_chol_solve<T, 5>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
+  else panel_chol_solve<T, 6>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
   for (int i = tid; i < n; i += blockDim.x) A.dx[i] = x[i];
   for (int i = tid; i < A.n_frames; i += blockDim.x) {
     const T* pc = A.poses_cur + 7 * (size_t)i;
