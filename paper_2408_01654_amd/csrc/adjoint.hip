@@ -173,13 +173,13 @@ template <typename T>
 __global__ void __launch_bounds__(256) tile_adjoint_rhs_kernel(const TileInfo* tiles, const T* U_s,
                                                                const T* pscale_s, const T* dbar, T* part_vec) {
   const TileInfo ti = tiles[blockIdx.x];
-  const int W6 = 6 * ti.n_blk;
+  const int W6 = 6 * ti.n_blk, Ws = tile_u_stride(ti.n_blk);
   const T* U = U_s + ti.u_begin;
   for (int x = threadIdx.x; x < W6; x += blockDim.x) {
     T v = (T)0;
     for (int k = 0; k < ti.n_patch; ++k) {
       const int q = ti.patch_begin + k;
-      v += U[(size_t)k * W6 + x] * (pscale_s[2 * q] * dbar[q]);
+      v += U[(size_t)k * Ws + x] * (pscale_s[2 * q] * dbar[q]);
     }
     part_vec[ti.vec_begin + x] = -v;
   }
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(256) tile_adjoint_backsub_kernel(
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* sU = reinterpret_cast<T*>(lds_raw);
   const TileInfo ti = tiles[blockIdx.x];
-  const int W6 = 6 * ti.n_blk;
+  const int W6 = 6 * ti.n_blk, Ws = tile_u_stride(ti.n_blk);
   T* sX = sU + W6;
   for (int x = threadIdx.x; x < W6; x += blockDim.x) {
     const int f = blk_pose[ti.blk_begin + x / 6];
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) tile_adjoint_backsub_kernel(
     const T is = pscale_s[2 * q], rs = pscale_s[2 * q + 1];
     T du = (T)0, dx = (T)0;
     for (int x = 0; x < W6; ++x) {
-      const T uk = U[(size_t)k * W6 + x];
+      const T uk = U[(size_t)k * Ws + x];
       du += uk * sU[x];
       dx += uk * sX[x];
     }

@@ -188,7 +188,7 @@ hipError_t upload(DevBuf& b, const std::vector<X>& v, hipStream_t st) {
 // Device copy of one tiling of the patch graph.
 struct Tiling {
   int n_tiles = 0, lds_bytes = 0, max_w6 = 0;
-  long long part_S = 0, part_vec = 0, u_elems = 0, grid_cells = 0, n_tp = 0;
+  long long part_S = 0, part_vec = 0, u_elems = 0, u_alloc = 0, grid_cells = 0, n_tp = 0;
   DevBuf tiles, tile_patch, slot_frame, slot_blk, edge_grid, blk_pose, s_off, s_src, v_off, v_src;
   DevBuf* bufs[10] = {&tiles, &tile_patch, &slot_frame, &slot_blk, &edge_grid, &blk_pose, &s_off, &s_src, &v_off,
                       &v_src};
@@ -412,7 +412,9 @@ struct HostTiling {
   std::vector<TileInfo> tiles;
   std::vector<int32_t> tile_patch, slot_frame, slot_blk, edge_grid, blk_pose, s_off, s_src, v_off;
   std::vector<int2> v_src;
-  long long part_S = 0, part_vec = 0, u_elems = 0;
+  long long part_S = 0, part_vec = 0;
+  long long u_elems = 0;  // entries of the stored Schur rows (K 6 n_blk per tile)
+  long long u_alloc = 0;  // their padded storage (tile_u_rows x tile_u_stride per tile)
   int lds = 0, max_w6 = 0;
 };
 
@@ -513,10 +515,11 @@ static bool plan_tiling(int N, int nf, const std::vector<int32_t>& jj, const std
     }
     t.part_begin = (int)H.part_S;
     t.vec_begin = (int)H.part_vec;
-    t.u_begin = (int)H.u_elems;
+    t.u_begin = (int)H.u_alloc;
     H.part_S += (long long)t.n_blk * (t.n_blk + 1) / 2 * 36;
     H.part_vec += 12LL * t.n_blk;
     H.u_elems += (long long)t.n_patch * 6 * t.n_blk;
+    H.u_alloc += (long long)tile_u_rows(t.n_patch) * tile_u_stride(t.n_blk);
     H.lds = std::max(H.lds, tile_lds_bytes(t.n_patch, Tn, t.n_blk, tsize));
     H.max_w6 = std::max(H.max_w6, 6 * t.n_blk);
     H.tiles.push_back(t);
@@ -547,7 +550,7 @@ static bool plan_tiling(int N, int nf, const std::vector<int32_t>& jj, const std
     }
     if (!cur.empty()) emit(f, cur, cur_mult);
   }
-  if (H.part_S > INT32_MAX || H.part_vec > INT32_MAX || H.u_elems > INT32_MAX) return false;
+  if (H.part_S > INT32_MAX || H.part_vec > INT32_MAX || H.u_alloc > INT32_MAX) return false;
   // gather lists: lower block (P >= Q) -> tile partial offsets, in tile order
   const long long n_lb = (long long)n_free * (n_free + 1) / 2;
   H.s_off.assign(n_lb + 1, 0);
@@ -597,6 +600,7 @@ static hipError_t upload_tiling(Tiling& T_, const HostTiling& H, hipStream_t st)
   T_.part_S = H.part_S;
   T_.part_vec = H.part_vec;
   T_.u_elems = H.u_elems;
+  T_.u_alloc = H.u_alloc;
   T_.grid_cells = (long long)H.edge_grid.size();
   T_.n_tp = (long long)H.tile_patch.size();
   return hipSuccess;
@@ -662,7 +666,7 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(ensure(c->part_vec, std::max(H32.part_vec * 4, H64.part_vec * 8)));
   HIP_TRY(ensure(c->part_cost, mx(H32.tiles.size(), H64.tiles.size()) * 8));
   HIP_TRY(ensure(c->part_invalid, mx(H32.tiles.size(), H64.tiles.size()) * 4));
-  HIP_TRY(ensure(c->U_s, std::max(H32.u_elems * 4, H64.u_elems * 8)));
+  HIP_TRY(ensure(c->U_s, std::max(H32.u_alloc * 4, H64.u_alloc * 8)));
   HIP_TRY(ensure(c->pscale_s, (size_t)P * 2 * 8));
   HIP_TRY(ensure(c->depth_s, (size_t)P * 8));
   HIP_TRY(ensure(c->xh_s, (size_t)P * 2 * 8));
@@ -1068,10 +1072,10 @@ static bool append_tiling(HostTiling& H, const HostTiling& Hb, int b, int frame_
   I.v_base = (int)H.v_off.size();
   const long long tp0 = (long long)H.tile_patch.size(), sl0 = (long long)H.slot_frame.size();
   const long long g0 = (long long)H.edge_grid.size(), bp0 = (long long)H.blk_pose.size();
-  const long long ps0 = H.part_S, pv0 = H.part_vec, u0 = H.u_elems;
+  const long long ps0 = H.part_S, pv0 = H.part_vec, u0 = H.u_alloc;
   const long long ss0 = (long long)H.s_src.size(), vs0 = (long long)H.v_src.size();
   if (g0 + (long long)Hb.edge_grid.size() > INT32_MAX || ps0 + Hb.part_S > INT32_MAX ||
-      pv0 + Hb.part_vec > INT32_MAX || u0 + Hb.u_elems > INT32_MAX)
+      pv0 + Hb.part_vec > INT32_MAX || u0 + Hb.u_alloc > INT32_MAX)
     return false;
   for (TileInfo t : Hb.tiles) {
     t.frame += frame_begin;
@@ -1097,6 +1101,7 @@ static bool append_tiling(HostTiling& H, const HostTiling& Hb, int b, int frame_
   H.part_S += Hb.part_S;
   H.part_vec += Hb.part_vec;
   H.u_elems += Hb.u_elems;
+  H.u_alloc += Hb.u_alloc;
   H.lds = std::max(H.lds, Hb.lds);
   H.max_w6 = std::max(H.max_w6, Hb.max_w6);
   return true;
@@ -1499,7 +1504,7 @@ dpvba_status dpvba_analyze_batch(dpvba_ctx* c, const dpvba_batch* b, const int32
   HIP_TRY(ensure(c->part_vec, std::max(H[0].part_vec * 4, H[1].part_vec * 8)));
   HIP_TRY(ensure(c->part_cost, std::max(H[0].tiles.size(), H[1].tiles.size()) * 8));
   HIP_TRY(ensure(c->part_invalid, std::max(H[0].tiles.size(), H[1].tiles.size()) * 4));
-  HIP_TRY(ensure(c->U_s, std::max(H[0].u_elems * 4, H[1].u_elems * 8)));
+  HIP_TRY(ensure(c->U_s, std::max(H[0].u_alloc * 4, H[1].u_alloc * 8)));
   HIP_TRY(ensure(c->pscale_s, (size_t)P * 2 * 8));
   HIP_TRY(ensure(c->depth_s, (size_t)P * 8));
   HIP_TRY(ensure(c->xh_s, (size_t)P * 2 * 8));

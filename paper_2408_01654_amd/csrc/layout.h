@@ -16,7 +16,12 @@
 namespace dpvba {
 
 constexpr int kMaxSlots = 64;     // slots per tile (one wavefront)
-constexpr int kTileThreads = 256;
+constexpr int kTileThreads = 256;      // single-launch solver (its dense factor assumes four wavefronts)
+constexpr int kTileThreadsWide = 512;  // float32 tile launches of the multi-launch path
+
+// Workgroup size of the multi-launch tile kernel for a compute type of
+// tsize bytes (float64 keeps 256: its per-thread partials would not fit).
+__host__ __device__ constexpr int tile_threads(int tsize) { return tsize == 4 ? kTileThreadsWide : kTileThreads; }
 constexpr int kRedWidth = 28;     // per-slot partial: 21 (M upper) + 6 (v) + 1 (cost)
 
 struct TileInfo {
@@ -32,7 +37,7 @@ struct TileInfo {
   int32_t blk_begin;   // into blk_pose[]
   int32_t part_begin;  // element offset of the partial block pairs (36 each)
   int32_t vec_begin;   // element offset of the partial vectors (rhs then diag, 6 * n_blk each)
-  int32_t u_begin;     // element offset of the stored Schur rows (n_patch * 6 n_blk)
+  int32_t u_begin;     // element offset of the stored Schur rows (tile_u_rows x tile_u_stride)
   int32_t inst;        // problem of a batch the tile belongs to (0 for one problem)
   int32_t pad[2];
 };
@@ -46,47 +51,63 @@ __host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 
 // Shared-memory plan of the tile kernel.  Compute-type (T) arrays: slot
 // relative poses, patch rays, per-patch sums, per-slot sums, and the
-// Schur-row matrix U
-// (K_pad x W_pad, rows = patches, columns = 6 n_blk block columns plus one
-// column for w / sqrt(C~), padded for 16x16x4 matrix-core tiles), which
-// first holds the per-thread partial sums.  Then a byte region of per-cell
-// records (target, weight) that each lane overwrites with its edge's
-// results, later reused for per-slot source blocks.  Then byte tables.
+// Schur-row matrix U (K_pad x W_pad, rows = patches, columns = 6 n_blk
+// block columns plus one column for w / sqrt(C~), padded for 16x16x4
+// matrix-core tiles; rows 16-byte aligned), which first holds the
+// per-thread partial sums.  Then a byte region of per-cell records (target,
+// weight) that each lane overwrites with its edge's results, later reused
+// for per-slot source blocks and their sums (and in phase 0 for the block
+// step).  Then the block -> slot range tables.
 struct TileLds {
   int slot, patch, psum, m, u, total_T;     // T offsets
   int K_pad, W_pad;
   int cell_bytes, rec_bytes;                // per cell, region
-  int pair_a, pair_b, blk_s0, blk_s1, slot_blk, tables;  // byte offsets in the table region
+  int blk_s0, blk_s1, tables;               // byte offsets in the table region
 };
 
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-__host__ __device__ inline TileLds tile_lds_plan(int K, int Tn, int nb, int tsize) {
+// Row stride of a tile's Schur-row matrix; the stored rows of a tile are
+// the same K_pad x W_pad matrix (padding included), so they move as
+// contiguous 16-byte vectors.
+__host__ __device__ inline int tile_u_stride(int nb) { return round_up(6 * nb + 1, 16); }
+__host__ __device__ inline int tile_u_rows(int K) { return round_up(K, 4); }
+
+// Per-slot source blocks (Ad^T M, Ad^T M Ad, Ad^T v: 80 entries with
+// padding) and, after them, their sums over the slots (36 + 6 + 6).
+constexpr int kSlotBlk = 80;
+constexpr int kSrcSums = 48;
+
+// Entries of the B-term table of phase 3 after those sums: per block its
+// diagonal block (36) and its source-row block (36), then the right-hand
+// side and Diag(B) terms of each row (2 x 6 n_blk), then one zero.
+__host__ __device__ inline int tile_bterm_entries(int nb) { return 72 * nb + 12 * nb + 1; }
+
+// nthreads: the workgroup size (the per-thread partial sums of phase 1
+// share the U region).  Host plans use tile_threads(tsize), never fewer
+// than the single-launch solver's, so one allocation fits both kernels.
+__host__ __device__ inline TileLds tile_lds_plan(int K, int Tn, int nb, int tsize, int nthreads) {
   TileLds L;
-  const int npairs = nb * (nb + 1) / 2;
-  L.K_pad = round_up(K, 4);
-  L.W_pad = round_up(6 * nb + 1, 16);
+  L.K_pad = tile_u_rows(K);
+  L.W_pad = tile_u_stride(nb);
   L.slot = 0;
   L.patch = L.slot + Tn * 18;
   L.psum = L.patch + K * 4;
   L.m = L.psum + K * 8;
-  L.u = L.m + Tn * kRedWidth;
-  L.total_T = L.u + imax(L.K_pad * L.W_pad, kTileThreads * kRedWidth);
+  L.u = round_up(L.m + Tn * kRedWidth, 4);
+  L.total_T = L.u + imax(L.K_pad * L.W_pad, nthreads * kRedWidth);
   L.cell_bytes = imax(16, 8 * tsize);
-  L.rec_bytes = imax(K * Tn * L.cell_bytes, imax(Tn * 80, 6 * nb) * tsize);
-  L.pair_a = 0;
-  L.pair_b = L.pair_a + npairs;
-  L.blk_s0 = L.pair_b + npairs;
+  L.rec_bytes = imax(K * Tn * L.cell_bytes, imax(Tn * kSlotBlk + kSrcSums + tile_bterm_entries(nb), L.W_pad) * tsize);
+  L.blk_s0 = 0;
   L.blk_s1 = L.blk_s0 + nb;
-  L.slot_blk = L.blk_s1 + nb;
-  L.tables = L.slot_blk + Tn;
+  L.tables = L.blk_s1 + nb;
   return L;
 }
 
 __host__ __device__ inline int align16(int b) { return (b + 15) / 16 * 16; }
 
 __host__ __device__ inline int tile_lds_bytes(int K, int Tn, int nb, int tsize) {
-  TileLds L = tile_lds_plan(K, Tn, nb, tsize);
+  TileLds L = tile_lds_plan(K, Tn, nb, tsize, tile_threads(tsize));
   return align16(L.total_T * tsize) + align16(L.rec_bytes) + align16(L.tables);
 }
 

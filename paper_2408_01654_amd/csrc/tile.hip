@@ -27,47 +27,129 @@
 
 namespace dpvba {
 
-// Phases 0-3 for one tile; the caller synchronises before reusing `lds`.
+// 16-byte vector of the compute type.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+// dots[k * ds] = [u_k | w_k / sqrt(C~_k)] . sX for the K stored Schur rows
+// of one tile (row stride Ws, a multiple of 16).  With sX = [dxi | 1 | 0...]
+// the depth step is dd_k = -dots[k] / sqrt(C~_k).  A wavefront takes eight
+// rows at a time, lanes along the rows with 16-byte loads (all eight in
+// flight), and sums the eight rows over its lanes together; sX lives in LDS.
 template <typename T>
+__device__ void schur_row_dots(const T* U, int K, int Ws, const T* sX, T* dots, int ds) {
+  typedef typename Vec16<T>::type vec_t;
+  constexpr int V = 16 / (int)sizeof(T);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int nv = Ws / V;
+  for (int k0 = 8 * wv; k0 < K; k0 += 8 * nwv) {
+    T part[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) part[u] = (T)0;
+    for (int c = lane; c < nv; c += 64) {
+      vec_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (k0 + u < K) x[u] = reinterpret_cast<const vec_t*>(U + (size_t)(k0 + u) * Ws)[c];
+        else x[u] = vec_t{};
+      }
+      const vec_t y = reinterpret_cast<const vec_t*>(sX)[c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int e = 0; e < V; ++e) part[u] += x[u][e] * y[e];
+    }
+    // halving butterfly: after it lane l holds the total of row
+    // 4 b5 + 2 b4 + b3 (b = bits of l)
+    T h4[4], h2[2];
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T give = b5 ? part[j] : part[4 + j];
+      h4[j] = (b5 ? part[4 + j] : part[j]) + __shfl_xor(give, 32);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const T give = b4 ? h4[j] : h4[2 + j];
+      h2[j] = (b4 ? h4[2 + j] : h4[j]) + __shfl_xor(give, 16);
+    }
+    T h = (b3 ? h2[1] : h2[0]) + __shfl_xor(b3 ? h2[0] : h2[1], 8);
+    h += __shfl_xor(h, 4);
+    h += __shfl_xor(h, 2);
+    h += __shfl_xor(h, 1);
+    const int row = k0 + 4 * (b5 ? 1 : 0) + 2 * (b4 ? 1 : 0) + (b3 ? 1 : 0);
+    if ((lane & 7) == 0 && row < K) dots[(size_t)row * ds] = h;
+  }
+}
+
+// NT 16x16 tiles of U^T U that share the row tile: acc[t] = sum over the
+// rows k of U[k][ua-tile]^T U[k][ub-tile + t] (16x16x4 steps, rows in
+// groups of four).
+template <typename T, int NT>
+__device__ __forceinline__ void utu_unit(const T* ua, const T* ub, int nk, int Wp,
+                                         typename Mfma<T>::acc_t* acc) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  // operands of step kq + 1 are loaded before the products of step kq
+  T fa = ua[0], fb[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) fb[t] = ub[16 * t];
+  for (int kq = 0; kq < nk; ++kq) {
+    const int kn = min(kq + 1, nk - 1);  // the last step reloads its own operands
+    const T na = ua[kn * 4 * Wp];
+    T nb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) nb[t] = ub[kn * 4 * Wp + 16 * t];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::step(fa, fb[t], acc[t]);
+    fa = na;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) fb[t] = nb[t];
+  }
+}
+
+// Phases 0-3 for one tile; the caller synchronises before reusing `lds`.
+// NT: the workgroup size.
+template <typename T, int NT>
 __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds) {
   const TileInfo ti = A.tiles[tile];
   const int tid = threadIdx.x;
   const int K = ti.n_patch, Tn = ti.n_slot, nb = ti.n_blk, W6 = 6 * nb;
-  const TileLds L = tile_lds_plan(K, Tn, nb, (int)sizeof(T));
+  const TileLds L = tile_lds_plan(K, Tn, nb, (int)sizeof(T), NT);
   const int Kp = L.K_pad, Wp = L.W_pad;
   T* base = reinterpret_cast<T*>(lds);
   T* sSlot = base + L.slot;   // [Tn][18]: R_ji (9), t_ji (3)
   T* sPatch = base + L.patch; // [K][4]: x^0, x^1, d, w / sqrt(C~)
-  T* sPs = base + L.psum;     // [K][8]: C (then 1 / sqrt(C~)), w, -sum_j Ad^T E_j
+  T* sPs = base + L.psum;     // [K][8]: C (then 1 / sqrt(C~)), w, -sum_j Ad^T E_j (phase 0: row dots)
   T* sM = base + L.m;         // [Tn][28]
   T* sU = base + L.u;         // [Kp][Wp]; first the per-thread partial sums
   T* sWork = sU;
   unsigned char* rec = lds + align16(L.total_T * (int)sizeof(T));
   const int cellT = L.cell_bytes / (int)sizeof(T);
   T* sCell = reinterpret_cast<T*>(rec);  // [K*Tn][cellT]
-  T* sB = reinterpret_cast<T*>(rec);     // later: [Tn][80]
-  T* sDx = reinterpret_cast<T*>(rec);    // phase 0: [W6]
+  T* sB = reinterpret_cast<T*>(rec);     // phase 2c: [Tn][kSlotBlk], then kSrcSums sums
+  T* sDx = reinterpret_cast<T*>(rec);    // phase 0: [Wp] block step
   unsigned char* tab = rec + align16(L.rec_bytes);
-  unsigned char* sPairA = tab + L.pair_a;
-  unsigned char* sPairB = tab + L.pair_b;
-  unsigned char* sBlkS0 = tab + L.blk_s0;
-  unsigned char* sBlkS1 = tab + L.blk_s1;
-  signed char* sSlotBlk = reinterpret_cast<signed char*>(tab + L.slot_blk);
+  unsigned char* sBlkS0 = tab + L.blk_s0;  // first slot of each block (its slots are consecutive)
+  unsigned char* sBlkS1 = tab + L.blk_s1;  // one past its last slot
   __shared__ int sInvalid;
 
-  // ---- phase 0: index tables, slot relative poses, previous depth step, records
-  if (tid == 0) sInvalid = 0;
-  for (int a = tid; a < nb; a += blockDim.x) {
-    for (int b = a; b < nb; ++b) {
-      const int q = upper_pair_index(a, b, nb);
-      sPairA[q] = (unsigned char)a;
-      sPairB[q] = (unsigned char)b;
+  // ---- phase 0: block -> slot ranges, slot relative poses, previous depth step
+  if (tid == 0) {
+    sInvalid = 0;
+    if (ti.src_blk >= 0) {  // the source pose is never a slot
+      sBlkS0[ti.src_blk] = 0;
+      sBlkS1[ti.src_blk] = 0;
     }
-    sBlkS0[a] = 255;
-    sBlkS1[a] = 0;
   }
+  const int* slot_blk = A.slot_blk + ti.slot_begin;
   for (int s = tid; s < Tn; s += blockDim.x) {
-    sSlotBlk[s] = (signed char)A.slot_blk[ti.slot_begin + s];
+    const int b = slot_blk[s];
+    if (b >= 0) {  // slots follow the frame order, so a block's slots are consecutive
+      if (s == 0 || slot_blk[s - 1] != b) sBlkS0[b] = (unsigned char)s;
+      if (s == Tn - 1 || slot_blk[s + 1] != b) sBlkS1[b] = (unsigned char)(s + 1);
+    }
     const int j = A.slot_frame[ti.slot_begin + s];
     T Ri[9], tiv[3], Rj[9], tj[3];
     const T* pi = A.poses_cur + 7 * (size_t)ti.frame;
@@ -79,23 +161,9 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
   }
   const bool apply_prev =
       !A.first && A.dx_prev && !(A.status_prev && A.status_prev[ti.inst * A.status_stride]);
-  if (apply_prev) {
-    for (int x = tid; x < W6; x += blockDim.x) sDx[x] = A.dx_prev[6 * A.blk_pose[ti.blk_begin + x / 6] + x % 6];
-    const T* src_u = A.U_s + ti.u_begin;
-    for (int x = tid; x < K * W6; x += blockDim.x) sU[(x / W6) * Wp + x % W6] = src_u[x];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int s = 0; s < Tn; ++s) {
-      const int b = sSlotBlk[s];
-      if (b < 0) continue;
-      if (sBlkS0[b] == 255) sBlkS0[b] = (unsigned char)s;
-      sBlkS1[b] = (unsigned char)(s + 1);
-    }
-  }
   const int pb = ti.patch_begin;
   for (int k = tid; k < K; k += blockDim.x) {
-    T x0, x1, d;
+    T x0, x1, d, is = (T)0;
     if (A.first) {
       const int pk = A.tile_patch[pb + k];
       const int c = (A.p - 1) / 2;
@@ -109,17 +177,28 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
       x0 = A.xh_s[2 * (pb + k)];
       x1 = A.xh_s[2 * (pb + k) + 1];
       d = A.depth_s[pb + k];
-      if (apply_prev) {
-        const T* u = sU + k * Wp;
-        T dot = (T)0;
-        for (int x = 0; x < W6; ++x) dot += u[x] * sDx[x];
-        d -= (A.pscale_s[2 * (pb + k) + 1] + dot) * A.pscale_s[2 * (pb + k)];
-      }
+      if (apply_prev) is = A.pscale_s[2 * (pb + k)];
     }
-    if (A.first || apply_prev) A.depth_s[pb + k] = d;
     sPatch[4 * k] = x0;
     sPatch[4 * k + 1] = x1;
     sPatch[4 * k + 2] = d;
+    sPatch[4 * k + 3] = is;
+  }
+  if (apply_prev)  // [dxi of the tile's blocks | 1 | 0 ...]
+    for (int x = tid; x < Wp; x += blockDim.x)
+      sDx[x] = x < W6 ? A.dx_prev[6 * A.blk_pose[ti.blk_begin + x / 6] + x % 6] : (x == W6 ? (T)1 : (T)0);
+  __syncthreads();
+  if (apply_prev) {
+    schur_row_dots<T>(A.U_s + ti.u_begin, K, Wp, sDx, sPs, 8);
+    __syncthreads();
+  }
+  for (int k = tid; k < K; k += blockDim.x) {
+    T d = sPatch[4 * k + 2];
+    if (apply_prev) {
+      d -= sPs[8 * k] * sPatch[4 * k + 3];
+      sPatch[4 * k + 2] = d;
+    }
+    if (A.first || apply_prev) A.depth_s[pb + k] = d;
     sPatch[4 * k + 3] = (T)0;
   }
   __syncthreads();
@@ -131,11 +210,11 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
     const int* grid = A.edge_grid + ti.grid_begin;
     const float2* tgt = reinterpret_cast<const float2*>(A.target);
     const float2* wgt = reinterpret_cast<const float2*>(A.weight);
-    for (int c0 = tid; c0 < ncell; c0 += 8 * kTileThreads) {
+    for (int c0 = tid; c0 < ncell; c0 += 8 * NT) {
       int e[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int c = c0 + u * kTileThreads;
+        const int c = c0 + u * NT;
         e[u] = c < ncell ? grid[c] : -1;
       }
       float2 tg[8], wt[8];
@@ -146,7 +225,7 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int c = c0 + u * kTileThreads;
+        const int c = c0 + u * NT;
         if (c < ncell)
           *reinterpret_cast<float4*>(rec + (size_t)c * L.cell_bytes) = make_float4(tg[u].x, tg[u].y, wt[u].x, wt[u].y);
       }
@@ -155,7 +234,7 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
   __syncthreads();
 
   // ---- phase 1: edges.  Thread (g, s) takes slot s of patches g, g + G, ...
-  const int G = kTileThreads / Tn;
+  const int G = NT / Tn;
   const int g = tid / Tn, s = tid - (tid / Tn) * Tn;
   T acc[kRedWidth];
 #pragma unroll
@@ -210,31 +289,45 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
   __syncthreads();
 
   // ---- phase 2b: Schur rows u_k = E_k / sqrt(C~_k), appended w_k / sqrt(C~_k).
-  // (i) thread k sums (C, w, -sum_j Ad(T_ji)^T E_j) of patch k over its slots
-  //     in slot order (the slot poses are read by every lane at once);
-  //     (ii) thread (k, x) writes row entry x.
+  // (i) two threads per patch k sum (C, w, -sum_j Ad(T_ji)^T E_j) over its
+  //     slots in slot order, one the rotation part (with C and w), the other
+  //     the translation part; (ii) C~, 1 / sqrt(C~) and w / sqrt(C~).
   const int src = ti.src_blk;
-  for (int k = tid; k < K; k += blockDim.x) {
-    T v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int idx = tid; idx < 2 * K; idx += blockDim.x) {
+    const int k = idx >> 1;
+    const bool tpart = idx & 1;  // 0: C, w and the rotation part; 1: the translation part
+    T v[5] = {0, 0, 0, 0, 0};
     for (int ss = 0; ss < Tn; ++ss) {
       const T* cell = sCell + (size_t)(k * Tn + ss) * cellT;
-      T c[8];
-#pragma unroll
-      for (int m = 0; m < 8; ++m) c[m] = cell[m];
       const T* R = sSlot + 18 * ss;
       const T* tt = R + 9;
-      v[0] += c[6];
-      v[1] += c[7];
+      T c[8];
+      if (!tpart) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) v[2 + q] -= R[q] * c[0] + R[3 + q] * c[1] + R[6 + q] * c[2];
-      const T b0 = c[3] - (tt[1] * c[2] - tt[2] * c[1]);
-      const T b1 = c[4] - (tt[2] * c[0] - tt[0] * c[2]);
-      const T b2 = c[5] - (tt[0] * c[1] - tt[1] * c[0]);
+        for (int m = 0; m < 3; ++m) c[m] = cell[m];
+        c[6] = cell[6];
+        c[7] = cell[7];
+        v[0] += c[6];
+        v[1] += c[7];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) v[5 + q] -= R[q] * b0 + R[3 + q] * b1 + R[6 + q] * b2;
+        for (int q = 0; q < 3; ++q) v[2 + q] -= R[q] * c[0] + R[3 + q] * c[1] + R[6 + q] * c[2];
+      } else {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) c[m] = cell[m];
+        const T b0 = c[3] - (tt[1] * c[2] - tt[2] * c[1]);
+        const T b1 = c[4] - (tt[2] * c[0] - tt[0] * c[2]);
+        const T b2 = c[5] - (tt[0] * c[1] - tt[1] * c[0]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] -= R[q] * b0 + R[3 + q] * b1 + R[6 + q] * b2;
+      }
     }
+    if (!tpart) {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) sPs[8 * k + m] = v[m];
+      for (int m = 0; m < 5; ++m) sPs[8 * k + m] = v[m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) sPs[8 * k + 5 + m] = v[m];
+    }
   }
   __syncthreads();
   for (int k = tid; k < K; k += blockDim.x) {
@@ -247,99 +340,177 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
     A.pscale_s[2 * (pb + k) + 1] = rs;
   }
   __syncthreads();
-  for (int idx = tid; idx < Kp * Wp; idx += blockDim.x) {
-    const int k = idx / Wp, x = idx - (idx / Wp) * Wp;
-    T v = (T)0;
-    if (k < K && x <= W6) {
-      const T rs = sPatch[4 * k + 3];
-      if (x == W6) {
-        v = rs;
+  // (iii) row k, block column b (6 entries; b == nb: the appended column
+  //       and the padding), zero rows beyond K
+  const int nbx = nb + 1;
+  for (int idx = tid; idx < Kp * nbx; idx += blockDim.x) {
+    const int k = idx / nbx, b = idx - k * nbx;
+    T* urow = sU + k * Wp;
+    if (b == nb) {
+      const T rs = k < K ? sPatch[4 * k + 3] : (T)0;
+      for (int x = W6; x < Wp; ++x) urow[x] = x == W6 ? rs : (T)0;
+      continue;
+    }
+    T v[6] = {0, 0, 0, 0, 0, 0};
+    if (k < K) {
+      const T is = sPs[8 * k];
+      if (b == src) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) v[m] = sPs[8 * k + 2 + m] * is;
       } else {
-        const int b = x / 6, m = x - (x / 6) * 6;
-        const T is = sPs[8 * k];
-        if (b == src) {
-          v = sPs[8 * k + 2 + m] * is;
-        } else {
-          for (int ss = sBlkS0[b]; ss < sBlkS1[b]; ++ss) v += sCell[(size_t)(k * Tn + ss) * cellT + m];
-          v *= is;
+        for (int ss = sBlkS0[b]; ss < sBlkS1[b]; ++ss) {
+          const T* cell = sCell + (size_t)(k * Tn + ss) * cellT;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) v[m] += cell[m];
         }
+#pragma unroll
+        for (int m = 0; m < 6; ++m) v[m] *= is;
       }
     }
-    sU[idx] = v;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) urow[6 * b + m] = v[m];
   }
   __syncthreads();
 
-  // ---- phase 2c: stored rows; per-slot source blocks Ad^T M, Ad^T M Ad, Ad^T v
-  for (int x = tid; x < K * W6; x += blockDim.x) A.U_s[ti.u_begin + x] = sU[(x / W6) * Wp + x % W6];
-  for (int ss = tid; ss < Tn; ss += blockDim.x) {
+  // ---- phase 2c: stored rows (the padded matrix as 16-byte vectors); per-slot
+  // source blocks Ad^T M, Ad^T M Ad and Ad^T v, then their sums over the
+  // slots in slot order
+  {
+    typedef typename Vec16<T>::type vec_t;
+    const int nvec = Kp * Wp * (int)sizeof(T) / 16;
+    const vec_t* from = reinterpret_cast<const vec_t*>(sU);
+    vec_t* to = reinterpret_cast<vec_t*>(A.U_s + ti.u_begin);
+    for (int x = tid; x < nvec; x += blockDim.x) to[x] = from[x];
+  }
+  for (int idx = tid; idx < Tn * 7; idx += blockDim.x) {  // column c of Ad^T M (c = 6: Ad^T v)
+    const int ss = idx / 7, c = idx - ss * 7;
     const T* R = sSlot + 18 * ss;
     const T* t = R + 9;
     const T* M21 = sM + ss * kRedWidth;
-    T* out = sB + 80 * ss;
-    T col[6], res[6];
-    for (int c = 0; c < 6; ++c) {
+    T* out = sB + kSlotBlk * ss;
+    if (c == 6) {
+      adjoint_transpose_apply<T>(R, t, M21 + 21, out + 72);
+    } else {
+      T col[6], res[6];
+#pragma unroll
       for (int r = 0; r < 6; ++r) col[r] = sym6<T>(M21, r, c);
       adjoint_transpose_apply<T>(R, t, col, res);
+#pragma unroll
       for (int r = 0; r < 6; ++r) out[r * 6 + c] = res[r];
     }
-    for (int r = 0; r < 6; ++r) {
-      for (int c = 0; c < 6; ++c) col[c] = out[r * 6 + c];
-      adjoint_transpose_apply<T>(R, t, col, res);
-      for (int c = 0; c < 6; ++c) out[36 + r * 6 + c] = res[c];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < Tn * 6; idx += blockDim.x) {  // row r of (Ad^T M) Ad
+    const int ss = idx / 6, r = idx - ss * 6;
+    const T* R = sSlot + 18 * ss;
+    const T* t = R + 9;
+    T* out = sB + kSlotBlk * ss;
+    T col[6], res[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) col[c] = out[r * 6 + c];
+    adjoint_transpose_apply<T>(R, t, col, res);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out[36 + r * 6 + c] = res[c];
+  }
+  __syncthreads();
+  T* sSrc = sB + kSlotBlk * Tn;  // sum of Ad^T M Ad (36), of Ad^T v (6), Diag of Ad^T M Ad (6)
+  for (int i = tid; i < kSrcSums; i += blockDim.x) {
+    const int off = i < 36 ? 36 + i : (i < 42 ? 72 + (i - 36) : 36 + 7 * (i - 42));
+    T v = (T)0;
+    for (int ss = 0; ss < Tn; ++ss) v += sB[kSlotBlk * ss + off];
+    sSrc[i] = v;
+  }
+  __syncthreads();
+  // B-term table: what phase 3 adds to -U^T U.  Diagonal block of a (the
+  // source: sum of Ad^T M Ad; a target: sum of its slots' M), source-row
+  // block (src, b) = -sum of b's slots' Ad^T M, then per row x the
+  // right-hand-side term (-v_x; the source: +sum Ad^T v) and Diag(B)_x.
+  T* sBt = sSrc + kSrcSums;
+  T* sDg = sBt;             // [nb][36]
+  T* sSr = sBt + 36 * nb;   // [nb][36]
+  T* sRv = sBt + 72 * nb;   // [6 nb]
+  T* sDv = sRv + W6;        // [6 nb]
+  T* sZero = sDv + W6;      // one zero (pairs without a B term)
+  for (int i = tid; i < 72 * nb + 1; i += blockDim.x) {
+    if (i == 72 * nb) {
+      *sZero = (T)0;
+      continue;
     }
-    adjoint_transpose_apply<T>(R, t, M21 + 21, out + 72);
+    const int blk = i / 36, rc = i - blk * 36, which = blk / nb, a = blk - which * nb;
+    const int r = rc / 6, c = rc - r * 6;
+    T v = (T)0;
+    if (which == 0) {
+      if (a == src) v = sSrc[rc];
+      else
+        for (int ss = sBlkS0[a]; ss < sBlkS1[a]; ++ss) v += sym6<T>(sM + ss * kRedWidth, r, c);
+    } else if (a != src) {
+      for (int ss = sBlkS0[a]; ss < sBlkS1[a]; ++ss) v -= sB[kSlotBlk * ss + rc];
+    }
+    sBt[i] = v;
+  }
+  for (int x = tid; x < W6; x += blockDim.x) {
+    const int a = x / 6, r = x - a * 6;
+    T rv = (T)0, dv = (T)0;
+    if (a == src) {
+      rv = sSrc[36 + r];
+      dv = sSrc[42 + r];
+    } else {
+      for (int ss = sBlkS0[a]; ss < sBlkS1[a]; ++ss) {
+        rv -= sM[ss * kRedWidth + 21 + r];
+        dv += sM[ss * kRedWidth + tri_index(r, r)];
+      }
+    }
+    sRv[x] = rv;
+    sDv[x] = dv;
   }
   __syncthreads();
 
-  // ---- phase 3: U^T U on the matrix cores, plus B; upper entries only
+  // ---- phase 3: U^T U on the matrix cores, plus B; upper entries only.
+  // A work unit is row tile ta against up to four column tiles tb0 ..: the
+  // row operand is loaded once per step and the four accumulators are
+  // independent, so the loads of one step overlap the products of another.
   T* outS = A.part_S + ti.part_begin;
   T* outV = A.part_vec + ti.vec_begin;
   const int T16 = Wp / 16;
-  const int lane = tid & 63, wv = tid >> 6;
-  for (int tp = wv; tp < T16 * (T16 + 1) / 2; tp += kTileThreads / 64) {
-    int ta = 0, rem = tp;
-    while (rem >= T16 - ta) { rem -= T16 - ta; ++ta; }
-    const int tb = ta + rem;
-    typename Mfma<T>::acc_t accv = {0, 0, 0, 0};
+  const int nk = Kp / 4;
+  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar unit loop
+  for (int unit = wv;; unit += NT / 64) {
+    int ta = 0, rem = unit;
+    while (ta < T16 && rem >= (T16 - ta + 3) / 4) {
+      rem -= (T16 - ta + 3) / 4;
+      ++ta;
+    }
+    if (ta >= T16) break;
+    const int tb0 = ta + 4 * rem, nt = min(4, T16 - tb0);
+    typename Mfma<T>::acc_t acc[4];
     const T* ua = sU + (lane >> 4) * Wp + ta * 16 + (lane & 15);
-    const T* ub = sU + (lane >> 4) * Wp + tb * 16 + (lane & 15);
-    for (int k0 = 0; k0 < Kp; k0 += 4) accv = Mfma<T>::step(ua[k0 * Wp], ub[k0 * Wp], accv);
+    const T* ub = sU + (lane >> 4) * Wp + tb0 * 16 + (lane & 15);
+    switch (nt) {
+      case 1: utu_unit<T, 1>(ua, ub, nk, Wp, acc); break;
+      case 2: utu_unit<T, 2>(ua, ub, nk, Wp, acc); break;
+      case 3: utu_unit<T, 3>(ua, ub, nk, Wp, acc); break;
+      default: utu_unit<T, 4>(ua, ub, nk, Wp, acc); break;
+    }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = ta * 16 + Mfma<T>::row(lane, v), col = tb * 16 + (lane & 15);
-      if (row > col || row >= W6 || col > W6) continue;
-      const int a = row / 6, r = row % 6;
-      if (col == W6) {  // right-hand side and Diag(B) of row `row`
-        T vb = (T)0, db = (T)0;
-        if (a == src) {
-          for (int ss = 0; ss < Tn; ++ss) {
-            vb -= sB[80 * ss + 72 + r];
-            db += sB[80 * ss + 36 + r * 7];
-          }
-        } else {
-          for (int ss = sBlkS0[a]; ss < sBlkS1[a]; ++ss) {
-            vb += sM[ss * kRedWidth + 21 + r];
-            db += sM[ss * kRedWidth + tri_index(r, r)];
-          }
+    for (int t = 0; t < 4; ++t) {
+      if (t >= nt) continue;
+      const int tb = tb0 + t;
+      const typename Mfma<T>::acc_t accv = acc[t];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ta * 16 + Mfma<T>::row(lane, v), col = tb * 16 + (lane & 15);
+        if (row > col || row >= W6 || col > W6) continue;
+        const int a = row / 6, r = row - a * 6;
+        if (col == W6) {  // right-hand side and Diag(B) of row `row`
+          outV[row] = accv[v] + sRv[row];
+          outV[W6 + row] = sDv[row];
+          continue;
         }
-        outV[row] = accv[v] - vb;
-        outV[W6 + row] = db;
-        continue;
+        const int b = col / 6, c = col - b * 6, rc = r * 6 + c;
+        const T* term = a == b ? sDg + 36 * a + rc
+                               : (a == src ? sSr + 36 * b + rc : (b == src ? sSr + 36 * a + c * 6 + r : sZero));
+        outS[upper_pair_index(a, b, nb) * 36 + rc] = *term - accv[v];
       }
-      const int b = col / 6, c = col % 6, rc = r * 6 + c;
-      T val = -accv[v];
-      if (a == b) {
-        if (a == src) {
-          for (int ss = 0; ss < Tn; ++ss) val += sB[80 * ss + 36 + rc];
-        } else {
-          for (int ss = sBlkS0[a]; ss < sBlkS1[a]; ++ss) val += sym6<T>(sM + ss * kRedWidth, r, c);
-        }
-      } else if (a == src) {
-        for (int ss = sBlkS0[b]; ss < sBlkS1[b]; ++ss) val -= sB[80 * ss + rc];
-      } else if (b == src) {
-        for (int ss = sBlkS0[a]; ss < sBlkS1[a]; ++ss) val -= sB[80 * ss + c * 6 + r];
-      }
-      outS[upper_pair_index(a, b, nb) * 36 + rc] = val;
     }
   }
   __syncthreads();
@@ -352,9 +523,9 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads) tile_iterate_kernel(IterArgs<T> A) {
+__global__ void __launch_bounds__(tile_threads(sizeof(T))) tile_iterate_kernel(IterArgs<T> A) {
   extern __shared__ __align__(16) unsigned char lds[];
-  tile_assemble<T>(A, blockIdx.x, lds);
+  tile_assemble<T, tile_threads(sizeof(T))>(A, blockIdx.x, lds);
 }
 
 // Damped reduced system of a small problem (packed lower triangle, row i at
@@ -502,27 +673,25 @@ __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, int* err) {
 
 // Depth write-back of one tile after the last iteration: apply its step
 // dd_k = -(w_k / sqrt(C~_k) + u_k . dxi) / sqrt(C~_k) and scatter to the
-// caller's array.
+// caller's array.  lds holds tile_u_stride(n_blk) + n_patch entries.
 template <typename T>
 __device__ void tile_writeback(const TileInfo& ti, const int* tile_patch, const int* blk_pose, const T* U_s,
                                const T* pscale_s, const T* depth_s, const T* dx, bool apply, T* depth_out,
-                               T* sDx) {
-  const int W6 = 6 * ti.n_blk;
-  T* sU = sDx + W6;  // the tile's Schur rows, copied once
+                               T* lds) {
+  const int W6 = 6 * ti.n_blk, Ws = tile_u_stride(ti.n_blk);
+  T* sX = lds;
+  T* sDot = lds + Ws;
   if (apply) {
-    for (int x = threadIdx.x; x < W6; x += blockDim.x) sDx[x] = dx[6 * blk_pose[ti.blk_begin + x / 6] + x % 6];
-    for (int x = threadIdx.x; x < ti.n_patch * W6; x += blockDim.x) sU[x] = U_s[ti.u_begin + x];
+    for (int x = threadIdx.x; x < Ws; x += blockDim.x)
+      sX[x] = x < W6 ? dx[6 * blk_pose[ti.blk_begin + x / 6] + x % 6] : (x == W6 ? (T)1 : (T)0);
+    __syncthreads();
+    schur_row_dots<T>(U_s + ti.u_begin, ti.n_patch, Ws, sX, sDot, 1);
   }
   __syncthreads();
   const int pb = ti.patch_begin;
   for (int k = threadIdx.x; k < ti.n_patch; k += blockDim.x) {
     T d = depth_s[pb + k];
-    if (apply) {
-      const T* u = sU + k * W6;
-      T dot = (T)0;
-      for (int xx = 0; xx < W6; ++xx) dot += u[xx] * sDx[xx];
-      d -= (pscale_s[2 * (pb + k) + 1] + dot) * pscale_s[2 * (pb + k)];
-    }
+    if (apply) d -= sDot[k] * pscale_s[2 * (pb + k)];
     depth_out[tile_patch[pb + k]] = d;
   }
   __syncthreads();
@@ -552,7 +721,7 @@ small_solve_kernel(SmallArgs<T> S) {
     A.cost_out = S.cost ? S.cost + t : nullptr;
     A.invalid_out = S.invalid ? S.invalid + t : nullptr;
     for (int tile = blockIdx.x; tile < A.n_tiles; tile += nb) {
-      tile_assemble<T>(A, tile, lds);
+      tile_assemble<T, kTileThreads>(A, tile, lds);
       __syncthreads();
     }
     if (!grid_sync(S.bar, nb, S.err)) return;
@@ -608,7 +777,7 @@ hipError_t launch_tile_iterate(const IterArgs<T>& A, int lds_bytes, hipStream_t 
   if (A.n_tiles == 0) return hipSuccess;
   hipError_t e = opt_in_lds((const void*)tile_iterate_kernel<T>, lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((tile_iterate_kernel<T>), dim3(A.n_tiles), dim3(kTileThreads), lds_bytes, st, A);
+  hipLaunchKernelGGL((tile_iterate_kernel<T>), dim3(A.n_tiles), dim3(tile_threads(sizeof(T))), lds_bytes, st, A);
   return hipGetLastError();
 }
 
