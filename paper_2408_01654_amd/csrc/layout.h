@@ -139,11 +139,11 @@ __host__ __device__ inline int small_solve_rows(int n) {
 }
 
 // Shared memory of the one-workgroup dense solve (register-blocked panels):
-// two published panels (2 x NR x 17), the reciprocal and damped diagonals,
-// the factor's rows (NR x NR) and the step.
+// two published panels (2 x NR x 17), the reciprocal diagonal, the damped
+// diagonal, the pivots, the factor's rows (NR x NR) and the step.
 __host__ __device__ inline int small_solve_lds_bytes(int n, int tsize) {
   const int nr = small_solve_rows(n);
-  return (37 * nr + nr * nr) * tsize;
+  return (38 * nr + nr * nr) * tsize;
 }
 
 // Shared memory of the one-workgroup packed solve (small_chol_solve_kernel):

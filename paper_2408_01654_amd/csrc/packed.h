@@ -8,6 +8,16 @@
 
 namespace dpvba {
 
+// 1 / sqrt(d) of a positive pivot: the hardware reciprocal square root for
+// float32 (within about one unit in the last place, far inside the float32
+// path's tolerance; it keeps the per-column dependency chain short); the
+// correctly rounded form for float64.
+template <typename T>
+__device__ __forceinline__ T pivot_rsqrt(T d) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rsqf(d);
+  else return (T)1 / sqrt(d);
+}
+
 __device__ __forceinline__ int packed_index(int i, int j) { return i * (i + 1) / 2 + j; }
 
 // In-place A = L L^T, right-looking with the column scaling deferred: step j
@@ -376,9 +386,10 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
   const int ty = tid & 15, tx = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
   T* PB = reinterpret_cast<T*>(lds);  // [2][NR][17] published panel
-  T* invd = PB + 2 * NR * 17;         // [NR]
-  T* dd = invd + NR;                  // [NR]
-  T* Lrow = dd + NR;                  // [NR][NR]
+  T* invd = PB + 2 * NR * 17;         // [NR] 1 / L_jj
+  T* dd = invd + NR;                  // [NR] damped diagonal (pivot report)
+  T* piv = dd + NR;                   // [NR] pivots before the square root
+  T* Lrow = piv + NR;                 // [NR][NR]
   for (int i = tid; i < n; i += blockDim.x) dd[i] = d0_g[i];
   T a[MB][MB];
 #pragma unroll
@@ -392,7 +403,6 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
       a[bi][bk] = v;
     }
   int bad = 0;
-  float minr = 3.0e38f;
 #pragma unroll
   for (int p = 0; p < MB; ++p) {
     if (16 * p >= n) continue;  // uniform: no pivot left
@@ -423,13 +433,12 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
           const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), c);
           d = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
         }
-        const float ratio = (float)(d / dd[j]);
-        if (!(ratio >= minr)) minr = ratio == ratio ? fmaxf(ratio, 0.f) : 0.f;
+        if (lane == 0) piv[j] = d;
         if (!(d > (T)0) || !(d < (T)3.0e38)) {
           bad = 1;
           d = (T)1;
         }
-        const T rs = (T)1 / dsqrt(d);
+        const T rs = pivot_rsqrt<T>(d);
         if (lane == 0) invd[j] = rs;
         ra[c] *= rs;  // row j's own entry becomes L_jj = sqrt(d)
         rb[c] *= rs;
@@ -482,28 +491,44 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
   if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }
   __syncthreads();
   if (bad) atomicOr(&bad_s, 1);
-  if (minr < 3.0e38f) atomicMin(&minr_s, __float_as_uint(minr));
+  if (tid < n) {  // pivot report: smallest pivot / damped diagonal
+    const float ratio = (float)(piv[tid] / dd[tid]);
+    atomicMin(&minr_s, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
+  }
   if (tid < 64) {  // backward substitution L^T x = y; lane l holds entries l, l + 64
     const int r0 = tid, r1 = tid + 64;
     T y0 = r0 < n ? Lrow[n * NR + r0] : (T)0;
     T y1 = r1 < n ? Lrow[n * NR + r1] : (T)0;
-    for (int i = n - 1; i >= 0; --i) {
-      const T yv = i >= 64 ? y1 : y0;
-      T yi;
-      if constexpr (sizeof(T) == 4) {
-        yi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), i & 63));
-      } else {
-        const long long bits = __double_as_longlong(yv);
-        const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), i & 63);
-        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), i & 63);
-        yi = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    for (int i0 = n - 1; i0 >= 0; i0 -= 16) {
+      // sixteen rows' entries first: the chain below only waits on y
+      T l0[16], l1[16], iv[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int i = max(i0 - c, 0);
+        l0[c] = Lrow[i * NR + r0];
+        l1[c] = r1 < NR ? Lrow[i * NR + r1] : (T)0;
+        iv[c] = invd[i];
       }
-      const T xi = yi * invd[i];
-      const T* Li = Lrow + i * NR;
-      if (r0 < i) y0 -= Li[r0] * xi;
-      if (r1 < i) y1 -= Li[r1] * xi;
-      if (r0 == i) y0 = xi;
-      if (r1 == i) y1 = xi;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int i = i0 - c;
+        if (i < 0) continue;  // uniform
+        const T yv = i >= 64 ? y1 : y0;
+        T yi;
+        if constexpr (sizeof(T) == 4) {
+          yi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), i & 63));
+        } else {
+          const long long bits = __double_as_longlong(yv);
+          const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), i & 63);
+          const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), i & 63);
+          yi = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        }
+        const T xi = yi * iv[c];
+        if (r0 < i) y0 -= l0[c] * xi;
+        if (r1 < i) y1 -= l1[c] * xi;
+        if (r0 == i) y0 = xi;
+        if (r1 == i) y1 = xi;
+      }
     }
     if (r0 < n) x[r0] = y0;
     if (r1 < n) x[r1] = y1;

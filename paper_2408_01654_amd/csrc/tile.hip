@@ -496,20 +496,41 @@ __device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds
       if (t >= nt) continue;
       const int tb = tb0 + t;
       const typename Mfma<T>::acc_t accv = acc[t];
+      // addresses of the four values' B terms first (no branches), so the
+      // LDS reads issue together
+      const T* t1[4];
+      const T* t2[4];
+      bool ok[4], rhs[4];
+      int dst[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = ta * 16 + Mfma<T>::row(lane, v), col = tb * 16 + (lane & 15);
-        if (row > col || row >= W6 || col > W6) continue;
-        const int a = row / 6, r = row - a * 6;
-        if (col == W6) {  // right-hand side and Diag(B) of row `row`
-          outV[row] = accv[v] + sRv[row];
-          outV[W6 + row] = sDv[row];
-          continue;
-        }
-        const int b = col / 6, c = col - b * 6, rc = r * 6 + c;
+        ok[v] = row <= col && row < W6 && col <= W6;
+        rhs[v] = col == W6;  // right-hand side and Diag(B) of row `row`
+        const int a = min(row, W6 - 1) / 6, r = min(row, W6 - 1) - 6 * (min(row, W6 - 1) / 6);
+        const int b = min(col, W6 - 1) / 6, c = min(col, W6 - 1) - 6 * (min(col, W6 - 1) / 6);
+        const int rc = r * 6 + c;
         const T* term = a == b ? sDg + 36 * a + rc
                                : (a == src ? sSr + 36 * b + rc : (b == src ? sSr + 36 * a + c * 6 + r : sZero));
-        outS[upper_pair_index(a, b, nb) * 36 + rc] = *term - accv[v];
+        t1[v] = !ok[v] ? sZero : (rhs[v] ? sRv + row : term);
+        t2[v] = ok[v] && rhs[v] ? sDv + row : sZero;
+        dst[v] = rhs[v] ? row : upper_pair_index(a, b, nb) * 36 + rc;
+      }
+      T x1[4], x2[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        x1[v] = *t1[v];
+        x2[v] = *t2[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (!ok[v]) continue;
+        if (rhs[v]) {
+          outV[dst[v]] = accv[v] + x1[v];
+          outV[W6 + dst[v]] = x2[v];
+        } else {
+          outS[dst[v]] = x1[v] - accv[v];
+        }
       }
     }
   }
@@ -609,7 +630,7 @@ __device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const
   __shared__ int bad;
   __shared__ float minr;
   const int nr = small_solve_rows(n);
-  T* x = reinterpret_cast<T*>(lds) + 36 * nr + nr * nr;  // after the solver's own arrays
+  T* x = reinterpret_cast<T*>(lds) + 37 * nr + nr * nr;  // after the solver's own arrays
   if (nr == 32) panel_chol_solve<T, 2>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
   else if (nr == 64) panel_chol_solve<T, 4>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
   else if (nr == 80) panel_chol_solve<T, 5>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
