@@ -23,6 +23,32 @@ namespace dpvba {
 
 constexpr int kNB = 64;
 
+// Two consecutive entries of the compute type (rows of S start on an even
+// element, since n = 6 n_free, so the pair loads are aligned).
+template <typename T> struct Pair2 { typedef T type __attribute__((ext_vector_type(2))); };
+
+// rows x cols (<= 64 x 64, cols even) block at src (row stride ld) into
+// dst[64][65], zero outside: each thread issues its eight pair loads before
+// any store, so the block arrives in one memory round trip.
+template <typename T>
+__device__ __forceinline__ void load_block64(const T* src, size_t ld, int rows, int cols, T (*dst)[kNB + 1]) {
+  typedef typename Pair2<T>::type T2;
+  constexpr int PER = kNB * kNB / 2 / 256;
+  const int tid = threadIdx.x;
+  T2 v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u, r = q / (kNB / 2), c = 2 * (q % (kNB / 2));
+    v[u] = (r < rows && c < cols) ? *reinterpret_cast<const T2*>(src + (size_t)r * ld + c) : T2{0, 0};
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u, r = q / (kNB / 2), c = 2 * (q % (kNB / 2));
+    dst[r][c] = v[u].x;
+    dst[r][c + 1] = v[u].y;
+  }
+}
+
 __device__ __forceinline__ void pivot_min(unsigned int* min_bits, float ratio) {
   if (!(ratio >= 0.f)) ratio = 0.f;
   atomicMin(min_bits, __float_as_uint(ratio));
@@ -64,25 +90,27 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
 // The block is factored together with an identity appended below it: the
 // Cholesky factor of [[A, I], [I, .]] has L^-T in its lower-left block, so
 // one elimination gives both L and its inverse.  The 128 x 64 working matrix
-// lives in registers on a 16 x 16 thread grid (entry (i, k) on the thread
-// with i = ty, k = tx mod 16; every register index is a compile-time
-// constant because the column loop is unrolled).  Column j: its 16 owners
-// (one wavefront) take the pivot by v_readlane, scale their entries and
-// publish the column in a double-buffered LDS vector with zeros at the rows
-// <= j of the block; after one barrier every thread subtracts c_i c_k from
-// all of its entries, which is a no-op wherever it must not act.
+// lives in registers on a 16 x 16 thread grid (entry (16 bi + ty, 16 bk + tx)
+// on thread (ty, tx) = (tid mod 16, tid / 16); the panel loop is unrolled, so
+// every register index is a compile-time constant).  Columns go in panels
+// of 16: the threads publish the panel's column block in LDS (P0 / P1, 128 x
+// 17 each, alternating); one wavefront factors its 16 columns alone (rows on
+// lanes, pivots and column entries broadcast by v_readlane); after one
+// barrier every thread takes back its factored entries and applies the
+// rank-16 update to its blocks right of and below the panel.  Entries above
+// the diagonal of the A part are never read as results.
 template <typename T>
 __device__ __forceinline__ void diag_factor(T* S, int n, int k0, int kb_in, T* Linv, const T* d0, int* status,
-                                            unsigned int* min_bits) {
+                                            unsigned int* min_bits, T* P0, T* P1) {
   constexpr int RB = 8, CB = 4;  // 128 rows, 64 columns
-  constexpr int R = 16 * RB;
-  __shared__ T colb[2][R];
+  __shared__ T piv[kNB];
   __shared__ T dd[kNB];
   __shared__ int bad_s;
   __shared__ unsigned int minr_s;
   const int kb = __builtin_amdgcn_readfirstlane(kb_in);
   const int tid = threadIdx.x;
   const int ty = tid & 15, tx = tid >> 4;
+  const int lane = tid & 63, wave = tid >> 6;
   if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }
   if (tid < kb) dd[tid] = d0[k0 + tid];
   T a[RB][CB];
@@ -99,50 +127,81 @@ __device__ __forceinline__ void diag_factor(T* S, int n, int k0, int kb_in, T* L
       }
       a[bi][bk] = v;
     }
-  __syncthreads();
   int bad = 0;
-  float minr = 3.0e38f;
 #pragma unroll
-  for (int j = 0; j < kNB; ++j) {
-    if (j >= kb) continue;  // uniform
-    const int bj = j >> 4, jm = j & 15;
-    T* cb = colb[j & 1];
-    if (tx == jm) {
-      T d;
-      const int src = (16 * jm + jm) & 63;
-      if constexpr (sizeof(T) == 4) {
-        d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[bj][bj]), src));
-      } else {
-        const long long bits = __double_as_longlong(a[bj][bj]);
-        const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), src);
-        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
-        d = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-      }
-      if (ty == jm) {
-        const float ratio = (float)(d / dd[j]);
-        if (!(ratio >= minr)) minr = ratio == ratio ? fmaxf(ratio, 0.f) : 0.f;
-        if (!(d > (T)0) || !(d < (T)3.0e38)) bad = 1;
-      }
-      if (!(d > (T)0) || !(d < (T)3.0e38)) d = (T)1;
-      const T rs = (T)1 / dsqrt(d);
+  for (int p = 0; p < CB; ++p) {
+    if (16 * p >= kb) continue;  // uniform
+    T* P = (p & 1) ? P1 : P0;
 #pragma unroll
-      for (int bi = 0; bi < RB; ++bi) {
-        const int i = 16 * bi + ty;
-        const T l = a[bi][bj] * rs;
-        if (i >= j) a[bi][bj] = l;
-        cb[i] = i > j ? l : (T)0;
+    for (int bi = p; bi < RB; ++bi) P[(16 * bi + ty) * 17 + tx] = a[bi][p];
+    __syncthreads();
+    if (wave == (p & 3)) {
+      // lane l holds rows 16 p + l and 16 p + l + 64 of the panel
+      const int rA = 16 * p + lane, rB = rA + 64;
+      T ra[16], rb[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        ra[c] = P[rA * 17 + c];
+        rb[c] = rB < 16 * RB ? P[rB * 17 + c] : (T)0;
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int j = 16 * p + c;
+        if (j >= kb) continue;  // uniform
+        T d;
+        if constexpr (sizeof(T) == 4) {
+          d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ra[c]), c));
+        } else {
+          const long long bits = __double_as_longlong(ra[c]);
+          const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), c);
+          const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), c);
+          d = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        }
+        if (lane == 0) piv[j] = d;
+        if (!(d > (T)0) || !(d < (T)3.0e38)) {
+          bad = 1;
+          d = (T)1;
+        }
+        const T rs = pivot_rsqrt<T>(d);
+        ra[c] *= rs;
+        rb[c] *= rs;
+#pragma unroll
+        for (int c2 = c + 1; c2 < 16; ++c2) {
+          T lk;  // entry (16 p + c2, j): lane c2's entry of column c
+          if constexpr (sizeof(T) == 4) {
+            lk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ra[c]), c2));
+          } else {
+            const long long bits = __double_as_longlong(ra[c]);
+            const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), c2);
+            const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), c2);
+            lk = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+          }
+          ra[c2] -= ra[c] * lk;
+          rb[c2] -= rb[c] * lk;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        P[rA * 17 + c] = ra[c];
+        if (rB < 16 * RB) P[rB * 17 + c] = rb[c];
       }
     }
     __syncthreads();
-    T ci[RB], ck[CB];
 #pragma unroll
-    for (int b = 0; b < RB; ++b) ci[b] = cb[16 * b + ty];
+    for (int bi = p; bi < RB; ++bi) a[bi][p] = P[(16 * bi + ty) * 17 + tx];
 #pragma unroll
-    for (int b = 0; b < CB; ++b) ck[b] = cb[16 * b + tx];
+    for (int bk = p + 1; bk < CB; ++bk) {
+      T lk[16];
 #pragma unroll
-    for (int bi = 0; bi < RB; ++bi)
+      for (int c = 0; c < 16; ++c) lk[c] = P[(16 * bk + tx) * 17 + c];
 #pragma unroll
-      for (int bk = 0; bk < CB; ++bk) a[bi][bk] -= ci[bi] * ck[bk];
+      for (int bi = bk; bi < RB; ++bi) {
+        T acc = (T)0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc += P[(16 * bi + ty) * 17 + c] * lk[c];
+        a[bi][bk] -= acc;
+      }
+    }
   }
 #pragma unroll
   for (int bi = 0; bi < RB; ++bi)
@@ -157,7 +216,10 @@ __device__ __forceinline__ void diag_factor(T* S, int n, int k0, int kb_in, T* L
       }
     }
   if (bad) atomicOr(&bad_s, 1);
-  if (minr < 3.0e38f) atomicMin(&minr_s, __float_as_uint(minr));
+  if (tid < kb) {  // pivot report: smallest pivot / damped diagonal
+    const float ratio = (float)(piv[tid] / dd[tid]);
+    atomicMin(&minr_s, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
+  }
   __syncthreads();
   if (tid == 0) {
     if (bad_s) atomicOr(status, 1);
@@ -168,7 +230,8 @@ __device__ __forceinline__ void diag_factor(T* S, int n, int k0, int kb_in, T* L
 template <typename T>
 __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, int kb, T* Linv, const T* d0,
                                                          int* status, unsigned int* min_bits) {
-  diag_factor<T>(S, n, k0, kb, Linv, d0, status, min_bits);
+  __shared__ T P[2][128 * 17];
+  diag_factor<T>(S, n, k0, kb, Linv, d0, status, min_bits, P[0], P[1]);
 }
 
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
@@ -180,11 +243,8 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int k0, in
   const int i0 = k0 + kb + blockIdx.x * kNB;
   const int rows = min(kNB, n - i0);
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < kNB * kNB; idx += blockDim.x) {
-    const int r = idx / kNB, c = idx % kNB;
-    Ab[r][c] = (r < rows && c < kb) ? S[(size_t)(i0 + r) * n + k0 + c] : (T)0;
-    Li[r][c] = (r < kb && c < kb) ? Linv[r * kNB + c] : (T)0;
-  }
+  load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
+  load_block64<T>(Linv, (size_t)kNB, kb, kb, Li);
   __syncthreads();
   typename Mfma<T>::acc_t acc[4];
 #pragma unroll
@@ -202,9 +262,12 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int k0, in
 
 // Trailing update A_IJ -= L_Ik L_Jk^T for 64x64 blocks I >= J of the trailing
 // matrix, on the matrix cores; blockIdx.x enumerates the lower block pairs.
+// float32: at least three wavefronts per SIMD (at most 170 registers), so
+// the trailing update keeps its occupancy although workgroup 0 also runs the
+// register-heavy diagonal factor (which still fits without spilling).
 template <typename T>
-__global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0,
-                                                          int* status, unsigned int* min_bits) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* status, unsigned int* min_bits) {
   __shared__ T Li[kNB][kNB + 1];
   __shared__ T Lj[kNB][kNB + 1];
   const int t0 = k0 + kb;
@@ -216,11 +279,8 @@ __global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, i
   const int i0 = t0 + I * kNB, j0 = t0 + J * kNB;
   const int ri = min(kNB, n - i0), rj = min(kNB, n - j0);
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < kNB * kNB; idx += blockDim.x) {
-    const int r = idx / kNB, c = idx % kNB;
-    Li[r][c] = (r < ri && c < kb) ? S[(size_t)(i0 + r) * n + k0 + c] : (T)0;
-    Lj[r][c] = (r < rj && c < kb) ? S[(size_t)(j0 + r) * n + k0 + c] : (T)0;
-  }
+  load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, ri, kb, Li);
+  load_block64<T>(S + (size_t)j0 * n + k0, (size_t)n, rj, kb, Lj);
   __syncthreads();
   typename Mfma<T>::acc_t acc[4];
 #pragma unroll
@@ -238,8 +298,8 @@ __global__ void __launch_bounds__(256) syrk_update_kernel(T* S, int n, int k0, i
   // other workgroups finish the trailing update (look-ahead of one panel)
   if (blk == 0 && Linv_next) {
     __threadfence_block();
-    __syncthreads();
-    diag_factor<T>(S, n, t0, ri, Linv_next, d0, status, min_bits);
+    __syncthreads();  // also frees Li and Lj for the factor's panels
+    diag_factor<T>(S, n, t0, ri, Linv_next, d0, status, min_bits, &Li[0][0], &Lj[0][0]);
   }
 }
 

@@ -365,6 +365,34 @@ __device__ __forceinline__ void block_chol_solve(int n_in, const T* Sp_g, const 
 }
 
 
+// Sixteen steps i = i_hi, i_hi - 1, ... (i < n) of L^T x = y on one
+// wavefront: x_i = y_i / L_ii with y_i broadcast from `src` (the half that
+// holds rows i), then y_r -= L_ir x_i (l0 / l1: L_ir of the lane's two
+// rows, zero unless r < i).  x_i is kept by the lane of row i, off the chain.
+template <typename T>
+__device__ __forceinline__ void back_sub16(int i_hi, int n, const T* l0, const T* l1, const T* iv, const T& src,
+                                           T& y0, T& y1, T& x0, T& x1, int r0, int r1) {
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int i = i_hi - c;
+    if (i >= n) continue;  // uniform
+    T yi;
+    if constexpr (sizeof(T) == 4) {
+      yi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(src), i & 63));
+    } else {
+      const long long bits = __double_as_longlong(src);
+      const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), i & 63);
+      const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), i & 63);
+      yi = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+    const T xi = yi * iv[c];
+    y0 -= l0[c] * xi;
+    y1 -= l1[c] * xi;
+    x0 = r0 == i ? xi : x0;
+    x1 = r1 == i ? xi : x1;
+  }
+}
+
 // Cholesky of the augmented matrix [[S, .], [s^T, .]] (n + 1 <= 16 MB rows)
 // in panels of 16 columns, by a 256-thread workgroup with the matrix in
 // registers: thread (ty, tx) = (tid mod 16, tid / 16) holds entries
@@ -499,39 +527,26 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
     const int r0 = tid, r1 = tid + 64;
     T y0 = r0 < n ? Lrow[n * NR + r0] : (T)0;
     T y1 = r1 < n ? Lrow[n * NR + r1] : (T)0;
-    for (int i0 = n - 1; i0 >= 0; i0 -= 16) {
-      // sixteen rows' entries first: the chain below only waits on y
+    T x0 = (T)0, x1 = (T)0;
+    // blocks of 16 rows from the last; a block lies in one half (64 is a
+    // multiple of 16), so the broadcast source is fixed per block
+#pragma unroll
+    for (int blk = MB - 1; blk >= 0; --blk) {
+      if (16 * blk >= n) continue;  // uniform
       T l0[16], l1[16], iv[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const int i = max(i0 - c, 0);
-        l0[c] = Lrow[i * NR + r0];
-        l1[c] = r1 < NR ? Lrow[i * NR + r1] : (T)0;
-        iv[c] = invd[i];
+      for (int c = 0; c < 16; ++c) {  // L_ir for r < i only (zero otherwise), loaded off the chain
+        const int i = 16 * blk + 15 - c;
+        const int ic = min(i, NR - 1);
+        l0[c] = r0 < i && i < n ? Lrow[ic * NR + r0] : (T)0;
+        l1[c] = r1 < i && i < n ? Lrow[ic * NR + r1] : (T)0;
+        iv[c] = invd[ic];
       }
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const int i = i0 - c;
-        if (i < 0) continue;  // uniform
-        const T yv = i >= 64 ? y1 : y0;
-        T yi;
-        if constexpr (sizeof(T) == 4) {
-          yi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), i & 63));
-        } else {
-          const long long bits = __double_as_longlong(yv);
-          const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), i & 63);
-          const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), i & 63);
-          yi = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-        }
-        const T xi = yi * iv[c];
-        if (r0 < i) y0 -= l0[c] * xi;
-        if (r1 < i) y1 -= l1[c] * xi;
-        if (r0 == i) y0 = xi;
-        if (r1 == i) y1 = xi;
-      }
+      if (blk >= 4) back_sub16<T>(16 * blk + 15, n, l0, l1, iv, y1, y0, y1, x0, x1, r0, r1);
+      else back_sub16<T>(16 * blk + 15, n, l0, l1, iv, y0, y0, y1, x0, x1, r0, r1);
     }
-    if (r0 < n) x[r0] = y0;
-    if (r1 < n) x[r1] = y1;
+    if (r0 < n) x[r0] = x0;
+    if (r1 < n) x[r1] = x1;
   }
   __syncthreads();
   if (tid < n && bad_s) x[tid] = (T)0;
