@@ -16,11 +16,13 @@
 namespace dpvba {
 
 constexpr int kMaxSlots = 64;     // slots per tile (one wavefront)
-constexpr int kTileThreads = 256;      // single-launch solver (its dense factor assumes four wavefronts)
-constexpr int kTileThreadsWide = 512;  // float32 tile launches of the multi-launch path
+constexpr int kTileThreads = 256;      // float64 tile work and the depth write-back
+constexpr int kTileThreadsWide = 512;  // float32 tile work
 
-// Workgroup size of the multi-launch tile kernel for a compute type of
-// tsize bytes (float64 keeps 256: its per-thread partials would not fit).
+// Workgroup size of the tile kernel and of the single-launch solver for a
+// compute type of tsize bytes (float64 keeps 256: its per-thread partials
+// would not fit).  The solver's dense factor works on a 16 x 16 register
+// grid of the first 256 threads; the others only meet its barriers.
 __host__ __device__ constexpr int tile_threads(int tsize) { return tsize == 4 ? kTileThreadsWide : kTileThreads; }
 constexpr int kRedWidth = 28;     // per-slot partial: 21 (M upper) + 6 (v) + 1 (cost)
 

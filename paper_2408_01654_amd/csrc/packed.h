@@ -413,6 +413,7 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
   const int tid = threadIdx.x;
   const int ty = tid & 15, tx = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
+  const bool grid = tid < 256;  // the 16 x 16 register grid (larger workgroups: the rest only meet the barriers)
   T* PB = reinterpret_cast<T*>(lds);  // [2][NR][17] published panel
   T* invd = PB + 2 * NR * 17;         // [NR] 1 / L_jj
   T* dd = invd + NR;                  // [NR] damped diagonal (pivot report)
@@ -426,8 +427,8 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
     for (int bk = 0; bk < MB; ++bk) {
       const int i = 16 * bi + ty, k = 16 * bk + tx;
       T v = (T)0;
-      if (k <= i && i < n) v = Sp_g[i * (i + 1) / 2 + k];
-      else if (i == n && k < n) v = rhs_g[k];
+      if (grid && k <= i && i < n) v = Sp_g[i * (i + 1) / 2 + k];
+      else if (grid && i == n && k < n) v = rhs_g[k];
       a[bi][bk] = v;
     }
   int bad = 0;
@@ -436,8 +437,9 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
     if (16 * p >= n) continue;  // uniform: no pivot left
     T* P = PB + (p & 1) * NR * 17;
     // publish the panel's column block (rows >= 16 p)
+    if (grid)
 #pragma unroll
-    for (int bi = p; bi < MB; ++bi) P[(16 * bi + ty) * 17 + tx] = a[bi][p];
+      for (int bi = p; bi < MB; ++bi) P[(16 * bi + ty) * 17 + tx] = a[bi][p];
     __syncthreads();
     if (wave == (p & 3)) {
       // lane l holds rows 16 p + l and 16 p + l + 64 of the panel
@@ -493,27 +495,30 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
     }
     __syncthreads();
     // factored entries back, then the rank-16 update right of and below the panel
+    if (grid) {
 #pragma unroll
-    for (int bi = p; bi < MB; ++bi) a[bi][p] = P[(16 * bi + ty) * 17 + tx];
+      for (int bi = p; bi < MB; ++bi) a[bi][p] = P[(16 * bi + ty) * 17 + tx];
 #pragma unroll
-    for (int bi = p + 1; bi < MB; ++bi) {
-      T li[16];
+      for (int bi = p + 1; bi < MB; ++bi) {
+        T li[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) li[c] = P[(16 * bi + ty) * 17 + c];
+        for (int c = 0; c < 16; ++c) li[c] = P[(16 * bi + ty) * 17 + c];
 #pragma unroll
-      for (int bk = p + 1; bk <= bi; ++bk) {
-        T acc = (T)0;
+        for (int bk = p + 1; bk <= bi; ++bk) {
+          T acc = (T)0;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc += li[c] * P[(16 * bk + tx) * 17 + c];
-        a[bi][bk] -= acc;
+          for (int c = 0; c < 16; ++c) acc += li[c] * P[(16 * bk + tx) * 17 + c];
+          a[bi][bk] -= acc;
+        }
       }
     }
   }
   // rows of L (and y in row n) to LDS
+  if (grid)
 #pragma unroll
-  for (int bi = 0; bi < MB; ++bi)
+    for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
-    for (int bk = 0; bk < MB; ++bk) Lrow[(16 * bi + ty) * NR + 16 * bk + tx] = a[bi][bk];
+      for (int bk = 0; bk < MB; ++bk) Lrow[(16 * bi + ty) * NR + 16 * bk + tx] = a[bi][bk];
   __shared__ int bad_s;
   __shared__ unsigned int minr_s;
   if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }

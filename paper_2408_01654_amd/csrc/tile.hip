@@ -723,7 +723,8 @@ __device__ void tile_writeback(const TileInfo& ti, const int* tile_patch, const 
 // reduced system, workgroup 0 factors, solves and retracts; finally the
 // depths are written back.  Poses ping-pong between two buffers.
 template <typename T>
-__global__ void __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ void __launch_bounds__(tile_threads(sizeof(T)))
+__attribute__((amdgpu_waves_per_eu(tile_threads(sizeof(T)) / 256, tile_threads(sizeof(T)) / 256)))
 small_solve_kernel(SmallArgs<T> S) {
   extern __shared__ __align__(16) unsigned char lds[];
   IterArgs<T> A = S.it;
@@ -742,7 +743,7 @@ small_solve_kernel(SmallArgs<T> S) {
     A.cost_out = S.cost ? S.cost + t : nullptr;
     A.invalid_out = S.invalid ? S.invalid + t : nullptr;
     for (int tile = blockIdx.x; tile < A.n_tiles; tile += nb) {
-      tile_assemble<T, kTileThreads>(A, tile, lds);
+      tile_assemble<T, tile_threads(sizeof(T))>(A, tile, lds);
       __syncthreads();
     }
     if (!grid_sync(S.bar, nb, S.err)) return;
@@ -834,7 +835,7 @@ int small_solve_grid(int lds_bytes) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   if (opt_in_lds((const void*)small_solve_kernel<T>, lds_bytes) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)small_solve_kernel<T>, kTileThreads,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)small_solve_kernel<T>, tile_threads(sizeof(T)),
                                                    lds_bytes) != hipSuccess)
     return 0;
   return cus * per_cu;
@@ -846,7 +847,7 @@ hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, hi
   if (e != hipSuccess) return e;
   SmallArgs<T> copy = S;
   void* args[] = {&copy};
-  return hipLaunchCooperativeKernel((const void*)small_solve_kernel<T>, dim3(grid), dim3(kTileThreads), args,
+  return hipLaunchCooperativeKernel((const void*)small_solve_kernel<T>, dim3(grid), dim3(tile_threads(sizeof(T))), args,
                                     lds_bytes, st);
 }
 
