@@ -112,7 +112,7 @@ __device__ __forceinline__ void utu_unit(const T* ua, const T* ub, int nk, int W
 // Phases 0-3 for one tile; the caller synchronises before reusing `lds`.
 // NT: the workgroup size.
 template <typename T, int NT>
-__device__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds) {
+__device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, unsigned char* lds) {
   const TileInfo ti = A.tiles[tile];
   const int tid = threadIdx.x;
   const int K = ti.n_patch, Tn = ti.n_slot, nb = ti.n_blk, W6 = 6 * nb;
@@ -556,7 +556,7 @@ __global__ void __launch_bounds__(tile_threads(sizeof(T))) tile_iterate_kernel(I
 // Diagonal entries get lam (Diag(B) + 1) and are kept in d0; the diagonal
 // blocks also produce s.
 template <typename T>
-__device__ void gather_slice(const IterArgs<T>& A, T* Sp, T* rhs, T* d0, int wave, int nwaves) {
+__device__ __forceinline__ void gather_slice(const IterArgs<T>& A, T* Sp, T* rhs, T* d0, int wave, int nwaves) {
   const int nf = A.n_free;
   const int lane = threadIdx.x & 63;
   const int r = lane / 6, c = lane - (lane / 6) * 6;
