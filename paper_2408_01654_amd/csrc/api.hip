@@ -98,6 +98,8 @@ template <typename T>
 int batch_solve_lds(int n_max, bool mixed, bool* lds_factor);
 template <typename T>
 hipError_t launch_batch_solve(const BatchArgs<T>& a, int n_inst, int lds_bytes, hipStream_t st);
+template <typename TS, typename TA>
+hipError_t launch_batch_gather(const BatchArgs<TS>& a, int n_inst, int n_max, hipStream_t st);
 hipError_t launch_batch_solve_mixed(const BatchArgs<float>& a, int n_inst, int lds_bytes, hipStream_t st);
 hipError_t launch_batch_cost(const BatchInst* inst, int n_inst, const double* part_cost, const int* part_invalid,
                              dpvba_report* rep, int it, hipStream_t st);
@@ -1395,6 +1397,15 @@ static hipError_t batch_impl(dpvba_ctx* c, const dpvba_batch* b, T* poses, T* de
     a.it = it;
     a.scratch = (double*)B.scratch_buf.p;
     a.lds_factor = lds_factor ? 1 : 0;
+    {
+      TraceScope tg(c, DPVBA_PHASE_GATHER, st);
+      if constexpr (sizeof(T) == 4)
+        e = mixed ? launch_batch_gather<float, double>(a, B.B, B.n_max, st)
+                  : launch_batch_gather<float, float>(a, B.B, B.n_max, st);
+      else
+        e = launch_batch_gather<double, double>(a, B.B, B.n_max, st);
+      if (e != hipSuccess) return e;
+    }
     TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
     if constexpr (sizeof(T) == 4) {
       if (mixed) e = launch_batch_solve_mixed(a, B.B, lds_solve, st);

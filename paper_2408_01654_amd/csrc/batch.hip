@@ -1,9 +1,11 @@
 // Batched solve: many independent BA problems (uneven sliding windows) in
 // the same launches.  The tiles of every problem form one grid, so the
 // assembly of all problems is load-balanced by the hardware dispatcher (the
-// tile kernel is unchanged; a tile knows its problem).  Then one workgroup
-// per problem gathers its damped reduced camera system (DPV-SLAM Appendix A)
-// from the tiles' shares, factors it, solves it and retracts its poses.
+// tile kernel is unchanged; a tile knows its problem).  Then one wavefront
+// per 6x6 block of every problem gathers the damped reduced camera systems
+// (DPV-SLAM Appendix A) from the tiles' shares into the problems' scratch
+// slices, and one workgroup per problem factors its system, solves it and
+// retracts its poses.
 //
 // Precision modes of the per-problem solve:
 //   float32  shares, packed factor and solve in float32 (shared memory);
@@ -46,38 +48,96 @@ struct BatchArgs {
   int lds_factor;         // packed factor in shared memory
 };
 
-// Damped system of one problem: packed lower A, right-hand side b and the
-// damped diagonal d0, summed from the shares in tile order in type TA.
+// Damped system of every problem, one wavefront per lower 6x6 block
+// (P >= Q) of problem blockIdx.y: the block is summed from its tiles' shares
+// in tile order (share offsets loaded once per wavefront and broadcast,
+// eight independent loads in flight), the diagonal gets lam (Diag(B) + 1),
+// and the problem's scratch slice receives, in type TA, the packed lower
+// matrix, then s, then the damped diagonal d0.
 template <typename TS, typename TA>
-__device__ void batch_gather(const BatchArgs<TS>& a, const BatchInst& I, TA* A, TA* b, TA* d0) {
-  const int n = 6 * I.n_free;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < n; i += blockDim.x) {
-    const int P = i / 6, m = i % 6;
-    TA vb = (TA)0, db = (TA)0;
-    for (int q = a.v_off[I.v_base + P]; q < a.v_off[I.v_base + P + 1]; ++q) {
-      const int2 o = a.v_src[q];
-      vb += (TA)a.part_vec[o.x + m];
-      db += (TA)a.part_vec[o.y + m];
+__global__ void __launch_bounds__(256) batch_gather_kernel(BatchArgs<TS> a) {
+  const BatchInst I = a.inst[blockIdx.y];
+  const int nf = I.n_free;
+  const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (blk >= nf * (nf + 1) / 2) return;  // whole wavefronts; the kernel has no barrier
+  const int lane = threadIdx.x & 63;
+  const int n = 6 * nf;
+  TA* A = reinterpret_cast<TA*>(a.scratch + I.scratch_off);
+  TA* sv_out = A + (size_t)n * (n + 1) / 2;
+  TA* d0_out = sv_out + n;
+  int P, Q;
+  lower_block_of(blk, P, Q);
+  const int r = lane / 6, c = lane - (lane / 6) * 6;
+  const bool lower = lane < 36 && (P > Q || r >= c);
+  const int eo = c * 6 + r;  // the shares hold upper entries: (r, c) of S_PQ is [c][r] of a share
+  TA v = (TA)0;
+  const int lo = a.s_off[I.s_base + blk], hi = a.s_off[I.s_base + blk + 1];
+  for (int b0 = lo; b0 < hi; b0 += 64) {
+    const int o_l = b0 + lane < hi ? a.s_src[b0 + lane] : 0;
+    const int nq = min(64, hi - b0);
+    for (int q0 = 0; q0 < nq; q0 += 8) {
+      TA part[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int o = __shfl(o_l, (q0 + u) & 63);
+        part[u] = (lower && q0 + u < nq) ? (TA)a.part_S[o + eo] : (TA)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += part[u];
     }
-    b[i] = vb;
-    d0[i] = db;  // Diag(B) for now
   }
-  __syncthreads();
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
-    const int i = idx / n, j = idx - (idx / n) * n;
-    if (j > i) continue;
-    const int P = i / 6, Q = j / 6, r = i % 6, c = j % 6;
-    const int blk = P * (P + 1) / 2 + Q;
-    const int eo = c * 6 + r;  // shares hold the upper entries of their block pairs
-    TA v = (TA)0;
-    for (int q = a.s_off[I.s_base + blk]; q < a.s_off[I.s_base + blk + 1]; ++q) v += (TA)a.part_S[a.s_src[q] + eo];
-    if (i == j) v += (TA)a.lambda * (d0[i] + (TA)1);
-    A[packed_index(i, j)] = v;
+  const int row = 6 * P + r, col = 6 * Q + c;
+  if (P == Q) {
+    // Diag(B) (lanes on the diagonal) and s (lanes 36..41) of pose P
+    const int m = lane < 36 ? r : lane - 36;
+    const bool want_d = lane < 36 && r == c, want_s = lane >= 36 && lane < 42;
+    const int vlo = a.v_off[I.v_base + P], vhi = a.v_off[I.v_base + P + 1];
+    TA db = (TA)0, sv = (TA)0;
+    for (int b0 = vlo; b0 < vhi; b0 += 64) {
+      const int2 o_l = b0 + lane < vhi ? a.v_src[b0 + lane] : make_int2(0, 0);
+      const int nq = min(64, vhi - b0);
+      for (int q0 = 0; q0 < nq; q0 += 8) {
+        TA pd[8], ps[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int ox = __shfl(o_l.x, (q0 + u) & 63), oy = __shfl(o_l.y, (q0 + u) & 63);
+          const bool in = q0 + u < nq;
+          pd[u] = (want_d && in) ? (TA)a.part_vec[oy + m] : (TA)0;
+          ps[u] = (want_s && in) ? (TA)a.part_vec[ox + m] : (TA)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          db += pd[u];
+          sv += ps[u];
+        }
+      }
+    }
+    if (want_s) sv_out[6 * P + m] = sv;
+    if (want_d) {
+      v += (TA)a.lambda * (db + (TA)1);
+      d0_out[row] = v;
+    }
   }
-  __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) d0[i] = A[packed_index(i, i)];
-  __syncthreads();
+  if (lower) A[packed_index(row, col)] = v;
+}
+
+// count entries from global memory into LDS, eight independent loads in
+// flight per thread.
+template <typename TD, typename TSRC>
+__device__ __forceinline__ void copy_in(const TSRC* src, TD* dst, int count) {
+  for (int q0 = threadIdx.x; q0 < count; q0 += 8 * blockDim.x) {
+    TSRC v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * blockDim.x;
+      v[u] = q < count ? src[q] : (TSRC)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * blockDim.x;
+      if (q < count) dst[q] = (TD)v[u];
+    }
+  }
 }
 
 // Write the step and retract the problem's free poses.
@@ -112,13 +172,17 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_kernel(BatchArgs<T>
   const int n = 6 * I.n_free;
   T* vb = reinterpret_cast<T*>(lds);
   T* d0 = vb + n;
-  T* A = a.lds_factor ? d0 + n : reinterpret_cast<T*>(a.scratch + I.scratch_off);
+  T* G = reinterpret_cast<T*>(a.scratch + I.scratch_off);  // gathered: packed, s, d0
+  T* A = a.lds_factor ? d0 + n : G;                          // else factored in place
   int* st = a.status + blockIdx.x * a.stride + a.it;
   if (n == 0) {
     batch_apply<T, T>(a, I, vb, false);
     return;
   }
-  batch_gather<T, T>(a, I, A, vb, d0);
+  const int np = n * (n + 1) / 2;
+  if (a.lds_factor) copy_in<T, T>(G, A, np);
+  copy_in<T, T>(G + np, vb, 2 * n);  // s and d0 are contiguous in both places
+  __syncthreads();
   packed_cholesky<T>(A, n, d0, &bad, &minr);
   packed_solve<T, T>(A, vb, n);
   const bool failed = bad != 0;
@@ -183,13 +247,10 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_mixed_kernel(BatchA
     }
     return;
   }
-  batch_gather<float, double>(a, I, S64, s64, d064);
   const int np = n * (n + 1) / 2;
-  for (int q = threadIdx.x; q < np; q += blockDim.x) A32[q] = (float)S64[q];
-  for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    c32[q] = (float)s64[q];
-    d32[q] = (float)d064[q];
-  }
+  copy_in<float, double>(S64, A32, np);  // gathered in float64 by batch_gather_kernel
+  copy_in<float, double>(s64, c32, n);
+  copy_in<float, double>(d064, d32, n);
   __syncthreads();
   packed_cholesky<float>(A32, n, d32, &bad, &minr);
   const int bad32 = bad;
@@ -320,6 +381,14 @@ int batch_solve_lds(int n_max, bool mixed, bool* lds_factor) {
   return *lds_factor ? full : vec;
 }
 
+template <typename TS, typename TA>
+hipError_t launch_batch_gather(const BatchArgs<TS>& a, int n_inst, int n_max, hipStream_t st) {
+  const int nf = n_max / 6, nlb = nf * (nf + 1) / 2;
+  if (n_inst == 0 || nlb == 0) return hipSuccess;
+  hipLaunchKernelGGL((batch_gather_kernel<TS, TA>), dim3((nlb + 3) / 4, n_inst), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_batch_solve(const BatchArgs<T>& a, int n_inst, int lds_bytes, hipStream_t st) {
   if (n_inst == 0) return hipSuccess;
@@ -368,5 +437,8 @@ hipError_t launch_batch_report(const BatchInst* inst, int n_inst, const T* poses
 DPVBA_BATCH_INST(float)
 DPVBA_BATCH_INST(double)
 #undef DPVBA_BATCH_INST
+template hipError_t launch_batch_gather<float, float>(const BatchArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_batch_gather<float, double>(const BatchArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_batch_gather<double, double>(const BatchArgs<double>&, int, int, hipStream_t);
 
 }  // namespace dpvba
