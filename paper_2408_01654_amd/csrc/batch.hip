@@ -162,29 +162,61 @@ __device__ __forceinline__ void batch_pivot_min(unsigned int* min_bits, float ra
   atomicMin(min_bits, __float_as_uint(ratio));
 }
 
-// float32 or float64: one precision throughout.
+// float32 or float64: one precision throughout.  With the factor in shared
+// memory: the gathered system with s appended as row n is factored by
+// packed_panel_factor (row n ends as y = L^-1 s) and L^T x = y is solved by
+// one wavefront.  Otherwise (float64 systems too wide for shared memory) the
+// packed factor works in the problem's scratch slice.
 template <typename T>
 __global__ void __launch_bounds__(kBatchThreads) batch_solve_kernel(BatchArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ int bad;
   __shared__ float minr;
+  __shared__ unsigned int minr_bits;
   const BatchInst I = a.inst[blockIdx.x];
   const int n = 6 * I.n_free;
-  T* vb = reinterpret_cast<T*>(lds);
-  T* d0 = vb + n;
   T* G = reinterpret_cast<T*>(a.scratch + I.scratch_off);  // gathered: packed, s, d0
-  T* A = a.lds_factor ? d0 + n : G;                          // else factored in place
   int* st = a.status + blockIdx.x * a.stride + a.it;
   if (n == 0) {
-    batch_apply<T, T>(a, I, vb, false);
+    batch_apply<T, T>(a, I, reinterpret_cast<T*>(lds), false);
     return;
   }
   const int np = n * (n + 1) / 2;
-  if (a.lds_factor) copy_in<T, T>(G, A, np);
-  copy_in<T, T>(G + np, vb, 2 * n);  // s and d0 are contiguous in both places
+  if (a.lds_factor) {
+    T* d0 = reinterpret_cast<T*>(lds);
+    T* invd = d0 + n;
+    T* piv = invd + n;
+    T* x = piv + n;
+    T* A = x + n;  // packed, n + 1 rows
+    copy_in<T, T>(G, A, np + n);  // the packed rows, then s as row n
+    copy_in<T, T>(G + np + n, d0, n);
+    if (threadIdx.x == 0) {
+      A[np + n] = (T)0;
+      bad = 0;
+      minr_bits = __float_as_uint(3.0e38f);
+    }
+    __syncthreads();
+    packed_panel_factor<T>(A, n, n + 1, invd, piv, &bad);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {  // smallest pivot / damped diagonal
+      const float ratio = (float)(piv[j] / d0[j]);
+      atomicMin(&minr_bits, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
+    }
+    packed_back_solve<T>(A, n, invd, A + np, x);
+    __syncthreads();
+    const bool failed = bad != 0;
+    batch_apply<T, T>(a, I, x, failed);
+    if (threadIdx.x == 0) {
+      *st = failed;
+      batch_pivot_min(a.min_bits + blockIdx.x * a.stride + a.it, __uint_as_float(minr_bits));
+    }
+    return;
+  }
+  T* vb = reinterpret_cast<T*>(lds);
+  T* d0 = vb + n;
+  copy_in<T, T>(G + np, vb, 2 * n);  // s and d0
   __syncthreads();
-  packed_cholesky<T>(A, n, d0, &bad, &minr);
-  packed_solve<T, T>(A, vb, n);
+  packed_cholesky<T>(G, n, d0, &bad, &minr);
+  packed_solve<T, T>(G, vb, n);
   const bool failed = bad != 0;
   batch_apply<T, T>(a, I, vb, failed);
   if (threadIdx.x == 0) {
@@ -234,10 +266,14 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_mixed_kernel(BatchA
   double* b64 = r64 + n;                          // [n] copy of s for the float64 fallback
   float* c32 = reinterpret_cast<float*>(b64 + n); // [n]
   float* d32 = c32 + n;                           // [n]
-  float* A32 = d32 + n;                           // packed
+  float* invd32 = d32 + n;                        // [n]
+  float* piv32 = invd32 + n;                      // [n]
+  float* A32 = piv32 + n;                         // packed, n + 1 rows (s appended)
   double* S64 = a.scratch + I.scratch_off;        // packed, then s [n], then d0 [n]
   double* s64 = S64 + (size_t)n * (n + 1) / 2;
   double* d064 = s64 + n;
+  __shared__ int bad32;
+  __shared__ unsigned int minr_bits;
   const int idx_st = blockIdx.x * a.stride + a.it;
   if (n == 0) {
     batch_apply<float, float>(a, I, c32, false);
@@ -248,14 +284,22 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_mixed_kernel(BatchA
     return;
   }
   const int np = n * (n + 1) / 2;
-  copy_in<float, double>(S64, A32, np);  // gathered in float64 by batch_gather_kernel
-  copy_in<float, double>(s64, c32, n);
+  copy_in<float, double>(S64, A32, np + n);  // gathered in float64: the packed rows, then s as row n
   copy_in<float, double>(d064, d32, n);
+  if (threadIdx.x == 0) {
+    A32[np + n] = 0.f;
+    bad32 = 0;
+    minr_bits = __float_as_uint(3.0e38f);
+  }
   __syncthreads();
-  packed_cholesky<float>(A32, n, d32, &bad, &minr);
-  const int bad32 = bad;
-  const float minr32 = minr;
-  packed_solve<float, float>(A32, c32, n);
+  packed_panel_factor<float>(A32, n, n + 1, invd32, piv32, &bad32);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const float ratio = piv32[j] / d32[j];
+    atomicMin(&minr_bits, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
+  }
+  packed_back_solve<float>(A32, n, invd32, A32 + np, c32);
+  __syncthreads();
+  const float minr32 = __uint_as_float(minr_bits);
   for (int q = threadIdx.x; q < n; q += blockDim.x) x64[q] = (double)c32[q];
   __syncthreads();
   double smax = 0.0;
@@ -275,7 +319,10 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_mixed_kernel(BatchA
     batch_residual(S64, s64, x64, r64, n, red);
     for (int q = threadIdx.x; q < n; q += blockDim.x) c32[q] = (float)r64[q];
     __syncthreads();
-    packed_solve<float, float>(A32, c32, n);
+    packed_fwd_solve<float>(A32, n, invd32, c32, c32);
+    __syncthreads();
+    packed_back_solve<float>(A32, n, invd32, c32, c32);
+    __syncthreads();
     for (int q = threadIdx.x; q < n; q += blockDim.x) x64[q] += (double)c32[q];
     __syncthreads();
   }
@@ -370,15 +417,14 @@ __global__ void __launch_bounds__(256) batch_report_kernel(
 
 template <typename T>
 int batch_solve_lds(int n_max, bool mixed, bool* lds_factor) {
-  const int np = n_max * (n_max + 1) / 2;
+  const int np1 = (n_max + 1) * (n_max + 2) / 2;  // packed, s appended as row n
   if (mixed) {
     *lds_factor = true;
-    return 3 * n_max * 8 + 2 * n_max * 4 + np * 4;
+    return 3 * n_max * 8 + 4 * n_max * 4 + np1 * 4;
   }
-  const int vec = 2 * n_max * (int)sizeof(T);
-  const int full = vec + np * (int)sizeof(T);
+  const int full = (4 * n_max + np1) * (int)sizeof(T);
   *lds_factor = full <= 150 * 1024;
-  return *lds_factor ? full : vec;
+  return *lds_factor ? full : 2 * n_max * (int)sizeof(T);
 }
 
 template <typename TS, typename TA>

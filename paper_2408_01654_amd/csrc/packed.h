@@ -562,4 +562,221 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Packed systems of up to 255 unknowns on one workgroup of 256 threads or
+// more: blocked factor and wavefront substitutions.
+
+// Value of v on lane l (uniform) of the wavefront.
+template <typename T>
+__device__ __forceinline__ T lane_bcast(T v, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+  } else {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+
+// In-place Cholesky of the packed lower triangle of rows 0..nr-1 of an
+// n-column system (nr = n, or n + 1 with the right-hand side appended as row
+// n, which then ends as y = L^-1 s; nr <= 256), in panels of 16 columns.
+// Panel j0: the first wavefront takes the panel's rows (row j0 + l + 64 t on
+// lane l, t < 4), factors its 16 columns alone (pivots and column entries
+// broadcast by v_readlane) and writes them back; after a barrier the first
+// 256 threads subtract the panel's rank-16 product from the trailing
+// triangle, thread (ty, tx) = (tid mod 16, tid / 16 mod 16) owning entry
+// (16 bi + ty, 16 bk + tx) of each 16 x 16 block.  Two barriers per panel.
+// invd[j] = 1 / L_jj and piv[j] = the pivot before its square root; a pivot
+// that is not positive or not finite is replaced by 1 and sets *bad (shared,
+// cleared by the caller).
+template <typename T>
+__device__ void packed_panel_factor(T* A, int n_in, int nr_in, T* invd, T* piv, int* bad) {
+  const int n = __builtin_amdgcn_readfirstlane(n_in);
+  const int nr = __builtin_amdgcn_readfirstlane(nr_in);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int ty = tid & 15, tx = (tid >> 4) & 15;
+  for (int j0 = 0; j0 < n; j0 += 16) {
+    if (tid < 64) {
+      T ra[4][16];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = j0 + lane + 64 * t;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          ra[t][c] = (i < nr && j0 + c <= i && j0 + c < n) ? A[packed_index(i, j0 + c)] : (T)0;
+      }
+      int badl = 0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int j = j0 + c;
+        if (j >= n) continue;  // uniform
+        T d = lane_bcast(ra[0][c], c);
+        if (lane == 0) piv[j] = d;
+        if (!(d > (T)0) || !(d < (T)3.0e38)) {
+          badl = 1;
+          d = (T)1;
+        }
+        const T rs = pivot_rsqrt<T>(d);
+        if (lane == 0) invd[j] = rs;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) ra[t][c] *= rs;
+#pragma unroll
+        for (int c2 = c + 1; c2 < 16; ++c2) {
+          const T lk = lane_bcast(ra[0][c], c2);  // entry (j0 + c2, j) of the panel
+#pragma unroll
+          for (int t = 0; t < 4; ++t) ra[t][c2] -= ra[t][c] * lk;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = j0 + lane + 64 * t;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (i < nr && j0 + c <= i && j0 + c < n) A[packed_index(i, j0 + c)] = ra[t][c];
+      }
+      if (badl && lane == 0) *bad = 1;
+    }
+    __syncthreads();
+    const int s0 = j0 + 16;  // trailing rows s0 .. nr - 1, columns s0 .. min(i, n - 1)
+    if (tid < 256 && s0 < nr) {
+      const int nbr = (nr - s0 + 15) >> 4;
+      for (int bi = 0; bi < nbr; ++bi) {
+        const int i = s0 + 16 * bi + ty;
+        if (i >= nr) continue;
+        T li[16];
+        const T* Li = A + packed_index(i, j0);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) li[c] = Li[c];
+        for (int bk = 0; bk <= bi; ++bk) {
+          const int k = s0 + 16 * bk + tx;
+          if (k > i || k >= n) continue;
+          const T* Lk = A + packed_index(k, j0);
+          T acc = (T)0;
+#pragma unroll
+          for (int c = 0; c < 16; ++c) acc += li[c] * Lk[c];
+          A[packed_index(i, k)] -= acc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Sixteen backward steps i = i_hi, i_hi - 1, ... (i < n) with row i held in
+// register set TI: x_i = y_i / L_ii, then y_r -= L_ir x_i on every lane (l:
+// L_ir of the lane's four rows, zero unless r < i); x_i is kept by the lane
+// of row i.
+template <typename T, int TI>
+__device__ __forceinline__ void packed_back16(int i_hi, int n, const T (*l)[16], const T* iv, T* y, T* xk,
+                                              int lane) {
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int i = i_hi - c;
+    if (i >= n) continue;  // uniform
+    const T xi = lane_bcast(y[TI], i & 63) * iv[c];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      y[t] -= l[t][c] * xi;
+      xk[t] = lane + 64 * t == i ? xi : xk[t];
+    }
+  }
+}
+
+// L^T x = y on the first wavefront for a packed factor with invd[j] = 1 /
+// L_jj (n <= 256; y and x may alias).  Rows r = l + 64 t sit on lane l;
+// blocks of 16 rows from the last, whose L entries are loaded before the
+// dependent chain.  The other threads return at once (no barrier inside).
+template <typename T>
+__device__ void packed_back_solve(const T* A, int n_in, const T* invd, const T* y_in, T* x) {
+  if (threadIdx.x >= 64) return;
+  const int n = __builtin_amdgcn_readfirstlane(n_in);
+  const int lane = threadIdx.x;
+  T y[4], xk[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    y[t] = lane + 64 * t < n ? y_in[lane + 64 * t] : (T)0;
+    xk[t] = (T)0;
+  }
+  for (int blk = (n - 1) >> 4; blk >= 0; --blk) {
+    T l[4][16], iv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int i = 16 * blk + 15 - c, ic = min(i, n - 1);
+      iv[c] = invd[ic];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = lane + 64 * t;
+        l[t][c] = (r < i && i < n) ? A[packed_index(ic, r)] : (T)0;
+      }
+    }
+    switch (blk >> 2) {  // the set that holds rows 16 blk .. 16 blk + 15
+      case 0: packed_back16<T, 0>(16 * blk + 15, n, l, iv, y, xk, lane); break;
+      case 1: packed_back16<T, 1>(16 * blk + 15, n, l, iv, y, xk, lane); break;
+      case 2: packed_back16<T, 2>(16 * blk + 15, n, l, iv, y, xk, lane); break;
+      default: packed_back16<T, 3>(16 * blk + 15, n, l, iv, y, xk, lane); break;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (lane + 64 * t < n) x[lane + 64 * t] = xk[t];
+}
+
+// Sixteen forward steps i = i_lo, i_lo + 1, ... (i < n), row i in set TI:
+// y_i = b_i / L_ii, then b_r -= L_ri y_i (l: L_ri, zero unless r > i).
+template <typename T, int TI>
+__device__ __forceinline__ void packed_fwd16(int i_lo, int n, const T (*l)[16], const T* iv, T* b, T* yk,
+                                             int lane) {
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int i = i_lo + c;
+    if (i >= n) continue;  // uniform
+    const T yi = lane_bcast(b[TI], i & 63) * iv[c];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      b[t] -= l[t][c] * yi;
+      yk[t] = lane + 64 * t == i ? yi : yk[t];
+    }
+  }
+}
+
+// L y = b on the first wavefront (the companion of packed_back_solve; b and
+// y may alias).
+template <typename T>
+__device__ void packed_fwd_solve(const T* A, int n_in, const T* invd, const T* b_in, T* y) {
+  if (threadIdx.x >= 64) return;
+  const int n = __builtin_amdgcn_readfirstlane(n_in);
+  const int lane = threadIdx.x;
+  T b[4], yk[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    b[t] = lane + 64 * t < n ? b_in[lane + 64 * t] : (T)0;
+    yk[t] = (T)0;
+  }
+  for (int blk = 0; 16 * blk < n; ++blk) {
+    T l[4][16], iv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int i = 16 * blk + c, ic = min(i, n - 1);
+      iv[c] = invd[ic];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = lane + 64 * t;
+        l[t][c] = (r > i && r < n) ? A[packed_index(r, ic)] : (T)0;
+      }
+    }
+    switch (blk >> 2) {
+      case 0: packed_fwd16<T, 0>(16 * blk, n, l, iv, b, yk, lane); break;
+      case 1: packed_fwd16<T, 1>(16 * blk, n, l, iv, b, yk, lane); break;
+      case 2: packed_fwd16<T, 2>(16 * blk, n, l, iv, b, yk, lane); break;
+      default: packed_fwd16<T, 3>(16 * blk, n, l, iv, b, yk, lane); break;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (lane + 64 * t < n) y[lane + 64 * t] = yk[t];
+}
+
 }  // namespace dpvba
