@@ -60,26 +60,39 @@ template <typename T>
 __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const T* rhs, int n, T* dx,
                                                                int* status, unsigned int* min_bits) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  T* A = reinterpret_cast<T*>(dyn_lds);  // packed lower, row i at i(i+1)/2
-  T* b = A + n * (n + 1) / 2;
-  T* d0 = b + n;
+  T* d0 = reinterpret_cast<T*>(dyn_lds);  // [n] damped diagonal (pivot report)
+  T* invd = d0 + n;                       // [n]
+  T* piv = invd + n;                      // [n]
+  T* x = piv + n;                         // [n]
+  T* A = x + n;                           // packed lower, row i at i(i+1)/2; s appended as row n
+  __shared__ int bad;
+  __shared__ unsigned int minr_bits;
   const int tid = threadIdx.x;
+  const int np = n * (n + 1) / 2;
   for (int i = tid; i < n; i += blockDim.x) {
     const T* row = S + (size_t)i * n;
     T* dst = A + i * (i + 1) / 2;
     for (int j = 0; j <= i; ++j) dst[j] = row[j];
-    b[i] = rhs[i];
+    A[np + i] = rhs[i];
     d0[i] = row[i];
   }
+  if (tid == 0) {
+    A[np + n] = (T)0;
+    bad = 0;
+    minr_bits = __float_as_uint(3.0e38f);
+  }
   __syncthreads();
-  __shared__ int bad;
-  __shared__ float minr;
-  packed_cholesky<T>(A, n, d0, &bad, &minr);
-  packed_solve<T, T>(A, b, n);
-  for (int i = tid; i < n; i += blockDim.x) dx[i] = bad ? (T)0 : b[i];
+  packed_panel_factor<T>(A, n, n + 1, invd, piv, &bad);  // row n ends as y = L^-1 s
+  for (int j = tid; j < n; j += blockDim.x) {              // smallest pivot / damped diagonal
+    const float ratio = (float)(piv[j] / d0[j]);
+    atomicMin(&minr_bits, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
+  }
+  packed_back_solve<T>(A, n, invd, A + np, x);
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) dx[i] = bad ? (T)0 : x[i];
   if (tid == 0) {
     if (bad) atomicOr(status, 1);
-    pivot_min(min_bits, minr);
+    pivot_min(min_bits, __uint_as_float(minr_bits));
   }
 }
 
@@ -429,7 +442,8 @@ __global__ void zero_on_status_kernel(T* dx, int n, const int* status) {
 
 // ------------------------------------------------------------------ launchers
 
-// packed factor in LDS; the solves keep the vector on one wavefront (n <= 256)
+// packed panel factor in LDS; the substitutions keep the vector on one
+// wavefront (n <= 255)
 int small_solve_max_n(int tsize) { return tsize == 4 ? 240 : 160; }
 
 // Blocked factorisation in place (lower triangle of S becomes L) with the

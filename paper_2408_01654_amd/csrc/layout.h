@@ -149,9 +149,10 @@ __host__ __device__ inline int small_solve_lds_bytes(int n, int tsize) {
 }
 
 // Shared memory of the one-workgroup packed solve (small_chol_solve_kernel):
-// the packed lower triangle, the right-hand side and the step.
+// four vectors (damped diagonal, 1 / L_jj, pivots, step) and the packed
+// lower triangle with the right-hand side appended as row n.
 __host__ __device__ inline int packed_solve_lds_bytes(int n, int tsize) {
-  return (n * (n + 1) / 2 + 2 * n) * tsize;
+  return (4 * n + (n + 1) * (n + 2) / 2) * tsize;
 }
 
 }  // namespace dpvba
