@@ -210,6 +210,7 @@ struct dpvba_ctx {
   DevBuf part_S, part_vec, part_cost, part_invalid, U_s, pscale_s, depth_s, xh_s, poses_a, poses_b;
   DevBuf S, rhs, dB, d0, dx, wb, wy, Linv, edge_part, ticket, dev_err;
   DevBuf chain_flags;  // per 64-row block: forward and backward publication epochs
+  DevBuf one_inst;     // the analysed problem as a one-problem batch (small mixed solves)
   int chain_epoch = 0;
   DevBuf status, min_bits, devrep;
   // edge lists of the adjoint: per patch (pcount / pedges, edge order), per
@@ -372,7 +373,7 @@ void dpvba_destroy(dpvba_ctx* c) {
   DevBuf* bufs[] = {&c->part_S, &c->part_vec, &c->part_cost, &c->part_invalid, &c->U_s, &c->pscale_s,
                     &c->depth_s, &c->xh_s, &c->poses_a, &c->poses_b, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx,
                     &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
-                    &c->chain_flags,
+                    &c->chain_flags, &c->one_inst,
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
                     &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
                     &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
@@ -659,6 +660,14 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
     HIP_TRY(upload(c->pose_off, pose_off, st));
     HIP_TRY(upload(c->pose_src, pose_src, st));
     HIP_TRY(upload(c->patch_pos, pos, st));
+    BatchInst one{};
+    one.n_frames = N;
+    one.n_fixed = nf;
+    one.n_free = n_free;
+    one.n_patches = P;
+    one.n_edges = E;
+    one.n_tiles = (int)H32.tiles.size();
+    HIP_TRY(upload(c->one_inst, std::vector<BatchInst>{one}, st));
   }
 
   const size_t n = 6 * (size_t)n_free;
@@ -1000,6 +1009,37 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
                                             (const int2*)tl.v_src.p, c->n_free, S64, s64, (double*)c->dB.p,
                                             (double)lambda, 1, d064, st);
       if (e != hipSuccess) return e;
+    }
+    if (n > 0 && n <= kBatchMaxUnknowns) {
+      // one workgroup: float32 panel factor, refinement against the float64
+      // residual and the float64 fallback without leaving the kernel; it
+      // also writes the step and retracts the poses
+      BatchArgs<float> a{};
+      a.inst = (const BatchInst*)c->one_inst.p;
+      a.part_S = (const float*)c->part_S.p;
+      a.part_vec = (const float*)c->part_vec.p;
+      a.s_off = (const int*)tl.s_off.p;
+      a.s_src = (const int*)tl.s_src.p;
+      a.v_off = (const int*)tl.v_off.p;
+      a.v_src = (const int2*)tl.v_src.p;
+      a.lambda = (double)lambda;
+      a.poses_cur = cur;
+      a.poses_next = next;
+      a.dx = dx;
+      a.status = status;
+      a.min_bits = mb;
+      a.refine_resid = resid;
+      a.fallback = fb;
+      a.stride = DPVBA_MAX_ITERS;
+      a.it = it;
+      a.scratch = S64;  // packed system, s and d0 (float64) of the one problem
+      a.lds_factor = 1;
+      bool lf = false;
+      const int lds_solve = batch_solve_lds<float>(n, true, &lf);
+      TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
+      if ((e = launch_batch_gather<float, double>(a, 1, n, st)) != hipSuccess) return e;
+      if ((e = launch_batch_solve_mixed(a, 1, lds_solve, st)) != hipSuccess) return e;
+      continue;
     }
     if (n > 0) {
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);

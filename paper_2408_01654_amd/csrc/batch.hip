@@ -225,19 +225,53 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_kernel(BatchArgs<T>
   }
 }
 
-// r = s - S x for the packed symmetric S (float64), one row per thread;
-// returns max |r| (all threads), reduced in a fixed order through `red`.
+// r = s - S x for the packed symmetric S (float64).  A wavefront takes
+// eight rows at a time, lanes along the rows (entry (i, j) read from row i
+// for j <= i, else from row j; every load of a step in flight together), and
+// sums the eight rows over its lanes together in a halving butterfly.
+// Returns max |r| (all threads), reduced in a fixed order through `red`.
 __device__ double batch_residual(const double* S, const double* s, const double* x, double* r, int n, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   double mx = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double v = 0.0;
-    const double* row = S + packed_index(i, 0);
-    for (int j = 0; j <= i; ++j) v += row[j] * x[j];
-    for (int j = i + 1; j < n; ++j) v += S[packed_index(j, i)] * x[j];
-    const double ri = s[i] - v;
-    r[i] = ri;
-    if (ri != ri) mx = ri;  // a NaN sticks
-    else if (mx == mx) mx = fmax(mx, fabs(ri));
+  for (int i0 = 8 * wv; i0 < n; i0 += 8 * nwv) {
+    double part[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) part[u] = 0.0;
+    for (int j = lane; j < n; j += 64) {
+      const double xj = x[j];
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = min(i0 + u, n - 1);
+        a[u] = j <= i ? S[packed_index(i, j)] : S[packed_index(j, i)];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) part[u] += a[u] * xj;
+    }
+    // after the butterfly lane l holds the total of row i0 + 4 b5 + 2 b4 + b3
+    double h4[4], h2[2];
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double give = b5 ? part[q] : part[4 + q];
+      h4[q] = (b5 ? part[4 + q] : part[q]) + __shfl_xor(give, 32);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double give = b4 ? h4[q] : h4[2 + q];
+      h2[q] = (b4 ? h4[2 + q] : h4[q]) + __shfl_xor(give, 16);
+    }
+    double h = (b3 ? h2[1] : h2[0]) + __shfl_xor(b3 ? h2[0] : h2[1], 8);
+    h += __shfl_xor(h, 4);
+    h += __shfl_xor(h, 2);
+    h += __shfl_xor(h, 1);
+    const int row = i0 + 4 * (b5 ? 1 : 0) + 2 * (b4 ? 1 : 0) + (b3 ? 1 : 0);
+    if ((lane & 7) == 0 && row < n) {
+      const double ri = s[row] - h;
+      r[row] = ri;
+      if (ri != ri) mx = ri;  // a NaN sticks
+      else if (mx == mx) mx = fmax(mx, fabs(ri));
+    }
   }
   red[threadIdx.x] = mx;
   __syncthreads();

@@ -69,13 +69,26 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
   __shared__ unsigned int minr_bits;
   const int tid = threadIdx.x;
   const int np = n * (n + 1) / 2;
-  for (int i = tid; i < n; i += blockDim.x) {
-    const T* row = S + (size_t)i * n;
-    T* dst = A + i * (i + 1) / 2;
-    for (int j = 0; j <= i; ++j) dst[j] = row[j];
-    A[np + i] = rhs[i];
-    d0[i] = row[i];
+  // lower triangle of the dense row-major S, eight independent loads in
+  // flight per thread
+  const int nn = n * n;
+  for (int q0 = tid; q0 < nn; q0 += 8 * blockDim.x) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * blockDim.x, i = q / n, j = q - (q / n) * n;
+      v[u] = (q < nn && j <= i) ? S[q] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * blockDim.x, i = q / n, j = q - (q / n) * n;
+      if (q < nn && j <= i) {
+        A[packed_index(i, j)] = v[u];
+        if (i == j) d0[i] = v[u];
+      }
+    }
   }
+  for (int i = tid; i < n; i += blockDim.x) A[np + i] = rhs[i];
   if (tid == 0) {
     A[np + n] = (T)0;
     bad = 0;
