@@ -1003,7 +1003,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       TraceScope ts(c, DPVBA_PHASE_GATHER, st);
       e = launch_report_reduce((const double*)c->part_cost.p, (const int*)c->part_invalid.p, tl.n_tiles,
                                &dev->cost[it], &dev->n_invalid[it], st);
-      if (e == hipSuccess)
+      if (e == hipSuccess && n > kBatchMaxUnknowns)  // small systems are gathered by the one-problem batch
         e = launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
                                             (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
                                             (const int2*)tl.v_src.p, c->n_free, S64, s64, (double*)c->dB.p,

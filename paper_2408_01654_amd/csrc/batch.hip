@@ -142,7 +142,7 @@ __device__ __forceinline__ void copy_in(const TSRC* src, TD* dst, int count) {
 
 // Write the step and retract the problem's free poses.
 template <typename TS, typename TX>
-__device__ void batch_apply(const BatchArgs<TS>& a, const BatchInst& I, const TX* x, bool bad) {
+__device__ __forceinline__ void batch_apply(const BatchArgs<TS>& a, const BatchInst& I, const TX* x, bool bad) {
   const int n = 6 * I.n_free;
   for (int q = threadIdx.x; q < n; q += blockDim.x) a.dx[6 * (size_t)I.free_begin + q] = bad ? (TS)0 : (TS)x[q];
   for (int f = threadIdx.x; f < I.n_frames; f += blockDim.x) {
@@ -168,7 +168,8 @@ __device__ __forceinline__ void batch_pivot_min(unsigned int* min_bits, float ra
 // one wavefront.  Otherwise (float64 systems too wide for shared memory) the
 // packed factor works in the problem's scratch slice.
 template <typename T>
-__global__ void __launch_bounds__(kBatchThreads) batch_solve_kernel(BatchArgs<T> a) {
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+batch_solve_kernel(BatchArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ int bad;
   __shared__ float minr;
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_kernel(BatchArgs<T>
 // for j <= i, else from row j; every load of a step in flight together), and
 // sums the eight rows over its lanes together in a halving butterfly.
 // Returns max |r| (all threads), reduced in a fixed order through `red`.
-__device__ double batch_residual(const double* S, const double* s, const double* x, double* r, int n, double* red) {
+__device__ __forceinline__ double batch_residual(const double* S, const double* s, const double* x, double* r, int n, double* red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   double mx = 0.0;
   for (int i0 = 8 * wv; i0 < n; i0 += 8 * nwv) {
@@ -288,7 +289,10 @@ __device__ double batch_residual(const double* S, const double* s, const double*
 }
 
 // Mixed precision: float32 state and shares, float64 system in the scratch.
-__global__ void __launch_bounds__(kBatchThreads) batch_solve_mixed_kernel(BatchArgs<float> a) {
+// (Both solve kernels run one workgroup per problem and take the whole
+// register file: their shared memory allows about one workgroup per CU.)
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+batch_solve_mixed_kernel(BatchArgs<float> a) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ int bad;
   __shared__ float minr;
@@ -349,6 +353,7 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_mixed_kernel(BatchA
     smax = red[0];
     __syncthreads();
   }
+#pragma unroll 1
   for (int k = 0; k < kBatchRefine; ++k) {
     batch_residual(S64, s64, x64, r64, n, red);
     for (int q = threadIdx.x; q < n; q += blockDim.x) c32[q] = (float)r64[q];

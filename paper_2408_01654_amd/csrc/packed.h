@@ -592,7 +592,7 @@ __device__ __forceinline__ T lane_bcast(T v, int l) {
 // that is not positive or not finite is replaced by 1 and sets *bad (shared,
 // cleared by the caller).
 template <typename T>
-__device__ void packed_panel_factor(T* A, int n_in, int nr_in, T* invd, T* piv, int* bad) {
+__device__ __forceinline__ void packed_panel_factor(T* A, int n_in, int nr_in, T* invd, T* piv, int* bad) {
   const int n = __builtin_amdgcn_readfirstlane(n_in);
   const int nr = __builtin_amdgcn_readfirstlane(nr_in);
   const int tid = threadIdx.x;
@@ -690,7 +690,7 @@ __device__ __forceinline__ void packed_back16(int i_hi, int n, const T (*l)[16],
 // blocks of 16 rows from the last, whose L entries are loaded before the
 // dependent chain.  The other threads return at once (no barrier inside).
 template <typename T>
-__device__ void packed_back_solve(const T* A, int n_in, const T* invd, const T* y_in, T* x) {
+__device__ __forceinline__ void packed_back_solve(const T* A, int n_in, const T* invd, const T* y_in, T* x) {
   if (threadIdx.x >= 64) return;
   const int n = __builtin_amdgcn_readfirstlane(n_in);
   const int lane = threadIdx.x;
@@ -745,7 +745,7 @@ __device__ __forceinline__ void packed_fwd16(int i_lo, int n, const T (*l)[16], 
 // L y = b on the first wavefront (the companion of packed_back_solve; b and
 // y may alias).
 template <typename T>
-__device__ void packed_fwd_solve(const T* A, int n_in, const T* invd, const T* b_in, T* y) {
+__device__ __forceinline__ void packed_fwd_solve(const T* A, int n_in, const T* invd, const T* b_in, T* y) {
   if (threadIdx.x >= 64) return;
   const int n = __builtin_amdgcn_readfirstlane(n_in);
   const int lane = threadIdx.x;
