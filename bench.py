@@ -31,6 +31,14 @@ sys.path.insert(0, ROOT)
 METRIC = "BA edges/s & GN iters/s (fwd, fwd+adjoint) at oracle tolerance; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (each scaled by what the counter reads for a plain 256 MiB copy: x2.000 and
+# x1.000) for the kernels as they are in this tree; the commands and counts
+# are in profiles/tile_assembly_traffic.md.  Re-measure when either kernel
+# changes.
+TRAFFIC_WINDOW_LAUNCH = 4.906e6       # small_solve_kernel<float>, one 22-frame window solve
+TRAFFIC_GLOBAL_ASSEMBLY = 131.65e6    # tile_iterate_kernel<float>, global BA, per launch
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -144,7 +152,7 @@ def bench_global(steps, precision=None):
            "assembly_roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": ach / HBM_PEAK_GBS, "alg_bytes_per_launch": alg,
                                  "kernel": "tile_iterate_kernel", "avg_launch_us": avg["assemble"],
-                                 "traffic": None},
+                                 "traffic": TRAFFIC_GLOBAL_ASSEMBLY if precision == dp.FP32 else None},
            "cost": rep["cost"], "status": rep["status"]}
     log(f"[bench] global BA {name}: {out['ms_per_solve']:.2f} ms/solve, {out['edges_per_s']:.4g} edge-iters/s, "
         f"assembly {avg['assemble']:.1f} us ({ach:.0f} GB/s), analysis {t_an:.2f}s, err {err:.2e}")
@@ -464,7 +472,7 @@ def main():
              + 4 * info["u_elems"] + Pn * 12 + 4 * n + Pn * 4 + N * 28)
     achieved = fused / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_WINDOW_LAUNCH,
                 "kernel": "small_solve_kernel<float> (one fused window solve per launch)", "phase": dom,
                 "avg_launch_us": avg[dom] * 1e3, "alg_bytes_per_launch": fused}
 
