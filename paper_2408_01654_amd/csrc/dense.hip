@@ -68,6 +68,21 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
   __shared__ int bad;
   __shared__ unsigned int minr_bits;
   const int tid = threadIdx.x;
+  if (n + 1 <= kSmallRows) {  // the register-resident panel solver
+    __shared__ float minr;
+    const int nr = small_solve_rows(n);
+    T* xr = reinterpret_cast<T*>(dyn_lds) + 37 * nr + nr * nr;  // after the solver's own arrays
+    if (nr == 32) panel_chol_solve<T, 2>(n, S, rhs, nullptr, dyn_lds, xr, &bad, &minr, n);
+    else if (nr == 64) panel_chol_solve<T, 4>(n, S, rhs, nullptr, dyn_lds, xr, &bad, &minr, n);
+    else if (nr == 80) panel_chol_solve<T, 5>(n, S, rhs, nullptr, dyn_lds, xr, &bad, &minr, n);
+    else panel_chol_solve<T, 6>(n, S, rhs, nullptr, dyn_lds, xr, &bad, &minr, n);
+    for (int i = tid; i < n; i += blockDim.x) dx[i] = xr[i];  // zero when a pivot failed
+    if (tid == 0) {
+      if (bad) atomicOr(status, 1);
+      pivot_min(min_bits, minr);
+    }
+    return;
+  }
   const int np = n * (n + 1) / 2;
   // lower triangle of the dense row-major S, eight independent loads in
   // flight per thread
@@ -511,12 +526,14 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
                              unsigned int* min_bits, int* flags, int epoch, int* err, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (n <= small_solve_max_n(sizeof(T))) {
+    const int lds = n + 1 <= kSmallRows
+                        ? std::max(packed_solve_lds_bytes(n, sizeof(T)), small_solve_lds_bytes(n, sizeof(T)))
+                        : packed_solve_lds_bytes(n, sizeof(T));
     {
-      hipError_t e = opt_in_lds((const void*)small_chol_solve_kernel<T>, packed_solve_lds_bytes(n, sizeof(T)));
+      hipError_t e = opt_in_lds((const void*)small_chol_solve_kernel<T>, lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((small_chol_solve_kernel<T>), dim3(1), dim3(256), packed_solve_lds_bytes(n, sizeof(T)),
-                       st, S, rhs, n, dx, status, min_bits);
+    hipLaunchKernelGGL((small_chol_solve_kernel<T>), dim3(1), dim3(256), lds, st, S, rhs, n, dx, status, min_bits);
     return hipGetLastError();
   }
   hipError_t e = launch_chol_factor<T>(S, n, Linv_all, d0, status, min_bits, st);

@@ -405,9 +405,13 @@ __device__ __forceinline__ void back_sub16(int i_hi, int n, const T* l0, const T
 // the panel.  Two barriers per panel instead of one per column.  The last
 // row ends as y = L^-1 s; then L^T x = y on one wavefront.  Returns the step
 // in x[0..n) (LDS; zero if a pivot was not positive).
+// ld > 0: Sp_g is instead a dense row-major matrix with row stride ld (its
+// lower triangle is read) and d0_g may be null (the damped diagonal is then
+// that matrix's diagonal).
 template <typename T, int MB>
 __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const T* rhs_g, const T* d0_g,
-                                                 unsigned char* lds, T* x, int* bad_out, float* minr_out) {
+                                                 unsigned char* lds, T* x, int* bad_out, float* minr_out,
+                                                 int ld = 0) {
   constexpr int NR = 16 * MB;
   const int n = __builtin_amdgcn_readfirstlane(n_in);
   const int tid = threadIdx.x;
@@ -419,7 +423,7 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
   T* dd = invd + NR;                  // [NR] damped diagonal (pivot report)
   T* piv = dd + NR;                   // [NR] pivots before the square root
   T* Lrow = piv + NR;                 // [NR][NR]
-  for (int i = tid; i < n; i += blockDim.x) dd[i] = d0_g[i];
+  for (int i = tid; i < n; i += blockDim.x) dd[i] = d0_g ? d0_g[i] : Sp_g[(size_t)i * ld + i];
   T a[MB][MB];
 #pragma unroll
   for (int bi = 0; bi < MB; ++bi)
@@ -427,7 +431,7 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
     for (int bk = 0; bk < MB; ++bk) {
       const int i = 16 * bi + ty, k = 16 * bk + tx;
       T v = (T)0;
-      if (grid && k <= i && i < n) v = Sp_g[i * (i + 1) / 2 + k];
+      if (grid && k <= i && i < n) v = ld > 0 ? Sp_g[(size_t)i * ld + k] : Sp_g[i * (i + 1) / 2 + k];
       else if (grid && i == n && k < n) v = rhs_g[k];
       a[bi][bk] = v;
     }

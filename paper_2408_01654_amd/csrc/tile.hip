@@ -662,7 +662,7 @@ __device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const
 // Grid-wide barrier of a cooperative launch: bar[0] counts arrivals,
 // bar[1] is the generation.  Every wait is bounded; on timeout *err is set
 // and false returned, so no workgroup can spin forever.
-constexpr long long kSpinLimit = 1LL << 22;
+constexpr long long kSpinLimit = 1LL << 19;  // polls of ~1000 cycles each: a timeout after ~0.2 s
 
 __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, int* err) {
   __shared__ int ok;
@@ -678,7 +678,7 @@ __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, int* err) {
     } else {
       long long spins = 0;
       while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_s_sleep(16);  // few polls of the shared word while workgroup 0 factors
         if (++spins > kSpinLimit) {
           ok = 0;
           atomicOr(err, 1);
