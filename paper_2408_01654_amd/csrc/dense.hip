@@ -345,15 +345,18 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
 }
 
 // Both triangular solves of a blocked factor in one cooperative launch.
-// Workgroup g owns the 64-row blocks I = g, g + G, ...  Forward (L y = b):
-// block I subtracts L_IK y_K for K < I as each y_K is published, then
-// y_I = inv(L_II) acc and publishes it; backward (L^T x = y) runs the same
-// chain from the last block down with L_KI^T and inv(L_II)^T.  A block is
-// published by storing the call's epoch into its flag (agent-scope release
-// after the data); a consumer reads the flag with an agent-scope acquire.
-// Every wait is bounded: on timeout *err is set and the workgroup returns,
-// so every workgroup exits.  The L blocks are loaded before the wait for
-// the vector they multiply, so the chain only carries the dependent part.
+// The 64-row blocks go in pairs (2P, 2P + 1), and workgroup g owns the pairs
+// P = g, g + G, ...  Forward (L y = b): pair Q subtracts L_IK y_K (I in the
+// pair, K in an earlier pair) as each earlier pair is published, solves its
+// first block with inv(L_II), subtracts that block's share from the second
+// inside the workgroup and solves the second; backward (L^T x = y) runs the
+// same chain from the last pair down with L_KI^T and inv(L_II)^T.  Pairing
+// halves the number of inter-workgroup hops on the dependent chain.  A pair
+// is published by storing the call's epoch into its flag (agent-scope
+// release after the data); a consumer reads the flag with an agent-scope
+// acquire.  Every wait is bounded: on timeout *err is set and the workgroup
+// returns, so every workgroup exits.  The L blocks are loaded before the wait
+// for the vector they multiply, so the chain only carries the dependent part.
 constexpr long long kChainSpin = 1LL << 22;
 
 __device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err) {
@@ -384,80 +387,183 @@ __device__ __forceinline__ void chain_publish(int* flag, int epoch) {
 template <typename T>
 __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, const T* Linv_all, const T* b, T* y,
                                                          T* x, int* flags, int epoch, int* err) {
-  __shared__ T Li[kNB][kNB + 1];
-  __shared__ T acc[kNB];
-  __shared__ T vk[kNB];
-  __shared__ T part[4][kNB + 1];
+  __shared__ T Li[2][kNB][kNB + 1];  // inverses of the pair's diagonal blocks
+  __shared__ T acc[2][kNB];
+  __shared__ T vk[2][kNB];
+  __shared__ T part[2][4][kNB + 1];
   const int nblk = (n + kNB - 1) / kNB;
+  const int npair = (nblk + 1) / 2;
   const int tid = threadIdx.x;
   const int G = gridDim.x;
   int* fwd = flags;
   int* bwd = flags + nblk;
-  // ---- forward
-  for (int I = blockIdx.x; I < nblk; I += G) {
-    const int i0 = I * kNB, ib = min(kNB, n - i0);
-    if (tid < ib) acc[tid] = b[i0 + tid];
-    for (int idx = tid; idx < kNB * kNB; idx += blockDim.x)
-      Li[idx / kNB][idx % kNB] = Linv_all[(size_t)I * kNB * kNB + idx];
-    const int r = tid >> 2, q = tid & 3;  // 4 threads per row, 16 columns each
-    for (int K = 0; K < I; ++K) {
-      T lrow[16];
-      const T* src = L + (size_t)(i0 + r) * n + K * kNB + 16 * q;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) lrow[m] = r < ib ? src[m] : (T)0;
-      if (!chain_wait(fwd + K, epoch, err)) return;
-      if (tid < kNB) vk[tid] = y[K * kNB + tid];
-      __syncthreads();
-      T v = (T)0;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) v += lrow[m] * vk[16 * q + m];
-      part[q][r] = v;
-      __syncthreads();
-      if (tid < ib) acc[tid] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
-      __syncthreads();
+  // ---- forward: thread (r, q) = (tid / 4, tid mod 4) takes row r, columns 16 q .. 16 q + 15
+  for (int Q = blockIdx.x; Q < npair; Q += G) {
+    const int I0 = 2 * Q, I1 = 2 * Q + 1;
+    const int i0 = I0 * kNB, rows0 = min(kNB, n - i0);
+    const int i1 = I1 * kNB, rows1 = I1 < nblk ? min(kNB, n - i1) : 0;
+    if (tid < kNB) {
+      acc[0][tid] = tid < rows0 ? b[i0 + tid] : (T)0;
+      acc[1][tid] = tid < rows1 ? b[i1 + tid] : (T)0;
     }
-    __syncthreads();
-    if (tid < ib) {
-      T v = (T)0;
-      for (int m = 0; m <= tid; ++m) v += Li[tid][m] * acc[m];
-      y[i0 + tid] = v;
+    for (int idx = tid; idx < kNB * kNB; idx += blockDim.x) {  // entries outside a partial block are never written
+      const int ra = idx / kNB, cb = idx % kNB;
+      Li[0][ra][cb] = (ra < rows0 && cb < rows0) ? Linv_all[(size_t)I0 * kNB * kNB + idx] : (T)0;
+      Li[1][ra][cb] = (ra < rows1 && cb < rows1) ? Linv_all[(size_t)I1 * kNB * kNB + idx] : (T)0;
     }
-    chain_publish(fwd + I, epoch);
-  }
-  // ---- backward, blocks in decreasing order
-  const int last = blockIdx.x + ((nblk - 1 - blockIdx.x) / G) * G;
-  for (int I = last; I >= 0 && blockIdx.x < nblk; I -= G) {
-    const int i0 = I * kNB, ib = min(kNB, n - i0);
-    if (tid < ib) acc[tid] = y[i0 + tid];
-    for (int idx = tid; idx < kNB * kNB; idx += blockDim.x)
-      Li[idx / kNB][idx % kNB] = Linv_all[(size_t)I * kNB * kNB + idx];
-    const int c = tid & 63, q = tid >> 6;  // thread per column, 4 groups of 16 rows
-    for (int K = nblk - 1; K > I; --K) {
-      const int k0 = K * kNB, kb = min(kNB, n - k0);
-      T lcol[16];
+    const int r = tid >> 2, q = tid & 3;
+    T lc[16];  // L_{I1, I0}: the in-pair block
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int rr = 16 * q + m;
-        lcol[m] = (rr < kb && c < ib) ? L[(size_t)(k0 + rr) * n + i0 + c] : (T)0;
+    for (int m = 0; m < 16; ++m) lc[m] = r < rows1 ? L[(size_t)(i1 + r) * n + i0 + 16 * q + m] : (T)0;
+    for (int P = 0; P < Q; ++P) {
+      const int k0 = 2 * P * kNB;  // both blocks of an earlier pair are full
+      T la[32], lb[32];
+#pragma unroll
+      for (int m = 0; m < 32; ++m) {
+        const int col = k0 + (m >> 4) * kNB + 16 * q + (m & 15);
+        la[m] = r < rows0 ? L[(size_t)(i0 + r) * n + col] : (T)0;
+        lb[m] = r < rows1 ? L[(size_t)(i1 + r) * n + col] : (T)0;
       }
-      if (!chain_wait(bwd + K, epoch, err)) return;
-      if (tid < kNB) vk[tid] = tid < kb ? x[k0 + tid] : (T)0;
+      if (!chain_wait(fwd + P, epoch, err)) return;
+      if (tid < kNB) {
+        vk[0][tid] = y[k0 + tid];
+        vk[1][tid] = y[k0 + kNB + tid];
+      }
       __syncthreads();
-      T v = (T)0;
+      T va = (T)0, vb = (T)0;
 #pragma unroll
-      for (int m = 0; m < 16; ++m) v += lcol[m] * vk[16 * q + m];
-      part[q][c] = v;
+      for (int m = 0; m < 32; ++m) {
+        const T v = vk[m >> 4][16 * q + (m & 15)];
+        va += la[m] * v;
+        vb += lb[m] * v;
+      }
+      part[0][q][r] = va;
+      part[1][q][r] = vb;
       __syncthreads();
-      if (tid < ib) acc[tid] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+      if (tid < 2 * kNB) {
+        const int h = tid >> 6, t = tid & 63;
+        acc[h][t] -= (part[h][0][t] + part[h][1][t]) + (part[h][2][t] + part[h][3][t]);
+      }
       __syncthreads();
     }
     __syncthreads();
-    if (tid < ib) {
+    {  // first block: y = inv(L_II) acc (thread (r, q): 16 terms of row r), kept in vk[0]
       T v = (T)0;
-      for (int m = tid; m < ib; ++m) v += Li[m][tid] * acc[m];
-      x[i0 + tid] = v;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v += Li[0][r][16 * q + m] * acc[0][16 * q + m];
+      part[0][q][r] = v;
+      __syncthreads();
+      if (tid < kNB) {
+        const T w = (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
+        vk[0][tid] = tid < rows0 ? w : (T)0;
+        if (tid < rows0) y[i0 + tid] = w;
+      }
+      __syncthreads();
     }
-    chain_publish(bwd + I, epoch);
+    if (rows1) {
+      T v = (T)0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v += lc[m] * vk[0][16 * q + m];
+      part[1][q][r] = v;
+      __syncthreads();
+      if (tid < kNB) acc[1][tid] -= (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
+      __syncthreads();
+      T w = (T)0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) w += Li[1][r][16 * q + m] * acc[1][16 * q + m];
+      part[0][q][r] = w;
+      __syncthreads();
+      if (tid < rows1) y[i1 + tid] = (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
+    }
+    chain_publish(fwd + Q, epoch);
+  }
+  // ---- backward, pairs in decreasing order: thread (c, q) = (tid mod 64, tid / 64)
+  // takes column c and rows 16 q .. 16 q + 15 of a block
+  const int last = blockIdx.x + ((npair - 1 - blockIdx.x) / G) * G;
+  for (int Q = last; Q >= 0 && blockIdx.x < npair; Q -= G) {
+    const int I0 = 2 * Q, I1 = 2 * Q + 1;
+    const int i0 = I0 * kNB, rows0 = min(kNB, n - i0);
+    const int i1 = I1 * kNB, rows1 = I1 < nblk ? min(kNB, n - i1) : 0;
+    if (tid < kNB) {
+      acc[0][tid] = tid < rows0 ? y[i0 + tid] : (T)0;
+      acc[1][tid] = tid < rows1 ? y[i1 + tid] : (T)0;
+    }
+    for (int idx = tid; idx < kNB * kNB; idx += blockDim.x) {  // entries outside a partial block are never written
+      const int ra = idx / kNB, cb = idx % kNB;
+      Li[0][ra][cb] = (ra < rows0 && cb < rows0) ? Linv_all[(size_t)I0 * kNB * kNB + idx] : (T)0;
+      Li[1][ra][cb] = (ra < rows1 && cb < rows1) ? Linv_all[(size_t)I1 * kNB * kNB + idx] : (T)0;
+    }
+    const int c = tid & 63, q = tid >> 6;
+    T lc[16];  // column c of L_{I1, I0}^T = L_{I1, I0} rows 16 q .., column c
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int rr = 16 * q + m;
+      lc[m] = (rr < rows1 && c < rows0) ? L[(size_t)(i1 + rr) * n + i0 + c] : (T)0;
+    }
+    for (int P = npair - 1; P > Q; --P) {
+      const int K0 = 2 * P, K1 = 2 * P + 1;
+      const int k0 = K0 * kNB, kb0 = min(kNB, n - k0);
+      const int k1 = K1 * kNB, kb1 = K1 < nblk ? min(kNB, n - k1) : 0;
+      T la[32], lb[32];  // columns c of blocks I0 / I1, rows of K0 (m < 16) and K1 (m >= 16)
+#pragma unroll
+      for (int m = 0; m < 32; ++m) {
+        const int rr = 16 * q + (m & 15);
+        const int kb = m < 16 ? kb0 : kb1, kr = m < 16 ? k0 : k1;
+        la[m] = (rr < kb && c < rows0) ? L[(size_t)(kr + rr) * n + i0 + c] : (T)0;
+        lb[m] = (rr < kb && c < rows1) ? L[(size_t)(kr + rr) * n + i1 + c] : (T)0;
+      }
+      if (!chain_wait(bwd + P, epoch, err)) return;
+      if (tid < kNB) {
+        vk[0][tid] = tid < kb0 ? x[k0 + tid] : (T)0;
+        vk[1][tid] = tid < kb1 ? x[k1 + tid] : (T)0;
+      }
+      __syncthreads();
+      T va = (T)0, vb = (T)0;
+#pragma unroll
+      for (int m = 0; m < 32; ++m) {
+        const T v = vk[m >> 4][16 * q + (m & 15)];
+        va += la[m] * v;
+        vb += lb[m] * v;
+      }
+      part[0][q][c] = va;
+      part[1][q][c] = vb;
+      __syncthreads();
+      if (tid < 2 * kNB) {
+        const int h = tid >> 6, t = tid & 63;
+        acc[h][t] -= (part[h][0][t] + part[h][1][t]) + (part[h][2][t] + part[h][3][t]);
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (rows1) {  // second block first: x = inv(L_II)^T acc (thread (c, q): 16 terms of column c), kept in vk[1]
+      T v = (T)0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v += Li[1][16 * q + m][c] * acc[1][16 * q + m];
+      part[1][q][c] = v;
+      __syncthreads();
+      if (tid < kNB) {
+        const T w = (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
+        vk[1][tid] = tid < rows1 ? w : (T)0;
+        if (tid < rows1) x[i1 + tid] = w;
+      }
+      __syncthreads();
+      T u = (T)0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) u += lc[m] * vk[1][16 * q + m];
+      part[0][q][c] = u;
+      __syncthreads();
+      if (tid < kNB) acc[0][tid] -= (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
+      __syncthreads();
+    }
+    {
+      T v = (T)0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v += Li[0][16 * q + m][c] * acc[0][16 * q + m];
+      part[1][q][c] = v;
+      __syncthreads();
+      if (tid < rows0) x[i0 + tid] = (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
+    }
+    chain_publish(bwd + Q, epoch);
   }
 }
 
@@ -504,7 +610,7 @@ int trsv_chain_grid(int nblk) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)trsv_chain_kernel<T>, 256, 0) !=
       hipSuccess)
     return 0;
-  return std::min(nblk, per_cu * cus);
+  return std::min((nblk + 1) / 2, per_cu * cus);  // one workgroup per pair of blocks at most
 }
 
 // x = (L L^T)^-1 rhs with a factor from launch_chol_factor: one cooperative

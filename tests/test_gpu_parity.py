@@ -110,9 +110,12 @@ def test_solve_matches_oracle(dp, ctx, mk, prec):
     _compare(s, P, D, Po, Do, TOL[prec], f"{s.name} {prec}")
 
 
-def test_large_reduced_system_uses_blocked_factorisation(dp, ctx):
-    # 60 frames, 58 free: n = 348 > the single-workgroup limit
-    s = tiny_scene(60, 12, seed=4, radius=5, trajectory="forward")
+@pytest.mark.parametrize("frames", [60, 52])
+def test_large_reduced_system_uses_blocked_factorisation(dp, ctx, frames):
+    # 60 frames, 58 free: n = 348 (six 64-row blocks: three pairs of the
+    # triangular-solve chain); 52 frames: n = 300 (five blocks: the last pair
+    # has one block); both above the single-workgroup limit
+    s = tiny_scene(frames, 12, seed=4, radius=5, trajectory="forward")
     _log(f"blocked path {s.name} E={s.n_edges}")
     Po, Do, _ = ba64.solve_scene(s)
     for prec in ("fp64", "mixed", "fp32"):
