@@ -198,10 +198,7 @@ batch_solve_kernel(BatchArgs<T> a) {
     }
     __syncthreads();
     packed_panel_factor<T>(A, n, n + 1, invd, piv, &bad);
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {  // smallest pivot / damped diagonal
-      const float ratio = (float)(piv[j] / d0[j]);
-      atomicMin(&minr_bits, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
-    }
+    pivot_ratio_min<T>(piv, d0, n, &minr_bits);  // smallest pivot / damped diagonal
     packed_back_solve<T>(A, n, invd, A + np, x);
     __syncthreads();
     const bool failed = bad != 0;
@@ -331,10 +328,7 @@ batch_solve_mixed_kernel(BatchArgs<float> a) {
   }
   __syncthreads();
   packed_panel_factor<float>(A32, n, n + 1, invd32, piv32, &bad32);
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const float ratio = piv32[j] / d32[j];
-    atomicMin(&minr_bits, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
-  }
+  pivot_ratio_min<float>(piv32, d32, n, &minr_bits);
   packed_back_solve<float>(A32, n, invd32, A32 + np, c32);
   __syncthreads();
   const float minr32 = __uint_as_float(minr_bits);

@@ -111,10 +111,7 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
   }
   __syncthreads();
   packed_panel_factor<T>(A, n, n + 1, invd, piv, &bad);  // row n ends as y = L^-1 s
-  for (int j = tid; j < n; j += blockDim.x) {              // smallest pivot / damped diagonal
-    const float ratio = (float)(piv[j] / d0[j]);
-    atomicMin(&minr_bits, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
-  }
+  pivot_ratio_min<T>(piv, d0, n, &minr_bits);              // smallest pivot / damped diagonal
   packed_back_solve<T>(A, n, invd, A + np, x);
   __syncthreads();
   for (int i = tid; i < n; i += blockDim.x) dx[i] = bad ? (T)0 : x[i];
@@ -257,10 +254,7 @@ __device__ __forceinline__ void diag_factor(T* S, int n, int k0, int kb_in, T* L
       }
     }
   if (bad) atomicOr(&bad_s, 1);
-  if (tid < kb) {  // pivot report: smallest pivot / damped diagonal
-    const float ratio = (float)(piv[tid] / dd[tid]);
-    atomicMin(&minr_s, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
-  }
+  pivot_ratio_min<T>(piv, dd, kb, &minr_s);  // pivot report: smallest pivot / damped diagonal
   __syncthreads();
   if (tid == 0) {
     if (bad_s) atomicOr(status, 1);

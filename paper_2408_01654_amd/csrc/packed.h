@@ -18,6 +18,24 @@ __device__ __forceinline__ T pivot_rsqrt(T d) {
   else return (T)1 / sqrt(d);
 }
 
+// Smallest pivot / damped-diagonal ratio of columns 0..n-1 (the bits of a
+// non-negative float, a NaN counting as 0) combined into *min_bits: every
+// thread takes columns tid, tid + blockDim.x, ..., each wavefront reduces its
+// lanes with shuffles, and one lane per wavefront issues the atomic minimum
+// (one LDS atomic per wavefront instead of one per column).  Called by every
+// thread of the workgroup.
+template <typename T>
+__device__ __forceinline__ void pivot_ratio_min(const T* piv, const T* dd, int n, unsigned int* min_bits) {
+  unsigned int m = __float_as_uint(3.0e38f);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const float ratio = (float)(piv[j] / dd[j]);
+    m = min(m, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = min(m, (unsigned int)__shfl_xor((int)m, o));
+  if ((threadIdx.x & 63) == 0) atomicMin(min_bits, m);
+}
+
 __device__ __forceinline__ int packed_index(int i, int j) { return i * (i + 1) / 2 + j; }
 
 // In-place A = L L^T, right-looking with the column scaling deferred: step j
@@ -528,10 +546,7 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
   if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }
   __syncthreads();
   if (bad) atomicOr(&bad_s, 1);
-  if (tid < n) {  // pivot report: smallest pivot / damped diagonal
-    const float ratio = (float)(piv[tid] / dd[tid]);
-    atomicMin(&minr_s, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
-  }
+  pivot_ratio_min<T>(piv, dd, n, &minr_s);  // pivot report: smallest pivot / damped diagonal
   if (tid < 64) {  // backward substitution L^T x = y; lane l holds entries l, l + 64
     const int r0 = tid, r1 = tid + 64;
     T y0 = r0 < n ? Lrow[n * NR + r0] : (T)0;
