@@ -631,10 +631,29 @@ __device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const
   __shared__ float minr;
   const int nr = small_solve_rows(n);
   T* x = reinterpret_cast<T*>(lds) + 37 * nr + nr * nr;  // after the solver's own arrays
+  // The tiles' costs and invalid-edge counts of this iteration: loaded in
+  // parallel before the factor (their latency overlaps it), summed in tile
+  // order after it.  At most 256 are staged; any beyond are read in order.
+  const int n_cost = A.cost_out ? A.n_tiles : 0;
+  const int n_stage = n_cost < 256 ? n_cost : 256;
+  double pcost = 0.0;
+  int pinv = 0;
+  if (tid < n_stage) {
+    pcost = A.part_cost[tid];
+    pinv = A.part_invalid[tid];
+  }
   if (nr == 32) panel_chol_solve<T, 2>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
   else if (nr == 64) panel_chol_solve<T, 4>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
   else if (nr == 80) panel_chol_solve<T, 5>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
   else panel_chol_solve<T, 6>(n, Sp_g, rhs_g, d0_g, lds, x, &bad, &minr);
+  // the published-panel area (2 x 32 x 17 values or more) is free after the factor
+  double* cost_s = reinterpret_cast<double*>(lds);
+  int* inv_s = reinterpret_cast<int*>(cost_s + 256);
+  if (tid < n_stage) {
+    cost_s[tid] = pcost;
+    inv_s[tid] = pinv;
+  }
+  __syncthreads();
   for (int i = tid; i < n; i += blockDim.x) A.dx[i] = x[i];
   for (int i = tid; i < A.n_frames; i += blockDim.x) {
     const T* pc = A.poses_cur + 7 * (size_t)i;
@@ -648,7 +667,11 @@ __device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const
     if (A.cost_out) {
       double cc = 0.0;
       int inv = 0;
-      for (int t = 0; t < A.n_tiles; ++t) {
+      for (int t = 0; t < n_stage; ++t) {
+        cc += cost_s[t];
+        inv += inv_s[t];
+      }
+      for (int t = n_stage; t < n_cost; ++t) {
         cc += A.part_cost[t];
         inv += A.part_invalid[t];
       }
