@@ -232,6 +232,18 @@ dpvba_status dpvba_reduced_system(dpvba_ctx* ctx, const dpvba_graph* g, const fl
 dpvba_status dpvba_solve(dpvba_ctx* ctx, const dpvba_graph* g, float* poses, float* inv_depth,
                          const dpvba_opts* opts, dpvba_report* report, void* stream);
 
+/* Launch of the single-launch solver that dpvba_solve uses for small
+ * reduced systems (6 x free poses + 1 <= 96; the sliding window of Sec. 3.1):
+ * one kernel whose workgroups meet at grid-wide barriers, never more
+ * workgroups than the device holds at once.  cooperative = 0 (the default):
+ * an ordinary launch, which relies on the device placing every workgroup
+ * while the first ones wait -- true when the device's other work finishes;
+ * every wait is bounded, so a violation returns DPVBA_EHIP rather than
+ * hanging.  cooperative = 1: a cooperative launch, whose co-residency the
+ * runtime guarantees, at a higher cost per launch.  Results are identical
+ * bit for bit.  EINVAL for other values.                                  */
+dpvba_status dpvba_set_cooperative(dpvba_ctx* ctx, int32_t cooperative);
+
 /* Adjoint of dpvba_solve, for training through the BA layer (Sec. 2: the
  * network is supervised on the camera poses that bundle adjustment
  * produces; objective eq. 3).  Given the gradient of a loss with respect to

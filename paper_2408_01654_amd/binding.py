@@ -100,6 +100,8 @@ def lib():
         L.dpvba_analyze_batch.restype = ctypes.c_int
         L.dpvba_solve_batch.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, ctypes.POINTER(Opts), vp, vp]
         L.dpvba_solve_batch.restype = ctypes.c_int
+        L.dpvba_set_cooperative.argtypes = [vp, ctypes.c_int32]
+        L.dpvba_set_cooperative.restype = ctypes.c_int
         L.dpvba_trace_begin.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         L.dpvba_trace_begin.restype = ctypes.c_int
         L.dpvba_trace_end.argtypes = [vp, vp, vp, vp]
@@ -367,6 +369,11 @@ class Context:
             return None
         (torch.cuda.current_stream() if stream is None else stream).synchronize()
         return [r.to_dict() for r in reps]
+
+    def set_cooperative(self, cooperative: bool):
+        """Cooperative (True) or ordinary (False, the default) launch of the
+        single-launch small-system solver; results are identical."""
+        _check(lib().dpvba_set_cooperative(self._h, int(bool(cooperative))), "dpvba_set_cooperative", self._h)
 
     def trace_begin(self, sample_every: int = 1, max_pairs: int = 1 << 16):
         _check(lib().dpvba_trace_begin(self._h, int(sample_every), int(max_pairs)), "dpvba_trace_begin", self._h)

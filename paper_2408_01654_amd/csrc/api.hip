@@ -32,7 +32,7 @@ hipError_t launch_retract_copy(const T* poses_cur, T* poses_next, const T* dx, i
 template <typename T>
 int small_solve_grid(int lds_bytes);
 template <typename T>
-hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, hipStream_t st);
+hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, bool cooperative, hipStream_t st);
 int small_solve_max_n(int tsize);
 template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
@@ -206,6 +206,7 @@ struct dpvba_ctx {
   const int32_t *ii = nullptr, *jj = nullptr, *kk = nullptr;
   Tiling tl[2];  // [0] float32 plan, [1] float64 plan
   int coop_grid32 = 0, coop_lds32 = -1, coop_grid64 = 0, coop_lds64 = -1;  // co-resident workgroups
+  bool coop_launch = false;  // single-launch solver: cooperative launch instead of an ordinary one
   // workspace
   DevBuf part_S, part_vec, part_cost, part_invalid, U_s, pscale_s, depth_s, xh_s, poses_a, poses_b;
   DevBuf S, rhs, dB, d0, dx, wb, wy, Linv, edge_part, ticket, dev_err;
@@ -304,6 +305,12 @@ dpvba_status dpvba_get_analysis_info(const dpvba_ctx* c, int32_t precision, dpvb
   info->grid_cells = t.grid_cells;
   info->u_elems = t.u_elems;
   info->lds_bytes = t.lds_bytes;
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_set_cooperative(dpvba_ctx* c, int32_t cooperative) {
+  if (!c || (cooperative != 0 && cooperative != 1)) return DPVBA_EINVAL;
+  c->coop_launch = cooperative == 1;
   return DPVBA_OK;
 }
 
@@ -884,7 +891,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     const int grid = std::min(tl.n_tiles, cap);
     if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
     TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
-    e = launch_small_solve<T>(S, grid, lds_small, st);
+    e = launch_small_solve<T>(S, grid, lds_small, c->coop_launch, st);
     if (e != hipSuccess) return e;
   }
   if (!small) {

@@ -682,7 +682,7 @@ __device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const
   __syncthreads();
 }
 
-// Grid-wide barrier of a cooperative launch: bar[0] counts arrivals,
+// Grid-wide barrier of the single-launch solver: bar[0] counts arrivals,
 // bar[1] is the generation.  Every wait is bounded; on timeout *err is set
 // and false returned, so no workgroup can spin forever.
 constexpr long long kSpinLimit = 1LL << 19;  // polls of ~1000 cycles each: a timeout after ~0.2 s
@@ -741,7 +741,7 @@ __device__ void tile_writeback(const TileInfo& ti, const int* tile_patch, const 
   __syncthreads();
 }
 
-// Whole solve of a small problem in one cooperative launch: per iteration
+// Whole solve of a small problem in one launch: per iteration
 // every workgroup assembles its tiles, all wavefronts gather the damped
 // reduced system, workgroup 0 factors, solves and retracts; finally the
 // depths are written back.  Poses ping-pong between two buffers.
@@ -864,11 +864,21 @@ int small_solve_grid(int lds_bytes) {
   return cus * per_cu;
 }
 
+// grid never exceeds small_solve_grid (the workgroups the device holds at
+// once).  The ordinary launch relies on the dispatcher placing every
+// workgroup while the first ones wait at a grid barrier, which holds on a
+// device whose other work finishes; the bounded waits of grid_sync turn a
+// violation into an error, never a hang.  The cooperative launch has the
+// runtime guarantee co-residency, at a higher launch cost.
 template <typename T>
-hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, hipStream_t st) {
+hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, bool cooperative, hipStream_t st) {
   hipError_t e = opt_in_lds((const void*)small_solve_kernel<T>, lds_bytes);
   if (e != hipSuccess) return e;
   SmallArgs<T> copy = S;
+  if (!cooperative) {
+    hipLaunchKernelGGL((small_solve_kernel<T>), dim3(grid), dim3(tile_threads(sizeof(T))), lds_bytes, st, copy);
+    return hipGetLastError();
+  }
   void* args[] = {&copy};
   return hipLaunchCooperativeKernel((const void*)small_solve_kernel<T>, dim3(grid), dim3(tile_threads(sizeof(T))), args,
                                     lds_bytes, st);
@@ -881,7 +891,7 @@ hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, hi
                                               T*, int, hipStream_t);                                       \
   template hipError_t launch_retract_copy<T>(const T*, T*, const T*, int, int, const int*, hipStream_t);  \
   template int small_solve_grid<T>(int);                                                                  \
-  template hipError_t launch_small_solve<T>(const SmallArgs<T>&, int, int, hipStream_t);
+  template hipError_t launch_small_solve<T>(const SmallArgs<T>&, int, int, bool, hipStream_t);
 
 DPVBA_TILE_INSTANTIATE(float)
 DPVBA_TILE_INSTANTIATE(double)

@@ -145,6 +145,22 @@ def test_bitwise_deterministic(dp, ctx):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_cooperative_launch_matches_ordinary(dp, ctx, prec):
+    # the single-launch solver gives the same bits under either launch
+    s = make_window(11)
+    try:
+        ctx.set_cooperative(True)
+        a = _gpu_solve(dp, ctx, s, PREC[prec])
+    finally:
+        ctx.set_cooperative(False)
+    b = _gpu_solve(dp, ctx, s, PREC[prec])
+    assert a[2]["status"] == 0 and b[2]["status"] == 0
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2]["cost"] == b[2]["cost"]
+    assert dp.binding.lib().dpvba_set_cooperative(ctx._h, 2) == dp.binding.DPVBA_EINVAL
+
+
 def _edit(s: Scene, **kw) -> Scene:
     d = dict(s.__dict__)
     d.update(kw)
