@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # x1.000) for the kernels as they are in this tree; the commands and counts
 # are in profiles/tile_assembly_traffic.md.  Re-measure when either kernel
 # changes.
-TRAFFIC_WINDOW_LAUNCH = 4.900e6       # small_solve_kernel<float>, one 22-frame window solve
+TRAFFIC_WINDOW_LAUNCH = 4.884e6       # small_solve_kernel<float>, one 22-frame window solve
 TRAFFIC_GLOBAL_ASSEMBLY = 131.65e6    # tile_iterate_kernel<float>, global BA, per launch
 
 
@@ -459,8 +459,8 @@ def main():
     share = {k: avg[k] * v[2] for k, v in phases.items()}
     dom = max(share, key=share.get)
     n = 6 * info["n_free"]
-    # One timed launch is one whole window solve (a single cooperative kernel for
-    # systems of this size): two tile passes, two gathers of the tile shares into
+    # One timed launch is one whole window solve (a single kernel for systems of
+    # this size): two tile passes, two gathers of the tile shares into
     # the packed reduced system (written, then read by the factorisation), the
     # pose updates and the final depth write-back.
     n = 6 * info["n_free"]
