@@ -25,9 +25,14 @@ __device__ __forceinline__ T pivot_rsqrt(T d) {
 // (one LDS atomic per wavefront instead of one per column).  Called by every
 // thread of the workgroup.
 template <typename T>
-__device__ __forceinline__ void pivot_ratio_min(const T* piv, const T* dd, int n, unsigned int* min_bits) {
+__device__ __forceinline__ void pivot_ratio_min(const T* piv, const T* dd, int n, unsigned int* min_bits,
+                                                int first = -1, int stride = 0) {
   unsigned int m = __float_as_uint(3.0e38f);
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  if (first < 0) {
+    first = threadIdx.x;
+    stride = blockDim.x;
+  }
+  for (int j = first; j < n; j += stride) {
     const float ratio = (float)(piv[j] / dd[j]);
     m = min(m, __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f));
   }
@@ -466,11 +471,12 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
     if (wave == (p & 3)) {
       // lane l holds rows 16 p + l and 16 p + l + 64 of the panel
       const int rA = 16 * p + lane, rB = rA + 64;
+      const bool hasB = 16 * p + 64 < NR;  // compile-time: rows in the second half exist
       T ra[16], rb[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
         ra[c] = rA < NR ? P[rA * 17 + c] : (T)0;
-        rb[c] = rB < NR ? P[rB * 17 + c] : (T)0;
+        rb[c] = (hasB && rB < NR) ? P[rB * 17 + c] : (T)0;
       }
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
@@ -493,7 +499,7 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
         const T rs = pivot_rsqrt<T>(d);
         if (lane == 0) invd[j] = rs;
         ra[c] *= rs;  // row j's own entry becomes L_jj = sqrt(d)
-        rb[c] *= rs;
+        if (hasB) rb[c] *= rs;
 #pragma unroll
         for (int c2 = c + 1; c2 < 16; ++c2) {
           T lk;  // l_{16p + c2, j}: lane c2's entry of column c
@@ -506,13 +512,13 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
             lk = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
           }
           ra[c2] -= ra[c] * lk;
-          rb[c2] -= rb[c] * lk;
+          if (hasB) rb[c2] -= rb[c] * lk;
         }
       }
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
         if (rA < NR) P[rA * 17 + c] = ra[c];
-        if (rB < NR) P[rB * 17 + c] = rb[c];
+        if (hasB && rB < NR) P[rB * 17 + c] = rb[c];
       }
     }
     __syncthreads();
@@ -546,7 +552,9 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
   if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }
   __syncthreads();
   if (bad) atomicOr(&bad_s, 1);
-  pivot_ratio_min<T>(piv, dd, n, &minr_s);  // pivot report: smallest pivot / damped diagonal
+  // pivot report (smallest pivot / damped diagonal) on the wavefronts other
+  // than the first, while the first runs the backward substitution
+  if (tid >= 64) pivot_ratio_min<T>(piv, dd, n, &minr_s, tid - 64, (int)blockDim.x - 64);
   if (tid < 64) {  // backward substitution L^T x = y; lane l holds entries l, l + 64
     const int r0 = tid, r1 = tid + 64;
     T y0 = r0 < n ? Lrow[n * NR + r0] : (T)0;
