@@ -189,12 +189,18 @@ hipError_t upload(DevBuf& b, const std::vector<X>& v, hipStream_t st) {
 
 // Device copy of one tiling of the patch graph.
 struct Tiling {
-  int n_tiles = 0, lds_bytes = 0, max_w6 = 0;
+  int n_tiles = 0, lds_bytes = 0, max_w6 = 0, max_k = 0;
   long long part_S = 0, part_vec = 0, u_elems = 0, u_alloc = 0, grid_cells = 0, n_tp = 0;
   DevBuf tiles, tile_patch, slot_frame, slot_blk, edge_grid, blk_pose, s_off, s_src, v_off, v_src;
   DevBuf* bufs[10] = {&tiles, &tile_patch, &slot_frame, &slot_blk, &edge_grid, &blk_pose, &s_off, &s_src, &v_off,
                       &v_src};
 };
+
+// Shared memory of the depth write-back (tile_writeback): the block step
+// row [dxi | 1 | 0 ...] of the widest tile and the dots of the largest one.
+static int writeback_lds_bytes(const Tiling& tl, int tsize) {
+  return (tile_u_stride(tl.max_w6 / 6) + tl.max_k) * tsize;
+}
 
 }  // namespace
 
@@ -425,7 +431,7 @@ struct HostTiling {
   long long part_S = 0, part_vec = 0;
   long long u_elems = 0;  // entries of the stored Schur rows (K 6 n_blk per tile)
   long long u_alloc = 0;  // their padded storage (tile_u_rows x tile_u_stride per tile)
-  int lds = 0, max_w6 = 0;
+  int lds = 0, max_w6 = 0, max_k = 0;
 };
 
 // Edge structure of one problem from host copies of its indices: edges
@@ -532,6 +538,7 @@ static bool plan_tiling(int N, int nf, const std::vector<int32_t>& jj, const std
     H.u_alloc += (long long)tile_u_rows(t.n_patch) * tile_u_stride(t.n_blk);
     H.lds = std::max(H.lds, tile_lds_bytes(t.n_patch, Tn, t.n_blk, tsize));
     H.max_w6 = std::max(H.max_w6, 6 * t.n_blk);
+    H.max_k = std::max(H.max_k, t.n_patch);
     H.tiles.push_back(t);
   };
   for (int f = 0; f < N; ++f) {
@@ -607,6 +614,7 @@ static hipError_t upload_tiling(Tiling& T_, const HostTiling& H, hipStream_t st)
   T_.n_tiles = (int)H.tiles.size();
   T_.lds_bytes = H.lds;
   T_.max_w6 = H.max_w6;
+  T_.max_k = H.max_k;
   T_.part_S = H.part_S;
   T_.part_vec = H.part_vec;
   T_.u_elems = H.u_elems;
@@ -934,7 +942,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
   }
   if (nit > 0 && !small) {
     TraceScope ts(c, DPVBA_PHASE_BACKSUB, st);
-    e = launch_tile_finalize<T>((const TileInfo*)tl.tiles.p, tl.n_tiles, tl.lds_bytes, (const int*)tl.tile_patch.p,
+    e = launch_tile_finalize<T>((const TileInfo*)tl.tiles.p, tl.n_tiles, writeback_lds_bytes(tl, (int)sizeof(T)), (const int*)tl.tile_patch.p,
                                 (const int*)tl.blk_pose.p, (const T*)c->U_s.p, (const T*)c->pscale_s.p,
                                 (const T*)c->depth_s.p, dx, status + nit - 1, 0, depth, pbuf[(nit - 1) & 1], poses,
                                 c->N, st);
@@ -1088,7 +1096,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
   }
   if (nit > 0) {
     TraceScope ts(c, DPVBA_PHASE_BACKSUB, st);
-    e = launch_tile_finalize<float>((const TileInfo*)tl.tiles.p, tl.n_tiles, tl.lds_bytes,
+    e = launch_tile_finalize<float>((const TileInfo*)tl.tiles.p, tl.n_tiles, writeback_lds_bytes(tl, 4),
                                     (const int*)tl.tile_patch.p, (const int*)tl.blk_pose.p, (const float*)c->U_s.p,
                                     (const float*)c->pscale_s.p, (const float*)c->depth_s.p, dx, status + nit - 1,
                                     0, depth, pbuf[(nit - 1) & 1], poses, c->N, st);
@@ -1153,6 +1161,7 @@ static bool append_tiling(HostTiling& H, const HostTiling& Hb, int b, int frame_
   H.u_alloc += Hb.u_alloc;
   H.lds = std::max(H.lds, Hb.lds);
   H.max_w6 = std::max(H.max_w6, Hb.max_w6);
+  H.max_k = std::max(H.max_k, Hb.max_k);
   return true;
 }
 
@@ -1464,7 +1473,7 @@ static hipError_t batch_impl(dpvba_ctx* c, const dpvba_batch* b, T* poses, T* de
   }
   if (nit > 0) {
     TraceScope ts(c, DPVBA_PHASE_BACKSUB, st);
-    e = launch_tile_finalize<T>((const TileInfo*)tl.tiles.p, tl.n_tiles, tl.lds_bytes, (const int*)tl.tile_patch.p,
+    e = launch_tile_finalize<T>((const TileInfo*)tl.tiles.p, tl.n_tiles, writeback_lds_bytes(tl, (int)sizeof(T)), (const int*)tl.tile_patch.p,
                                 (const int*)tl.blk_pose.p, (const T*)c->U_s.p, (const T*)c->pscale_s.p,
                                 (const T*)c->depth_s.p, (const T*)c->dx.p, status + nit - 1, stride, depth,
                                 pbuf[(nit - 1) & 1], poses, B.N, st);
