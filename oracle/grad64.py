@@ -155,6 +155,34 @@ def unrolled(poses0, d0, centres, ii, jj, kk, target, weight, intr, n_fixed, n_i
     return torch.cat([t, q], -1), d
 
 
+def rotation_angle_sq(q, q_ref):
+    """||Log(R_ref^T R)||^2 of unit quaternions (x, y, z, w): the squared angle
+    2 atan2(|v|, |w|) of the relative rotation q_ref^-1 q = (v, w), written so
+    that autograd stays finite at zero angle (atan2(s, c) / s -> 1 / c)."""
+    qr_inv = torch.cat([-q_ref[..., :3], q_ref[..., 3:]], -1)
+    rel = quat_mul(qr_inv, q / q.norm(dim=-1, keepdim=True))
+    v, w = rel[..., :3], rel[..., 3].abs()
+    s2 = (v * v).sum(-1)
+    small = s2 < 1e-24
+    s = torch.where(small, torch.ones_like(s2), s2).sqrt()
+    f = torch.where(small, 1.0 / w, torch.atan2(s, w) / s)
+    return 4.0 * f * f * s2
+
+
+def pose_loss(poses, poses_ref, n_fixed):
+    """The supervision loss on the poses BA produces (the differentiable BA
+    layer of Sec. 2): sum over free poses of ||t - t_ref||^2 + ||Log(R_ref^T R)||^2."""
+    t, q = poses[n_fixed:, :3], poses[n_fixed:, 3:]
+    tr, qr = poses_ref[n_fixed:, :3], poses_ref[n_fixed:, 3:]
+    return ((t - tr) ** 2).sum() + rotation_angle_sq(q, qr).sum()
+
+
+def scene_pose_loss(scene):
+    """pose_loss against the scene's ground-truth poses, as a callable of (poses, d)."""
+    ref = torch.as_tensor(scene.poses_gt, dtype=DT)
+    return lambda poses, d: pose_loss(poses, ref, int(scene.n_fixed))
+
+
 def pose_depth_loss(poses, d, poses_ref, d_ref, n_fixed):
     """A test loss touching every output: squared translation error,
     1 - <q, q_ref>^2 per free pose (sign invariant), and the mean squared

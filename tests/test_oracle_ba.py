@@ -320,3 +320,86 @@ def test_cost_decreases_on_small_configs():
     P, D, rep = ba64.solve_scene(s)
     assert rep.cost[-1] < rep.cost[0] * 0.01
     assert rep.n_invalid == [0, 0]
+
+
+# ---------------------------------------------------------------- cost of eq. 3 (hand-worked values)
+
+def _two_camera_problem(targets, weights, depths, pose_j):
+    """Two patches of frame 0 seen from frame 1 (one edge each)."""
+    P = len(depths)
+    centres = np.array([[400.0, 200.0]] * P)
+    return ba64.Problem(
+        poses=np.stack([IDENT, pose_j]).astype(np.float64), centres=centres,
+        inv_depth=np.asarray(depths, dtype=np.float64), ii=np.zeros(P, dtype=np.int64),
+        jj=np.ones(P, dtype=np.int64), kk=np.arange(P), target=np.asarray(targets, dtype=np.float64),
+        weight=np.asarray(weights, dtype=np.float64), intrinsics=np.array([320.0, 320.0, 320.0, 240.0]),
+        n_fixed=0)
+
+
+def test_cost_single_edge_hand_value():
+    # sideways translation b = 0.1, d = 0.5: the centre lands at (384, 200)
+    # (u' = u - fx b d).  Target (380, 197): r = (4, 3); w = (0.5, 1):
+    # cost = 1/2 (0.5 * 16 + 1 * 9) = 8.5
+    pb = _two_camera_problem([[380.0, 197.0]], [[0.5, 1.0]], [0.5], _pose([0.1, 0, 0]))
+    t = ba64.edge_terms(pb)
+    np.testing.assert_allclose(t.r[0], [4.0, 3.0], atol=1e-12)
+    assert abs(ba64.cost(pb, t) - 8.5) < 1e-12
+    # only x off the target: r = (4, 0), w = (0.5, 1): cost = 1/2 * 0.5 * 16 = 4
+    pb = _two_camera_problem([[380.0, 200.0]], [[0.5, 1.0]], [0.5], _pose([0.1, 0, 0]))
+    assert abs(ba64.cost(pb, ba64.edge_terms(pb)) - 4.0) < 1e-12
+
+
+def test_cost_skips_invalid_edges():
+    # edge 0 as above (cost 8.5); edge 1 has a negative inverse depth, so it is
+    # invalid and contributes nothing however far its reprojection lands
+    pb = _two_camera_problem([[380.0, 197.0], [-5000.0, 9000.0]], [[0.5, 1.0], [1.0, 1.0]], [0.5, -0.5],
+                             _pose([0.1, 0, 0]))
+    t = ba64.edge_terms(pb)
+    assert t.valid.tolist() == [True, False]
+    assert abs(ba64.cost(pb, t) - 8.5) < 1e-12
+
+
+def test_cost_is_zero_at_ground_truth_noise_free():
+    s = tiny_scene(6, 8, seed=31, noise_px=0.0, init="gt")
+    pb = ba64.Problem.from_scene(s)
+    pb.poses = s.poses_gt.copy(); pb.inv_depth = s.inv_depth_gt.copy(); pb.target = s.target64.copy()
+    assert ba64.cost(pb, ba64.edge_terms(pb)) < 1e-18 * s.n_edges + 1e-20
+    # and equals the hand sum over edges once every target moves by (1, -2) px
+    pb.target = s.target64 + np.array([1.0, -2.0])
+    want = 0.5 * float(np.sum(pb.weight[:, 0] * 1.0 + pb.weight[:, 1] * 4.0))
+    assert abs(ba64.cost(pb, ba64.edge_terms(pb)) - want) < 1e-9 * want
+
+
+# ---------------------------------------------------------------- full-patch reprojection (eq. 2 per pixel)
+
+def test_reproject_every_pixel_sideways_translation():
+    # every pixel of the patch moves by -fx b d along x (one inverse depth per patch)
+    b, d = 0.1, 0.5
+    pb = _problem_single_edge(400.0, 200.0, d, IDENT, _pose([b, 0, 0]))
+    full, valid = ba64.reproject(pb)
+    want = pb.patches[0].copy()
+    want[..., 0] -= 320.0 * b * d
+    np.testing.assert_allclose(full[0], want, atol=1e-12)
+    assert valid.all()
+
+
+def test_reproject_every_pixel_forward_translation():
+    # camera moved forward by b along its axis: every pixel scales about the
+    # principal point by 1 / (1 - b d)
+    b, d = 0.1, 0.5
+    pb = _problem_single_edge(400.0, 300.0, d, IDENT, _pose([0, 0, b]))
+    full, _ = ba64.reproject(pb)
+    want = np.empty_like(pb.patches[0])
+    want[..., 0] = 320.0 + (pb.patches[0][..., 0] - 320.0) / (1 - b * d)
+    want[..., 1] = 240.0 + (pb.patches[0][..., 1] - 240.0) / (1 - b * d)
+    np.testing.assert_allclose(full[0], want, atol=1e-12)
+
+
+def test_reproject_centre_matches_edge_terms():
+    s = tiny_scene(5, 6, seed=32)
+    pb = ba64.Problem.from_scene(s)
+    full, valid = ba64.reproject(pb)
+    t = ba64.edge_terms(pb)
+    c = (s.patches.shape[1] - 1) // 2
+    np.testing.assert_allclose(full[:, c, c, :], t.proj, atol=1e-9)
+    assert (valid == t.valid).all()

@@ -105,3 +105,60 @@ def test_zero_iterations_give_zero_gradients():
     L, gt, gw, gp, gd = grad64.loss_and_grads(s, n_iters=0)
     assert np.all(gt == 0) and np.all(gw == 0)
     assert np.abs(gp).max() > 0 and np.abs(gd).max() > 0
+
+
+def test_pose_loss_closed_form():
+    """Squared translation error plus squared rotation angle of R_ref^T R."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(7)
+    ref = np.zeros((4, 7))
+    ref[:, :3] = rng.normal(size=(4, 3))
+    ref[:, 3:] = Rotation.from_rotvec(rng.normal(size=(4, 3))).as_quat()
+    out = ref.copy()
+    want = 0.0
+    for a in range(2, 4):  # poses 0, 1 held: excluded from the loss
+        delta = rng.normal(size=3) * 0.3
+        axis = rng.normal(size=3)
+        axis /= np.linalg.norm(axis)
+        theta = 0.05 + 0.4 * a
+        out[a, :3] += delta
+        R = Rotation.from_quat(ref[a, 3:]) * Rotation.from_rotvec(theta * axis)
+        q = R.as_quat()
+        out[a, 3:] = -q if a == 3 else q  # the sign of a quaternion does not matter
+        want += float(delta @ delta) + theta ** 2
+    out[0, :3] += 5.0  # held pose: ignored
+    L = grad64.pose_loss(torch.as_tensor(out), torch.as_tensor(ref), 2)
+    assert abs(float(L) - want) < 1e-12 * max(1.0, want)
+
+
+def test_rotation_angle_gradient_finite_at_zero():
+    q = torch.tensor([[0.1, -0.2, 0.3, 0.9]], dtype=torch.float64)
+    q = (q / q.norm()).requires_grad_(True)
+    a2 = grad64.rotation_angle_sq(q, q.detach().clone())
+    (g,) = torch.autograd.grad(a2.sum(), q)
+    assert float(a2) < 1e-30 and torch.isfinite(g).all() and float(g.abs().max()) < 1e-12
+    # small angle: derivative of theta^2 along the generator matches central differences
+    from scipy.spatial.transform import Rotation
+    base = Rotation.from_rotvec([0.0, 0.0, 1e-3])
+    qq = torch.as_tensor(base.as_quat()[None], dtype=torch.float64)
+    ref = torch.tensor([[0.0, 0.0, 0.0, 1.0]], dtype=torch.float64)
+    assert abs(float(grad64.rotation_angle_sq(qq, ref)) - 1e-6) < 1e-18
+
+
+def test_pose_loss_gradients_match_central_differences():
+    s = tiny_scene(5, 5, seed=49)
+    loss = grad64.scene_pose_loss(s)
+    L, gt, gw, _, _ = grad64.loss_and_grads(s, loss_fn=loss)
+    rng = np.random.default_rng(49)
+    h = 1e-6
+    tgt = s.target.astype(np.float64)
+    wgt = s.weight.astype(np.float64)
+    for arr, g, which in ((tgt, gt, 0), (wgt, gw, 1)):
+        dirs = rng.normal(size=arr.shape)
+        if which == 0:
+            fd = (grad64.loss_value(s, tgt + h * dirs, wgt, loss_fn=loss) -
+                  grad64.loss_value(s, tgt - h * dirs, wgt, loss_fn=loss)) / (2 * h)
+        else:
+            fd = (grad64.loss_value(s, tgt, wgt + h * dirs, loss_fn=loss) -
+                  grad64.loss_value(s, tgt, wgt - h * dirs, loss_fn=loss)) / (2 * h)
+        assert abs(fd - np.sum(g * dirs)) <= 1e-6 * max(1.0, abs(fd)), (which, fd, np.sum(g * dirs))
