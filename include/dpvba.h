@@ -30,20 +30,24 @@
  * Memory and ownership.  Unless marked "host", every pointer is a device
  * pointer owned by the caller, who keeps it alive until the work enqueued on
  * the given stream has completed.  The library never frees or retains caller
- * buffers.  A context owns all of its workspace.  dpvba_analyze is the only
- * call that may allocate device memory (besides the first dpvba_solve_backward
- * of a given size, which sizes its own workspace); the numeric calls
- * (dpvba_solve, dpvba_reduced_system, dpvba_reproject) allocate nothing, synchronise
- * nothing and only enqueue work on the caller's stream (dpvba_solve with a
- * non-NULL report enqueues one device-to-host copy into it and the caller
- * reads it after synchronising the stream).  A context is used by one host
+ * buffers.  A context owns all of its workspace.  The analyses
+ * (dpvba_analyze, dpvba_analyze_batch) are the only calls that allocate
+ * device memory; the numeric calls (dpvba_solve, dpvba_solve_backward,
+ * dpvba_reduced_system, dpvba_reproject, dpvba_solve_batch) allocate
+ * nothing and only enqueue work on the caller's stream (a non-NULL report
+ * is one device-to-host copy into it, read by the caller after
+ * synchronising the stream).  The exception to "no synchronisation" is the
+ * float64 fallback decision of DPVBA_MIXED on reduced systems whose solve is
+ * not one workgroup's (see dpvba_solve).  A context is used by one host
  * thread at a time.
  *
  * Errors.  Every call returns a dpvba_status.  Argument errors found on the
  * host return immediately with nothing enqueued.  Conditions found on the
- * device (non-positive pivot) are reported through dpvba_report.status once
- * the stream has completed.  No C++ exception crosses this interface and
- * nothing aborts.
+ * device are reported through dpvba_report.status once the stream has
+ * completed; failures that invalidate results (an expired bounded wait,
+ * invalid inputs) are also recorded in the context and returned as
+ * DPVBA_EDEVICE by every later call (dpvba_device_status).  No C++
+ * exception crosses this interface and nothing aborts.
  */
 #ifndef DPVBA_H
 #define DPVBA_H
@@ -60,7 +64,10 @@ typedef enum {
   DPVBA_ENOTPD = 2,   /* reduced camera system not positive definite            */
   DPVBA_ENOMEM = 3,   /* device allocation failed (dpvba_analyze / create)       */
   DPVBA_EHIP = 4,     /* a HIP runtime call failed                               */
-  DPVBA_ESTATE = 5    /* numeric call without a matching dpvba_analyze           */
+  DPVBA_ESTATE = 5,   /* numeric call without a matching dpvba_analyze           */
+  DPVBA_EDEVICE = 6   /* an earlier call's device work failed: a bounded device-
+                         wide wait expired, or it met a target / weight outside
+                         the documented range; see dpvba_device_status          */
 } dpvba_status;
 
 typedef enum {
@@ -106,8 +113,19 @@ typedef struct {
  *   lambda     damping, finite, >= 0 (rounded to float in DPVBA_FP32).
  *   z_min      validity threshold, finite, >= 0.
  *   precision  dpvba_precision.
- *   flags      reserved, must be 0.                                      */
+ *   flags      0 or an OR of the DPVBA_FLAG_* bits below; any other bit is
+ *              EINVAL.                                                   */
 #define DPVBA_MAX_ITERS 32
+/* Damping H~ = H + lambda I (Levenberg) instead of the default
+ * H + lambda (Diag(H) + I) (Levenberg-Marquardt).  Every numeric call.     */
+#define DPVBA_FLAG_LEVENBERG 2u
+/* DPVBA_MIXED only: solve every iteration with the float64 Cholesky, as if
+ * the refined float32 solve had not converged (the float32 factor,
+ * refinement and report fields are still computed).  EINVAL otherwise.    */
+#define DPVBA_FLAG_FORCE_FP64_CHOL 4u
+/* DPVBA_MIXED only: no refinement steps; the float64 residual of the plain
+ * float32 solve decides the fallback.  EINVAL otherwise.                  */
+#define DPVBA_FLAG_NO_REFINE 8u
 typedef struct {
   int32_t n_iters;
   int32_t precision;
@@ -123,10 +141,11 @@ typedef struct {
  *   n_invalid[t]    invalid edges at iterate t (t < n_iters).
  *   min_pivot[t]    smallest L_ii^2 / S_ii of the Cholesky at iteration t.
  *   status          DPVBA_OK, DPVBA_ENOTPD if a pivot was not positive
- *                   (that iteration's step is then zero), or DPVBA_EHIP if
- *                   a bounded device-wide wait of the single-launch solver
- *                   expired (the results are then invalid and the context
- *                   must be destroyed).
+ *                   (that iteration's step is then zero), DPVBA_EINVAL if a
+ *                   target or weight was non-finite or a weight negative
+ *                   (the edge is used as given; the results follow that
+ *                   arithmetic), or DPVBA_EHIP if a bounded device-wide wait
+ *                   expired (the results are then invalid).
  *   refine_resid[t] DPVBA_MIXED: max |s - S dxi| / max |s| in float64 after
  *                   the refinement steps of iteration t (before any float64
  *                   fallback); 0 in the other modes.
@@ -153,8 +172,10 @@ void dpvba_destroy(dpvba_ctx* ctx);
  * structure of the block-sparse normal equations of eq. 3, Appendix A):
  * groups every patch's edges, splits each source frame's patches into
  * tiles, and builds the index lists that assemble the reduced camera
- * system.  Copies ii/jj/kk to the host (synchronising `stream`), validates
- * them, and (re)allocates the workspace for this graph.  Must be repeated
+ * system.  Copies ii/jj/kk, targets and weights to the host (synchronising
+ * `stream`), validates them (weights finite and >= 0, targets finite), and
+ * (re)allocates the workspace for this graph, including that of
+ * dpvba_solve_backward for up to DPVBA_MAX_ITERS iterations.  Must be repeated
  * whenever ii, jj, kk or any size changes; targets, weights, patches,
  * poses and depths may change freely between numeric calls.
  * Returns EINVAL on any index or ownership violation, ENOMEM on allocation
@@ -266,9 +287,9 @@ dpvba_status dpvba_set_cooperative(dpvba_ctx* ctx, int32_t cooperative);
  *   grad_inv_depth [P] or NULL (zero): dL/d(final inverse depths).
  *   grad_target, grad_weight [E, 2] (written): dL/d target, dL/d weight.
  * All six arrays are float32, or float64 when opts->precision is DPVBA_FP64
- * (the pointers are then reinterpreted).  The first call for a given
- * (n_iters, size) allocates its workspace in the context, about
- * (n_iters + 1) 7 N + n_iters (P + 6 N) + 15 E elements.
+ * (the pointers are then reinterpreted).  The workspace (about
+ * (n_iters + 1) 7 N + n_iters (P + 6 N) + 15 E float64 elements for
+ * n_iters = DPVBA_MAX_ITERS) is allocated by dpvba_analyze.
  * Needs dpvba_analyze on this graph.  EINVAL on bad arguments.             */
 dpvba_status dpvba_solve_backward(dpvba_ctx* ctx, const dpvba_graph* g, const float* poses0,
                                   const float* inv_depth0, const dpvba_opts* opts,
@@ -356,6 +377,21 @@ dpvba_status dpvba_trace_begin(dpvba_ctx* ctx, int32_t sample_every, int32_t max
  * sampled launches and the number of launches seen (host arrays of
  * DPVBA_N_PHASES entries; any may be NULL).                               */
 dpvba_status dpvba_trace_end(dpvba_ctx* ctx, double* ms, int32_t* n_sampled, int64_t* n_launched);
+
+/* Device-side failures of the calls enqueued so far on this context.
+ * Kernels that detect a failure -- a bounded device-wide wait that expired
+ * (the co-residency that a grid barrier or a chained solve needs was not
+ * met), or a non-finite target / weight or a negative weight -- record it
+ * in a host-visible word of the context.  Every later call on the context
+ * checks that word first and, once such a failure has been recorded,
+ * returns DPVBA_EDEVICE without enqueuing anything (results of the failed
+ * call and of calls enqueued after it are invalid).  This call
+ * synchronises `stream`, returns DPVBA_EDEVICE if a failure was recorded
+ * (DPVBA_OK otherwise), and clears the record, re-arming the context's
+ * device-wide barriers; *cause (host, may be NULL) receives the failure
+ * bits: 1 expired grid barrier, 2 expired chained triangular solve,
+ * 4 invalid target or weight.                                             */
+dpvba_status dpvba_device_status(dpvba_ctx* ctx, void* stream, int32_t* cause);
 
 /* Text of the last HIP failure seen by a call on this context (the failing
  * call and HIP's message), "" if none.  Owned by the context.             */

@@ -216,11 +216,13 @@ class ReducedSystem:
     Bt_diag: np.ndarray
 
 
-def reduce(ne: NormalEquations, lam: float) -> ReducedSystem:
-    """Damp H~ = H + lam (Diag(H) + I), then eliminate the depths:
+def reduce(ne: NormalEquations, lam: float, levenberg: bool = False) -> ReducedSystem:
+    """Damp H~ = H + lam (Diag(H) + I) (Levenberg-Marquardt; with
+    levenberg=True the plain H + lam I), then eliminate the depths:
     S = B~ - E C~^-1 E^T, s = -v + E C~^-1 w."""
-    Bt = ne.B + lam * np.diag(np.diag(ne.B) + 1.0)
-    Ct = ne.C + lam * (ne.C + 1.0)
+    mq = 0.0 if levenberg else 1.0
+    Bt = ne.B + lam * np.diag(mq * np.diag(ne.B) + 1.0)
+    Ct = ne.C + lam * (mq * ne.C + 1.0)
     Einv = ne.E @ sp.diags(1.0 / Ct)
     S = Bt - (Einv @ ne.E.T).toarray()
     s = -ne.v + Einv @ ne.w
@@ -260,10 +262,10 @@ class Report:
     min_pivot_ratio: list = field(default_factory=list)
 
 
-def gn_iteration(pb: Problem, poses, inv_depth, lam=1e-4, z_min=0.1, report=None):
+def gn_iteration(pb: Problem, poses, inv_depth, lam=1e-4, z_min=0.1, report=None, levenberg=False):
     terms = edge_terms(pb, poses, inv_depth, z_min)
     ne = normal_equations(pb, terms)
-    rs = reduce(ne, lam)
+    rs = reduce(ne, lam, levenberg)
     dxi = solve_reduced(rs)
     dd = back_substitute(ne, rs, dxi)
     if report is not None:
@@ -274,20 +276,20 @@ def gn_iteration(pb: Problem, poses, inv_depth, lam=1e-4, z_min=0.1, report=None
     return apply_step(pb, poses, inv_depth, dxi, dd)
 
 
-def solve(pb: Problem, n_iters=2, lam=1e-4, z_min=0.1):
+def solve(pb: Problem, n_iters=2, lam=1e-4, z_min=0.1, levenberg=False):
     """Fixed-count Gauss-Newton; returns (poses [N,7], inv_depth [P], report)."""
     rep = Report()
     poses, d = pb.poses.copy(), pb.inv_depth.copy()
     for _ in range(n_iters):
-        poses, d = gn_iteration(pb, poses, d, lam, z_min, rep)
+        poses, d = gn_iteration(pb, poses, d, lam, z_min, rep, levenberg)
     rep.cost.append(cost(pb, edge_terms(pb, poses, d, z_min)))
     return poses, d, rep
 
 
-def solve_scene(scene, n_iters=None, lam=None, z_min=None):
+def solve_scene(scene, n_iters=None, lam=None, z_min=None, levenberg=False):
     pb = Problem.from_scene(scene)
     return solve(pb, scene.n_iters if n_iters is None else n_iters,
-                 scene.lam if lam is None else lam, scene.z_min if z_min is None else z_min)
+                 scene.lam if lam is None else lam, scene.z_min if z_min is None else z_min, levenberg)
 
 
 def pose_errors(poses_a, poses_b):

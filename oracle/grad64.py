@@ -81,8 +81,9 @@ def retract_right(t, q, xi):
     return tn, qn / qn.norm(dim=-1, keepdim=True)
 
 
-def gn_iteration(t, q, d, centres, ii, jj, kk, target, weight, intr, n_fixed, lam, z_min):
-    """One damped GN step on the stored coordinates; returns (t, q, d)."""
+def gn_iteration(t, q, d, centres, ii, jj, kk, target, weight, intr, n_fixed, lam, z_min, levenberg=False):
+    """One damped GN step on the stored coordinates; returns (t, q, d).
+    Damping H + lam (Diag(H) + I), or H + lam I with levenberg=True."""
     fx, fy, cx, cy = intr
     R = quat_to_rot(q)
     N, P = R.shape[0], d.shape[0]
@@ -133,8 +134,9 @@ def gn_iteration(t, q, d, centres, ii, jj, kk, target, weight, intr, n_fixed, la
     B = Bpp.reshape(Nf, Nf, 6, 6).permute(0, 2, 1, 3).reshape(n, n)
     Em = Epd.reshape(Nf, P, 6).permute(0, 2, 1).reshape(n, P)
     v = gp.reshape(n)
-    Bt = B + lam * torch.diag(torch.diagonal(B) + 1)
-    Ct = C + lam * (C + 1)
+    mq = 0.0 if levenberg else 1.0
+    Bt = B + lam * torch.diag(mq * torch.diagonal(B) + 1)
+    Ct = C + lam * (mq * C + 1)
     S = Bt - (Em / Ct) @ Em.T
     s = -v + Em @ (gd / Ct)
     if n:
@@ -147,11 +149,11 @@ def gn_iteration(t, q, d, centres, ii, jj, kk, target, weight, intr, n_fixed, la
     return torch.cat([t[:nf], tn], 0), torch.cat([q[:nf], qn], 0), d + dd
 
 
-def unrolled(poses0, d0, centres, ii, jj, kk, target, weight, intr, n_fixed, n_iters, lam, z_min):
+def unrolled(poses0, d0, centres, ii, jj, kk, target, weight, intr, n_fixed, n_iters, lam, z_min, levenberg=False):
     """poses [N,7] (t, q) and depths [P] after n_iters iterations."""
     t, q, d = poses0[:, :3], poses0[:, 3:], d0
     for _ in range(n_iters):
-        t, q, d = gn_iteration(t, q, d, centres, ii, jj, kk, target, weight, intr, n_fixed, lam, z_min)
+        t, q, d = gn_iteration(t, q, d, centres, ii, jj, kk, target, weight, intr, n_fixed, lam, z_min, levenberg)
     return torch.cat([t, q], -1), d
 
 
@@ -209,24 +211,24 @@ def _tensors(scene):
         n_fixed=int(scene.n_fixed))
 
 
-def _run(scene, target, weight, n_iters, lam, z_min, track=False):
+def _run(scene, target, weight, n_iters, lam, z_min, track=False, levenberg=False):
     T = _tensors(scene)
     if track:  # keep the outputs in the graph even without iterations
         T["poses0"].requires_grad_(True)
         T["d0"].requires_grad_(True)
     return unrolled(T["poses0"], T["d0"], T["centres"], T["ii"], T["jj"], T["kk"], target, weight, T["intr"],
                     T["n_fixed"], scene.n_iters if n_iters is None else n_iters,
-                    scene.lam if lam is None else lam, scene.z_min if z_min is None else z_min)
+                    scene.lam if lam is None else lam, scene.z_min if z_min is None else z_min, levenberg)
 
 
-def loss_and_grads(scene, loss_fn=None, n_iters=None, lam=None, z_min=None):
+def loss_and_grads(scene, loss_fn=None, n_iters=None, lam=None, z_min=None, levenberg=False):
     """L = loss_fn(poses_T, d_T) after the unrolled iterations, and (numpy
     float64) dL/d target [E,2], dL/d weight [E,2], dL/d poses_T [N,7],
     dL/d d_T [P].  loss_fn defaults to scene_loss(scene)."""
     loss_fn = scene_loss(scene) if loss_fn is None else loss_fn
     target = torch.as_tensor(scene.target, dtype=DT).clone().requires_grad_(True)
     weight = torch.as_tensor(scene.weight, dtype=DT).clone().requires_grad_(True)
-    poses, d = _run(scene, target, weight, n_iters, lam, z_min, track=True)
+    poses, d = _run(scene, target, weight, n_iters, lam, z_min, track=True, levenberg=levenberg)
     L = loss_fn(poses, d)
     ins = (target, weight, poses, d)
     gr = torch.autograd.grad(L, ins, allow_unused=True)
@@ -234,18 +236,18 @@ def loss_and_grads(scene, loss_fn=None, n_iters=None, lam=None, z_min=None):
     return float(L.detach()), gt.numpy(), gw.numpy(), gp.detach().numpy(), gd.detach().numpy()
 
 
-def loss_value(scene, target, weight, loss_fn=None, n_iters=None, lam=None, z_min=None):
+def loss_value(scene, target, weight, loss_fn=None, n_iters=None, lam=None, z_min=None, levenberg=False):
     """The loss alone, for given float64 targets / weights (numpy)."""
     loss_fn = scene_loss(scene) if loss_fn is None else loss_fn
     with torch.no_grad():
         poses, d = _run(scene, torch.as_tensor(target, dtype=DT), torch.as_tensor(weight, dtype=DT), n_iters,
-                        lam, z_min)
+                        lam, z_min, levenberg=levenberg)
         return float(loss_fn(poses, d))
 
 
-def forward_state(scene, n_iters=None):
+def forward_state(scene, n_iters=None, levenberg=False):
     """(poses [N,7], d [P]) after the unrolled iterations, numpy float64."""
     with torch.no_grad():
         poses, d = _run(scene, torch.as_tensor(scene.target, dtype=DT), torch.as_tensor(scene.weight, dtype=DT),
-                        n_iters, None, None)
+                        n_iters, None, None, levenberg=levenberg)
     return poses.numpy(), d.numpy()

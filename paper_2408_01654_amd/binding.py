@@ -16,9 +16,12 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdpvba.so")
 
-DPVBA_OK, DPVBA_EINVAL, DPVBA_ENOTPD, DPVBA_ENOMEM, DPVBA_EHIP, DPVBA_ESTATE = range(6)
+DPVBA_OK, DPVBA_EINVAL, DPVBA_ENOTPD, DPVBA_ENOMEM, DPVBA_EHIP, DPVBA_ESTATE, DPVBA_EDEVICE = range(7)
 FP32, MIXED, FP64 = 0, 1, 2
 FLAG_GRAPH = 1
+FLAG_LEVENBERG = 2          # H + lambda I instead of H + lambda (Diag(H) + I)
+FLAG_FORCE_FP64_CHOL = 4    # MIXED: always take the float64 Cholesky
+FLAG_NO_REFINE = 8          # MIXED: no refinement steps
 MAX_ITERS = 32
 PHASES = ("assemble", "gather", "factor", "backsub", "retract", "cost")
 
@@ -114,6 +117,8 @@ def lib():
         L.dpvba_last_error.restype = ctypes.c_char_p
         L.dpvba_status_string.argtypes = [ctypes.c_int]
         L.dpvba_status_string.restype = ctypes.c_char_p
+        L.dpvba_device_status.argtypes = [vp, vp, vp]
+        L.dpvba_device_status.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -274,11 +279,20 @@ class Context:
         return coords, valid
 
     @staticmethod
-    def _opts(n_iters, lam, z_min, precision):
-        return Opts(int(n_iters), int(precision), float(lam), float(z_min), 0)
+    def _opts(n_iters, lam, z_min, precision, flags=0):
+        return Opts(int(n_iters), int(precision), float(lam), float(z_min), int(flags))
+
+    def device_status(self, stream=None):
+        """Synchronise the stream and return (status, cause bits) of the
+        device-side failures recorded since the last call; clears them."""
+        cause = ctypes.c_int32(0)
+        st = lib().dpvba_device_status(self._h, _stream(stream), ctypes.byref(cause))
+        if st not in (DPVBA_OK, DPVBA_EDEVICE):
+            _check(st, "dpvba_device_status", self._h)
+        return st, int(cause.value)
 
     def reduced_system(self, g: GraphTensors, poses, inv_depth, lam=1e-4, z_min=0.1, precision=FP32,
-                       stream=None):
+                       stream=None, flags=0):
         """S [n,n] and s [n] at (poses, inv_depth); float64 for FP64 and
         MIXED (float32 assembly gathered in float64), else float32."""
         dt = torch.float64 if precision in (FP64, MIXED) else torch.float32
@@ -286,7 +300,7 @@ class Context:
         S = torch.empty((n, n), dtype=dt, device=poses.device)
         s = torch.empty((n,), dtype=dt, device=poses.device)
         cost = torch.empty((1,), dtype=torch.float64, device=poses.device)
-        o = self._opts(0, lam, z_min, precision)
+        o = self._opts(0, lam, z_min, precision, flags)
         gs = g.struct()
         _check(lib().dpvba_reduced_system(self._h, ctypes.byref(gs), _ptr(poses), _ptr(inv_depth),
                                           ctypes.byref(o), _ptr(S), _ptr(s), _ptr(cost), _stream(stream)),
@@ -294,7 +308,7 @@ class Context:
         return S, s, cost
 
     def solve(self, g: GraphTensors, poses, inv_depth, n_iters=2, lam=1e-4, z_min=0.1, precision=FP32,
-              report=True, stream=None):
+              report=True, stream=None, flags=0):
         """In-place solve of poses [N,7] and inv_depth [P] (float32 for FP32 and
         MIXED, float64 for FP64).  Returns the report as a dict (after
         synchronising the stream) or None."""
@@ -303,7 +317,7 @@ class Context:
             raise TypeError(f"poses and inv_depth must be {want}")
         if not (poses.is_contiguous() and inv_depth.is_contiguous()):
             raise ValueError("poses and inv_depth must be contiguous")
-        o = self._opts(n_iters, lam, z_min, precision)
+        o = self._opts(n_iters, lam, z_min, precision, flags)
         gs = g.struct()
         rep = Report() if report else None
         _check(lib().dpvba_solve(self._h, ctypes.byref(gs), _ptr(poses), _ptr(inv_depth), ctypes.byref(o),
@@ -314,7 +328,7 @@ class Context:
         return rep.to_dict()
 
     def solve_backward(self, g: GraphTensors, poses0, inv_depth0, grad_poses=None, grad_inv_depth=None, n_iters=2,
-                       lam=1e-4, z_min=0.1, precision=FP32, stream=None):
+                       lam=1e-4, z_min=0.1, precision=FP32, stream=None, flags=0):
         """Gradients (target [E,2], weight [E,2]) of a loss whose gradients
         with respect to the poses and inverse depths that `solve` returns
         from (poses0, inv_depth0) are grad_poses [N,7] and grad_inv_depth [P]
@@ -327,7 +341,7 @@ class Context:
         E = g.ii.shape[0]
         gt = torch.empty((E, 2), dtype=want, device=poses0.device)
         gw = torch.empty((E, 2), dtype=want, device=poses0.device)
-        o = self._opts(n_iters, lam, z_min, precision)
+        o = self._opts(n_iters, lam, z_min, precision, flags)
         gs = g.struct()
         _check(lib().dpvba_solve_backward(self._h, ctypes.byref(gs), _ptr(poses0), _ptr(inv_depth0), ctypes.byref(o),
                                           _ptr(grad_poses), _ptr(grad_inv_depth), _ptr(gt), _ptr(gw),
@@ -348,7 +362,7 @@ class Context:
                self._h)
 
     def solve_batch(self, b: "BatchTensors", poses, inv_depth, n_iters=2, lam=1e-4, z_min=0.1, precision=FP32,
-                    report=True, graph=False, stream=None):
+                    report=True, graph=False, stream=None, flags=0):
         """In-place solve of every problem of an analysed batch: poses
         [sum N,7], inv_depth [sum P] (float32 for FP32 / MIXED, float64 for
         FP64).  graph=True records the launches in a HIP graph on first use
@@ -360,7 +374,7 @@ class Context:
         if not (poses.is_contiguous() and inv_depth.is_contiguous()):
             raise ValueError("poses and inv_depth must be contiguous")
         bs = b.struct()
-        o = Opts(int(n_iters), int(precision), float(lam), float(z_min), FLAG_GRAPH if graph else 0)
+        o = Opts(int(n_iters), int(precision), float(lam), float(z_min), (FLAG_GRAPH if graph else 0) | int(flags))
         reps = (Report * b.n_problems)() if report else None
         _check(lib().dpvba_solve_batch(self._h, ctypes.byref(bs), _ptr(poses), _ptr(inv_depth), ctypes.byref(o),
                                        ctypes.cast(reps, ctypes.c_void_p) if reps is not None else None,

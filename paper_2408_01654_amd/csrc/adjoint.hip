@@ -63,7 +63,7 @@ template <typename T>
 __global__ void __launch_bounds__(128) edge_adjoint_kernel(
     const T* poses, const T* depth_t, const int* patch_pos, const float* patches, int p, const int* ii,
     const int* jj, const int* kk, const float* target, const float* weight, int n_edges, int n_fixed, T fx, T fy,
-    T cx, T cy, T z_min, T lambda, const T* u_pose, const T* u_depth, const T* dxi, const T* dd,
+    T cx, T cy, T z_min, T lam_diag, const T* u_pose, const T* u_depth, const T* dxi, const T* dd,
     const int* status, T* grad_target, T* grad_weight, T* edge_xbar) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_edges) return;
@@ -103,11 +103,11 @@ __global__ void __launch_bounds__(128) edge_adjoint_kernel(
       b += J[c][m] * D[m];
       sd += J[c][m] * J[c][m] * u[m] * D[m];
     }
-    grad_weight[2 * e + c] += -a * b - lambda * sd - r[c] * a;
+    grad_weight[2 * e + c] += -a * b - lam_diag * sd - r[c] * a;
     grad_target[2 * e + c] += w * a;
     rb[c] = -w * a;
     for (int m = 0; m < 13; ++m)
-      Jb[c][m] = w * (-(r[c] + b) * u[m] - a * D[m] - (T)2 * lambda * J[c][m] * u[m] * D[m]);
+      Jb[c][m] = w * (-(r[c] + b) * u[m] - a * D[m] - (T)2 * lam_diag * J[c][m] * u[m] * D[m]);
   }
   // directional derivatives of (r, J) along each stored coordinate
   using D1 = Dual<T>;

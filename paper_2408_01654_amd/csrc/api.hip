@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -37,7 +38,7 @@ int small_solve_max_n(int tsize);
 template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
-                         int mirror, T* diag_out, hipStream_t st);
+                         T lam_diag, int mirror, T* diag_out, hipStream_t st);
 template <typename T, typename P>
 hipError_t launch_edge_cost(const P* poses, const P* inv_depth, const float* patches, int p, const int* ii,
                             const int* jj, const int* kk, const float* target, const float* weight,
@@ -49,18 +50,18 @@ hipError_t launch_reproject(const float* poses, const float* inv_depth, const fl
                             float cx, float cy, float z_min, float* coords, uint8_t* valid, hipStream_t st);
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
-                             unsigned int* min_bits, int* flags, int epoch, int* err, hipStream_t st);
-hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st);
+                             unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err, hipStream_t st);
+hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st, int* err_clear = nullptr);
 template <typename TP, typename T>
 hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
                             const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
-                            int mirror, T* diag_out, hipStream_t st);
+                            T lam_diag, int mirror, T* diag_out, hipStream_t st);
 template <typename T>
 hipError_t launch_chol_factor(T* S, int n, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
                               hipStream_t st);
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
-                             int epoch, int* err, hipStream_t st);
+                             int epoch, int* err, int* host_err, hipStream_t st);
 // mixed-precision helpers (mixed.hip)
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st);
@@ -68,8 +69,8 @@ hipError_t launch_lower_to_f32(const double* S64, float* S32, int n, hipStream_t
 hipError_t launch_residual64(const double* S, const double* s, const double* x, int n, double* r,
                              unsigned long long* maxes, hipStream_t st);
 hipError_t launch_accumulate(double* x, const float* c, int n, hipStream_t st);
-hipError_t launch_refine_decide(const unsigned long long* maxes, const int* status32, double tol, double* resid_out,
-                                int* fallback_out, int* host_flag, hipStream_t st);
+hipError_t launch_refine_decide(const unsigned long long* maxes, const int* status32, double tol, int force,
+                                double* resid_out, int* fallback_out, int* host_flag, hipStream_t st);
 hipError_t launch_step_to_f32(const double* x, float* dx, int n, const int* fallback, const int* status64,
                               int* status, hipStream_t st);
 // batch kernels (batch.hip)
@@ -83,6 +84,9 @@ struct BatchArgs {
   const int* v_off;
   const int2* v_src;
   double lambda;
+  double lam_diag;
+  int n_refine;
+  int force_fb;
   const TS* poses_cur;
   TS* poses_next;
   TS* dx;
@@ -163,9 +167,14 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Bumped whenever a workspace buffer moves: a captured HIP graph that bakes
+// in workspace addresses is valid only while it is unchanged.
+uint64_t g_workspace_generation = 0;
+
 hipError_t ensure(DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.bytes >= bytes) return hipSuccess;
+  ++g_workspace_generation;
   if (b.p) {
     hipError_t e = hipFree(b.p);
     if (e != hipSuccess) return e;
@@ -215,7 +224,15 @@ struct dpvba_ctx {
   bool coop_launch = false;  // single-launch solver: cooperative launch instead of an ordinary one
   // workspace
   DevBuf part_S, part_vec, part_cost, part_invalid, U_s, pscale_s, depth_s, xh_s, poses_a, poses_b;
+  // ticket: grid-barrier slots of the single-launch solver (slot p at
+  // ticket[8 p .. 8 p + 1]); dev_err: failure words of a call (small-solve
+  // launch parity p at [4 p], large path [8], batch [12]); host_err:
+  // host-visible sticky failure words (pinned, mapped), host_err_dev its
+  // device address
   DevBuf S, rhs, dB, d0, dx, wb, wy, Linv, edge_part, ticket, dev_err;
+  int* host_err = nullptr;
+  int* host_err_dev = nullptr;
+  long long small_launches = 0;
   DevBuf chain_flags;  // per 64-row block: forward and backward publication epochs
   DevBuf one_inst;     // the analysed problem as a one-problem batch (small mixed solves)
   int chain_epoch = 0;
@@ -364,6 +381,7 @@ const char* dpvba_status_string(dpvba_status s) {
     case DPVBA_ENOMEM: return "out of device memory";
     case DPVBA_EHIP: return "HIP runtime error";
     case DPVBA_ESTATE: return "numeric call without a matching dpvba_analyze";
+    case DPVBA_EDEVICE: return "device work of an earlier call failed (see dpvba_device_status)";
   }
   return "unknown status";
 }
@@ -376,8 +394,47 @@ dpvba_status dpvba_create(dpvba_ctx** out, int32_t device) {
   dpvba_ctx* c = new (std::nothrow) dpvba_ctx();
   if (!c) return DPVBA_ENOMEM;
   c->device = device;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->host_err, kHostErrWords * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) {
+    for (int q = 0; q < kHostErrWords; ++q) c->host_err[q] = 0;
+    e = hipHostGetDevicePointer((void**)&c->host_err_dev, c->host_err, 0);
+  }
+  if (e == hipSuccess) e = ensure(c->ticket, 64);
+  if (e == hipSuccess) e = ensure(c->dev_err, 64);
+  if (e == hipSuccess) e = hipMemset(c->ticket.p, 0, 64);
+  if (e == hipSuccess) e = hipMemset(c->dev_err.p, 0, 64);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    dpvba_destroy(c);
+    return hip_status(e);
+  }
   *out = c;
   return DPVBA_OK;
+}
+
+// Failure bits recorded by earlier calls' kernels in the host-visible words.
+static int recorded_failure(const dpvba_ctx* c) {
+  int bits = 0;
+  for (int q = 0; q < kHostErrWords; ++q)
+    if (__atomic_load_n(c->host_err + q, __ATOMIC_ACQUIRE)) bits |= 1 << q;
+  return bits;
+}
+
+dpvba_status dpvba_device_status(dpvba_ctx* c, void* stream, int32_t* cause) {
+  if (!c) return DPVBA_EINVAL;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  const int bits = recorded_failure(c);
+  if (cause) *cause = bits;
+  if (!bits) return DPVBA_OK;
+  // re-arm: barrier slots and failure words start from zero again
+  HIP_TRY(hipMemsetAsync(c->ticket.p, 0, 64, (hipStream_t)stream));
+  HIP_TRY(hipMemsetAsync(c->dev_err.p, 0, 64, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  for (int q = 0; q < kHostErrWords; ++q) __atomic_store_n(c->host_err + q, 0, __ATOMIC_RELEASE);
+  return DPVBA_EDEVICE;
 }
 
 void dpvba_destroy(dpvba_ctx* c) {
@@ -398,6 +455,7 @@ void dpvba_destroy(dpvba_ctx* c) {
       if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->host_flag) (void)hipHostFree(c->host_flag);
+  if (c->host_err) (void)hipHostFree(c->host_err);
   {
     DevBuf* bb[] = {&c->bt.inst[0], &c->bt.inst[1], &c->bt.status, &c->bt.min_bits, &c->bt.refine, &c->bt.fallback,
                     &c->bt.reps, &c->bt.scratch_buf};
@@ -411,6 +469,8 @@ void dpvba_destroy(dpvba_ctx* c) {
   delete c;
 }
 
+static hipError_t backward_workspace(dpvba_ctx* c, int N, long long ntp, long long E, int n);
+
 static bool graph_sizes_ok(const dpvba_graph* g) {
   if (!g) return false;
   if (g->n_frames < 1 || g->n_patches < 0 || g->n_edges < 0) return false;
@@ -421,6 +481,23 @@ static bool graph_sizes_ok(const dpvba_graph* g) {
   if (g->n_edges > 0 && (!g->ii || !g->jj || !g->kk || !g->target || !g->weight)) return false;
   if (g->n_patches > 0 && !g->patches) return false;
   return true;
+}
+
+// Targets and weights of E edges copied to the host (synchronising st) and
+// checked: every value finite, every weight >= 0.
+static hipError_t inputs_valid(const float* target, const float* weight, long long E, hipStream_t st, bool* ok) {
+  *ok = true;
+  if (E <= 0) return hipSuccess;
+  std::vector<float> tw(4 * (size_t)E);
+  hipError_t e = hipMemcpyAsync(tw.data(), target, (size_t)E * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(tw.data() + 2 * E, weight, (size_t)E * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  for (size_t q = 0; q < 2 * (size_t)E; ++q)
+    if (!(std::fabs(tw[q]) <= FLT_MAX)) *ok = false;
+  for (size_t q = 2 * (size_t)E; q < 4 * (size_t)E; ++q)
+    if (!(tw[q] >= 0.f && tw[q] <= FLT_MAX)) *ok = false;
+  return hipSuccess;
 }
 
 // Host copy of one tiling.
@@ -647,6 +724,11 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   }
   ProblemIndex X;
   if (!index_problem(N, P, E, ii.data(), jj.data(), kk.data(), X)) return DPVBA_EINVAL;
+  {
+    bool ok = true;
+    HIP_TRY(inputs_valid(g->target, g->weight, E, st, &ok));
+    if (!ok) return DPVBA_EINVAL;
+  }
   const std::vector<int32_t>& pcount = X.pcount;
   const std::vector<int32_t>& pedges = X.pedges;
   const std::vector<std::vector<int32_t>>& frame_patches = X.frame_patches;
@@ -713,13 +795,6 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
     c->chain_epoch = 0;
   }
   HIP_TRY(ensure(c->edge_part, ((size_t)(E + 255) / 256) * 8));
-  if (!c->ticket.p) {
-    HIP_TRY(ensure(c->ticket, 64));
-    HIP_TRY(ensure(c->dev_err, 64));
-    HIP_TRY(hipMemsetAsync(c->ticket.p, 0, 64, st));
-    HIP_TRY(hipMemsetAsync(c->dev_err.p, 0, 64, st));
-    HIP_TRY(hipStreamSynchronize(st));
-  }
   HIP_TRY(ensure(c->status, 2 * DPVBA_MAX_ITERS * 4));  // [MAX, 2 MAX): float64 fallback solves
   HIP_TRY(ensure(c->min_bits, 2 * DPVBA_MAX_ITERS * 4));
   HIP_TRY(ensure(c->S32, n * n * 4));
@@ -734,6 +809,8 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(ensure(c->mx_flag, 16));
   if (!c->host_flag) HIP_TRY(hipHostMalloc((void**)&c->host_flag, sizeof(int), hipHostMallocDefault));
   HIP_TRY(ensure(c->devrep, sizeof(dpvba_report)));
+  HIP_TRY(backward_workspace(c, N, std::max((long long)H32.tile_patch.size(), (long long)H64.tile_patch.size()), E,
+                             (int)n));
 
   c->N = N; c->P = P; c->E = E; c->p = g->patch_size; c->n_fixed = nf; c->n_free = n_free;
   c->ii = g->ii; c->jj = g->jj; c->kk = g->kk;
@@ -755,20 +832,32 @@ static dpvba_status check_analysed(const dpvba_ctx* c, const dpvba_graph* g) {
   return DPVBA_OK;
 }
 
-static dpvba_status check_opts(const dpvba_opts* o) {
+// Options of a numeric call; `extra` are the flag bits that call accepts
+// besides the damping flag.
+static dpvba_status check_opts(const dpvba_opts* o, uint32_t extra = 0) {
   if (!o) return DPVBA_EINVAL;
   if (o->n_iters < 0 || o->n_iters > DPVBA_MAX_ITERS) return DPVBA_EINVAL;
   if (!(o->lambda >= 0.0) || !(o->lambda < (double)FLT_MAX)) return DPVBA_EINVAL;
   if (!(o->z_min >= 0.0) || !(o->z_min < (double)FLT_MAX)) return DPVBA_EINVAL;
   if (o->precision != DPVBA_FP32 && o->precision != DPVBA_MIXED && o->precision != DPVBA_FP64) return DPVBA_EINVAL;
-  if (o->flags != 0) return DPVBA_EINVAL;
+  const uint32_t mixed_only = DPVBA_FLAG_FORCE_FP64_CHOL | DPVBA_FLAG_NO_REFINE;
+  if (o->flags & ~(DPVBA_FLAG_LEVENBERG | mixed_only | extra)) return DPVBA_EINVAL;
+  if ((o->flags & mixed_only) && o->precision != DPVBA_MIXED) return DPVBA_EINVAL;
   return DPVBA_OK;
+}
+
+// Marquardt coefficient of the damping H~ = H + lam_diag Diag(H) + lambda I.
+static double lam_diag_of(const dpvba_opts* o) {
+  return (o->flags & DPVBA_FLAG_LEVENBERG) ? 0.0 : o->lambda;
 }
 
 template <typename T>
 static IterArgs<T> make_iter_args(dpvba_ctx* c, const dpvba_graph* g, const Tiling& tl, const T* poses_cur,
-                                  T* poses_next, const T* depth_in, T lambda, T z_min) {
+                                  T* poses_next, const T* depth_in, T lambda, T z_min, T lam_diag, int* dev_err) {
   IterArgs<T> A{};
+  A.lam_diag = lam_diag;
+  A.dev_err = dev_err;
+  A.host_err = c->host_err_dev;
   A.patches = g->patches;
   A.p = g->patch_size;
   A.target = g->target;
@@ -812,11 +901,16 @@ static bool use_small_path(const dpvba_ctx* c) {
   return n + 1 <= kSmallRows && small_solve_lds_bytes(n, (int)sizeof(T)) <= 160 * 1024;
 }
 
+// Failure word of the calls that run as several launches (cleared by their
+// report initialisation).
+static int* large_err(dpvba_ctx* c) { return (int*)c->dev_err.p + 8; }
+static int* batch_err(dpvba_ctx* c) { return (int*)c->dev_err.p + 12; }
+
 template <typename T>
 static hipError_t reduced_impl(dpvba_ctx* c, const dpvba_graph* g, const T* poses, const T* depth, T lambda,
-                               T z_min, T* S, T* rhs, double* cost_out, hipStream_t st) {
+                               T lam_diag, T z_min, T* S, T* rhs, double* cost_out, hipStream_t st) {
   const Tiling& tl = c->tl[sizeof(T) == 8 ? 1 : 0];
-  IterArgs<T> A = make_iter_args<T>(c, g, tl, poses, nullptr, depth, lambda, z_min);
+  IterArgs<T> A = make_iter_args<T>(c, g, tl, poses, nullptr, depth, lambda, z_min, lam_diag, large_err(c));
   hipError_t e;
   {
     TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
@@ -831,15 +925,15 @@ static hipError_t reduced_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pose
   }
   return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
                           (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free, S,
-                          rhs, (T*)c->dB.p, lambda, 1, (T*)c->d0.p, st);
+                          rhs, (T*)c->dB.p, lambda, lam_diag, 1, (T*)c->d0.p, st);
 }
 
 // Float32 tile assembly gathered in float64 (the DPVBA_MIXED system).
 static hipError_t reduced_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, const float* poses, const float* depth,
-                                     float lambda, float z_min, double* S, double* rhs, double* cost_out,
-                                     hipStream_t st) {
+                                     float lambda, float lam_diag, float z_min, double* S, double* rhs,
+                                     double* cost_out, hipStream_t st) {
   const Tiling& tl = c->tl[0];
-  IterArgs<float> A = make_iter_args<float>(c, g, tl, poses, nullptr, depth, lambda, z_min);
+  IterArgs<float> A = make_iter_args<float>(c, g, tl, poses, nullptr, depth, lambda, z_min, lam_diag, large_err(c));
   hipError_t e;
   {
     TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
@@ -855,13 +949,13 @@ static hipError_t reduced_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, const f
   return launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
                                          (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
                                          (const int2*)tl.v_src.p, c->n_free, S, rhs, (double*)c->dB.p,
-                                         (double)lambda, 1, (double*)c->d0.p, st);
+                                         (double)lambda, (double)lam_diag, 1, (double*)c->d0.p, st);
 }
 
 template <typename T>
 static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* depth, const dpvba_opts* o,
                              dpvba_report* report, hipStream_t st) {
-  const T lambda = (T)o->lambda, z_min = (T)o->z_min;
+  const T lambda = (T)o->lambda, z_min = (T)o->z_min, lam_diag = (T)lam_diag_of(o);
   const Tiling& tl = c->tl[sizeof(T) == 8 ? 1 : 0];
   const int n = 6 * c->n_free;
   const int nit = o->n_iters;
@@ -872,9 +966,12 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
   T* pbuf[2] = {(T*)c->poses_a.p, (T*)c->poses_b.p};
   T* dx = (T*)c->dx.p;
   hipError_t e;
+  // the call's failure word: that of the single launch's parity, else the large path's
+  const int parity = (int)(c->small_launches & 1);
+  int* err = small && nit > 0 ? (int*)c->dev_err.p + 4 * parity : large_err(c);
   if (small && nit > 0) {
     SmallArgs<T> S{};
-    S.it = make_iter_args<T>(c, g, tl, poses, pbuf[0], depth, lambda, z_min);
+    S.it = make_iter_args<T>(c, g, tl, poses, pbuf[0], depth, lambda, z_min, lam_diag, err);
     S.poses_io = poses;
     S.depth_io = depth;
     S.pbuf0 = pbuf[0];
@@ -887,8 +984,10 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     S.cost = dev->cost;
     S.invalid = dev->n_invalid;
     S.n_iters = nit;
-    S.bar = (unsigned int*)c->ticket.p;
-    S.err = (int*)c->dev_err.p;
+    S.bar = (unsigned int*)c->ticket.p + 8 * parity;
+    S.bar_next = (unsigned int*)c->ticket.p + 8 * (1 - parity);
+    S.err = err;
+    S.err_next = (int*)c->dev_err.p + 4 * (1 - parity);
     const int lds_small = std::max(tl.lds_bytes, small_solve_lds_bytes(n, (int)sizeof(T)));
     int& cap = sizeof(T) == 8 ? c->coop_grid64 : c->coop_grid32;
     int& cap_lds = sizeof(T) == 8 ? c->coop_lds64 : c->coop_lds32;
@@ -901,15 +1000,16 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     TraceScope ts(c, DPVBA_PHASE_ASSEMBLE, st);
     e = launch_small_solve<T>(S, grid, lds_small, c->coop_launch, st);
     if (e != hipSuccess) return e;
+    ++c->small_launches;
   }
   if (!small) {
-    e = launch_report_init(status, mb, DPVBA_MAX_ITERS, st);
+    e = launch_report_init(status, mb, DPVBA_MAX_ITERS, st, err);
     if (e != hipSuccess) return e;
   }
   for (int it = 0; it < nit && !small; ++it) {
     const T* cur = it == 0 ? poses : pbuf[(it - 1) & 1];
     T* next = pbuf[it & 1];
-    IterArgs<T> A = make_iter_args<T>(c, g, tl, cur, next, depth, lambda, z_min);
+    IterArgs<T> A = make_iter_args<T>(c, g, tl, cur, next, depth, lambda, z_min, lam_diag, err);
     A.first = it == 0;
     A.dx_prev = it ? dx : nullptr;
     A.status_prev = it ? status + it - 1 : nullptr;
@@ -925,13 +1025,13 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
       if (e == hipSuccess)
         e = launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
                              (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
-                             (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, 0, (T*)c->d0.p, st);
+                             (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, lam_diag, 0, (T*)c->d0.p, st);
     }
     if (e != hipSuccess) return e;
     {
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
       e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, dx, (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p,
-                               status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), (int*)c->dev_err.p, st);
+                               status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st);
     }
     if (e != hipSuccess) return e;
     {
@@ -959,7 +1059,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
   e = launch_report_reduce((const double*)c->edge_part.p, nullptr, (g->n_edges + 255) / 256, &dev->cost[nit],
                            nullptr, st);
   if (e != hipSuccess) return e;
-  e = launch_report_finalize(dev, status, mb, nit, (const int*)c->dev_err.p, st);
+  e = launch_report_finalize(dev, status, mb, nit, err, st);
   if (e != hipSuccess) return e;
   return hipMemcpyAsync(report, dev, sizeof(dpvba_report), hipMemcpyDeviceToHost, st);
 }
@@ -972,10 +1072,14 @@ constexpr double kRefineTol = 1e-8;
 // DPVBA_MIXED: float32 state and tile assembly, float64 gather of the
 // shares, float32 Cholesky with float64 iterative refinement, float64
 // Cholesky when refinement does not reach kRefineTol (decided on the host
-// after one stream synchronisation per iteration).
+// after one stream synchronisation per iteration, unless the fallback is
+// forced by DPVBA_FLAG_FORCE_FP64_CHOL).
 static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* poses, float* depth,
                                    const dpvba_opts* o, dpvba_report* report, hipStream_t st) {
-  const float lambda = (float)o->lambda, z_min = (float)o->z_min;
+  const float lambda = (float)o->lambda, z_min = (float)o->z_min, lam_diag = (float)lam_diag_of(o);
+  const bool force_fb = (o->flags & DPVBA_FLAG_FORCE_FP64_CHOL) != 0;
+  const int n_refine = (o->flags & DPVBA_FLAG_NO_REFINE) ? 0 : kRefineSteps;
+  int* err = large_err(c);
   const Tiling& tl = c->tl[0];
   const int n = 6 * c->n_free;
   const int nit = o->n_iters;
@@ -1000,13 +1104,13 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
   double* resid = (double*)c->mx_resid.p;
   int* fb = (int*)c->mx_fb.p;
   hipError_t e;
-  if ((e = launch_report_init(status, mb, 2 * DPVBA_MAX_ITERS, st)) != hipSuccess) return e;
+  if ((e = launch_report_init(status, mb, 2 * DPVBA_MAX_ITERS, st, err)) != hipSuccess) return e;
   if ((e = launch_fill<double>(resid, DPVBA_MAX_ITERS, 0.0, st)) != hipSuccess) return e;
   if ((e = launch_fill<int>(fb, DPVBA_MAX_ITERS, 0, st)) != hipSuccess) return e;
   for (int it = 0; it < nit; ++it) {
     const float* cur = it == 0 ? poses : pbuf[(it - 1) & 1];
     float* next = pbuf[it & 1];
-    IterArgs<float> A = make_iter_args<float>(c, g, tl, cur, next, depth, lambda, z_min);
+    IterArgs<float> A = make_iter_args<float>(c, g, tl, cur, next, depth, lambda, z_min, lam_diag, err);
     A.first = it == 0;
     A.dx_prev = it ? dx : nullptr;
     A.status_prev = it ? status + it - 1 : nullptr;
@@ -1022,7 +1126,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
         e = launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
                                             (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
                                             (const int2*)tl.v_src.p, c->n_free, S64, s64, (double*)c->dB.p,
-                                            (double)lambda, 1, d064, st);
+                                            (double)lambda, (double)lam_diag, 1, d064, st);
       if (e != hipSuccess) return e;
     }
     if (n > 0 && n <= kBatchMaxUnknowns) {
@@ -1038,6 +1142,9 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       a.v_off = (const int*)tl.v_off.p;
       a.v_src = (const int2*)tl.v_src.p;
       a.lambda = (double)lambda;
+      a.lam_diag = (double)lam_diag;
+      a.n_refine = n_refine;
+      a.force_fb = force_fb ? 1 : 0;
       a.poses_cur = cur;
       a.poses_next = next;
       a.dx = dx;
@@ -1063,27 +1170,31 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       if ((e = launch_convert<double, float>(s64, rhs32, n, st)) != hipSuccess) return e;
       if ((e = launch_chol_factor<float>(S32, n, Linv32, d032, status + it, mb + it, st)) != hipSuccess) return e;
       if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
-                                    next_epoch(c), (int*)c->dev_err.p, st)) != hipSuccess)
+                                    next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
         return e;
       if ((e = launch_convert<float, double>(c32, x64, n, st)) != hipSuccess) return e;
-      for (int k = 0; k < kRefineSteps; ++k) {
+      for (int k = 0; k < n_refine; ++k) {
         if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
         if ((e = launch_convert<double, float>(r64, rhs32, n, st)) != hipSuccess) return e;
         if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
-                                      next_epoch(c), (int*)c->dev_err.p, st)) != hipSuccess)
+                                      next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
           return e;
         if ((e = launch_accumulate(x64, c32, n, st)) != hipSuccess) return e;
       }
       if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
-      if ((e = launch_refine_decide(maxes, status + it, kRefineTol, resid + it, fb + it, (int*)c->mx_flag.p, st)) !=
-          hipSuccess)
+      if ((e = launch_refine_decide(maxes, status + it, kRefineTol, force_fb ? 1 : 0, resid + it, fb + it,
+                                    (int*)c->mx_flag.p, st)) != hipSuccess)
         return e;
-      if ((e = hipMemcpyAsync(c->host_flag, c->mx_flag.p, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
-        return e;
-      if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-      if (*c->host_flag) {
+      bool run64 = force_fb;
+      if (!force_fb) {
+        if ((e = hipMemcpyAsync(c->host_flag, c->mx_flag.p, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+          return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        run64 = *c->host_flag != 0;
+      }
+      if (run64) {
         if ((e = launch_chol_solve<double>(S64, s64, n, x64, (double*)c->wy.p, (double*)c->Linv.p, d064, status64 + it,
-                                           mb64 + it, (int*)c->chain_flags.p, next_epoch(c), (int*)c->dev_err.p,
+                                           mb64 + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev,
                                            st)) != hipSuccess)
           return e;
       }
@@ -1113,7 +1224,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
   e = launch_report_reduce((const double*)c->edge_part.p, nullptr, (g->n_edges + 255) / 256, &dev->cost[nit], nullptr,
                            st);
   if (e != hipSuccess) return e;
-  e = launch_report_finalize(dev, status, mb, nit, (const int*)c->dev_err.p, st, resid, fb);
+  e = launch_report_finalize(dev, status, mb, nit, err, st, resid, fb);
   if (e != hipSuccess) return e;
   return hipMemcpyAsync(report, dev, sizeof(dpvba_report), hipMemcpyDeviceToHost, st);
 }
@@ -1184,26 +1295,15 @@ static bool batch_sizes_ok(const dpvba_batch* b) {
   return true;
 }
 
-// Adjoint of `n_iters` iterations started from (poses0, depth0): replays
-// the iterations storing x_t and the pose steps, then walks them backwards
-// (see adjoint.hip), recomputing each iteration's Schur system at x_t.
-template <typename T>
-static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* poses0, const T* depth0,
-                                const dpvba_opts* o, const T* grad_poses, const T* grad_depth, T* grad_target,
-                                T* grad_weight, hipStream_t st) {
-  const T lambda = (T)o->lambda, z_min = (T)o->z_min;
-  const Tiling& tl = c->tl[sizeof(T) == 8 ? 1 : 0];
-  const int N = c->N, nf = c->n_fixed, n = 6 * c->n_free, nit = o->n_iters, E = c->E;
-  const long long ntp = tl.n_tp, np7 = 7LL * N;
-  const size_t ts = sizeof(T);
+// Workspace of dpvba_solve_backward for up to DPVBA_MAX_ITERS iterations in
+// float64 (float32 uses a prefix of every buffer).
+static hipError_t backward_workspace(dpvba_ctx* c, int N, long long ntp, long long E, int n) {
+  const size_t ts = 8, np7 = 7 * (size_t)N, it = DPVBA_MAX_ITERS;
   hipError_t e;
-  if ((e = launch_fill<T>(grad_target, 2LL * E, (T)0, st)) != hipSuccess) return e;
-  if ((e = launch_fill<T>(grad_weight, 2LL * E, (T)0, st)) != hipSuccess) return e;
-  if (nit == 0) return hipSuccess;
-  if ((e = ensure(c->bw_poses, (size_t)(nit + 1) * np7 * ts)) != hipSuccess) return e;
-  if ((e = ensure(c->bw_depth, (size_t)nit * ntp * ts)) != hipSuccess) return e;
-  if ((e = ensure(c->bw_dx, (size_t)nit * n * ts)) != hipSuccess) return e;
-  if ((e = ensure(c->bw_pbar, (size_t)np7 * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_poses, (it + 1) * np7 * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_depth, it * (size_t)ntp * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_dx, it * (size_t)n * ts)) != hipSuccess) return e;
+  if ((e = ensure(c->bw_pbar, np7 * ts)) != hipSuccess) return e;
   if ((e = ensure(c->bw_dbar, (size_t)ntp * ts)) != hipSuccess) return e;
   if ((e = ensure(c->bw_dxbar, (size_t)n * ts)) != hipSuccess) return e;
   if ((e = ensure(c->bw_rhs, (size_t)n * ts)) != hipSuccess) return e;
@@ -1212,7 +1312,30 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
   if ((e = ensure(c->bw_dd, (size_t)ntp * ts)) != hipSuccess) return e;
   if ((e = ensure(c->bw_edge, (size_t)E * 15 * ts)) != hipSuccess) return e;
   if ((e = ensure(c->bw_status, 2 * DPVBA_MAX_ITERS * 4)) != hipSuccess) return e;
-  if ((e = ensure(c->bw_minbits, 2 * DPVBA_MAX_ITERS * 4)) != hipSuccess) return e;
+  return ensure(c->bw_minbits, 2 * DPVBA_MAX_ITERS * 4);
+}
+
+// Adjoint of `n_iters` iterations started from (poses0, depth0): replays
+// the iterations storing x_t and the pose steps, then walks them backwards
+// (see adjoint.hip), recomputing each iteration's Schur system at x_t.
+template <typename T>
+static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* poses0, const T* depth0,
+                                const dpvba_opts* o, const T* grad_poses, const T* grad_depth, T* grad_target,
+                                T* grad_weight, hipStream_t st) {
+  const T lambda = (T)o->lambda, z_min = (T)o->z_min, lam_diag = (T)lam_diag_of(o);
+  const Tiling& tl = c->tl[sizeof(T) == 8 ? 1 : 0];
+  const int N = c->N, nf = c->n_fixed, n = 6 * c->n_free, nit = o->n_iters, E = c->E;
+  int* err = large_err(c);
+  const long long ntp = tl.n_tp, np7 = 7LL * N;
+  const size_t ts = sizeof(T);
+  hipError_t e;
+  if ((e = launch_fill<T>(grad_target, 2LL * E, (T)0, st)) != hipSuccess) return e;
+  if ((e = launch_fill<T>(grad_weight, 2LL * E, (T)0, st)) != hipSuccess) return e;
+  if (nit == 0) return hipSuccess;
+  // workspace sized by the analysis (backward_workspace) for DPVBA_MAX_ITERS
+  if (c->bw_poses.bytes < (size_t)(nit + 1) * np7 * ts || c->bw_depth.bytes < (size_t)nit * ntp * ts ||
+      c->bw_edge.bytes < (size_t)E * 15 * ts)
+    return hipErrorInvalidValue;
   T* Xp = (T*)c->bw_poses.p;
   T* Xd = (T*)c->bw_depth.p;
   T* DX = (T*)c->bw_dx.p;
@@ -1227,17 +1350,17 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
   int* status = (int*)c->bw_status.p;  // [0, MAX): replayed steps, [MAX, 2 MAX): adjoint solves
   unsigned int* mb = (unsigned int*)c->bw_minbits.p;
   const TileInfo* tiles = (const TileInfo*)tl.tiles.p;
-  if ((e = launch_report_init(status, mb, 2 * DPVBA_MAX_ITERS, st)) != hipSuccess) return e;
+  if ((e = launch_report_init(status, mb, 2 * DPVBA_MAX_ITERS, st, err)) != hipSuccess) return e;
   if ((e = launch_copy<T>(poses0, Xp, np7, st)) != hipSuccess) return e;
   auto gather = [&]() {
     return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
                             (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
-                            (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, 0, (T*)c->d0.p, st);
+                            (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, lam_diag, 0, (T*)c->d0.p, st);
   };
   // replay: x_0 .. x_T, depths d_0 .. d_{T-1} in tile order, steps of the poses
   for (int it = 0; it < nit; ++it) {
     T* xt = Xp + it * np7;
-    IterArgs<T> A = make_iter_args<T>(c, g, tl, xt, nullptr, depth0, lambda, z_min);
+    IterArgs<T> A = make_iter_args<T>(c, g, tl, xt, nullptr, depth0, lambda, z_min, lam_diag, err);
     A.first = it == 0;
     A.dx_prev = it ? DX + (size_t)(it - 1) * n : nullptr;
     A.status_prev = it ? status + it - 1 : nullptr;
@@ -1246,7 +1369,7 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
     if ((e = gather()) != hipSuccess) return e;
     if ((e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, DX + (size_t)it * n, (T*)c->wy.p,
                                   (T*)c->Linv.p, (const T*)c->d0.p, status + it, mb + it, (int*)c->chain_flags.p,
-                                  next_epoch(c), (int*)c->dev_err.p, st)) != hipSuccess)
+                                  next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
       return e;
     if ((e = launch_retract_copy<T>(xt, xt + np7, DX + (size_t)it * n, nf, N, status + it, st)) != hipSuccess)
       return e;
@@ -1262,7 +1385,7 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
     const T* dx_t = DX + (size_t)it * n;
     const int* stt = status + it;
     if ((e = launch_retract_adjoint<T>(xt, dx_t, stt, nf, N, pbar, dxbar, st)) != hipSuccess) return e;
-    IterArgs<T> A = make_iter_args<T>(c, g, tl, xt, nullptr, depth0, lambda, z_min);
+    IterArgs<T> A = make_iter_args<T>(c, g, tl, xt, nullptr, depth0, lambda, z_min, lam_diag, err);
     A.first = 0;
     A.dx_prev = nullptr;
     A.depth_s = Xd + it * ntp;
@@ -1274,7 +1397,7 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
       return e;
     if ((e = launch_chol_solve<T>((T*)c->S.p, urhs, n, up, (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p,
                                   status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it, (int*)c->chain_flags.p,
-                                  next_epoch(c), (int*)c->dev_err.p, st)) != hipSuccess)
+                                  next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
       return e;
     if ((e = launch_adjoint_backsub<T>(tiles, tl.n_tiles, tl.max_w6, (const int*)tl.blk_pose.p,
                                        (const T*)c->U_s.p, (const T*)c->pscale_s.p, dbar, up, dx_t, stt, ud, dd,
@@ -1282,7 +1405,7 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
       return e;
     if ((e = launch_edge_adjoint<T>(xt, Xd + it * ntp, (const int*)c->patch_pos.p, g->patches, g->patch_size, g->ii,
                                     g->jj, g->kk, g->target, g->weight, E, nf, (T)g->fx, (T)g->fy, (T)g->cx,
-                                    (T)g->cy, z_min, lambda, up, ud, dx_t, dd, stt, grad_target, grad_weight, exb,
+                                    (T)g->cy, z_min, lam_diag, up, ud, dx_t, dd, stt, grad_target, grad_weight, exb,
                                     st)) != hipSuccess)
       return e;
     if ((e = launch_adjoint_reduce<T>(exb, (const int*)c->pose_off.p, (const int*)c->pose_src.p, nf, N, pbar,
@@ -1300,6 +1423,7 @@ dpvba_status dpvba_reproject(dpvba_ctx* c, const dpvba_graph* g, const float* po
   if (!c || !graph_sizes_ok(g)) return DPVBA_EINVAL;
   if (!(z_min >= 0.f) || !(z_min < FLT_MAX)) return DPVBA_EINVAL;
   if (g->n_edges > 0 && (!poses || !inv_depth || !coords)) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(launch_reproject(poses, inv_depth, g->patches, g->patch_size, g->ii, g->jj, g->kk, g->n_edges, g->fx,
                            g->fy, g->cx, g->cy, z_min, coords, valid, (hipStream_t)stream));
@@ -1314,17 +1438,19 @@ dpvba_status dpvba_reduced_system(dpvba_ctx* c, const dpvba_graph* g, const floa
   rc = check_analysed(c, g);
   if (rc != DPVBA_OK) return rc;
   if (!poses || (!inv_depth && c->P > 0) || (c->n_free > 0 && (!S || !s))) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   if (o->precision == DPVBA_FP64) {
     HIP_TRY(reduced_impl<double>(c, g, (const double*)(const void*)poses, (const double*)(const void*)inv_depth,
-                                 (double)o->lambda, (double)o->z_min, (double*)S, (double*)s, cost, st));
+                                 (double)o->lambda, lam_diag_of(o), (double)o->z_min, (double*)S, (double*)s, cost,
+                                 st));
   } else if (o->precision == DPVBA_MIXED) {
-    HIP_TRY(reduced_mixed_impl(c, g, poses, inv_depth, (float)o->lambda, (float)o->z_min, (double*)S, (double*)s,
-                               cost, st));
+    HIP_TRY(reduced_mixed_impl(c, g, poses, inv_depth, (float)o->lambda, (float)lam_diag_of(o), (float)o->z_min,
+                               (double*)S, (double*)s, cost, st));
   } else {
-    HIP_TRY(reduced_impl<float>(c, g, poses, inv_depth, (float)o->lambda, (float)o->z_min, (float*)S, (float*)s,
-                                cost, st));
+    HIP_TRY(reduced_impl<float>(c, g, poses, inv_depth, (float)o->lambda, (float)lam_diag_of(o), (float)o->z_min,
+                                (float*)S, (float*)s, cost, st));
   }
   return DPVBA_OK;
 }
@@ -1337,6 +1463,7 @@ dpvba_status dpvba_solve(dpvba_ctx* c, const dpvba_graph* g, float* poses, float
   rc = check_analysed(c, g);
   if (rc != DPVBA_OK) return rc;
   if (!poses || (!inv_depth && c->P > 0)) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   if (o->precision == DPVBA_FP64) {
@@ -1361,6 +1488,7 @@ dpvba_status dpvba_solve_backward(dpvba_ctx* c, const dpvba_graph* g, const floa
   if (!poses0 || (!inv_depth0 && c->P > 0)) return DPVBA_EINVAL;
   if (c->E > 0 && (!grad_target || !grad_weight)) return DPVBA_EINVAL;
   if (o->precision == DPVBA_MIXED) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   if (o->precision == DPVBA_FP64) {
@@ -1384,14 +1512,15 @@ static hipError_t batch_impl(dpvba_ctx* c, const dpvba_batch* b, T* poses, T* de
   auto& B = c->bt;
   const int ti = sizeof(T) == 8 ? 1 : 0;
   const Tiling& tl = B.tl[ti];
-  const T lambda = (T)o->lambda, z_min = (T)o->z_min;
+  const T lambda = (T)o->lambda, z_min = (T)o->z_min, lam_diag = (T)lam_diag_of(o);
   const int nit = o->n_iters;
   const int stride = DPVBA_MAX_ITERS;
   int* status = (int*)B.status.p;
   unsigned int* mb = (unsigned int*)B.min_bits.p;
   T* pbuf[2] = {(T*)c->poses_a.p, (T*)c->poses_b.p};
+  int* err = batch_err(c);
   hipError_t e;
-  if ((e = launch_report_init(status, mb, B.B * stride, st)) != hipSuccess) return e;
+  if ((e = launch_report_init(status, mb, B.B * stride, st, err)) != hipSuccess) return e;
   bool lds_factor = false;
   const int lds_solve = batch_solve_lds<T>(B.n_max, mixed, &lds_factor);
   for (int it = 0; it < nit; ++it) {
@@ -1405,6 +1534,9 @@ static hipError_t batch_impl(dpvba_ctx* c, const dpvba_batch* b, T* poses, T* de
     A.fx = b->fx; A.fy = b->fy; A.cx = b->cx; A.cy = b->cy;
     A.z_min = z_min;
     A.lambda = lambda;
+    A.lam_diag = lam_diag;
+    A.dev_err = err;
+    A.host_err = c->host_err_dev;
     A.n_tiles = tl.n_tiles;
     A.poses_cur = cur;
     A.depth_in = depth;
@@ -1442,6 +1574,9 @@ static hipError_t batch_impl(dpvba_ctx* c, const dpvba_batch* b, T* poses, T* de
     a.v_off = (const int*)tl.v_off.p;
     a.v_src = (const int2*)tl.v_src.p;
     a.lambda = (double)lambda;
+    a.lam_diag = (double)lam_diag;
+    a.n_refine = (o->flags & DPVBA_FLAG_NO_REFINE) ? 0 : 2;
+    a.force_fb = (o->flags & DPVBA_FLAG_FORCE_FP64_CHOL) ? 1 : 0;
     a.poses_cur = cur;
     a.poses_next = next;
     a.dx = (T*)c->dx.p;
@@ -1517,6 +1652,11 @@ dpvba_status dpvba_analyze_batch(dpvba_ctx* c, const dpvba_batch* b, const int32
     HIP_TRY(hipMemcpyAsync(jj.data(), b->jj, (size_t)E * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(kk.data(), b->kk, (size_t)E * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+  }
+  {
+    bool ok = true;
+    HIP_TRY(inputs_valid(b->target, b->weight, E, st, &ok));
+    if (!ok) return DPVBA_EINVAL;
   }
   HostTiling H[2];
   std::vector<BatchInst> inst[2];
@@ -1616,13 +1756,11 @@ dpvba_status dpvba_solve_batch(dpvba_ctx* c, const dpvba_batch* b, float* poses,
       !std::equal(Bt.edge_off.begin(), Bt.edge_off.end(), b->edge_off) ||
       !std::equal(Bt.n_fixed.begin(), Bt.n_fixed.end(), b->n_fixed))
     return DPVBA_ESTATE;
-  dpvba_opts oo = *o;
   const bool graph = (o->flags & DPVBA_FLAG_GRAPH) != 0;
-  oo.flags = 0;
-  dpvba_status rc = check_opts(&oo);
+  dpvba_status rc = check_opts(o, DPVBA_FLAG_GRAPH);
   if (rc != DPVBA_OK) return rc;
-  if (o->flags & ~DPVBA_FLAG_GRAPH) return DPVBA_EINVAL;
   if (!poses || (!inv_depth && Bt.P > 0)) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
   if (graph && !stream) return DPVBA_EINVAL;
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
@@ -1633,14 +1771,22 @@ dpvba_status dpvba_solve_batch(dpvba_ctx* c, const dpvba_batch* b, float* poses,
     return batch_impl<float>(c, b, poses, inv_depth, o, mixed, st);
   };
   if (graph && !c->tracing) {
+    // everything the recorded launches bake in: the caller's pointers, the
+    // options, the camera, the stream, and the workspace addresses (any
+    // reallocation of a workspace buffer, by either analysis, changes the
+    // generation)
     double lam = o->lambda, zm = o->z_min;
     uint64_t lb, zb;
     std::memcpy(&lb, &lam, 8);
     std::memcpy(&zb, &zm, 8);
+    float cam[4] = {b->fx, b->fy, b->cx, b->cy};
+    uint64_t cb[2];
+    std::memcpy(cb, cam, 16);
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)poses, (uint64_t)(uintptr_t)inv_depth,
                                  (uint64_t)(uintptr_t)b->patches, (uint64_t)(uintptr_t)b->target,
                                  (uint64_t)(uintptr_t)b->weight, (uint64_t)o->n_iters, (uint64_t)o->precision, lb,
-                                 zb, (uint64_t)(uintptr_t)st};
+                                 zb, (uint64_t)o->flags, cb[0], cb[1], (uint64_t)(uintptr_t)st,
+                                 g_workspace_generation};
     if (!Bt.exec || key != Bt.key) {
       if (Bt.exec) {
         HIP_TRY(hipGraphExecDestroy(Bt.exec));

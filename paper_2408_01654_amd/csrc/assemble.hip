@@ -26,11 +26,12 @@ __global__ void gather_vec_kernel(const TP* part_vec, const int* off, const int2
 }
 
 // Gather of every lower 6x6 block (P >= Q) of the damped reduced system from
-// the tile partials (zero where no tile contributes), with the Marquardt
-// diagonal lam (Diag(B) + 1) added.  `mirror` also writes the upper triangle.
+// the tile partials (zero where no tile contributes), with the damping
+// lam_diag Diag(B) + lambda added to the diagonal.  `mirror` also writes the
+// upper triangle.
 template <typename TP, typename T>
 __global__ void gather_S_kernel(const TP* part_S, const int* off, const int* src, int n_free, T* S,
-                                const T* dB, T lambda, int mirror, T* diag_out) {
+                                const T* dB, T lambda, T lam_diag, int mirror, T* diag_out) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nblk = (long long)n_free * (n_free + 1) / 2;
   if (g >= nblk * 36) return;
@@ -51,7 +52,7 @@ __global__ void gather_S_kernel(const TP* part_S, const int* off, const int* src
   const int n = 6 * n_free;
   const int row = 6 * Pb + r, col = 6 * Qb + c;
   if (row == col) {
-    v += lambda * (dB[row] + (T)1);
+    v += lam_diag * dB[row] + lambda;
     if (diag_out) diag_out[row] = v;
   }
   S[(size_t)row * n + col] = v;
@@ -157,12 +158,13 @@ __global__ void reproject_kernel(const float* poses, const float* inv_depth, con
 
 
 // Per-solve report state: step status words and pivot minima per iteration.
-__global__ void report_init_kernel(int* status, unsigned int* min_bits, int n) {
+__global__ void report_init_kernel(int* status, unsigned int* min_bits, int n, int* err_clear) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     status[i] = 0;
     min_bits[i] = 0x7f7fffffu;  // bits of FLT_MAX
   }
+  if (i == 0 && err_clear) *err_clear = 0;
 }
 
 __global__ void report_finalize_kernel(dpvba_report* rep, const int* status, const unsigned int* min_bits,
@@ -175,13 +177,14 @@ __global__ void report_finalize_kernel(dpvba_report* rep, const int* status, con
     rep->refine_resid[t] = refine ? refine[t] : 0.0;
     rep->fp64_fallback[t] = fallback ? fallback[t] : 0;
   }
-  if (err && *err) st = DPVBA_EHIP;
+  if (err && (*err & kErrInput)) st = DPVBA_EINVAL;
+  if (err && (*err & (kErrBarrier | kErrChain))) st = DPVBA_EHIP;
   rep->status = st;
   rep->n_iters = n_iters;
 }
 
-hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st) {
-  hipLaunchKernelGGL(report_init_kernel, dim3((n + 63) / 64), dim3(64), 0, st, status, min_bits, n);
+hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st, int* err_clear) {
+  hipLaunchKernelGGL(report_init_kernel, dim3((n + 63) / 64), dim3(64), 0, st, status, min_bits, n, err_clear);
   return hipGetLastError();
 }
 
@@ -198,23 +201,23 @@ hipError_t launch_report_finalize(dpvba_report* rep, const int* status, const un
 template <typename TP, typename T>
 hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
                             const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
-                            int mirror, T* diag_out, hipStream_t st) {
+                            T lam_diag, int mirror, T* diag_out, hipStream_t st) {
   if (n_free == 0) return hipSuccess;
   const int n = 6 * n_free;
   hipLaunchKernelGGL((gather_vec_kernel<TP, T>), dim3((n + 255) / 256), dim3(256), 0, st, part_vec, v_off,
                      v_src, n, rhs, dB);
   const long long tot = (long long)n_free * (n_free + 1) / 2 * 36;
   hipLaunchKernelGGL((gather_S_kernel<TP, T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,
-                     s_off, s_src, n_free, S, dB, lambda, mirror, diag_out);
+                     s_off, s_src, n_free, S, dB, lambda, lam_diag, mirror, diag_out);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
-                         int mirror, T* diag_out, hipStream_t st) {
-  return launch_gather_as<T, T>(part_S, part_vec, s_off, s_src, v_off, v_src, n_free, S, rhs, dB, lambda, mirror,
-                                diag_out, st);
+                         T lam_diag, int mirror, T* diag_out, hipStream_t st) {
+  return launch_gather_as<T, T>(part_S, part_vec, s_off, s_src, v_off, v_src, n_free, S, rhs, dB, lambda, lam_diag,
+                                mirror, diag_out, st);
 }
 
 template <typename T, typename P>
@@ -252,13 +255,13 @@ hipError_t launch_reproject(const float* poses, const float* inv_depth, const fl
 DPVBA_INSTANTIATE(float, float)
 DPVBA_INSTANTIATE(double, double)
 template hipError_t launch_gather<float>(const float*, const float*, const int*, const int*, const int*,
-                                         const int2*, int, float*, float*, float*, float, int, float*,
+                                         const int2*, int, float*, float*, float*, float, float, int, float*,
                                          hipStream_t);
 template hipError_t launch_gather<double>(const double*, const double*, const int*, const int*, const int*,
-                                          const int2*, int, double*, double*, double*, double, int, double*,
-                                          hipStream_t);
+                                          const int2*, int, double*, double*, double*, double, double, int,
+                                          double*, hipStream_t);
 template hipError_t launch_gather_as<float, double>(const float*, const float*, const int*, const int*,
                                                     const int*, const int2*, int, double*, double*, double*,
-                                                    double, int, double*, hipStream_t);
+                                                    double, double, int, double*, hipStream_t);
 
 }  // namespace dpvba

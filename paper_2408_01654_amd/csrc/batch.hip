@@ -17,6 +17,8 @@
 //            scratch copy when the refined residual stays above the tolerance
 //            or a float32 pivot failed.
 #include "edge.h"
+#include <cfloat>
+
 #include "packed.h"
 #include "dpvba.h"
 
@@ -35,7 +37,10 @@ struct BatchArgs {
   const int* s_src;
   const int* v_off;
   const int2* v_src;
-  double lambda;
+  double lambda;          // H~ = H + lam_diag Diag(H) + lambda I
+  double lam_diag;
+  int n_refine;           // mixed: refinement steps
+  int force_fb;           // mixed: always take the float64 factorisation
   const TS* poses_cur;
   TS* poses_next;
   TS* dx;
@@ -114,7 +119,7 @@ __global__ void __launch_bounds__(256) batch_gather_kernel(BatchArgs<TS> a) {
     }
     if (want_s) sv_out[6 * P + m] = sv;
     if (want_d) {
-      v += (TA)a.lambda * (db + (TA)1);
+      v += (TA)a.lam_diag * db + (TA)a.lambda;
       d0_out[row] = v;
     }
   }
@@ -348,7 +353,7 @@ batch_solve_mixed_kernel(BatchArgs<float> a) {
     __syncthreads();
   }
 #pragma unroll 1
-  for (int k = 0; k < kBatchRefine; ++k) {
+  for (int k = 0; k < a.n_refine; ++k) {
     batch_residual(S64, s64, x64, r64, n, red);
     for (int q = threadIdx.x; q < n; q += blockDim.x) c32[q] = (float)r64[q];
     __syncthreads();
@@ -361,7 +366,7 @@ batch_solve_mixed_kernel(BatchArgs<float> a) {
   }
   const double rmax = batch_residual(S64, s64, x64, r64, n, red);
   const double rel = smax > 0.0 ? rmax / smax : rmax;
-  const bool fb = bad32 != 0 || !(rel <= kBatchRefineTol);
+  const bool fb = a.force_fb || bad32 != 0 || !(rel <= kBatchRefineTol);
   bool failed = false;
   if (fb) {  // float64 factorisation of the scratch copy
     for (int q = threadIdx.x; q < n; q += blockDim.x) b64[q] = s64[q];
@@ -405,8 +410,12 @@ __global__ void __launch_bounds__(256) batch_report_kernel(
     const int* status, const unsigned int* min_bits, const double* refine, const int* fallback, int stride,
     int n_iters, dpvba_report* rep) {
   __shared__ double sred[256];
+  __shared__ int bad_in;
   const BatchInst I = inst[blockIdx.x];
+  if (threadIdx.x == 0) bad_in = 0;
+  __syncthreads();
   double cst = 0.0;
+  bool bad = false;
   for (int q = threadIdx.x; q < I.n_edges; q += blockDim.x) {
     const int e = I.edge_begin + q;
     T Ri[9], Rj[9], ti_[3], tj[3], Rt[12];
@@ -421,10 +430,13 @@ __global__ void __launch_bounds__(256) batch_report_kernel(
     EdgeTerms<T> o;
     const float2 tg = reinterpret_cast<const float2*>(target)[e];
     const float2 wt = reinterpret_cast<const float2*>(weight)[e];
+    bad |= !(wt.x >= 0.f && wt.y >= 0.f && wt.x <= FLT_MAX && wt.y <= FLT_MAX && fabsf(tg.x) <= FLT_MAX &&
+             fabsf(tg.y) <= FLT_MAX);
     if (edge_eval<T>(Rt, ((T)cen[0] - cx) / fx, ((T)cen[1] - cy) / fy, inv_depth[k], fx, fy, cx, cy, z_min, tg.x,
                      tg.y, wt.x, wt.y, o))
       cst += 0.5 * ((double)o.w[0] * o.r[0] * o.r[0] + (double)o.w[1] * o.r[1] * o.r[1]);
   }
+  if (bad) bad_in = 1;
   sred[threadIdx.x] = cst;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -442,6 +454,7 @@ __global__ void __launch_bounds__(256) batch_report_kernel(
     R->refine_resid[t] = refine ? refine[q] : 0.0;
     R->fp64_fallback[t] = fallback ? fallback[q] : 0;
   }
+  if (bad_in) s = DPVBA_EINVAL;  // a target or weight outside the documented range
   R->status = s;
   R->n_iters = n_iters;
 }

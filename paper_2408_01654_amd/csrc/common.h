@@ -21,6 +21,19 @@ inline hipError_t opt_in_lds(const void* fn, int bytes) {
 template <typename T>
 __device__ __forceinline__ T dsqrt(T x) { return sqrt(x); }
 
+// Failure bits of a call's device work.  The kernel that meets one ORs it
+// into the call's device word (read by the report) and stores 1 into the
+// context's host-visible word of that cause (host memory mapped into the
+// device's address space: a plain store, no read-modify-write across the
+// bus), which the host checks before every later call.
+__device__ __forceinline__ void report_device_error(int* dev_err, int* host_err, int bit) {
+  if (dev_err) atomicOr(dev_err, bit);
+  if (host_err) {
+    const int word = bit == kErrBarrier ? 0 : (bit == kErrChain ? 1 : 2);
+    __hip_atomic_store(host_err + word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // Rotation matrix (row-major) of a quaternion (x, y, z, w), normalised first.
 template <typename T, typename Q>
 __device__ __forceinline__ void quat_to_rot(const Q* q, T R[9]) {

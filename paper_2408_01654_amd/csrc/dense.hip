@@ -353,7 +353,7 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
 // for the vector they multiply, so the chain only carries the dependent part.
 constexpr long long kChainSpin = 1LL << 22;
 
-__device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err) {
+__device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err, int* host_err) {
   __shared__ int ok_s;
   if (threadIdx.x == 0) {
     long long spins = 0;
@@ -361,7 +361,7 @@ __device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err)
     while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kChainSpin || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        atomicOr(err, 2);
+        report_device_error(err, host_err, kErrChain);
         ok = 0;
         break;
       }
@@ -380,7 +380,7 @@ __device__ __forceinline__ void chain_publish(int* flag, int epoch) {
 
 template <typename T>
 __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, const T* Linv_all, const T* b, T* y,
-                                                         T* x, int* flags, int epoch, int* err) {
+                                                         T* x, int* flags, int epoch, int* err, int* host_err) {
   __shared__ T Li[2][kNB][kNB + 1];  // inverses of the pair's diagonal blocks
   __shared__ T acc[2][kNB];
   __shared__ T vk[2][kNB];
@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
         la[m] = r < rows0 ? L[(size_t)(i0 + r) * n + col] : (T)0;
         lb[m] = r < rows1 ? L[(size_t)(i1 + r) * n + col] : (T)0;
       }
-      if (!chain_wait(fwd + P, epoch, err)) return;
+      if (!chain_wait(fwd + P, epoch, err, host_err)) return;
       if (tid < kNB) {
         vk[0][tid] = y[k0 + tid];
         vk[1][tid] = y[k0 + kNB + tid];
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
         la[m] = (rr < kb && c < rows0) ? L[(size_t)(kr + rr) * n + i0 + c] : (T)0;
         lb[m] = (rr < kb && c < rows1) ? L[(size_t)(kr + rr) * n + i1 + c] : (T)0;
       }
-      if (!chain_wait(bwd + P, epoch, err)) return;
+      if (!chain_wait(bwd + P, epoch, err, host_err)) return;
       if (tid < kNB) {
         vk[0][tid] = tid < kb0 ? x[k0 + tid] : (T)0;
         vk[1][tid] = tid < kb1 ? x[k1 + tid] : (T)0;
@@ -612,18 +612,19 @@ int trsv_chain_grid(int nblk) {
 // library never resets: each call passes a fresh epoch.
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
-                             int epoch, int* err, hipStream_t st) {
+                             int epoch, int* err, int* host_err, hipStream_t st) {
   const int nblk = (n + kNB - 1) / kNB;
   const int grid = trsv_chain_grid<T>(nblk);
   if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
   void* args[] = {(void*)&L, (void*)&n, (void*)&Linv_all, (void*)&rhs, (void*)&work_y, (void*)&x, (void*)&flags,
-                  (void*)&epoch, (void*)&err};
+                  (void*)&epoch, (void*)&err, (void*)&host_err};
   return hipLaunchCooperativeKernel((const void*)trsv_chain_kernel<T>, dim3(grid), dim3(256), args, 0, st);
 }
 
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
-                             unsigned int* min_bits, int* flags, int epoch, int* err, hipStream_t st) {
+                             unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err,
+                             hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (n <= small_solve_max_n(sizeof(T))) {
     const int lds = n + 1 <= kSmallRows
@@ -638,18 +639,18 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
   }
   hipError_t e = launch_chol_factor<T>(S, n, Linv_all, d0, status, min_bits, st);
   if (e != hipSuccess) return e;
-  e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, st);
+  e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((zero_on_status_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, dx, n, status);
   return hipGetLastError();
 }
 
 template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, float*, float*, const float*, int*,
-                                             unsigned int*, int*, int, int*, hipStream_t);
+                                             unsigned int*, int*, int, int*, int*, hipStream_t);
 template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, const double*,
-                                              int*, unsigned int*, int*, int, int*, hipStream_t);
+                                              int*, unsigned int*, int*, int, int*, int*, hipStream_t);
 template hipError_t launch_chol_factor<float>(float*, int, float*, const float*, int*, unsigned int*, hipStream_t);
 template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, int*, int,
-                                             int*, hipStream_t);
+                                             int*, int*, hipStream_t);
 
 }  // namespace dpvba

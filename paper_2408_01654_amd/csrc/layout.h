@@ -15,6 +15,13 @@
 
 namespace dpvba {
 
+// Failure bits of a call's device work (see report_device_error), and the
+// number of host-visible words (one per cause).
+constexpr int kErrBarrier = 1;  // a grid barrier's bounded wait expired
+constexpr int kErrChain = 2;    // a chained triangular solve's bounded wait expired
+constexpr int kErrInput = 4;    // a non-finite target / weight or a negative weight
+constexpr int kHostErrWords = 3;
+
 constexpr int kMaxSlots = 64;     // slots per tile (one wavefront)
 constexpr int kTileThreads = 256;      // float64 tile work and the depth write-back
 constexpr int kTileThreadsWide = 512;  // float32 tile work

@@ -59,13 +59,13 @@ __global__ void accumulate_kernel(double* x, const float* c, int n) {
 }
 
 // Accept or fall back; records the relative residual and the decision.
-__global__ void refine_decide_kernel(const unsigned long long* m, const int* status32, double tol, double* resid_out,
-                                     int* fallback_out, int* host_flag) {
+__global__ void refine_decide_kernel(const unsigned long long* m, const int* status32, double tol, int force,
+                                     double* resid_out, int* fallback_out, int* host_flag) {
   if (threadIdx.x != 0) return;
   const double rmax = __longlong_as_double((long long)m[0]);
   const double smax = __longlong_as_double((long long)m[1]);
   const double rel = smax > 0.0 ? rmax / smax : rmax;
-  const int fb = (*status32 != 0) || !(rel <= tol);
+  const int fb = force || (*status32 != 0) || !(rel <= tol);
   *resid_out = rel;
   *fallback_out = fb;
   *host_flag = fb;
@@ -112,10 +112,10 @@ hipError_t launch_accumulate(double* x, const float* c, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_refine_decide(const unsigned long long* maxes, const int* status32, double tol, double* resid_out,
-                                int* fallback_out, int* host_flag, hipStream_t st) {
-  hipLaunchKernelGGL(refine_decide_kernel, dim3(1), dim3(64), 0, st, maxes, status32, tol, resid_out, fallback_out,
-                     host_flag);
+hipError_t launch_refine_decide(const unsigned long long* maxes, const int* status32, double tol, int force,
+                                double* resid_out, int* fallback_out, int* host_flag, hipStream_t st) {
+  hipLaunchKernelGGL(refine_decide_kernel, dim3(1), dim3(64), 0, st, maxes, status32, tol, force, resid_out,
+                     fallback_out, host_flag);
   return hipGetLastError();
 }
 

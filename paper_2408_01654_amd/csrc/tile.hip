@@ -19,6 +19,8 @@
 //     s = -v + E C~^-1 w and Diag(B).
 // All sums run in a fixed order, so results are reproducible bit for bit; no
 // floating-point atomics are used.
+#include <cfloat>
+
 #include "edge.h"
 #include "mfma.h"
 #include "packed.h"
@@ -202,14 +204,17 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
     sPatch[4 * k + 3] = (T)0;
   }
   __syncthreads();
-  // records: (target, weight) per cell, weight -1 marks a cell without an
-  // edge; batches of 8 cells per thread keep the index loads and the
-  // dependent record loads in flight together
+  // records: (target, weight) per cell and, after them, whether the cell
+  // holds an edge (cells without one are marked by the edge id, never by
+  // a value); batches of 8 cells per thread keep the index loads and the
+  // dependent record loads in flight together.  A non-finite target or
+  // weight, or a negative weight, is used as given and reported.
   {
     const int ncell = K * Tn;
     const int* grid = A.edge_grid + ti.grid_begin;
     const float2* tgt = reinterpret_cast<const float2*>(A.target);
     const float2* wgt = reinterpret_cast<const float2*>(A.weight);
+    bool bad_in = false;
     for (int c0 = tid; c0 < ncell; c0 += 8 * NT) {
       int e[8];
 #pragma unroll
@@ -221,15 +226,21 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         tg[u] = e[u] >= 0 ? tgt[e[u]] : make_float2(0.f, 0.f);
-        wt[u] = e[u] >= 0 ? wgt[e[u]] : make_float2(-1.f, -1.f);
+        wt[u] = e[u] >= 0 ? wgt[e[u]] : make_float2(0.f, 0.f);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int c = c0 + u * NT;
-        if (c < ncell)
-          *reinterpret_cast<float4*>(rec + (size_t)c * L.cell_bytes) = make_float4(tg[u].x, tg[u].y, wt[u].x, wt[u].y);
+        if (c < ncell) {
+          unsigned char* cell = rec + (size_t)c * L.cell_bytes;
+          *reinterpret_cast<float4*>(cell) = make_float4(tg[u].x, tg[u].y, wt[u].x, wt[u].y);
+          *reinterpret_cast<int*>(cell + 16) = e[u] >= 0;
+          bad_in |= e[u] >= 0 && !(wt[u].x >= 0.f && wt[u].y >= 0.f && wt[u].x <= FLT_MAX && wt[u].y <= FLT_MAX &&
+                                   fabsf(tg[u].x) <= FLT_MAX && fabsf(tg[u].y) <= FLT_MAX);
+        }
       }
     }
+    if (bad_in) report_device_error(A.dev_err, A.host_err, kErrInput);
   }
   __syncthreads();
 
@@ -245,7 +256,7 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
     for (int k = g; k < K; k += G) {
       T* cell = sCell + (size_t)(k * Tn + s) * cellT;
       const float4 r4 = *reinterpret_cast<const float4*>(cell);
-      const bool has = r4.z >= 0.f;
+      const bool has = *reinterpret_cast<const int*>(reinterpret_cast<const unsigned char*>(cell) + 16) != 0;
       EdgeTerms<T> o;
       const bool ok = has && edge_eval<T>(Rt, sPatch[4 * k], sPatch[4 * k + 1], sPatch[4 * k + 2], A.fx, A.fy,
                                           A.cx, A.cy, A.z_min, r4.x, r4.y, r4.z, r4.w, o);
@@ -331,7 +342,7 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
   }
   __syncthreads();
   for (int k = tid; k < K; k += blockDim.x) {
-    const T Ct = sPs[8 * k] * ((T)1 + A.lambda) + A.lambda;
+    const T Ct = sPs[8 * k] * ((T)1 + A.lam_diag) + A.lambda;
     const T is = (T)1 / dsqrt(Ct);
     const T rs = sPs[8 * k + 1] * is;
     sPs[8 * k] = is;
@@ -610,7 +621,7 @@ __device__ __forceinline__ void gather_slice(const IterArgs<T>& A, T* Sp, T* rhs
       }
       if (want_s) rhs[6 * P + m] = sv;
       if (want_d) {
-        v += A.lambda * (db + (T)1);
+        v += A.lam_diag * db + A.lambda;
         d0[row] = v;
       }
     }
@@ -683,11 +694,14 @@ __device__ __forceinline__ void factor_solve_retract(const IterArgs<T>& A, const
 }
 
 // Grid-wide barrier of the single-launch solver: bar[0] counts arrivals,
-// bar[1] is the generation.  Every wait is bounded; on timeout *err is set
-// and false returned, so no workgroup can spin forever.
+// bar[1] is the generation.  Every wait is bounded; on timeout the failure
+// is recorded and false returned, so no workgroup can spin forever.  A
+// launch uses one of two slots and clears the other for the next launch on
+// the stream, so arrivals left behind by a launch whose wait expired never
+// reach a later launch's barriers.
 constexpr long long kSpinLimit = 1LL << 19;  // polls of ~1000 cycles each: a timeout after ~0.2 s
 
-__device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, int* err) {
+__device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, int* err, int* host_err) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -704,7 +718,7 @@ __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, int* err) {
         __builtin_amdgcn_s_sleep(16);  // few polls of the shared word while workgroup 0 factors
         if (++spins > kSpinLimit) {
           ok = 0;
-          atomicOr(err, 1);
+          report_device_error(err, host_err, kErrBarrier);
           break;
         }
       }
@@ -754,6 +768,9 @@ small_solve_kernel(SmallArgs<T> S) {
   const unsigned int nb = gridDim.x;
   const int w = blockIdx.x * blockDim.x + threadIdx.x, nw = gridDim.x * blockDim.x;
   const int wave = w >> 6, nwaves = nw >> 6;
+  // the other slot: no launch uses it before this one ends
+  if (blockIdx.x == 0 && threadIdx.x < 2) S.bar_next[threadIdx.x] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 2) *S.err_next = 0;
   for (int t = 0; t < S.n_iters; ++t) {
     A.first = t == 0;
     A.poses_cur = t == 0 ? S.poses_io : ((t - 1) & 1 ? S.pbuf1 : S.pbuf0);
@@ -769,11 +786,11 @@ small_solve_kernel(SmallArgs<T> S) {
       tile_assemble<T, tile_threads(sizeof(T))>(A, tile, lds);
       __syncthreads();
     }
-    if (!grid_sync(S.bar, nb, S.err)) return;
+    if (!grid_sync(S.bar, nb, S.err, A.host_err)) return;
     gather_slice<T>(A, S.Sp, S.rhs, S.d0, wave, nwaves);
-    if (!grid_sync(S.bar, nb, S.err)) return;
+    if (!grid_sync(S.bar, nb, S.err, A.host_err)) return;
     if (blockIdx.x == 0) factor_solve_retract<T>(A, S.Sp, S.rhs, S.d0, lds);
-    if (!grid_sync(S.bar, nb, S.err)) return;
+    if (!grid_sync(S.bar, nb, S.err, A.host_err)) return;
   }
   if (S.n_iters == 0) return;
   const T* fin = ((S.n_iters - 1) & 1) ? S.pbuf1 : S.pbuf0;

@@ -13,7 +13,9 @@ struct IterArgs {
   int p;
   const float* target;
   const float* weight;
-  T fx, fy, cx, cy, z_min, lambda;
+  T fx, fy, cx, cy, z_min;
+  T lambda;                // additive damping: H~ = H + lam_diag Diag(H) + lambda I
+  T lam_diag;              // lambda (Levenberg-Marquardt) or 0 (Levenberg)
   int n_frames, n_fixed, n_free, n_tiles;
   const T* poses_cur;      // [N,7] x_t
   T* poses_next;           // [N,7] x_{t+1} (written by the last workgroup)
@@ -46,6 +48,8 @@ struct IterArgs {
   unsigned int* min_bits;
   double* cost_out;
   int* invalid_out;
+  int* dev_err;            // device failure word of the call (bit 4: invalid target / weight)
+  int* host_err;           // host-visible sticky copy of the failure bits
 };
 
 // Arguments of the single-launch solver of small problems.
@@ -64,8 +68,10 @@ struct SmallArgs {
   double* cost;         // per iteration, or null
   int* invalid;
   int n_iters;
-  unsigned int* bar;
-  int* err;
+  unsigned int* bar;       // this launch's grid-barrier slot (arrivals, generation)
+  unsigned int* bar_next;  // the next launch's slot, cleared by this one
+  int* err;                // this launch's failure word
+  int* err_next;           // the next launch's failure word, cleared by this one
 };
 
 }  // namespace dpvba

@@ -31,8 +31,8 @@ def test_library_exports_every_declared_function():
 
 
 def test_status_strings():
-    for s in range(6):
-        assert binding.status_string(s)
+    for s in range(7):
+        assert binding.status_string(s) != "unknown status"
     assert binding.status_string(99) == "unknown status"
 
 

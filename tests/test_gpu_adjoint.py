@@ -5,9 +5,17 @@ central differences).
 Tolerances, relative to the largest oracle gradient entry: float64 mode
 1e-8 (each iteration's adjoint solves a system with condition number up to
 ~1e5 at these sizes, so a few 1e-11 per solve, summed over the iterations
-and edges); float32 mode 2e-2 (the same solves in float32, eps 6e-8 times
-the condition number, plus the float32 forward iterates the gradients are
-evaluated at).
+and edges).  Float32 mode: a bound derived per scene from the conditioning
+of its damped reduced system S: T unrolled iterations take 2T + 1 solves
+with S-like systems (forward step, adjoint solve, and the float32 iterate the
+Jacobians are evaluated at), each with relative error up to about
+kappa(S) eps32; a factor 10 covers the per-edge sums, so
+tol32 = 10 (2T + 1) kappa(S) eps32 (about 5e-4 for a 22-frame window,
+kappa(S) = 161).
+
+The supervision loss of the cfg3 windows is the pose loss
+sum ||t - t_gt||^2 + ||Log(R_gt^T R)||^2 over free poses; other tests use a
+loss that also touches the inverse depths.
 """
 import numpy as np
 import pytest
@@ -18,7 +26,15 @@ from scenes import make_config, make_window, tiny_scene
 
 pytestmark = pytest.mark.gpu
 
-TOL64, TOL32 = 1e-8, 2e-2
+TOL64 = 1e-8
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+def _tol32(s):
+    from oracle import ba64
+    pb = ba64.Problem.from_scene(s)
+    rs = ba64.reduce(ba64.normal_equations(pb, ba64.edge_terms(pb, z_min=s.z_min)), s.lam)
+    return 10 * (2 * s.n_iters + 1) * float(np.linalg.cond(rs.S)) * EPS32
 
 
 @pytest.fixture(scope="module")
@@ -82,6 +98,8 @@ SCENES = [
     ("invalid", lambda: _behind_camera(tiny_scene(5, 5, seed=47), 3), None),
     ("cfg0", lambda: make_config(0), None),
     ("window", lambda: make_window(0), None),
+    # 60 frames, 58 free: n = 348, the blocked factorisation of the large path
+    ("blocked", lambda: tiny_scene(60, 12, seed=4, radius=5, trajectory="forward"), None),
 ]
 
 
@@ -139,5 +157,37 @@ def test_autograd_layer_fp32(dp, ctx, mk):
     et = _rel(target.grad.double().cpu().numpy(), gt_o)
     ew = _rel(weight.grad.double().cpu().numpy(), gw_o)
     _log(f"autograd fp32 {s.name}: loss {float(loss):.6e} vs {L:.6e}; target rel {et:.3e} weight rel {ew:.3e}")
+    tol = _tol32(s)
+    _log(f"  float32 tolerance {tol:.3e}")
     assert abs(float(loss) - L) <= 1e-3 * max(1.0, abs(L))
-    assert et < TOL32 and ew < TOL32
+    assert et < tol and ew < tol
+
+
+@pytest.mark.parametrize("i", range(16))
+def test_adjoint_windows_pose_loss_fp64(dp, ctx, i):
+    """Every window of the 16-window adjoint workload (12-22 frames x 64-96
+    patches), supervised with the pose loss, against the gradient oracle."""
+    s = make_config(3, i)
+    loss = grad64.scene_pose_loss(s)
+    L, gt_o, gw_o, gp_o, gd_o = grad64.loss_and_grads(s, loss_fn=loss)
+    assert np.all(gd_o == 0)
+    gt, gw = _gpu_backward64(dp, ctx, s, gp_o, None, s.n_iters)
+    et, ew = _rel(gt, gt_o), _rel(gw, gw_o)
+    _log(f"window {i} F={s.n_frames} E={s.n_edges}: target rel {et:.3e} weight rel {ew:.3e}")
+    assert et < TOL64 and ew < TOL64
+
+
+def test_adjoint_levenberg_fp64(dp, ctx):
+    s = tiny_scene(5, 5, seed=51)
+    s.lam = 1e-2
+    L, gt_o, gw_o, gp_o, gd_o = grad64.loss_and_grads(s, levenberg=True)
+    g = dp.GraphTensors.from_scene(s)
+    ctx.analyze(g)
+    p0 = torch.as_tensor(s.poses, dtype=torch.float64).cuda().contiguous()
+    d0 = torch.as_tensor(s.inv_depth, dtype=torch.float64).cuda().contiguous()
+    gt, gw = ctx.solve_backward(g, p0, d0, torch.as_tensor(gp_o).cuda(), torch.as_tensor(gd_o).cuda(),
+                                n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, precision=dp.FP64,
+                                flags=dp.binding.FLAG_LEVENBERG)
+    et, ew = _rel(gt.cpu().numpy(), gt_o), _rel(gw.cpu().numpy(), gw_o)
+    _log(f"adjoint levenberg: target rel {et:.3e} weight rel {ew:.3e}")
+    assert et < TOL64 and ew < TOL64

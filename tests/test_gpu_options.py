@@ -1,0 +1,200 @@
+"""GPU checks of the option flags, input validation, device-failure
+reporting and HIP-graph invalidation of the C ABI (include/dpvba.h).
+
+Parity against the float64 oracle uses the tolerances of the other GPU
+tests: float64 1e-9, float32 / mixed 1e-4 (pose translation, rotation in
+rad, inverse depth relative)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ba64
+from scenes import make_config, make_window, tiny_scene
+from scenes.patchgraph import Scene
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "fp32": 1e-4, "mixed": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import paper_2408_01654_amd as dp
+    return dp
+
+
+@pytest.fixture(scope="module")
+def ctx(dp):
+    c = dp.Context(0)
+    yield c
+    c.close()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _errors(P, D, Po, Do):
+    dt, dr = ba64.pose_errors(P, Po)
+    rel = np.abs(D - Do) / np.maximum(np.abs(Do), 1e-12)
+    return float(dt.max()), float(dr.max()), float(rel.max())
+
+
+def _solve(dp, ctx, s, precision, flags=0, lam=None, analyze=True):
+    g = dp.GraphTensors.from_scene(s)
+    if analyze:
+        ctx.analyze(g)
+    dt = torch.float64 if precision == dp.FP64 else torch.float32
+    poses = torch.as_tensor(s.poses, dtype=dt).cuda().contiguous()
+    depth = torch.as_tensor(s.inv_depth, dtype=dt).cuda().contiguous()
+    rep = ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam if lam is None else lam, z_min=s.z_min,
+                    precision=precision, flags=flags)
+    return poses.double().cpu().numpy(), depth.double().cpu().numpy(), rep
+
+
+def _blocked_scene():
+    # 52 frames, 50 free: n = 300, above the one-workgroup solve
+    return tiny_scene(52, 12, seed=4, radius=5, trajectory="forward")
+
+
+LEV_SCENES = [("window", lambda: make_window(5)), ("blocked", _blocked_scene), ("cfg0", lambda: make_config(0))]
+
+
+@pytest.mark.parametrize("name,mk", LEV_SCENES, ids=[x[0] for x in LEV_SCENES])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_levenberg_damping_matches_oracle(dp, ctx, name, mk, prec):
+    s = mk()
+    lam = 1e-2
+    _log(f"levenberg {name} {prec} lam={lam}")
+    Po, Do, rep_o = ba64.solve_scene(s, lam=lam, levenberg=True)
+    precision = {"fp64": dp.FP64, "fp32": dp.FP32, "mixed": dp.MIXED}[prec]
+    P, D, rep = _solve(dp, ctx, s, precision, flags=dp.binding.FLAG_LEVENBERG, lam=lam)
+    e = _errors(P, D, Po, Do)
+    _log(f"  errors {e} status {rep['status']}")
+    assert rep["status"] == 0 and max(e) < TOL[prec]
+    # the damping form matters: the default damping gives a different iterate
+    Pm, Dm, _ = ba64.solve_scene(s, lam=lam)
+    assert max(_errors(Pm, Dm, Po, Do)) > 10 * TOL[prec]
+
+
+FORCE_SCENES = [("window", lambda: make_window(7)), ("blocked", _blocked_scene)]
+
+
+@pytest.mark.parametrize("name,mk", FORCE_SCENES, ids=[x[0] for x in FORCE_SCENES])
+def test_forced_float64_fallback(dp, ctx, name, mk):
+    s = mk()
+    Po, Do, _ = ba64.solve_scene(s)
+    P, D, rep = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_FORCE_FP64_CHOL)
+    e = _errors(P, D, Po, Do)
+    _log(f"forced fallback {name}: fallback {rep['fp64_fallback']} refine {rep['refine_resid']} errors {e}")
+    assert rep["status"] == 0
+    assert rep["fp64_fallback"] == [1] * s.n_iters
+    assert max(e) < TOL["mixed"]
+    # unforced: the same iterate up to the float32 factor's refined accuracy
+    P2, D2, rep2 = _solve(dp, ctx, s, dp.MIXED, analyze=False)
+    assert max(_errors(P2, D2, P, D)) < 1e-5
+
+
+def test_no_refine_flag(dp, ctx):
+    s = _blocked_scene()
+    Po, Do, _ = ba64.solve_scene(s)
+    P, D, rep = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_NO_REFINE)
+    e = _errors(P, D, Po, Do)
+    _log(f"no refine: resid {rep['refine_resid']} fallback {rep['fp64_fallback']} errors {e}")
+    assert rep["status"] == 0 and max(e) < TOL["mixed"]
+    assert all(r <= 1e-8 or f == 1 for r, f in zip(rep["refine_resid"], rep["fp64_fallback"]))
+
+
+def test_global_ba_forced_fallback_matches_golden(dp, ctx):
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "global_ba_oracle.npz"))
+    s = make_config(2)
+    _log(f"global BA forced float64 fallback: E={s.n_edges}")
+    P, D, rep = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_FORCE_FP64_CHOL)
+    e = _errors(P, D, gold["poses"], gold["inv_depth"])
+    _log(f"  fallback {rep['fp64_fallback']} refine {rep['refine_resid']} errors {e}")
+    assert rep["status"] == 0 and rep["fp64_fallback"] == [1] * s.n_iters
+    assert max(e) < TOL["mixed"]
+
+
+def test_flags_rejected_outside_their_mode(dp, ctx):
+    s = tiny_scene(4, 5, seed=1)
+    for prec in (dp.FP32, dp.FP64):
+        with pytest.raises(dp.DpvbaError):
+            _solve(dp, ctx, s, prec, flags=dp.binding.FLAG_FORCE_FP64_CHOL)
+        with pytest.raises(dp.DpvbaError):
+            _solve(dp, ctx, s, prec, flags=dp.binding.FLAG_NO_REFINE)
+    with pytest.raises(dp.DpvbaError):
+        _solve(dp, ctx, s, dp.FP32, flags=1 << 10)
+
+
+def _with(s, **kw):
+    d = dict(s.__dict__)
+    d.update(kw)
+    return Scene(**d)
+
+
+@pytest.mark.parametrize("bad", ["negative", "nan_weight", "inf_target"])
+def test_analysis_rejects_invalid_targets_and_weights(dp, ctx, bad):
+    s = tiny_scene(4, 5, seed=2)
+    w, t = s.weight.copy(), s.target.copy()
+    if bad == "negative":
+        w[3, 1] = -0.5
+    elif bad == "nan_weight":
+        w[4, 0] = np.nan
+    else:
+        t[5, 0] = np.inf
+    with pytest.raises(dp.DpvbaError) as ei:
+        ctx.analyze(dp.GraphTensors.from_scene(_with(s, weight=w, target=t)))
+    assert ei.value.status == dp.binding.DPVBA_EINVAL
+
+
+@pytest.mark.parametrize("name,mk", [("window", lambda: make_window(2)), ("blocked", _blocked_scene)],
+                         ids=["window", "blocked"])
+def test_invalid_weight_after_analysis_is_reported(dp, ctx, name, mk):
+    s = mk()
+    g = dp.GraphTensors.from_scene(s)
+    ctx.analyze(g)
+    assert ctx.device_status() == (dp.binding.DPVBA_OK, 0)
+    g.weight[7, 0] = -1.0   # changed between numeric calls, after the analysis checked it
+    poses = torch.as_tensor(s.poses).cuda().contiguous()
+    depth = torch.as_tensor(s.inv_depth).cuda().contiguous()
+    rep = ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, precision=dp.FP32)
+    _log(f"invalid weight {name}: report status {rep['status']}")
+    assert rep["status"] == dp.binding.DPVBA_EINVAL
+    with pytest.raises(dp.DpvbaError) as ei:   # recorded: every later call refuses
+        ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, precision=dp.FP32)
+    assert ei.value.status == dp.binding.DPVBA_EDEVICE
+    assert ctx.device_status() == (dp.binding.DPVBA_EDEVICE, 4)
+    g.weight[7, 0] = 0.5
+    rep = ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, precision=dp.FP32)
+    assert rep["status"] == 0 and ctx.device_status() == (dp.binding.DPVBA_OK, 0)
+
+
+def test_batch_graph_rerecorded_after_workspace_moves(dp, ctx):
+    scenes = [make_config(3, i) for i in range(3)]
+    b = dp.BatchTensors.from_scenes(scenes)
+    ctx.analyze_batch(b)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    p0, d0 = b.poses.clone(), b.inv_depth.clone()
+    out = {}
+    with torch.cuda.stream(st):
+        poses, depth = p0.clone(), d0.clone()
+        for mode in ("direct", "graph1", "graph2"):
+            if mode == "graph2":
+                # a larger single-problem analysis on the same context moves the
+                # workspace the recorded batch launches point into
+                big = tiny_scene(120, 96, seed=5, radius=10, trajectory="forward")
+                ctx.analyze(dp.GraphTensors.from_scene(big), stream=st)
+            for _ in range(2):
+                poses.copy_(p0)
+                depth.copy_(d0)
+                ctx.solve_batch(b, poses, depth, n_iters=2, lam=1e-4, z_min=0.1, precision=dp.FP32,
+                                report=False, graph=mode != "direct", stream=st)
+            st.synchronize()
+            out[mode] = (poses.clone(), depth.clone())
+    torch.cuda.synchronize()
+    for m in ("graph1", "graph2"):
+        assert torch.equal(out[m][0], out["direct"][0]) and torch.equal(out[m][1], out["direct"][1]), m

@@ -403,3 +403,20 @@ def test_reproject_centre_matches_edge_terms():
     c = (s.patches.shape[1] - 1) // 2
     np.testing.assert_allclose(full[:, c, c, :], t.proj, atol=1e-9)
     assert (valid == t.valid).all()
+
+
+def test_levenberg_damping_pins():
+    # H + lam I: equals the dense solve of that system, and tends to -g / lam
+    s = tiny_scene(4, 5, seed=15)
+    pb = ba64.Problem.from_scene(s)
+    ne = ba64.normal_equations(pb, ba64.edge_terms(pb))
+    H = ne.H.toarray()
+    for lam in (1e-3, 1e14):  # the limit needs lam far above H's entries (up to ~1e7 here)
+        rs = ba64.reduce(ne, lam, levenberg=True)
+        dxi = ba64.solve_reduced(rs)
+        dd = ba64.back_substitute(ne, rs, dxi)
+        delta = np.concatenate([dxi, dd])
+        want = np.linalg.solve(H + lam * np.eye(H.shape[0]), -ne.g)
+        np.testing.assert_allclose(delta, want, rtol=1e-8, atol=1e-12 * np.abs(want).max())
+        if lam > 1e6:
+            np.testing.assert_allclose(delta, -ne.g / lam, rtol=1e-4, atol=1e-4 * np.abs(ne.g / lam).max())

@@ -162,3 +162,23 @@ def test_pose_loss_gradients_match_central_differences():
             fd = (grad64.loss_value(s, tgt, wgt + h * dirs, loss_fn=loss) -
                   grad64.loss_value(s, tgt, wgt - h * dirs, loss_fn=loss)) / (2 * h)
         assert abs(fd - np.sum(g * dirs)) <= 1e-6 * max(1.0, abs(fd)), (which, fd, np.sum(g * dirs))
+
+
+def test_levenberg_forward_and_gradients():
+    """With the plain H + lam I damping the gradient oracle still agrees with
+    the numpy oracle's forward and with central differences."""
+    s = tiny_scene(5, 5, seed=50)
+    s.lam = 1e-2
+    P, D, _ = ba64.solve_scene(s, levenberg=True)
+    poses, d = grad64.forward_state(s, levenberg=True)
+    np.testing.assert_allclose(poses[:, :3], P[:, :3], atol=1e-12)
+    np.testing.assert_allclose(d, D, rtol=1e-11)
+    L, gt, gw, _, _ = grad64.loss_and_grads(s, levenberg=True)
+    rng = np.random.default_rng(50)
+    h = 1e-6
+    tgt = s.target.astype(np.float64)
+    wgt = s.weight.astype(np.float64)
+    dirs = rng.normal(size=wgt.shape)
+    fd = (grad64.loss_value(s, tgt, wgt + h * dirs, levenberg=True) -
+          grad64.loss_value(s, tgt, wgt - h * dirs, levenberg=True)) / (2 * h)
+    assert abs(fd - np.sum(gw * dirs)) <= 1e-6 * max(1.0, abs(fd))
