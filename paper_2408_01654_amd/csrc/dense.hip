@@ -349,7 +349,9 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
 // is published by storing the call's epoch into its flag (agent-scope
 // release after the data); a consumer reads the flag with an agent-scope
 // acquire.  Every wait is bounded: on timeout *err is set and the workgroup
-// returns, so every workgroup exits.  The L blocks are loaded before the wait
+// returns, so every workgroup exits; a wait also gives up as soon as another
+// workgroup's wait (or a grid barrier of the call) has expired, but not for an
+// input-range report, which leaves the arithmetic valid.  The L blocks are loaded before the wait
 // for the vector they multiply, so the chain only carries the dependent part.
 constexpr long long kChainSpin = 1LL << 22;
 
@@ -360,7 +362,8 @@ __device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err,
     int ok = 1;
     while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > kChainSpin || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      if (++spins > kChainSpin ||
+          (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrChain | kErrBarrier))) {
         report_device_error(err, host_err, kErrChain);
         ok = 0;
         break;

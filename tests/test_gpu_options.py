@@ -42,16 +42,17 @@ def _errors(P, D, Po, Do):
     return float(dt.max()), float(dr.max()), float(rel.max())
 
 
-def _solve(dp, ctx, s, precision, flags=0, lam=None, analyze=True):
-    g = dp.GraphTensors.from_scene(s)
-    if analyze:
+def _solve(dp, ctx, s, precision, flags=0, lam=None, g=None):
+    """Solve scene s; analyses a fresh upload unless the analysed graph g is given."""
+    if g is None:
+        g = dp.GraphTensors.from_scene(s)
         ctx.analyze(g)
     dt = torch.float64 if precision == dp.FP64 else torch.float32
     poses = torch.as_tensor(s.poses, dtype=dt).cuda().contiguous()
     depth = torch.as_tensor(s.inv_depth, dtype=dt).cuda().contiguous()
     rep = ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam if lam is None else lam, z_min=s.z_min,
                     precision=precision, flags=flags)
-    return poses.double().cpu().numpy(), depth.double().cpu().numpy(), rep
+    return poses.double().cpu().numpy(), depth.double().cpu().numpy(), rep, g
 
 
 def _blocked_scene():
@@ -62,15 +63,24 @@ def _blocked_scene():
 LEV_SCENES = [("window", lambda: make_window(5)), ("blocked", _blocked_scene), ("cfg0", lambda: make_config(0))]
 
 
-@pytest.mark.parametrize("name,mk", LEV_SCENES, ids=[x[0] for x in LEV_SCENES])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+# Pure additive damping leaves the 300-unknown forward-motion system with a
+# condition number of about 1.1e6 (1.7e2 for the window, 2.6e2 for the
+# all-pairs scene), so a float32 factor there is only good to about
+# kappa * 2^-24 ~ 7e-2 relative in the step: the float32 path is checked on the
+# well-conditioned scenes, the blocked scene by float64 and by the mixed solve,
+# whose float64 refinement is what such systems are for.
+LEV_CASES = [(prec, name, mk) for prec in ("fp64", "fp32", "mixed") for name, mk in LEV_SCENES
+             if not (prec == "fp32" and name == "blocked")]
+
+
+@pytest.mark.parametrize("prec,name,mk", LEV_CASES, ids=[f"{p}-{n}" for p, n, _ in LEV_CASES])
 def test_levenberg_damping_matches_oracle(dp, ctx, name, mk, prec):
     s = mk()
     lam = 1e-2
     _log(f"levenberg {name} {prec} lam={lam}")
     Po, Do, rep_o = ba64.solve_scene(s, lam=lam, levenberg=True)
     precision = {"fp64": dp.FP64, "fp32": dp.FP32, "mixed": dp.MIXED}[prec]
-    P, D, rep = _solve(dp, ctx, s, precision, flags=dp.binding.FLAG_LEVENBERG, lam=lam)
+    P, D, rep, g = _solve(dp, ctx, s, precision, flags=dp.binding.FLAG_LEVENBERG, lam=lam)
     e = _errors(P, D, Po, Do)
     _log(f"  errors {e} status {rep['status']}")
     assert rep["status"] == 0 and max(e) < TOL[prec]
@@ -86,21 +96,21 @@ FORCE_SCENES = [("window", lambda: make_window(7)), ("blocked", _blocked_scene)]
 def test_forced_float64_fallback(dp, ctx, name, mk):
     s = mk()
     Po, Do, _ = ba64.solve_scene(s)
-    P, D, rep = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_FORCE_FP64_CHOL)
+    P, D, rep, g = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_FORCE_FP64_CHOL)
     e = _errors(P, D, Po, Do)
     _log(f"forced fallback {name}: fallback {rep['fp64_fallback']} refine {rep['refine_resid']} errors {e}")
     assert rep["status"] == 0
     assert rep["fp64_fallback"] == [1] * s.n_iters
     assert max(e) < TOL["mixed"]
     # unforced: the same iterate up to the float32 factor's refined accuracy
-    P2, D2, rep2 = _solve(dp, ctx, s, dp.MIXED, analyze=False)
+    P2, D2, rep2, _ = _solve(dp, ctx, s, dp.MIXED, g=g)
     assert max(_errors(P2, D2, P, D)) < 1e-5
 
 
 def test_no_refine_flag(dp, ctx):
     s = _blocked_scene()
     Po, Do, _ = ba64.solve_scene(s)
-    P, D, rep = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_NO_REFINE)
+    P, D, rep, g = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_NO_REFINE)
     e = _errors(P, D, Po, Do)
     _log(f"no refine: resid {rep['refine_resid']} fallback {rep['fp64_fallback']} errors {e}")
     assert rep["status"] == 0 and max(e) < TOL["mixed"]
@@ -111,7 +121,7 @@ def test_global_ba_forced_fallback_matches_golden(dp, ctx):
     gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "global_ba_oracle.npz"))
     s = make_config(2)
     _log(f"global BA forced float64 fallback: E={s.n_edges}")
-    P, D, rep = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_FORCE_FP64_CHOL)
+    P, D, rep, g = _solve(dp, ctx, s, dp.MIXED, flags=dp.binding.FLAG_FORCE_FP64_CHOL)
     e = _errors(P, D, gold["poses"], gold["inv_depth"])
     _log(f"  fallback {rep['fp64_fallback']} refine {rep['refine_resid']} errors {e}")
     assert rep["status"] == 0 and rep["fp64_fallback"] == [1] * s.n_iters
