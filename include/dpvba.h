@@ -65,9 +65,11 @@ typedef enum {
   DPVBA_ENOMEM = 3,   /* device allocation failed (dpvba_analyze / create)       */
   DPVBA_EHIP = 4,     /* a HIP runtime call failed                               */
   DPVBA_ESTATE = 5,   /* numeric call without a matching dpvba_analyze           */
-  DPVBA_EDEVICE = 6   /* an earlier call's device work failed: a bounded device-
+  DPVBA_EDEVICE = 6,  /* an earlier call's device work failed: a bounded device-
                          wide wait expired, or it met a target / weight outside
                          the documented range; see dpvba_device_status          */
+  DPVBA_ELIMIT = 7    /* the problem exceeds a fixed capacity of the call
+                         (dpvba_solve_noalloc); dpvba_last_error says which     */
 } dpvba_status;
 
 typedef enum {
@@ -252,6 +254,28 @@ dpvba_status dpvba_reduced_system(dpvba_ctx* ctx, const dpvba_graph* g, const fl
  * Needs dpvba_analyze on this graph.                                      */
 dpvba_status dpvba_solve(dpvba_ctx* ctx, const dpvba_graph* g, float* poses, float* inv_depth,
                          const dpvba_opts* opts, dpvba_report* report, void* stream);
+
+/* dpvba_solve for callers that cannot allocate device memory during the
+ * call -- code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation: the same iteration and kernels as dpvba_solve on the
+ * single-launch path, with the per-call buffers (tile partial systems,
+ * stored Schur rows, tile-ordered depths and rays, ping-pong poses, the
+ * packed reduced system, step, status words and report staging) taken from
+ * a fixed static device array of 16 MiB instead of the context's workspace.
+ * The array exists once per device for the life of the process and is
+ * shared by every call on that device: each call overwrites what it uses
+ * before reading it, so results never depend on an earlier call's contents,
+ * but calls whose work overlaps on one device (other streams, other
+ * contexts) race on it and must be serialised by the caller.  The context
+ * still provides the analysis tables and its barrier and failure words.
+ * Arguments, results and report as dpvba_solve; precision DPVBA_FP32 or
+ * DPVBA_FP64 only (EINVAL for DPVBA_MIXED), n_iters >= 1 (EINVAL for 0).
+ * DPVBA_ELIMIT when 6 (N - n_fixed) + 1 > 96 (the reduced system is not
+ * the single-launch solver's) or when the buffers exceed the 16 MiB array
+ * (dpvba_last_error gives the size).  Calls no allocator, host or device.
+ * Needs dpvba_analyze on this graph.                                      */
+dpvba_status dpvba_solve_noalloc(dpvba_ctx* ctx, const dpvba_graph* g, float* poses, float* inv_depth,
+                                 const dpvba_opts* opts, dpvba_report* report, void* stream);
 
 /* Launch of the single-launch solver that dpvba_solve uses for small
  * reduced systems (6 x free poses + 1 <= 96; the sliding window of Sec. 3.1):

@@ -16,7 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdpvba.so")
 
-DPVBA_OK, DPVBA_EINVAL, DPVBA_ENOTPD, DPVBA_ENOMEM, DPVBA_EHIP, DPVBA_ESTATE, DPVBA_EDEVICE = range(7)
+DPVBA_OK, DPVBA_EINVAL, DPVBA_ENOTPD, DPVBA_ENOMEM, DPVBA_EHIP, DPVBA_ESTATE, DPVBA_EDEVICE, DPVBA_ELIMIT = range(8)
 FP32, MIXED, FP64 = 0, 1, 2
 FLAG_GRAPH = 1
 FLAG_LEVENBERG = 2          # H + lambda I instead of H + lambda (Diag(H) + I)
@@ -96,6 +96,9 @@ def lib():
         L.dpvba_solve.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts),
                                   ctypes.POINTER(Report), vp]
         L.dpvba_solve.restype = ctypes.c_int
+        L.dpvba_solve_noalloc.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts),
+                                          ctypes.POINTER(Report), vp]
+        L.dpvba_solve_noalloc.restype = ctypes.c_int
         L.dpvba_solve_backward.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp,
                                            vp]
         L.dpvba_solve_backward.restype = ctypes.c_int
@@ -129,7 +132,7 @@ def status_string(s: int) -> str:
 
 def _check(status: int, what: str, ctx=None):
     if status != DPVBA_OK:
-        if ctx is not None and status == DPVBA_EHIP:
+        if ctx is not None and status in (DPVBA_EHIP, DPVBA_ELIMIT):
             what = f"{what} [{lib().dpvba_last_error(ctx).decode()}]"
         raise DpvbaError(status, what)
 
@@ -308,10 +311,12 @@ class Context:
         return S, s, cost
 
     def solve(self, g: GraphTensors, poses, inv_depth, n_iters=2, lam=1e-4, z_min=0.1, precision=FP32,
-              report=True, stream=None, flags=0):
+              report=True, stream=None, flags=0, noalloc=False):
         """In-place solve of poses [N,7] and inv_depth [P] (float32 for FP32 and
         MIXED, float64 for FP64).  Returns the report as a dict (after
-        synchronising the stream) or None."""
+        synchronising the stream) or None.  noalloc=True calls
+        dpvba_solve_noalloc (per-call buffers in the library's static device
+        array) instead of dpvba_solve."""
         want = torch.float64 if precision == FP64 else torch.float32
         if poses.dtype != want or inv_depth.dtype != want:
             raise TypeError(f"poses and inv_depth must be {want}")
@@ -320,8 +325,9 @@ class Context:
         o = self._opts(n_iters, lam, z_min, precision, flags)
         gs = g.struct()
         rep = Report() if report else None
-        _check(lib().dpvba_solve(self._h, ctypes.byref(gs), _ptr(poses), _ptr(inv_depth), ctypes.byref(o),
-                                 ctypes.byref(rep) if rep is not None else None, _stream(stream)), "dpvba_solve", self._h)
+        fn, name = (lib().dpvba_solve_noalloc, "dpvba_solve_noalloc") if noalloc else (lib().dpvba_solve, "dpvba_solve")
+        _check(fn(self._h, ctypes.byref(gs), _ptr(poses), _ptr(inv_depth), ctypes.byref(o),
+                  ctypes.byref(rep) if rep is not None else None, _stream(stream)), name, self._h)
         if rep is None:
             return None
         (torch.cuda.current_stream() if stream is None else stream).synchronize()

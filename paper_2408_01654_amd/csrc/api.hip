@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -194,6 +195,41 @@ hipError_t upload(DevBuf& b, const std::vector<X>& v, hipStream_t st) {
   e = hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(st);
+}
+
+// Static workspace of dpvba_solve_noalloc: the per-call buffers of a
+// single-launch solve, carved from one fixed array per device instead of
+// the context's allocations.  In host code `scratch` names a host-side
+// stand-in; its device address is resolved once per device, with that device
+// current, by resolve_scratch (called from dpvba_create), and only that
+// address is ever passed to kernels or copies.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+hipError_t g_scratch_err[kMaxScratchDevices] = {};
+bool g_scratch_done[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+static hipError_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_done[device] = true;
+  }
+  return g_scratch_err[device];
+}
+
+static void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_done[device] ? g_scratch_ptr[device] : nullptr;
 }
 
 // Device copy of one tiling of the patch graph.
@@ -382,6 +418,7 @@ const char* dpvba_status_string(dpvba_status s) {
     case DPVBA_EHIP: return "HIP runtime error";
     case DPVBA_ESTATE: return "numeric call without a matching dpvba_analyze";
     case DPVBA_EDEVICE: return "device work of an earlier call failed (see dpvba_device_status)";
+    case DPVBA_ELIMIT: return "problem exceeds a fixed capacity (see dpvba_last_error)";
   }
   return "unknown status";
 }
@@ -395,6 +432,9 @@ dpvba_status dpvba_create(dpvba_ctx** out, int32_t device) {
   if (!c) return DPVBA_ENOMEM;
   c->device = device;
   hipError_t e = hipSetDevice(device);
+  // the static scratch of dpvba_solve_noalloc: its address on this device,
+  // resolved once per device (a failure is kept and returned by that call)
+  if (e == hipSuccess) (void)resolve_scratch(device);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&c->host_err, kHostErrWords * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) {
@@ -851,9 +891,81 @@ static double lam_diag_of(const dpvba_opts* o) {
   return (o->flags & DPVBA_FLAG_LEVENBERG) ? 0.0 : o->lambda;
 }
 
+// Per-call buffers of a solve: the context's workspace (ctx_ws), or slices
+// of the static scratch (carve_ws, dpvba_solve_noalloc).
 template <typename T>
-static IterArgs<T> make_iter_args(dpvba_ctx* c, const dpvba_graph* g, const Tiling& tl, const T* poses_cur,
-                                  T* poses_next, const T* depth_in, T lambda, T z_min, T lam_diag, int* dev_err) {
+struct SolveWs {
+  T *part_S, *part_vec, *U_s, *pscale_s, *depth_s, *xh_s, *pbuf0, *pbuf1, *S, *rhs, *d0, *dx;
+  double *part_cost, *edge_part;
+  int *part_invalid, *status;
+  unsigned int* min_bits;
+  dpvba_report* devrep;
+};
+
+template <typename T>
+static SolveWs<T> ctx_ws(dpvba_ctx* c) {
+  SolveWs<T> w;
+  w.part_S = (T*)c->part_S.p;
+  w.part_vec = (T*)c->part_vec.p;
+  w.U_s = (T*)c->U_s.p;
+  w.pscale_s = (T*)c->pscale_s.p;
+  w.depth_s = (T*)c->depth_s.p;
+  w.xh_s = (T*)c->xh_s.p;
+  w.pbuf0 = (T*)c->poses_a.p;
+  w.pbuf1 = (T*)c->poses_b.p;
+  w.S = (T*)c->S.p;
+  w.rhs = (T*)c->rhs.p;
+  w.d0 = (T*)c->d0.p;
+  w.dx = (T*)c->dx.p;
+  w.part_cost = (double*)c->part_cost.p;
+  w.edge_part = (double*)c->edge_part.p;
+  w.part_invalid = (int*)c->part_invalid.p;
+  w.status = (int*)c->status.p;
+  w.min_bits = (unsigned int*)c->min_bits.p;
+  w.devrep = (dpvba_report*)c->devrep.p;
+  return w;
+}
+
+// Lays the buffers of a single-launch solve of the analysed problem (plan
+// tl, element type T) out from `base` at 256-byte boundaries; returns the
+// bytes needed.  With base == nullptr only the size is computed.
+template <typename T>
+static size_t carve_ws(const dpvba_ctx* c, const Tiling& tl, unsigned char* base, SolveWs<T>* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* q = base ? base + off : nullptr;
+    off += (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+    return (void*)q;
+  };
+  const size_t n = 6 * (size_t)c->n_free, P = (size_t)c->P, N = (size_t)c->N;
+  const size_t ts = sizeof(T);
+  SolveWs<T> v;
+  v.part_S = (T*)take((size_t)tl.part_S * ts);
+  v.part_vec = (T*)take((size_t)tl.part_vec * ts);
+  v.U_s = (T*)take((size_t)tl.u_alloc * ts);
+  v.pscale_s = (T*)take(P * 2 * ts);
+  v.depth_s = (T*)take(P * ts);
+  v.xh_s = (T*)take(P * 2 * ts);
+  v.pbuf0 = (T*)take(N * 7 * ts);
+  v.pbuf1 = (T*)take(N * 7 * ts);
+  v.S = (T*)take(n * n * ts);
+  v.rhs = (T*)take(n * ts);
+  v.d0 = (T*)take(n * ts);
+  v.dx = (T*)take(n * ts);
+  v.part_cost = (double*)take((size_t)tl.n_tiles * 8);
+  v.edge_part = (double*)take(((size_t)c->E + 255) / 256 * 8);
+  v.part_invalid = (int*)take((size_t)tl.n_tiles * 4);
+  v.status = (int*)take(DPVBA_MAX_ITERS * 4);
+  v.min_bits = (unsigned int*)take(DPVBA_MAX_ITERS * 4);
+  v.devrep = (dpvba_report*)take(sizeof(dpvba_report));
+  if (w) *w = v;
+  return off;
+}
+
+template <typename T>
+static IterArgs<T> make_iter_args(dpvba_ctx* c, const SolveWs<T>& w, const dpvba_graph* g, const Tiling& tl,
+                                  const T* poses_cur, T* poses_next, const T* depth_in, T lambda, T z_min,
+                                  T lam_diag, int* dev_err) {
   IterArgs<T> A{};
   A.lam_diag = lam_diag;
   A.dev_err = dev_err;
@@ -872,27 +984,34 @@ static IterArgs<T> make_iter_args(dpvba_ctx* c, const dpvba_graph* g, const Tili
   A.poses_cur = poses_cur;
   A.poses_next = poses_next;
   A.depth_in = depth_in;
-  A.depth_s = (T*)c->depth_s.p;
-  A.xh_s = (T*)c->xh_s.p;
-  A.U_s = (T*)c->U_s.p;
-  A.pscale_s = (T*)c->pscale_s.p;
+  A.depth_s = w.depth_s;
+  A.xh_s = w.xh_s;
+  A.U_s = w.U_s;
+  A.pscale_s = w.pscale_s;
   A.tiles = (const TileInfo*)tl.tiles.p;
   A.tile_patch = (const int*)tl.tile_patch.p;
   A.slot_frame = (const int*)tl.slot_frame.p;
   A.slot_blk = (const int*)tl.slot_blk.p;
   A.edge_grid = (const int*)tl.edge_grid.p;
   A.blk_pose = (const int*)tl.blk_pose.p;
-  A.part_S = (T*)c->part_S.p;
-  A.part_vec = (T*)c->part_vec.p;
-  A.part_cost = (double*)c->part_cost.p;
-  A.part_invalid = (int*)c->part_invalid.p;
+  A.part_S = w.part_S;
+  A.part_vec = w.part_vec;
+  A.part_cost = w.part_cost;
+  A.part_invalid = w.part_invalid;
   A.s_off = (const int*)tl.s_off.p;
   A.s_src = (const int*)tl.s_src.p;
   A.v_off = (const int*)tl.v_off.p;
   A.v_src = (const int2*)tl.v_src.p;
-  A.dx = (T*)c->dx.p;
+  A.dx = w.dx;
   A.first = 1;
   return A;
+}
+
+template <typename T>
+static IterArgs<T> make_iter_args(dpvba_ctx* c, const dpvba_graph* g, const Tiling& tl, const T* poses_cur,
+                                  T* poses_next, const T* depth_in, T lambda, T z_min, T lam_diag, int* dev_err) {
+  return make_iter_args<T>(c, ctx_ws<T>(c), g, tl, poses_cur, poses_next, depth_in, lambda, z_min, lam_diag,
+                           dev_err);
 }
 
 template <typename T>
@@ -954,31 +1073,32 @@ static hipError_t reduced_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, const f
 
 template <typename T>
 static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* depth, const dpvba_opts* o,
-                             dpvba_report* report, hipStream_t st) {
+                             dpvba_report* report, hipStream_t st, const SolveWs<T>* ws_in = nullptr) {
+  const SolveWs<T> ws = ws_in ? *ws_in : ctx_ws<T>(c);
   const T lambda = (T)o->lambda, z_min = (T)o->z_min, lam_diag = (T)lam_diag_of(o);
   const Tiling& tl = c->tl[sizeof(T) == 8 ? 1 : 0];
   const int n = 6 * c->n_free;
   const int nit = o->n_iters;
   const bool small = use_small_path<T>(c);
-  dpvba_report* dev = (dpvba_report*)c->devrep.p;
-  int* status = (int*)c->status.p;
-  unsigned int* mb = (unsigned int*)c->min_bits.p;
-  T* pbuf[2] = {(T*)c->poses_a.p, (T*)c->poses_b.p};
-  T* dx = (T*)c->dx.p;
+  dpvba_report* dev = ws.devrep;
+  int* status = ws.status;
+  unsigned int* mb = ws.min_bits;
+  T* pbuf[2] = {ws.pbuf0, ws.pbuf1};
+  T* dx = ws.dx;
   hipError_t e;
   // the call's failure word: that of the single launch's parity, else the large path's
   const int parity = (int)(c->small_launches & 1);
   int* err = small && nit > 0 ? (int*)c->dev_err.p + 4 * parity : large_err(c);
   if (small && nit > 0) {
     SmallArgs<T> S{};
-    S.it = make_iter_args<T>(c, g, tl, poses, pbuf[0], depth, lambda, z_min, lam_diag, err);
+    S.it = make_iter_args<T>(c, ws, g, tl, poses, pbuf[0], depth, lambda, z_min, lam_diag, err);
     S.poses_io = poses;
     S.depth_io = depth;
     S.pbuf0 = pbuf[0];
     S.pbuf1 = pbuf[1];
-    S.Sp = (T*)c->S.p;
-    S.rhs = (T*)c->rhs.p;
-    S.d0 = (T*)c->d0.p;
+    S.Sp = ws.S;
+    S.rhs = ws.rhs;
+    S.d0 = ws.d0;
     S.status = status;
     S.min_bits = mb;
     S.cost = dev->cost;
@@ -1009,7 +1129,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
   for (int it = 0; it < nit && !small; ++it) {
     const T* cur = it == 0 ? poses : pbuf[(it - 1) & 1];
     T* next = pbuf[it & 1];
-    IterArgs<T> A = make_iter_args<T>(c, g, tl, cur, next, depth, lambda, z_min, lam_diag, err);
+    IterArgs<T> A = make_iter_args<T>(c, ws, g, tl, cur, next, depth, lambda, z_min, lam_diag, err);
     A.first = it == 0;
     A.dx_prev = it ? dx : nullptr;
     A.status_prev = it ? status + it - 1 : nullptr;
@@ -1020,17 +1140,16 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     if (e != hipSuccess) return e;
     {
       TraceScope ts(c, DPVBA_PHASE_GATHER, st);
-      e = launch_report_reduce((const double*)c->part_cost.p, (const int*)c->part_invalid.p, tl.n_tiles,
-                               &dev->cost[it], &dev->n_invalid[it], st);
+      e = launch_report_reduce(ws.part_cost, ws.part_invalid, tl.n_tiles, &dev->cost[it], &dev->n_invalid[it], st);
       if (e == hipSuccess)
-        e = launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
+        e = launch_gather<T>(ws.part_S, ws.part_vec, (const int*)tl.s_off.p,
                              (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
-                             (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, lam_diag, 0, (T*)c->d0.p, st);
+                             ws.S, ws.rhs, (T*)c->dB.p, lambda, lam_diag, 0, ws.d0, st);
     }
     if (e != hipSuccess) return e;
     {
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
-      e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, dx, (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p,
+      e = launch_chol_solve<T>(ws.S, ws.rhs, n, dx, (T*)c->wy.p, (T*)c->Linv.p, ws.d0,
                                status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st);
     }
     if (e != hipSuccess) return e;
@@ -1043,8 +1162,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
   if (nit > 0 && !small) {
     TraceScope ts(c, DPVBA_PHASE_BACKSUB, st);
     e = launch_tile_finalize<T>((const TileInfo*)tl.tiles.p, tl.n_tiles, writeback_lds_bytes(tl, (int)sizeof(T)), (const int*)tl.tile_patch.p,
-                                (const int*)tl.blk_pose.p, (const T*)c->U_s.p, (const T*)c->pscale_s.p,
-                                (const T*)c->depth_s.p, dx, status + nit - 1, 0, depth, pbuf[(nit - 1) & 1], poses,
+                                (const int*)tl.blk_pose.p, ws.U_s, ws.pscale_s, ws.depth_s, dx, status + nit - 1, 0, depth, pbuf[(nit - 1) & 1], poses,
                                 c->N, st);
     if (e != hipSuccess) return e;
   }
@@ -1053,11 +1171,10 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     TraceScope ts_cost(c, DPVBA_PHASE_COST, st);
     e = launch_edge_cost<T, T>(poses, depth, g->patches, g->patch_size, g->ii, g->jj, g->kk, g->target, g->weight,
                                g->n_edges, (T)g->fx, (T)g->fy, (T)g->cx, (T)g->cy, z_min,
-                               (double*)c->edge_part.p, st);
+                               ws.edge_part, st);
   }
   if (e != hipSuccess) return e;
-  e = launch_report_reduce((const double*)c->edge_part.p, nullptr, (g->n_edges + 255) / 256, &dev->cost[nit],
-                           nullptr, st);
+  e = launch_report_reduce(ws.edge_part, nullptr, (g->n_edges + 255) / 256, &dev->cost[nit], nullptr, st);
   if (e != hipSuccess) return e;
   e = launch_report_finalize(dev, status, mb, nit, err, st);
   if (e != hipSuccess) return e;
@@ -1472,6 +1589,51 @@ dpvba_status dpvba_solve(dpvba_ctx* c, const dpvba_graph* g, float* poses, float
     HIP_TRY(solve_mixed_impl(c, g, poses, inv_depth, o, report, st));
   } else {
     HIP_TRY(solve_impl<float>(c, g, poses, inv_depth, o, report, st));
+  }
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_solve_noalloc(dpvba_ctx* c, const dpvba_graph* g, float* poses, float* inv_depth,
+                                 const dpvba_opts* o, dpvba_report* report, void* stream) {
+  if (!c || !graph_sizes_ok(g)) return DPVBA_EINVAL;
+  dpvba_status rc = check_opts(o);
+  if (rc != DPVBA_OK) return rc;
+  if (o->precision == DPVBA_MIXED) return DPVBA_EINVAL;
+  rc = check_analysed(c, g);
+  if (rc != DPVBA_OK) return rc;
+  if (!poses || (!inv_depth && c->P > 0)) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const bool f64 = o->precision == DPVBA_FP64;
+  const bool small = f64 ? use_small_path<double>(c) : use_small_path<float>(c);
+  if (!small || o->n_iters == 0) {
+    snprintf(c->err, sizeof(c->err),
+             "dpvba_solve_noalloc: %s", o->n_iters == 0 ? "n_iters must be >= 1"
+                                                      : "reduced system beyond the single-launch solver (6 free poses + 1 > 96)");
+    return o->n_iters == 0 ? DPVBA_EINVAL : DPVBA_ELIMIT;
+  }
+  unsigned char* base = (unsigned char*)scratch_ptr(c->device);
+  if (!base) {
+    const hipError_t e = c->device < kMaxScratchDevices ? g_scratch_err[c->device] : hipErrorInvalidDevice;
+    record_error(c, e == hipSuccess ? hipErrorInvalidSymbol : e, "dpvba_solve_noalloc: static scratch address");
+    return DPVBA_EHIP;
+  }
+  const Tiling& tl = c->tl[f64 ? 1 : 0];
+  const size_t need = f64 ? carve_ws<double>(c, tl, nullptr, nullptr) : carve_ws<float>(c, tl, nullptr, nullptr);
+  if (need > kScratchBytes) {
+    snprintf(c->err, sizeof(c->err), "dpvba_solve_noalloc: workspace of %zu bytes exceeds the static scratch of %zu",
+             need, kScratchBytes);
+    return DPVBA_ELIMIT;
+  }
+  if (f64) {
+    SolveWs<double> w;
+    carve_ws<double>(c, tl, base, &w);
+    HIP_TRY(solve_impl<double>(c, g, (double*)(void*)poses, (double*)(void*)inv_depth, o, report, st, &w));
+  } else {
+    SolveWs<float> w;
+    carve_ws<float>(c, tl, base, &w);
+    HIP_TRY(solve_impl<float>(c, g, poses, inv_depth, o, report, st, &w));
   }
   return DPVBA_OK;
 }

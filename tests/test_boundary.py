@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_status_strings():
-    for s in range(7):
+    for s in range(8):
         assert binding.status_string(s) != "unknown status"
     assert binding.status_string(99) == "unknown status"
 
