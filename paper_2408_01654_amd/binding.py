@@ -254,6 +254,13 @@ class Context:
             lib().dpvba_destroy(self._h)
             self._h = ctypes.c_void_p(0)
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
         try:
             self.close()

@@ -59,7 +59,8 @@ __host__ __device__ inline int upper_pair_index(int a, int b, int nb) {
 __host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 
 // Shared-memory plan of the tile kernel.  Compute-type (T) arrays: slot
-// relative poses, patch rays, per-patch sums, per-slot sums, and the
+// relative poses, patch rays (and, in float32 plans, both again in
+// float64 for the residuals), per-patch sums, per-slot sums, and the
 // Schur-row matrix U (K_pad x W_pad, rows = patches, columns = 6 n_blk
 // block columns plus one column for w / sqrt(C~), padded for 16x16x4
 // matrix-core tiles; rows 16-byte aligned), which first holds the
@@ -68,7 +69,7 @@ __host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 // for per-slot source blocks and their sums (and in phase 0 for the block
 // step).  Then the block -> slot range tables.
 struct TileLds {
-  int slot, patch, psum, m, u, total_T;     // T offsets
+  int slot, patch, hp, psum, m, u, total_T; // T offsets
   int K_pad, W_pad;
   int cell_bytes, rec_bytes;                // per cell, region
   int blk_s0, blk_s1, tables;               // byte offsets in the table region
@@ -101,7 +102,10 @@ __host__ __device__ inline TileLds tile_lds_plan(int K, int Tn, int nb, int tsiz
   L.W_pad = tile_u_stride(nb);
   L.slot = 0;
   L.patch = L.slot + Tn * 18;
-  L.psum = L.patch + K * 4;
+  // float32 plans: the slots' relative poses (12 doubles) and the patches'
+  // rays (2 doubles) in float64, for the residuals
+  L.hp = round_up(L.patch + K * 4, 4);
+  L.psum = L.hp + (tsize == 4 ? Tn * 24 + K * 4 : 0);
   L.m = L.psum + K * 8;
   L.u = round_up(L.m + Tn * kRedWidth, 4);
   L.total_T = L.u + imax(L.K_pad * L.W_pad, nthreads * kRedWidth);

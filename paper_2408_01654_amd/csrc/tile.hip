@@ -123,6 +123,8 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
   T* base = reinterpret_cast<T*>(lds);
   T* sSlot = base + L.slot;   // [Tn][18]: R_ji (9), t_ji (3)
   T* sPatch = base + L.patch; // [K][4]: x^0, x^1, d, w / sqrt(C~)
+  double* sSlot64 = reinterpret_cast<double*>(base + L.hp);  // float32 plans: [Tn][12] R_ji, t_ji in float64
+  double* sRay64 = sSlot64 + 12 * Tn;                         // float32 plans: [K][2] x^ in float64
   T* sPs = base + L.psum;     // [K][8]: C (then 1 / sqrt(C~)), w, -sum_j Ad^T E_j (phase 0: row dots)
   T* sM = base + L.m;         // [Tn][28]
   T* sU = base + L.u;         // [Kp][Wp]; first the per-thread partial sums
@@ -160,6 +162,13 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
     quat_to_rot<T, T>(pj + 3, Rj);
     for (int m = 0; m < 3; ++m) { tiv[m] = pi[m]; tj[m] = pj[m]; }
     relative_pose<T>(Ri, tiv, Rj, tj, sSlot + 18 * s, sSlot + 18 * s + 9);
+    if constexpr (sizeof(T) == 4) {
+      double Ri64[9], ti64[3], Rj64[9], tj64[3];
+      quat_to_rot<double, T>(pi + 3, Ri64);
+      quat_to_rot<double, T>(pj + 3, Rj64);
+      for (int m = 0; m < 3; ++m) { ti64[m] = (double)pi[m]; tj64[m] = (double)pj[m]; }
+      relative_pose<double>(Ri64, ti64, Rj64, tj64, sSlot64 + 12 * s, sSlot64 + 12 * s + 9);
+    }
   }
   const bool apply_prev =
       !A.first && A.dx_prev && !(A.status_prev && A.status_prev[ti.inst * A.status_stride]);
@@ -185,6 +194,13 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
     sPatch[4 * k + 1] = x1;
     sPatch[4 * k + 2] = d;
     sPatch[4 * k + 3] = is;
+    if constexpr (sizeof(T) == 4) {  // the ray again in float64, from the centre pixel
+      const int pk = A.tile_patch[pb + k];
+      const int c = (A.p - 1) / 2;
+      const float* cen = A.patches + ((size_t)pk * A.p * A.p + (size_t)c * A.p + c) * 2;
+      sRay64[2 * k] = ((double)cen[0] - (double)A.cx) / (double)A.fx;
+      sRay64[2 * k + 1] = ((double)cen[1] - (double)A.cy) / (double)A.fy;
+    }
   }
   if (apply_prev)  // [dxi of the tile's blocks | 1 | 0 ...]
     for (int x = tid; x < Wp; x += blockDim.x)
@@ -258,8 +274,13 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
       const float4 r4 = *reinterpret_cast<const float4*>(cell);
       const bool has = *reinterpret_cast<const int*>(reinterpret_cast<const unsigned char*>(cell) + 16) != 0;
       EdgeTerms<T> o;
-      const bool ok = has && edge_eval<T>(Rt, sPatch[4 * k], sPatch[4 * k + 1], sPatch[4 * k + 2], A.fx, A.fy,
-                                          A.cx, A.cy, A.z_min, r4.x, r4.y, r4.z, r4.w, o);
+      bool ok;
+      if constexpr (sizeof(T) == 4)
+        ok = has && edge_eval_r64(Rt, sSlot64 + 12 * s, sRay64[2 * k], sRay64[2 * k + 1], sPatch[4 * k + 2], A.fx,
+                                  A.fy, A.cx, A.cy, A.z_min, r4.x, r4.y, r4.z, r4.w, o);
+      else
+        ok = has && edge_eval<T>(Rt, sPatch[4 * k], sPatch[4 * k + 1], sPatch[4 * k + 2], A.fx, A.fy, A.cx, A.cy,
+                                 A.z_min, r4.x, r4.y, r4.z, r4.w, o);
       if (has && !ok) ++n_invalid;
       T out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (ok) {
