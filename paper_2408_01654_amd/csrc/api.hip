@@ -58,11 +58,11 @@ hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_o
                             const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
                             T lam_diag, int mirror, T* diag_out, hipStream_t st);
 template <typename T>
-hipError_t launch_chol_factor(T* S, int n, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
+hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
                               hipStream_t st);
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
-                             int epoch, int* err, int* host_err, hipStream_t st);
+                             int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0);
 // mixed-precision helpers (mixed.hip)
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st);
@@ -820,7 +820,7 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(ensure(c->xh_s, (size_t)P * 2 * 8));
   HIP_TRY(ensure(c->poses_a, (size_t)N * 7 * 8));
   HIP_TRY(ensure(c->poses_b, (size_t)N * 7 * 8));
-  HIP_TRY(ensure(c->S, n * n * 8));
+  HIP_TRY(ensure(c->S, (n + 1) * n * 8));  // the float32 large path appends s as row n
   HIP_TRY(ensure(c->rhs, n * 8));
   HIP_TRY(ensure(c->dB, n * 8));
   HIP_TRY(ensure(c->d0, n * 8));
@@ -948,7 +948,7 @@ static size_t carve_ws(const dpvba_ctx* c, const Tiling& tl, unsigned char* base
   v.xh_s = (T*)take(P * 2 * ts);
   v.pbuf0 = (T*)take(N * 7 * ts);
   v.pbuf1 = (T*)take(N * 7 * ts);
-  v.S = (T*)take(n * n * ts);
+  v.S = (T*)take((n + 1) * n * ts);
   v.rhs = (T*)take(n * ts);
   v.d0 = (T*)take(n * ts);
   v.dx = (T*)take(n * ts);
@@ -1285,7 +1285,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       if ((e = launch_lower_to_f32(S64, S32, n, st)) != hipSuccess) return e;
       if ((e = launch_convert<double, float>(d064, d032, n, st)) != hipSuccess) return e;
       if ((e = launch_convert<double, float>(s64, rhs32, n, st)) != hipSuccess) return e;
-      if ((e = launch_chol_factor<float>(S32, n, Linv32, d032, status + it, mb + it, st)) != hipSuccess) return e;
+      if ((e = launch_chol_factor<float>(S32, n, n, Linv32, d032, status + it, mb + it, st)) != hipSuccess) return e;
       if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
                                     next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
         return e;

@@ -272,11 +272,11 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, in
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
 // block per workgroup, on the matrix cores.
 template <typename T>
-__global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int k0, int kb, const T* Linv) {
+__global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int nrows, int k0, int kb, const T* Linv) {
   __shared__ T Ab[kNB][kNB + 1];
   __shared__ T Li[kNB][kNB + 1];
   const int i0 = k0 + kb + blockIdx.x * kNB;
-  const int rows = min(kNB, n - i0);
+  const int rows = min(kNB, nrows - i0);
   const int tid = threadIdx.x;
   load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
   load_block64<T>(Linv, (size_t)kNB, kb, kb, Li);
@@ -338,6 +338,160 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
   }
 }
 
+// Trailing update with 128 x 128 output tiles (float32): A_IJ -= L_Ik L_Jk^T
+// for the lower tiles of the trailing rows [t0, nrows) x columns [t0, n),
+// K = 64 (one panel).  Each of the four wavefronts takes one 64 x 64
+// quadrant as 4 x 4 matrix-core tiles accumulating L_I L_J^T; the quadrant
+// above the diagonal of a diagonal tile is skipped.  The products are then
+// staged in LDS and the tile is read and written row by row (contiguous
+// 512-byte rows): A - L_I L_J^T.  Four times the products per byte of panel
+// rows of a 64 x 64 update.  Rows beyond n (the right-hand side appended as
+// row n) are updated like any other row.
+//
+// Look-ahead: with Linv_next, workgroup 0 updates only the next diagonal
+// block (64 x 64; its quadrant of tile (0, 0) is left to it) and factors it
+// at once, so the factor of the next panel starts with the launch instead of
+// after a whole tile.
+constexpr int kTB = 128;
+constexpr int kPanLd = 68;   // LDS row stride of the staged panel rows
+constexpr int kOutLd = 132;  // LDS row stride of the staged products
+constexpr int kSyrk128Lds = 2 * kTB * kPanLd * 4;
+
+__global__ void __launch_bounds__(256) syrk128_kernel(float* S, int n, int nrows, int k0, int kb, float* Linv_next,
+                                                      const float* d0, int* status, unsigned int* min_bits) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  float* Pi = reinterpret_cast<float*>(dyn_lds);
+  float* Pj = Pi + kTB * kPanLd;
+  const int t0 = k0 + kb;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const bool look = Linv_next != nullptr;
+  if (look && blockIdx.x == 0) {
+    // next diagonal block: A_kk -= L_k L_k^T (64 x 64), then its factor
+    float (*Lk)[kNB + 1] = reinterpret_cast<float (*)[kNB + 1]>(Pi);
+    const int rb = min(kNB, n - t0);
+    load_block64<float>(S + (size_t)t0 * n + k0, (size_t)n, rb, kb, Lk);
+    __syncthreads();
+    floatx4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    gemm_nt_64<float>(&Lk[0][0], &Lk[0][0], kNB + 1, kNB, acc);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + Mfma<float>::row(lane, v), c = 16 * t + (lane & 15);
+        if (r < rb && c <= r) S[(size_t)(t0 + r) * n + t0 + c] -= acc[t][v];
+      }
+    __threadfence_block();
+    __syncthreads();
+    diag_factor<float>(S, n, t0, rb, Linv_next, d0, status, min_bits, Pi, Pi + kTB * 17);
+    return;
+  }
+  const int Tc = (n - t0 + kTB - 1) / kTB;
+  const int ntri = Tc * (Tc + 1) / 2;
+  const int blk = blockIdx.x - (look ? 1 : 0);
+  int I, J;
+  if (blk < ntri) {
+    I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > blk) --I;
+    while ((I + 1) * (I + 2) / 2 <= blk) ++I;
+    J = blk - I * (I + 1) / 2;
+  } else {  // the extra row tile below the last full one (rows up to nrows > n)
+    I = Tc;
+    J = blk - ntri;
+  }
+  const int i0 = t0 + I * kTB, j0 = t0 + J * kTB;
+  const int ri = min(kTB, nrows - i0), rj = min(kTB, n - j0);
+  const int wr = w >> 1, wc = w & 1;
+  // the next diagonal block (rows and columns [t0, t0 + lb) of tile (0, 0)) is the look-ahead's
+  const bool skip_lead = look && I == 0 && J == 0;
+  const int lb = min(kNB, n - t0);
+  const bool active = !(I == J && wr < wc);
+  // accumulators (lane: column 16 tj + (lane & 15), rows 4 (lane >> 4) + v of
+  // tile ti) collect L_I L_J^T from zero and are subtracted from A once:
+  // starting them from A would round every step at the size of A, which the
+  // update nearly cancels on the ill-conditioned directions
+  floatx4_t acc[4][4];
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+  // panel rows: 128 x kb of columns k0.. for the row tile and the column tile
+  {
+    f2 va[16], vb[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = tid + 256 * u, r = q >> 5, c = 2 * (q & 31);
+      va[u] = (r < ri && c < kb) ? *reinterpret_cast<const f2*>(S + (size_t)(i0 + r) * n + k0 + c) : f2{0.f, 0.f};
+      vb[u] = (r < rj && c < kb) ? *reinterpret_cast<const f2*>(S + (size_t)(j0 + r) * n + k0 + c) : f2{0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = tid + 256 * u, r = q >> 5, c = 2 * (q & 31);
+      *reinterpret_cast<f2*>(Pi + r * kPanLd + c) = va[u];
+      *reinterpret_cast<f2*>(Pj + r * kPanLd + c) = vb[u];
+    }
+  }
+  __syncthreads();
+  if (active) {
+    const float* pa = Pi + (64 * wr + (lane & 15)) * kPanLd + (lane >> 4);
+    const float* pb = Pj + (64 * wc + (lane & 15)) * kPanLd + (lane >> 4);
+    for (int k = 0; k < kNB; k += 4) {
+      float a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = pa[16 * t * kPanLd + k];
+        b[t] = pb[16 * t * kPanLd + k];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // the panel rows are dead: their LDS takes the products
+  float* Out = Pi;  // [128][kOutLd]
+  if (active) {
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 64 * wr + 16 * ti + 4 * (lane >> 4) + v, c = 64 * wc + 16 * tj + (lane & 15);
+          Out[r * kOutLd + c] = acc[ti][tj][v];
+        }
+  }
+  __syncthreads();
+  // wavefront w takes rows w, w + 4, ...; lane l columns 2 l, 2 l + 1 (each
+  // access instruction covers one contiguous 512-byte row)
+  {
+    const int c = 2 * lane;
+    f2 av[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int r = w + 4 * u;
+      av[u] = (r < ri && c < rj) ? *reinterpret_cast<const f2*>(S + (size_t)(i0 + r) * n + j0 + c)
+                                 : f2{0.f, 0.f};  // rj is even: n and j0 are
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int r = w + 4 * u;
+      if (r >= ri || c >= rj) continue;
+      if (skip_lead && r < lb && c < lb) continue;
+      const float* o = Out + r * kOutLd + c;
+      const f2 nv = av[u] - f2{o[0], o[1]};
+      float* dst = S + (size_t)(i0 + r) * n + j0 + c;
+      if (I != J || c + 1 <= r) {
+        *reinterpret_cast<f2*>(dst) = nv;
+      } else if (c == r) {
+        dst[0] = nv.x;
+      }
+    }
+  }
+}
+
 // Both triangular solves of a blocked factor in one cooperative launch.
 // The 64-row blocks go in pairs (2P, 2P + 1), and workgroup g owns the pairs
 // P = g, g + G, ...  Forward (L y = b): pair Q subtracts L_IK y_K (I in the
@@ -383,7 +537,8 @@ __device__ __forceinline__ void chain_publish(int* flag, int epoch) {
 
 template <typename T>
 __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, const T* Linv_all, const T* b, T* y,
-                                                         T* x, int* flags, int epoch, int* err, int* host_err) {
+                                                         T* x, int* flags, int epoch, int* err, int* host_err,
+                                                         int backward_only) {
   __shared__ T Li[2][kNB][kNB + 1];  // inverses of the pair's diagonal blocks
   __shared__ T acc[2][kNB];
   __shared__ T vk[2][kNB];
@@ -395,7 +550,8 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
   int* fwd = flags;
   int* bwd = flags + nblk;
   // ---- forward: thread (r, q) = (tid / 4, tid mod 4) takes row r, columns 16 q .. 16 q + 15
-  for (int Q = blockIdx.x; Q < npair; Q += G) {
+  // (skipped when the factor already produced y = L^-1 b in y)
+  for (int Q = backward_only ? npair : blockIdx.x; Q < npair; Q += G) {
     const int I0 = 2 * Q, I1 = 2 * Q + 1;
     const int i0 = I0 * kNB, rows0 = min(kNB, n - i0);
     const int i1 = I1 * kNB, rows1 = I1 < nblk ? min(kNB, n - i1) : 0;
@@ -565,6 +721,12 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
 }
 
 template <typename T>
+__global__ void copy_vec_kernel(T* dst, const T* src, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+template <typename T>
 __global__ void zero_on_status_kernel(T* dx, int n, const int* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n && *status) dx[i] = (T)0;
@@ -578,22 +740,44 @@ __global__ void zero_on_status_kernel(T* dx, int n, const int* status) {
 int small_solve_max_n(int tsize) { return tsize == 4 ? 240 : 160; }
 
 // Blocked factorisation in place (lower triangle of S becomes L) with the
-// diagonal-block inverses in Linv_all.
+// diagonal-block inverses in Linv_all.  nrows >= n rows of S (row stride n)
+// take part: with the right-hand side appended as row n (nrows = n + 1,
+// float32 only) that row ends as y = L^-1 s, the forward substitution
+// done by the factorisation's own panel solves and trailing updates.
 template <typename T>
-hipError_t launch_chol_factor(T* S, int n, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
-                              hipStream_t st) {
+hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, int* status,
+                              unsigned int* min_bits, hipStream_t st) {
   const int nblk = (n + kNB - 1) / kNB;
   if (nblk == 0) return hipSuccess;
+  if (sizeof(T) == 8 && nrows != n) return hipErrorInvalidValue;
   hipLaunchKernelGGL((potrf_diag_kernel<T>), dim3(1), dim3(256), 0, st, S, n, 0, min(kNB, n), Linv_all, d0, status,
                      min_bits);
+  if constexpr (sizeof(T) == 4) {
+    hipError_t e = opt_in_lds((const void*)syrk128_kernel, kSyrk128Lds);
+    if (e != hipSuccess) return e;
+  }
   for (int k = 0; k + 1 < nblk; ++k) {
     const int k0 = k * kNB, kb = min(kNB, n - k0);
     T* Linv = Linv_all + (size_t)k * kNB * kNB;
-    const int rest = nblk - k - 1;
-    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(rest), dim3(256), 0, st, S, n, k0, kb, Linv);
+    const int t0 = k0 + kb;
+    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - t0 + kNB - 1) / kNB), dim3(256), 0, st, S, n, nrows,
+                       k0, kb, Linv);
     // the trailing update also factors diagonal block k + 1 (its workgroup 0)
-    hipLaunchKernelGGL((syrk_update_kernel<T>), dim3(rest * (rest + 1) / 2), dim3(256), 0, st, S, n, k0, kb,
-                       Linv + kNB * kNB, d0, status, min_bits);
+    if constexpr (sizeof(T) == 4) {
+      const int Tc = (n - t0 + kTB - 1) / kTB, Tr = (nrows - t0 + kTB - 1) / kTB;
+      const int tiles = Tc * (Tc + 1) / 2 + (Tr > Tc ? Tc : 0);
+      hipLaunchKernelGGL(syrk128_kernel, dim3(tiles + 1), dim3(256), kSyrk128Lds, st, S, n, nrows, k0, kb,
+                         Linv + kNB * kNB, d0, status, min_bits);
+    } else {
+      const int rest = nblk - k - 1;
+      hipLaunchKernelGGL((syrk_update_kernel<T>), dim3(rest * (rest + 1) / 2), dim3(256), 0, st, S, n, k0, kb,
+                         Linv + kNB * kNB, d0, status, min_bits);
+    }
+  }
+  if (nrows > n) {  // the appended rows below the last diagonal block: their last panel solve
+    const int k0 = (nblk - 1) * kNB;
+    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(256), 0, st, S, n, nrows, k0,
+                       n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB);
   }
   return hipGetLastError();
 }
@@ -613,14 +797,15 @@ int trsv_chain_grid(int nblk) {
 // x = (L L^T)^-1 rhs with a factor from launch_chol_factor: one cooperative
 // launch (trsv_chain_kernel).  flags holds 2 ceil(n / 64) ints that the
 // library never resets: each call passes a fresh epoch.
+// backward_only: work_y already holds y = L^-1 rhs (rhs unused).
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
-                             int epoch, int* err, int* host_err, hipStream_t st) {
+                             int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0) {
   const int nblk = (n + kNB - 1) / kNB;
   const int grid = trsv_chain_grid<T>(nblk);
   if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
   void* args[] = {(void*)&L, (void*)&n, (void*)&Linv_all, (void*)&rhs, (void*)&work_y, (void*)&x, (void*)&flags,
-                  (void*)&epoch, (void*)&err, (void*)&host_err};
+                  (void*)&epoch, (void*)&err, (void*)&host_err, (void*)&backward_only};
   return hipLaunchCooperativeKernel((const void*)trsv_chain_kernel<T>, dim3(grid), dim3(256), args, 0, st);
 }
 
@@ -640,9 +825,20 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
     hipLaunchKernelGGL((small_chol_solve_kernel<T>), dim3(1), dim3(256), lds, st, S, rhs, n, dx, status, min_bits);
     return hipGetLastError();
   }
-  hipError_t e = launch_chol_factor<T>(S, n, Linv_all, d0, status, min_bits, st);
-  if (e != hipSuccess) return e;
-  e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st);
+  hipError_t e;
+  if constexpr (sizeof(T) == 4) {
+    // s appended as row n of S (which has room for n + 1 rows): the factor
+    // leaves y = L^-1 s there and only the backward chain remains
+    T* yrow = S + (size_t)n * n;
+    hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, yrow, rhs, n);
+    e = launch_chol_factor<T>(S, n, n + 1, Linv_all, d0, status, min_bits, st);
+    if (e != hipSuccess) return e;
+    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1);
+  } else {
+    e = launch_chol_factor<T>(S, n, n, Linv_all, d0, status, min_bits, st);
+    if (e != hipSuccess) return e;
+    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st);
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((zero_on_status_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, dx, n, status);
   return hipGetLastError();
@@ -652,8 +848,9 @@ template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, 
                                              unsigned int*, int*, int, int*, int*, hipStream_t);
 template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, const double*,
                                               int*, unsigned int*, int*, int, int*, int*, hipStream_t);
-template hipError_t launch_chol_factor<float>(float*, int, float*, const float*, int*, unsigned int*, hipStream_t);
+template hipError_t launch_chol_factor<float>(float*, int, int, float*, const float*, int*, unsigned int*,
+                                              hipStream_t);
 template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, int*, int,
-                                             int*, int*, hipStream_t);
+                                             int*, int*, hipStream_t, int);
 
 }  // namespace dpvba

@@ -178,6 +178,8 @@ def test_invalid_weight_after_analysis_is_reported(dp, ctx, name, mk):
     assert ei.value.status == dp.binding.DPVBA_EDEVICE
     assert ctx.device_status() == (dp.binding.DPVBA_EDEVICE, 4)
     g.weight[7, 0] = 0.5
+    poses = torch.as_tensor(s.poses).cuda().contiguous()   # the failed calls overwrote them
+    depth = torch.as_tensor(s.inv_depth).cuda().contiguous()
     rep = ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, precision=dp.FP32)
     assert rep["status"] == 0 and ctx.device_status() == (dp.binding.DPVBA_OK, 0)
 
