@@ -69,7 +69,8 @@ typedef enum {
                          wide wait expired, or it met a target / weight outside
                          the documented range; see dpvba_device_status          */
   DPVBA_ELIMIT = 7    /* the problem exceeds a fixed capacity of the call
-                         (dpvba_solve_noalloc); dpvba_last_error says which     */
+                         (dpvba_solve_noalloc) or an output's capacity
+                         (dpvba_proximity_edges); dpvba_last_error says which   */
 } dpvba_status;
 
 typedef enum {
@@ -229,6 +230,42 @@ dpvba_status dpvba_get_analysis_info(const dpvba_ctx* ctx, int32_t precision,
 dpvba_status dpvba_reproject(dpvba_ctx* ctx, const dpvba_graph* g, const float* poses,
                              const float* inv_depth, float z_min, float* coords,
                              uint8_t* valid, void* stream);
+
+/* Proximity loop closure (Sec. 3.2, "Proximity Loop Closure" and
+ * "Constructing the Patch Graph"): loops are detected from the cameras'
+ * proximity to previously visited locations, and every stored patch of an
+ * old frame gets a uni-directional edge to each recent frame found near it
+ * (the destination frame is the one whose dense features the correlation of
+ * eq. 4 needs).  The edges, appended to the temporal ones, form the graph of
+ * the global BA that follows.
+ * Rule: frame j is a loop target of frame i when j >= first_recent,
+ * j - i > min_gap and the camera centres (translations of the poses) satisfy
+ * |c_i - c_j|^2 < radius^2; frame i keeps its max_targets nearest targets,
+ * ties to the lower frame index.  The comparisons are made in float32 with
+ * d2 = (dx*dx + dy*dy) + dz*dz, every operation rounded on its own (no fused
+ * multiply-add), against radius*radius rounded to float32.
+ *   poses      [N, 7] float32 camera-to-world (read).
+ *   patch_off  [N + 1] int32, non-decreasing, patch_off[0] = 0: the patches
+ *              of frame i are [patch_off[i], patch_off[i+1]) (read).
+ *   counts     [N] int32 (written): loop targets of each frame.
+ *   targets    [N, max_targets] int32 (written): frame i's targets in
+ *              increasing order, -1 after the last; may be NULL when
+ *              max_targets = 0.
+ *   edge_off   [N + 1] int64 (written): frame i's edges are
+ *              [edge_off[i], edge_off[i+1]).
+ *   ii, jj, kk [max_edges] int32 (written): source frame, target frame and
+ *              patch of each edge, by frame, then patch, then target.
+ *   n_edges    host: total loop edges.  The call synchronises `stream` to
+ *              read it; if it exceeds max_edges, the first max_edges edges
+ *              are written and DPVBA_ELIMIT is returned.
+ * 0 <= first_recent <= N, min_gap >= 0, radius finite and >= 0,
+ * 0 <= max_targets <= DPVBA_MAX_LOOP_TARGETS, max_edges >= 0; EINVAL
+ * otherwise.  Needs no analysis.                                          */
+#define DPVBA_MAX_LOOP_TARGETS 32
+dpvba_status dpvba_proximity_edges(dpvba_ctx* ctx, const float* poses, int32_t n_frames, const int32_t* patch_off,
+                                   int32_t first_recent, int32_t min_gap, float radius, int32_t max_targets,
+                                   int32_t* counts, int32_t* targets, int64_t* edge_off, int32_t* ii, int32_t* jj,
+                                   int32_t* kk, int64_t max_edges, int64_t* n_edges, void* stream);
 
 /* Damped reduced camera system at the given iterate (eq. 3 linearised,
  * Appendix A): S = B~ - E C~^-1 E^T and s = -v + E C~^-1 w over the free

@@ -99,6 +99,10 @@ def lib():
         L.dpvba_solve_noalloc.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts),
                                           ctypes.POINTER(Report), vp]
         L.dpvba_solve_noalloc.restype = ctypes.c_int
+        L.dpvba_proximity_edges.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                            ctypes.c_int32, vp, vp, vp, vp, vp, vp, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int64), vp]
+        L.dpvba_proximity_edges.restype = ctypes.c_int
         L.dpvba_solve_backward.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp,
                                            vp]
         L.dpvba_solve_backward.restype = ctypes.c_int
@@ -278,6 +282,28 @@ class Context:
         info = AnalysisInfo()
         _check(lib().dpvba_get_analysis_info(self._h, int(precision), ctypes.byref(info)), "dpvba_get_analysis_info")
         return {f: getattr(info, f) for f, _ in AnalysisInfo._fields_}
+
+    def proximity_edges(self, poses, patch_off, first_recent=0, min_gap=100, radius=2.0, max_targets=10,
+                        stream=None):
+        """Loop-closure edges by camera proximity (dpvba_proximity_edges).
+        poses [N,7] float32 and patch_off [N+1] int32 on the device.  Returns
+        (counts [N], targets [N,max_targets], edge_off [N+1], ii, jj, kk)."""
+        n = int(poses.shape[0])
+        dev = poses.device
+        counts = torch.empty((n,), dtype=torch.int32, device=dev)
+        targets = torch.empty((n, max(1, max_targets)), dtype=torch.int32, device=dev)
+        edge_off = torch.empty((n + 1,), dtype=torch.int64, device=dev)
+        cap = int(patch_off[-1].item()) * int(max_targets)
+        ii = torch.empty((max(1, cap),), dtype=torch.int32, device=dev)
+        jj = torch.empty_like(ii)
+        kk = torch.empty_like(ii)
+        ne = ctypes.c_int64(0)
+        _check(lib().dpvba_proximity_edges(self._h, _ptr(poses), n, _ptr(patch_off), int(first_recent), int(min_gap),
+                                           float(radius), int(max_targets), _ptr(counts), _ptr(targets),
+                                           _ptr(edge_off), _ptr(ii), _ptr(jj), _ptr(kk), cap, ctypes.byref(ne),
+                                           _stream(stream)), "dpvba_proximity_edges", self._h)
+        m = int(ne.value)
+        return counts, targets[:, :max_targets], edge_off, ii[:m], jj[:m], kk[:m]
 
     def reproject(self, g: GraphTensors, poses, inv_depth, z_min=0.1, stream=None):
         E, p = g.ii.shape[0], g.patches.shape[1]

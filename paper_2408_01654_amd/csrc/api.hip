@@ -36,6 +36,9 @@ int small_solve_grid(int lds_bytes);
 template <typename T>
 hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, bool cooperative, hipStream_t st);
 int small_solve_max_n(int tsize);
+hipError_t launch_proximity_edges(const float* poses, int n, const int* patch_off, int first_recent, int min_gap,
+                                  float r2, int max_t, int* counts, int* targets, long long* edge_off, int* ii,
+                                  int* jj, int* kk, long long max_edges, hipStream_t st);
 template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
@@ -1544,6 +1547,34 @@ dpvba_status dpvba_reproject(dpvba_ctx* c, const dpvba_graph* g, const float* po
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(launch_reproject(poses, inv_depth, g->patches, g->patch_size, g->ii, g->jj, g->kk, g->n_edges, g->fx,
                            g->fy, g->cx, g->cy, z_min, coords, valid, (hipStream_t)stream));
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_proximity_edges(dpvba_ctx* c, const float* poses, int32_t n_frames, const int32_t* patch_off,
+                                   int32_t first_recent, int32_t min_gap, float radius, int32_t max_targets,
+                                   int32_t* counts, int32_t* targets, int64_t* edge_off, int32_t* ii, int32_t* jj,
+                                   int32_t* kk, int64_t max_edges, int64_t* n_edges, void* stream) {
+  if (!c || !n_edges || n_frames < 0 || !patch_off || !edge_off) return DPVBA_EINVAL;
+  if (first_recent < 0 || first_recent > n_frames || min_gap < 0) return DPVBA_EINVAL;
+  if (!(radius >= 0.f) || !(radius <= FLT_MAX)) return DPVBA_EINVAL;
+  if (max_targets < 0 || max_targets > DPVBA_MAX_LOOP_TARGETS || max_edges < 0) return DPVBA_EINVAL;
+  if (n_frames > 0 && (!poses || !counts || (max_targets > 0 && !targets))) return DPVBA_EINVAL;
+  if (max_edges > 0 && (!ii || !jj || !kk)) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const float r2 = radius * radius;  // rounded to float, as the decisions are
+  HIP_TRY(launch_proximity_edges(poses, n_frames, patch_off, first_recent, min_gap, r2, max_targets, counts, targets,
+                                 (long long*)edge_off, ii, jj, kk, (long long)max_edges, st));
+  long long total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, edge_off + n_frames, sizeof(total), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *n_edges = total;
+  if (total > max_edges) {
+    snprintf(c->err, sizeof(c->err), "dpvba_proximity_edges: %lld edges exceed max_edges %lld", total,
+             (long long)max_edges);
+    return DPVBA_ELIMIT;
+  }
   return DPVBA_OK;
 }
 
