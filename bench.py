@@ -463,6 +463,83 @@ def _adjoint(ctx, scenes, steps):
 
 
 
+def bench_correlation(steps=20):
+    """Patch correlation of eq. 4 over one sliding window: 37,440 edges of
+    3 x 3 patches, 128-channel features, 22 feature maps of 120 x 160
+    (a quarter of the 640 x 480 image), coordinates from dpvba_reproject."""
+    import torch
+    import paper_2408_01654_amd as dp
+    from oracle import correlation
+    from scenes import make_window
+    s = make_window(0)
+    D, H, W = 128, 120, 160
+    rng = np.random.default_rng(11)
+    with dp.Context(0) as ctx:
+        g = dp.GraphTensors.from_scene(s)
+        coords, _ = ctx.reproject(g, torch.as_tensor(s.poses).cuda(), torch.as_tensor(s.inv_depth).cuda())
+        xy = (coords / 4.0).contiguous()
+        gm = torch.as_tensor(rng.standard_normal((s.n_patches, 3, 3, D)).astype(np.float32)).cuda()
+        fm = torch.as_tensor(rng.standard_normal((s.n_frames, H, W, D)).astype(np.float32)).cuda()
+        out = torch.empty((s.n_edges, 3, 3, 7, 7), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            ctx.patch_correlation(gm, fm, g.kk, g.jj, xy, out=out)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            ctx.patch_correlation(gm, fm, g.kk, g.jj, xy, out=out)
+        ev1.record()
+        ev1.synchronize()
+        us = 1e3 * ev0.elapsed_time(ev1) / steps
+        sample = rng.choice(s.n_edges, 64, replace=False)
+        xs = xy.cpu().numpy()[sample]
+        gn, fn = gm.cpu().numpy(), fm.cpu().numpy()
+        want = correlation.correlation(gn, fn, s.kk[sample], s.jj[sample], xs)
+        bound = (D + 8) * 2.0 ** -24 * correlation.correlation(np.abs(gn), np.abs(fn), s.kk[sample], s.jj[sample],
+                                                               xs)
+        ratio = float((np.abs(out.cpu().numpy()[sample] - want) / (bound + 1e-30)).max())
+    E, P = s.n_edges, s.n_patches
+    alg = P * 9 * D * 4 + E * (100 * D * 4 + 72 + 9 * 49 * 4 + 8)
+    ach = alg / (us * 1e-6) / 1e9
+    rec = {"workload": "patch correlation (eq. 4), one sliding window: 37,440 edges, 3x3 patches, 7x7 grid, "
+                       "128 channels, 22 maps of 120x160",
+           "us_per_call": us, "edges_per_s": E / (us * 1e-6),
+           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "alg_bytes_per_launch": alg,
+                        "kernel": "patch_corr_kernel<2>", "avg_launch_us": us},
+           "sampled_edges": 64, "max_err_over_bound": ratio, "ok": ratio <= 1.0}
+    log(f"[bench] correlation: {us:.1f} us per call ({ach:.0f} GB/s algorithmic), err/bound {ratio:.3f}")
+    return rec
+
+
+def bench_proximity(steps=20):
+    """Proximity loop-closure edges of the 1000-keyframe workload on the
+    device (cameras at the drifted start, +-100 frame gap, 2 m, 10 targets)."""
+    import torch
+    import paper_2408_01654_amd as dp
+    from oracle import proximity
+    from scenes import make_config
+    s = make_config(2)
+    with dp.Context(0) as ctx:
+        P = torch.as_tensor(s.poses).cuda()
+        off = torch.arange(0, 96 * (s.n_frames + 1), 96, dtype=torch.int32).cuda()
+        ctx.proximity_edges(P, off, 0, 100, 2.0, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = ctx.proximity_edges(P, off, 0, 100, 2.0, 10)
+        sec = (time.perf_counter() - t0) / steps
+    want = proximity.loop_targets(s.poses[:, :3], 0, 100, 2.0, 10)
+    wi, wj, wk = proximity.loop_edges(want, np.arange(0, 96 * (s.n_frames + 1), 96))
+    ok = (np.array_equal(res[3].cpu().numpy(), wi) and np.array_equal(res[4].cpu().numpy(), wj)
+          and np.array_equal(res[5].cpu().numpy(), wk))
+    rec = {"workload": "proximity loop-closure edges, 1000 keyframes x 96 patches, gap 100, radius 2 m, "
+                       "10 targets per frame", "ms_per_call": 1e3 * sec, "edges": int(len(wi)),
+           "identical_to_oracle": bool(ok), "note": "call time includes the host read of the edge count"}
+    log(f"[bench] proximity edges: {1e3 * sec:.3f} ms per call, {len(wi)} edges, identical {ok}")
+    return rec
+
+
 def bench_window(args):
     """Sliding-window local BA, 1000 calls (side record)."""
     import paper_2408_01654_amd as dp
@@ -599,7 +676,7 @@ def main():
     ap.add_argument("--trace-every", type=int, default=7, help="window record: event pair every n-th launch")
     ap.add_argument("--check", type=int, default=4, help="windows checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--side", default="window,mixed,batch,adjoint",
+    ap.add_argument("--side", default="window,mixed,batch,adjoint,correlation,proximity",
                     help="comma list of side records: window (sliding-window BA), mixed (window and global BA in "
                          "DPVBA_MIXED), batch (256 uneven windows, every instance checked), adjoint (16 windows "
                          "forward+adjoint); empty: none")
@@ -657,6 +734,10 @@ def main():
         side["batch_mixed"] = bench_batch(dp.MIXED, graph=True, steps=5, oracle_res=ores)
     if "adjoint" in wanted:
         side["adjoint"] = bench_adjoint(steps=3)
+    if "correlation" in wanted:
+        side["correlation"] = bench_correlation()
+    if "proximity" in wanted:
+        side["proximity"] = bench_proximity()
 
     cpu = None
     if not args.no_cpu_baseline:

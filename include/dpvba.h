@@ -231,6 +231,31 @@ dpvba_status dpvba_reproject(dpvba_ctx* ctx, const dpvba_graph* g, const float* 
                              const float* inv_depth, float z_min, float* coords,
                              uint8_t* valid, void* stream);
 
+/* Patch correlation of eq. 4 (Sec. 3.1, "Patch correlation"): for every
+ * edge, at every patch pixel (u, v), the dot product of the patch feature
+ * vector g(u, v) with the target frame's feature map sampled bilinearly at
+ * the reprojected pixel shifted by each offset of a 7 x 7 grid centred at 0:
+ *   corr[e, u, v, a, b] = < g_kk[e](u, v), f_jj[e](x + a - 3, y + b - 3) >,
+ * (x, y) = coords[e, u, v] in feature-map pixels (pixel (x, y) holds
+ * map[y, x]); bilinear weights from the point's distances to its four
+ * pixels, pixels outside the map count as zero.  The reprojected patches
+ * come from dpvba_reproject with patches and intrinsics given at the feature
+ * map's resolution.
+ *   gmap   [n_patches, p, p, dim] float32: patch features, row u, column v.
+ *   fmaps  [n_maps, height, width, dim] float32: feature maps (channels last).
+ *   kk, jj [n_edges] int32: patch and feature map of each edge (jj indexes
+ *          fmaps, e.g. the slot of the target frame's stored map); an index
+ *          out of range gives zeros for that edge and is recorded as an
+ *          invalid input (later calls return DPVBA_EDEVICE).
+ *   coords [n_edges, p, p, 2] float32 (x, y).
+ *   corr   [n_edges, p, p, 7, 7] float32 (written).
+ * dim a multiple of 64 up to 256; p odd, at most 15; EINVAL otherwise.
+ * Accumulates in float32.  Needs no analysis.                             */
+dpvba_status dpvba_patch_correlation(dpvba_ctx* ctx, int32_t n_edges, int32_t patch_size, int32_t dim,
+                                     const float* gmap, int32_t n_patches, const float* fmaps, int32_t n_maps,
+                                     int32_t height, int32_t width, const int32_t* kk, const int32_t* jj,
+                                     const float* coords, float* corr, void* stream);
+
 /* Proximity loop closure (Sec. 3.2, "Proximity Loop Closure" and
  * "Constructing the Patch Graph"): loops are detected from the cameras'
  * proximity to previously visited locations, and every stored patch of an

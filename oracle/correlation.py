@@ -31,6 +31,10 @@ def bilinear(fmap: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
     """Feature vectors [..., D] of one map [H, W, D] at points (x, y) [...],
     zero outside."""
     H, W, D = fmap.shape
+    # points farther out than any map are outside either way; the clip only
+    # keeps the integer conversion defined
+    x = np.clip(x, -1e9, 1e9)
+    y = np.clip(y, -1e9, 1e9)
     x0 = np.floor(x).astype(np.int64)
     y0 = np.floor(y).astype(np.int64)
     fx = x - x0

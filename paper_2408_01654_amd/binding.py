@@ -103,6 +103,9 @@ def lib():
                                             ctypes.c_int32, vp, vp, vp, vp, vp, vp, ctypes.c_int64,
                                             ctypes.POINTER(ctypes.c_int64), vp]
         L.dpvba_proximity_edges.restype = ctypes.c_int
+        L.dpvba_patch_correlation.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32,
+                                              vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
+        L.dpvba_patch_correlation.restype = ctypes.c_int
         L.dpvba_solve_backward.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp,
                                            vp]
         L.dpvba_solve_backward.restype = ctypes.c_int
@@ -282,6 +285,19 @@ class Context:
         info = AnalysisInfo()
         _check(lib().dpvba_get_analysis_info(self._h, int(precision), ctypes.byref(info)), "dpvba_get_analysis_info")
         return {f: getattr(info, f) for f, _ in AnalysisInfo._fields_}
+
+    def patch_correlation(self, gmap, fmaps, kk, jj, coords, out=None, stream=None):
+        """corr [E, p, p, 7, 7] of eq. 4 (dpvba_patch_correlation): gmap
+        [P, p, p, D], fmaps [M, H, W, D] float32, kk / jj [E] int32, coords
+        [E, p, p, 2] float32, all on the device."""
+        E, p = int(coords.shape[0]), int(coords.shape[1])
+        D = int(gmap.shape[-1])
+        corr = out if out is not None else torch.empty((E, p, p, 7, 7), dtype=torch.float32, device=coords.device)
+        _check(lib().dpvba_patch_correlation(self._h, E, p, D, _ptr(gmap), int(gmap.shape[0]), _ptr(fmaps),
+                                             int(fmaps.shape[0]), int(fmaps.shape[1]), int(fmaps.shape[2]), _ptr(kk),
+                                             _ptr(jj), _ptr(coords), _ptr(corr), _stream(stream)),
+               "dpvba_patch_correlation", self._h)
+        return corr
 
     def proximity_edges(self, poses, patch_off, first_recent=0, min_gap=100, radius=2.0, max_targets=10,
                         stream=None):

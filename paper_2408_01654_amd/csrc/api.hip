@@ -36,6 +36,9 @@ int small_solve_grid(int lds_bytes);
 template <typename T>
 hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, bool cooperative, hipStream_t st);
 int small_solve_max_n(int tsize);
+hipError_t launch_patch_correlation(int n_edges, int p, int dim, const float* gmap, int n_patches, const float* fmaps,
+                                    int n_maps, int H, int W, const int* kk, const int* jj, const float* coords,
+                                    float* corr, int* dev_err, int* host_err, hipStream_t st);
 hipError_t launch_proximity_edges(const float* poses, int n, const int* patch_off, int first_recent, int min_gap,
                                   float r2, int max_t, int* counts, int* targets, long long* edge_off, int* ii,
                                   int* jj, int* kk, long long max_edges, hipStream_t st);
@@ -1547,6 +1550,23 @@ dpvba_status dpvba_reproject(dpvba_ctx* c, const dpvba_graph* g, const float* po
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(launch_reproject(poses, inv_depth, g->patches, g->patch_size, g->ii, g->jj, g->kk, g->n_edges, g->fx,
                            g->fy, g->cx, g->cy, z_min, coords, valid, (hipStream_t)stream));
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_patch_correlation(dpvba_ctx* c, int32_t n_edges, int32_t patch_size, int32_t dim,
+                                     const float* gmap, int32_t n_patches, const float* fmaps, int32_t n_maps,
+                                     int32_t height, int32_t width, const int32_t* kk, const int32_t* jj,
+                                     const float* coords, float* corr, void* stream) {
+  if (!c || n_edges < 0 || patch_size < 1 || patch_size % 2 == 0 || patch_size > 15) return DPVBA_EINVAL;
+  if (dim < 64 || dim > 256 || dim % 64 != 0 || n_patches < 0 || n_maps < 0 || height < 0 || width < 0)
+    return DPVBA_EINVAL;
+  if ((long long)height * width * dim > (1LL << 31)) return DPVBA_EINVAL;
+  if (n_edges > 0 && (!gmap || !fmaps || !kk || !jj || !coords || !corr)) return DPVBA_EINVAL;
+  if ((long long)n_edges * patch_size * patch_size > INT32_MAX) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(launch_patch_correlation(n_edges, patch_size, dim, gmap, n_patches, fmaps, n_maps, height, width, kk, jj,
+                                   coords, corr, nullptr, c->host_err_dev, (hipStream_t)stream));
   return DPVBA_OK;
 }
 
