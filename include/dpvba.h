@@ -339,16 +339,19 @@ dpvba_status dpvba_solve(dpvba_ctx* ctx, const dpvba_graph* g, float* poses, flo
 dpvba_status dpvba_solve_noalloc(dpvba_ctx* ctx, const dpvba_graph* g, float* poses, float* inv_depth,
                                  const dpvba_opts* opts, dpvba_report* report, void* stream);
 
-/* Launch of the single-launch solver that dpvba_solve uses for small
- * reduced systems (6 x free poses + 1 <= 96; the sliding window of Sec. 3.1):
- * one kernel whose workgroups meet at grid-wide barriers, never more
- * workgroups than the device holds at once.  cooperative = 0 (the default):
- * an ordinary launch, which relies on the device placing every workgroup
- * while the first ones wait -- true when the device's other work finishes;
- * every wait is bounded, so a violation returns DPVBA_EHIP rather than
- * hanging.  cooperative = 1: a cooperative launch, whose co-residency the
- * runtime guarantees, at a higher cost per launch.  Results are identical
- * bit for bit.  EINVAL for other values.                                  */
+/* Launch mode of the kernels whose workgroups wait for each other: the
+ * single-launch solver that dpvba_solve uses for small reduced systems
+ * (6 x free poses + 1 <= 96; the sliding window of Sec. 3.1), whose
+ * workgroups meet at grid-wide barriers, and the chained triangular solves
+ * of larger systems, whose workgroups wait for the blocks before theirs.
+ * Neither grid exceeds the workgroups the device holds at once.
+ * cooperative = 0 (the default): ordinary launches, which rely on the device
+ * placing every workgroup while the first ones wait -- true when the
+ * device's other work finishes; every wait is bounded, so a violation is
+ * reported (report status DPVBA_EHIP, later calls DPVBA_EDEVICE) rather
+ * than hanging.  cooperative = 1: cooperative launches, whose co-residency
+ * the runtime guarantees, at a higher cost per launch.  Results are
+ * identical bit for bit.  EINVAL for other values.                        */
 dpvba_status dpvba_set_cooperative(dpvba_ctx* ctx, int32_t cooperative);
 
 /* Adjoint of dpvba_solve, for training through the BA layer (Sec. 2: the

@@ -57,7 +57,7 @@ hipError_t launch_reproject(const float* poses, const float* inv_depth, const fl
                             float cx, float cy, float z_min, float* coords, uint8_t* valid, hipStream_t st);
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
-                             unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err, hipStream_t st);
+                             unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err, hipStream_t st, bool cooperative = false);
 hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st, int* err_clear = nullptr);
 template <typename TP, typename T>
 hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
@@ -68,7 +68,8 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
                               hipStream_t st);
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
-                             int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0);
+                             int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0,
+                             bool cooperative = false);
 // mixed-precision helpers (mixed.hip)
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st);
@@ -1156,7 +1157,8 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     {
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
       e = launch_chol_solve<T>(ws.S, ws.rhs, n, dx, (T*)c->wy.p, (T*)c->Linv.p, ws.d0,
-                               status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st);
+                               status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st,
+                               c->coop_launch);
     }
     if (e != hipSuccess) return e;
     {
@@ -1293,14 +1295,14 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       if ((e = launch_convert<double, float>(s64, rhs32, n, st)) != hipSuccess) return e;
       if ((e = launch_chol_factor<float>(S32, n, n, Linv32, d032, status + it, mb + it, st)) != hipSuccess) return e;
       if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
-                                    next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
+                                    next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch)) != hipSuccess)
         return e;
       if ((e = launch_convert<float, double>(c32, x64, n, st)) != hipSuccess) return e;
       for (int k = 0; k < n_refine; ++k) {
         if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
         if ((e = launch_convert<double, float>(r64, rhs32, n, st)) != hipSuccess) return e;
         if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
-                                      next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
+                                      next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch)) != hipSuccess)
           return e;
         if ((e = launch_accumulate(x64, c32, n, st)) != hipSuccess) return e;
       }
@@ -1318,7 +1320,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       if (run64) {
         if ((e = launch_chol_solve<double>(S64, s64, n, x64, (double*)c->wy.p, (double*)c->Linv.p, d064, status64 + it,
                                            mb64 + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev,
-                                           st)) != hipSuccess)
+                                           st, c->coop_launch)) != hipSuccess)
           return e;
       }
       if ((e = launch_step_to_f32(x64, dx, n, fb + it, status64 + it, status + it, st)) != hipSuccess) return e;
@@ -1492,7 +1494,7 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
     if ((e = gather()) != hipSuccess) return e;
     if ((e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, DX + (size_t)it * n, (T*)c->wy.p,
                                   (T*)c->Linv.p, (const T*)c->d0.p, status + it, mb + it, (int*)c->chain_flags.p,
-                                  next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
+                                  next_epoch(c), err, c->host_err_dev, st, c->coop_launch)) != hipSuccess)
       return e;
     if ((e = launch_retract_copy<T>(xt, xt + np7, DX + (size_t)it * n, nf, N, status + it, st)) != hipSuccess)
       return e;
@@ -1520,7 +1522,7 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
       return e;
     if ((e = launch_chol_solve<T>((T*)c->S.p, urhs, n, up, (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p,
                                   status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it, (int*)c->chain_flags.p,
-                                  next_epoch(c), err, c->host_err_dev, st)) != hipSuccess)
+                                  next_epoch(c), err, c->host_err_dev, st, c->coop_launch)) != hipSuccess)
       return e;
     if ((e = launch_adjoint_backsub<T>(tiles, tl.n_tiles, tl.max_w6, (const int*)tl.blk_pose.p,
                                        (const T*)c->U_s.p, (const T*)c->pscale_s.p, dbar, up, dx_t, stt, ud, dd,

@@ -797,13 +797,26 @@ int trsv_chain_grid(int nblk) {
 // x = (L L^T)^-1 rhs with a factor from launch_chol_factor: one cooperative
 // launch (trsv_chain_kernel).  flags holds 2 ceil(n / 64) ints that the
 // library never resets: each call passes a fresh epoch.
-// backward_only: work_y already holds y = L^-1 rhs (rhs unused).
+// backward_only: work_y already holds y = L^-1 rhs (rhs unused).  The grid
+// never exceeds the workgroups the device holds at once (at most one per
+// pair of 64-row blocks).  cooperative = false (the default): an ordinary
+// launch, relying on the device placing every workgroup while the others
+// wait for their predecessors -- true when the device's other work finishes;
+// every wait is bounded, so a violation is reported (kErrChain), never a
+// hang.  cooperative = true: the runtime guarantees co-residency, at the
+// cost of a cooperative launch.
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
-                             int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0) {
+                             int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0,
+                             bool cooperative = false) {
   const int nblk = (n + kNB - 1) / kNB;
   const int grid = trsv_chain_grid<T>(nblk);
   if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
+  if (!cooperative) {
+    hipLaunchKernelGGL((trsv_chain_kernel<T>), dim3(grid), dim3(256), 0, st, L, n, Linv_all, rhs, work_y, x, flags,
+                       epoch, err, host_err, backward_only);
+    return hipGetLastError();
+  }
   void* args[] = {(void*)&L, (void*)&n, (void*)&Linv_all, (void*)&rhs, (void*)&work_y, (void*)&x, (void*)&flags,
                   (void*)&epoch, (void*)&err, (void*)&host_err, (void*)&backward_only};
   return hipLaunchCooperativeKernel((const void*)trsv_chain_kernel<T>, dim3(grid), dim3(256), args, 0, st);
@@ -812,7 +825,7 @@ hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs,
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
                              unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err,
-                             hipStream_t st) {
+                             hipStream_t st, bool cooperative) {
   if (n == 0) return hipSuccess;
   if (n <= small_solve_max_n(sizeof(T))) {
     const int lds = n + 1 <= kSmallRows
@@ -833,11 +846,11 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
     hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, yrow, rhs, n);
     e = launch_chol_factor<T>(S, n, n + 1, Linv_all, d0, status, min_bits, st);
     if (e != hipSuccess) return e;
-    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1);
+    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1, cooperative);
   } else {
     e = launch_chol_factor<T>(S, n, n, Linv_all, d0, status, min_bits, st);
     if (e != hipSuccess) return e;
-    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st);
+    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st, 0, cooperative);
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((zero_on_status_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, dx, n, status);
@@ -845,12 +858,12 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
 }
 
 template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, float*, float*, const float*, int*,
-                                             unsigned int*, int*, int, int*, int*, hipStream_t);
+                                             unsigned int*, int*, int, int*, int*, hipStream_t, bool);
 template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, const double*,
-                                              int*, unsigned int*, int*, int, int*, int*, hipStream_t);
+                                              int*, unsigned int*, int*, int, int*, int*, hipStream_t, bool);
 template hipError_t launch_chol_factor<float>(float*, int, int, float*, const float*, int*, unsigned int*,
                                               hipStream_t);
 template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, int*, int,
-                                             int*, int*, hipStream_t, int);
+                                             int*, int*, hipStream_t, int, bool);
 
 }  // namespace dpvba

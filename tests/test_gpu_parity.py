@@ -145,10 +145,12 @@ def test_bitwise_deterministic(dp, ctx):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_cooperative_launch_matches_ordinary(dp, ctx, prec):
-    # the single-launch solver gives the same bits under either launch
-    s = make_window(11)
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "mixed"])
+@pytest.mark.parametrize("scene", ["window", "blocked"])
+def test_cooperative_launch_matches_ordinary(dp, ctx, prec, scene):
+    # the single-launch solver (window) and the chained triangular solves of
+    # the blocked factorisation (300 unknowns) give the same bits under either launch
+    s = make_window(11) if scene == "window" else tiny_scene(52, 12, seed=4, radius=5, trajectory="forward")
     try:
         ctx.set_cooperative(True)
         a = _gpu_solve(dp, ctx, s, PREC[prec])
