@@ -540,6 +540,34 @@ def bench_proximity(steps=20):
     return rec
 
 
+def bench_pgo(n=1000, iters=10):
+    """Sim(3) pose-graph optimisation (eq. 5-7) of a 1000-keyframe loop with
+    5 % scale drift and 50 loop measurements, 10 iterations, float64; the
+    oracle checks a 200-keyframe problem of the same kind."""
+    import torch
+    import paper_2408_01654_amd as dp
+    from oracle import sim3_pgo
+    from scenes.posegraph import loop_problem
+    p0, _, lj, lk, lr = loop_problem(n=n, seed=1, drift=0.05)
+    with dp.Context(0) as ctx:
+        P0, LR = torch.as_tensor(p0).cuda(), torch.as_tensor(lr).cuda()
+        ctx.pgo_sim3(P0, lj, lk, LR, n_iters=iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sims, costs = ctx.pgo_sim3(P0, lj, lk, LR, n_iters=iters)
+        sec = time.perf_counter() - t0
+        q0, _, qj, qk, qr = loop_problem(n=200, seed=3, drift=0.08)
+        s2, c2 = ctx.pgo_sim3(torch.as_tensor(q0).cuda(), qj, qk, torch.as_tensor(qr).cuda(), n_iters=8)
+    want, cw = sim3_pgo.optimise(q0, qj, qk, qr, n_iters=8)
+    err = float(np.abs(s2.cpu().numpy()[:, [0, 1, 2, 7]] - want[:, [0, 1, 2, 7]]).max())
+    rec = {"workload": f"Sim(3) pose-graph optimisation, {n} keyframes, {len(lj)} loops, {iters} iterations, "
+                       "float64 (dense 7(N-1) system)", "ms_per_solve": 1e3 * sec,
+           "cost": [costs[0], costs[-1]], "parity_200_keyframes_max_err": err, "ok": err < 1e-9}
+    log(f"[bench] pgo: {1e3 * sec:.1f} ms for {iters} iterations at N={n}, cost {costs[0]:.3e} -> {costs[-1]:.3e}, "
+        f"parity (N=200) {err:.2e}")
+    return rec
+
+
 def bench_window(args):
     """Sliding-window local BA, 1000 calls (side record)."""
     import paper_2408_01654_amd as dp
@@ -676,7 +704,7 @@ def main():
     ap.add_argument("--trace-every", type=int, default=7, help="window record: event pair every n-th launch")
     ap.add_argument("--check", type=int, default=4, help="windows checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--side", default="window,mixed,batch,adjoint,correlation,proximity",
+    ap.add_argument("--side", default="window,mixed,batch,adjoint,correlation,proximity,pgo",
                     help="comma list of side records: window (sliding-window BA), mixed (window and global BA in "
                          "DPVBA_MIXED), batch (256 uneven windows, every instance checked), adjoint (16 windows "
                          "forward+adjoint); empty: none")
@@ -738,6 +766,8 @@ def main():
         side["correlation"] = bench_correlation()
     if "proximity" in wanted:
         side["proximity"] = bench_proximity()
+    if "pgo" in wanted:
+        side["pgo"] = bench_pgo()
 
     cpu = None
     if not args.no_cpu_baseline:

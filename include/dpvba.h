@@ -231,6 +231,42 @@ dpvba_status dpvba_reproject(dpvba_ctx* ctx, const dpvba_graph* g, const float* 
                              const float* inv_depth, float z_min, float* coords,
                              uint8_t* valid, void* stream);
 
+/* Sim(3) pose-graph optimisation of the classical loop closure (Sec. 3.3,
+ * "Optimization", eq. 5-7).  Every keyframe gets an absolute similarity
+ * S_i = (R_i, t_i, s_i), x -> s_i R_i x + t_i, initialised from its pose
+ * with scale 1; smoothness residuals r_i = log(DeltaS_(i,i+1)^-1 S_i^-1
+ * S_(i+1)) with DeltaS_(i,i+1) = S_i^-1 S_(i+1) of the initial similarities,
+ * loop residuals r_jk = log(DeltaS^loop_jk S_j^-1 S_k); sum |r|^2 minimised
+ * by n_iters damped Gauss-Newton (Levenberg-Marquardt) steps with
+ * H~ = H + lambda (Diag(H) + I) (H + lambda I with DPVBA_FLAG_LEVENBERG), a
+ * fixed lambda and no step rejection, right perturbations S <- S Exp(xi),
+ * xi = (rho, phi, sigma), Exp(xi) = expm([[sigma I + [phi]x, rho], [0, 0]]).
+ * The first n_fixed similarities are held (the objective is invariant to a
+ * global similarity).  Float64 throughout; the dense 7 (N - n_fixed) system is
+ * factored by the library's Cholesky.
+ *   poses     [N, 7] float64 camera-to-world (t, q) (read).
+ *   loop_j, loop_k  host [L] int32: loop frame pairs, j != k.
+ *   loop_rel  [L, 8] float64 (t, q, s): DeltaS^loop_jk (read).
+ *   sims      [N, 8] float64 (written): the optimised (t, q, s).
+ *   cost      host [n_iters + 1] or NULL: sum |r|^2 before each iteration
+ *             and at the end.
+ * The call builds its block lists on the host, allocates its workspace in
+ * the context (a dense (7 (N - n_fixed))^2 float64 system, N - n_fixed <=
+ * 2857), and synchronises `stream` at the end.  Returns DPVBA_ENOTPD if an
+ * iteration's system was not positive definite (its step was skipped).
+ * EINVAL for bad sizes, indices or flags.                                  */
+#define DPVBA_MAX_PGO_ITERS 64
+dpvba_status dpvba_pgo_sim3(dpvba_ctx* ctx, int32_t n_frames, int32_t n_fixed, const double* poses, int32_t n_loops,
+                            const int32_t* loop_j, const int32_t* loop_k, const double* loop_rel, int32_t n_iters,
+                            double lambda, uint32_t flags, double* sims, double* cost, void* stream);
+
+/* The last step of Sec. 3.3: G_i <- (t_i, R_i) and d <- d / s_i for the
+ * patches of frame i, [patch_off[i], patch_off[i+1]) (patch_off [N + 1]
+ * int32, device).  sims [N, 8] float64 from dpvba_pgo_sim3; poses [N, 7] and
+ * inv_depth [P] float32, overwritten.                                      */
+dpvba_status dpvba_pgo_apply(dpvba_ctx* ctx, int32_t n_frames, const double* sims, const int32_t* patch_off,
+                             float* poses, float* inv_depth, void* stream);
+
 /* Patch correlation of eq. 4 (Sec. 3.1, "Patch correlation"): for every
  * edge, at every patch pixel (u, v), the dot product of the patch feature
  * vector g(u, v) with the target frame's feature map sampled bilinearly at

@@ -106,6 +106,11 @@ def lib():
         L.dpvba_patch_correlation.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32,
                                               vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.dpvba_patch_correlation.restype = ctypes.c_int
+        L.dpvba_pgo_sim3.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32, vp, vp, vp,
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_uint32, vp, vp, vp]
+        L.dpvba_pgo_sim3.restype = ctypes.c_int
+        L.dpvba_pgo_apply.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+        L.dpvba_pgo_apply.restype = ctypes.c_int
         L.dpvba_solve_backward.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp,
                                            vp]
         L.dpvba_solve_backward.restype = ctypes.c_int
@@ -285,6 +290,29 @@ class Context:
         info = AnalysisInfo()
         _check(lib().dpvba_get_analysis_info(self._h, int(precision), ctypes.byref(info)), "dpvba_get_analysis_info")
         return {f: getattr(info, f) for f, _ in AnalysisInfo._fields_}
+
+    def pgo_sim3(self, poses, loop_j, loop_k, loop_rel, n_fixed=1, n_iters=10, lam=1e-4, levenberg=False,
+                 stream=None):
+        """Sim(3) pose-graph optimisation (dpvba_pgo_sim3): poses [N,7] and
+        loop_rel [L,8] float64 on the device, loop_j / loop_k host int
+        sequences.  Returns (sims [N,8] float64 device, costs list)."""
+        n = int(poses.shape[0])
+        lj = np.ascontiguousarray(np.asarray(loop_j, dtype=np.int32))
+        lk = np.ascontiguousarray(np.asarray(loop_k, dtype=np.int32))
+        sims = torch.empty((n, 8), dtype=torch.float64, device=poses.device)
+        cost = (ctypes.c_double * (int(n_iters) + 1))()
+        st = lib().dpvba_pgo_sim3(self._h, n, int(n_fixed), _ptr(poses), len(lj),
+                                  lj.ctypes.data_as(ctypes.c_void_p), lk.ctypes.data_as(ctypes.c_void_p),
+                                  _ptr(loop_rel) if len(lj) else None, int(n_iters), float(lam),
+                                  FLAG_LEVENBERG if levenberg else 0, _ptr(sims), ctypes.cast(cost, ctypes.c_void_p),
+                                  _stream(stream))
+        _check(st, "dpvba_pgo_sim3", self._h)
+        return sims, list(cost)
+
+    def pgo_apply(self, sims, patch_off, poses, inv_depth, stream=None):
+        """G_i <- (t_i, R_i), d <- d / s_i in place (dpvba_pgo_apply)."""
+        _check(lib().dpvba_pgo_apply(self._h, int(sims.shape[0]), _ptr(sims), _ptr(patch_off), _ptr(poses),
+                                     _ptr(inv_depth), _stream(stream)), "dpvba_pgo_apply", self._h)
 
     def patch_correlation(self, gmap, fmaps, kk, jj, coords, out=None, stream=None):
         """corr [E, p, p, 7, 7] of eq. 4 (dpvba_patch_correlation): gmap

@@ -36,6 +36,18 @@ int small_solve_grid(int lds_bytes);
 template <typename T>
 hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, bool cooperative, hipStream_t st);
 int small_solve_max_n(int tsize);
+hipError_t launch_pgo_init(const double* poses, int n, double* sims, const double* loop_rel, int n_loops, double* C,
+                           hipStream_t st);
+hipError_t launch_pgo_linearise(const double* sims, const double* C, const int* ea, const int* eb, int n_edges,
+                                double* r, double* J, double* cost, hipStream_t st);
+hipError_t launch_pgo_normal(const double* J, const double* r, const int* blk_pq, const int* blk_off,
+                             const int* blk_src, int n_blocks, const int* pose_off, const int* pose_src, int nf,
+                             double lambda, double lam_diag, double* H, double* d0, double* rhs, hipStream_t st);
+hipError_t launch_pgo_retract(double* sims, int n, int n_fixed, const double* dx, const int* status, hipStream_t st);
+hipError_t launch_pgo_apply(const double* sims, int n, const int* patch_off, float* poses, float* inv_depth,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T* x, long long n, T v, hipStream_t st);
 hipError_t launch_patch_correlation(int n_edges, int p, int dim, const float* gmap, int n_patches, const float* fmaps,
                                     int n_maps, int H, int W, const int* kk, const int* jj, const float* coords,
                                     float* corr, int* dev_err, int* host_err, hipStream_t st);
@@ -300,6 +312,10 @@ struct dpvba_ctx {
     std::vector<uint64_t> key;
   } bt;
   // adjoint workspace
+  // Sim(3) pose-graph optimisation workspace
+  DevBuf pg_C, pg_ea, pg_eb, pg_r, pg_J, pg_H, pg_rhs, pg_dx, pg_d0, pg_wy, pg_Linv, pg_flags, pg_status, pg_mb,
+      pg_cost, pg_blk_pq, pg_blk_off, pg_blk_src, pg_pose_off, pg_pose_src;
+  int pg_epoch = 0;
   DevBuf bw_poses, bw_depth, bw_dx, bw_pbar, bw_dbar, bw_dxbar, bw_rhs, bw_up, bw_ud, bw_dd, bw_edge, bw_status,
       bw_minbits;
   char err[256] = {0};
@@ -494,7 +510,10 @@ void dpvba_destroy(dpvba_ctx* c) {
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
                     &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
                     &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
-                    &c->d0_32, &c->mx_max, &c->mx_resid, &c->mx_fb, &c->mx_flag};
+                    &c->d0_32, &c->mx_max, &c->mx_resid, &c->mx_fb, &c->mx_flag, &c->pg_C, &c->pg_ea, &c->pg_eb,
+                    &c->pg_r, &c->pg_J, &c->pg_H, &c->pg_rhs, &c->pg_dx, &c->pg_d0, &c->pg_wy, &c->pg_Linv,
+                    &c->pg_flags, &c->pg_status, &c->pg_mb, &c->pg_cost, &c->pg_blk_pq, &c->pg_blk_off,
+                    &c->pg_blk_src, &c->pg_pose_off, &c->pg_pose_src};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (Tiling& t : c->tl)
@@ -1552,6 +1571,121 @@ dpvba_status dpvba_reproject(dpvba_ctx* c, const dpvba_graph* g, const float* po
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(launch_reproject(poses, inv_depth, g->patches, g->patch_size, g->ii, g->jj, g->kk, g->n_edges, g->fx,
                            g->fy, g->cx, g->cy, z_min, coords, valid, (hipStream_t)stream));
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_pgo_sim3(dpvba_ctx* c, int32_t n_frames, int32_t n_fixed, const double* poses, int32_t n_loops,
+                            const int32_t* loop_j, const int32_t* loop_k, const double* loop_rel, int32_t n_iters,
+                            double lambda, uint32_t flags, double* sims, double* cost, void* stream) {
+  if (!c || n_frames < 1 || n_fixed < 0 || n_fixed > n_frames || n_loops < 0 || !poses || !sims) return DPVBA_EINVAL;
+  if (n_iters < 0 || n_iters > DPVBA_MAX_PGO_ITERS || !(lambda >= 0.0) || !(lambda < 1e300)) return DPVBA_EINVAL;
+  if (flags & ~DPVBA_FLAG_LEVENBERG) return DPVBA_EINVAL;
+  if (n_loops > 0 && (!loop_j || !loop_k || !loop_rel)) return DPVBA_EINVAL;
+  const int nf = n_frames - n_fixed;
+  if ((long long)nf * 7 > 20000) return DPVBA_EINVAL;  // the dense system must stay a few GB
+  for (int l = 0; l < n_loops; ++l)
+    if (loop_j[l] < 0 || loop_j[l] >= n_frames || loop_k[l] < 0 || loop_k[l] >= n_frames || loop_j[l] == loop_k[l])
+      return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  // residual list: the n - 1 smoothness terms, then the loops
+  const int E = n_frames - 1 + n_loops;
+  std::vector<int32_t> ea(std::max(E, 1)), eb(std::max(E, 1));
+  for (int e = 0; e < n_frames - 1; ++e) { ea[e] = e; eb[e] = e + 1; }
+  for (int l = 0; l < n_loops; ++l) { ea[n_frames - 1 + l] = loop_j[l]; eb[n_frames - 1 + l] = loop_k[l]; }
+  // block lists of the free poses' normal equations, contributions in residual order
+  std::map<std::pair<int, int>, std::vector<int32_t>> blocks;
+  std::vector<std::vector<int32_t>> pose_list(std::max(nf, 0));
+  for (int e = 0; e < E; ++e) {
+    const int fa = ea[e] - n_fixed, fb = eb[e] - n_fixed;
+    if (fa >= 0) { blocks[{fa, fa}].push_back(4 * e + 0); pose_list[fa].push_back(2 * e); }
+    if (fb >= 0) { blocks[{fb, fb}].push_back(4 * e + 3); pose_list[fb].push_back(2 * e + 1); }
+    if (fa >= 0 && fb >= 0) {
+      if (fa > fb) blocks[{fa, fb}].push_back(4 * e + 1);
+      else blocks[{fb, fa}].push_back(4 * e + 2);
+    }
+  }
+  std::vector<int32_t> blk_pq, blk_off{0}, blk_src, pose_off{0}, pose_src;
+  for (auto& kv : blocks) {
+    blk_pq.push_back(kv.first.first);
+    blk_pq.push_back(kv.first.second);
+    blk_src.insert(blk_src.end(), kv.second.begin(), kv.second.end());
+    blk_off.push_back((int32_t)blk_src.size());
+  }
+  for (auto& l : pose_list) {
+    pose_src.insert(pose_src.end(), l.begin(), l.end());
+    pose_off.push_back((int32_t)pose_src.size());
+  }
+  const size_t n = 7 * (size_t)nf, nblk64 = (n + 63) / 64;
+  HIP_TRY(upload(c->pg_ea, ea, st));
+  HIP_TRY(upload(c->pg_eb, eb, st));
+  HIP_TRY(upload(c->pg_blk_pq, blk_pq, st));
+  HIP_TRY(upload(c->pg_blk_off, blk_off, st));
+  HIP_TRY(upload(c->pg_blk_src, blk_src, st));
+  HIP_TRY(upload(c->pg_pose_off, pose_off, st));
+  HIP_TRY(upload(c->pg_pose_src, pose_src, st));
+  HIP_TRY(ensure(c->pg_C, (size_t)std::max(E, 1) * 13 * 8));
+  HIP_TRY(ensure(c->pg_r, (size_t)std::max(E, 1) * 7 * 8));
+  HIP_TRY(ensure(c->pg_J, (size_t)std::max(E, 1) * 7 * 14 * 8));
+  HIP_TRY(ensure(c->pg_H, std::max<size_t>(n * n, 1) * 8));
+  HIP_TRY(ensure(c->pg_rhs, std::max<size_t>(n, 1) * 8));
+  HIP_TRY(ensure(c->pg_dx, std::max<size_t>(n, 1) * 8));
+  HIP_TRY(ensure(c->pg_d0, std::max<size_t>(n, 1) * 8));
+  HIP_TRY(ensure(c->pg_wy, std::max<size_t>(n, 1) * 8));
+  HIP_TRY(ensure(c->pg_Linv, std::max<size_t>(nblk64, 1) * 64 * 64 * 8));
+  if (c->pg_flags.bytes < 2 * nblk64 * 4 + 16) {
+    HIP_TRY(ensure(c->pg_flags, 2 * nblk64 * 4 + 16));
+    HIP_TRY(hipMemsetAsync(c->pg_flags.p, 0, c->pg_flags.bytes, st));
+    c->pg_epoch = 0;
+  }
+  HIP_TRY(ensure(c->pg_status, (DPVBA_MAX_PGO_ITERS + 1) * 4));
+  HIP_TRY(ensure(c->pg_mb, (DPVBA_MAX_PGO_ITERS + 1) * 4));
+  HIP_TRY(ensure(c->pg_cost, (DPVBA_MAX_PGO_ITERS + 1) * 8));
+  int* status = (int*)c->pg_status.p;
+  double* costd = (double*)c->pg_cost.p;
+  double* H = (double*)c->pg_H.p;
+  const double lam_diag = (flags & DPVBA_FLAG_LEVENBERG) ? 0.0 : lambda;
+  int* err = large_err(c);
+  HIP_TRY(launch_report_init(status, (unsigned int*)c->pg_mb.p, DPVBA_MAX_PGO_ITERS + 1, st, err));
+  HIP_TRY(launch_pgo_init(poses, n_frames, sims, loop_rel, n_loops, (double*)c->pg_C.p, st));
+  for (int it = 0; it < n_iters; ++it) {
+    HIP_TRY(launch_pgo_linearise(sims, (const double*)c->pg_C.p, (const int*)c->pg_ea.p, (const int*)c->pg_eb.p, E,
+                                 (double*)c->pg_r.p, (double*)c->pg_J.p, costd + it, st));
+    if (nf == 0) continue;
+    HIP_TRY(launch_fill<double>(H, (long long)(n * n), 0.0, st));
+    HIP_TRY(launch_pgo_normal((const double*)c->pg_J.p, (const double*)c->pg_r.p, (const int*)c->pg_blk_pq.p,
+                              (const int*)c->pg_blk_off.p, (const int*)c->pg_blk_src.p, (int)blocks.size(),
+                              (const int*)c->pg_pose_off.p, (const int*)c->pg_pose_src.p, nf, lambda, lam_diag, H,
+                              (double*)c->pg_d0.p, (double*)c->pg_rhs.p, st));
+    c->pg_epoch = c->pg_epoch >= 0x3fffffff ? 1 : c->pg_epoch + 1;
+    HIP_TRY(launch_chol_solve<double>(H, (const double*)c->pg_rhs.p, (int)n, (double*)c->pg_dx.p,
+                                      (double*)c->pg_wy.p, (double*)c->pg_Linv.p, (const double*)c->pg_d0.p,
+                                      status + it, (unsigned int*)c->pg_mb.p + it, (int*)c->pg_flags.p, c->pg_epoch,
+                                      err, c->host_err_dev, st, c->coop_launch));
+    HIP_TRY(launch_pgo_retract(sims, n_frames, n_fixed, (const double*)c->pg_dx.p, status + it, st));
+  }
+  HIP_TRY(launch_pgo_linearise(sims, (const double*)c->pg_C.p, (const int*)c->pg_ea.p, (const int*)c->pg_eb.p, E,
+                               (double*)c->pg_r.p, (double*)c->pg_J.p, costd + n_iters, st));
+  std::vector<int32_t> hs(DPVBA_MAX_PGO_ITERS + 1);
+  std::vector<double> hc(DPVBA_MAX_PGO_ITERS + 1);
+  HIP_TRY(hipMemcpyAsync(hs.data(), status, hs.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hc.data(), costd, hc.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (cost)
+    for (int it = 0; it <= n_iters; ++it) cost[it] = hc[it];
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
+  for (int it = 0; it < n_iters; ++it)
+    if (hs[it]) return DPVBA_ENOTPD;
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_pgo_apply(dpvba_ctx* c, int32_t n_frames, const double* sims, const int32_t* patch_off,
+                             float* poses, float* inv_depth, void* stream) {
+  if (!c || n_frames < 0 || (n_frames > 0 && (!sims || !patch_off || !poses || !inv_depth))) return DPVBA_EINVAL;
+  if (recorded_failure(c)) return DPVBA_EDEVICE;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(launch_pgo_apply(sims, n_frames, patch_off, poses, inv_depth, (hipStream_t)stream));
   return DPVBA_OK;
 }
 

@@ -1,4 +1,5 @@
-// Forward-mode dual numbers a + b eps (eps^2 = 0) for the adjoint kernels.
+// Forward-mode dual numbers a + b eps (eps^2 = 0) for the adjoint kernels
+// and the Jacobians of the pose-graph residuals.
 //
 // Evaluating a function on Dual<S> arguments seeded with one unit tangent
 // returns its value and its directional derivative along that tangent.  The
@@ -47,7 +48,22 @@ struct Dual {
   }
   friend __device__ __forceinline__ Dual sin(const Dual& a) { return {::sin(a.v), ::cos(a.v) * a.d}; }
   friend __device__ __forceinline__ Dual cos(const Dual& a) { return {::cos(a.v), -::sin(a.v) * a.d}; }
+  friend __device__ __forceinline__ Dual exp(const Dual& a) {
+    const S e = ::exp(a.v);
+    return {e, e * a.d};
+  }
+  friend __device__ __forceinline__ Dual log(const Dual& a) { return {::log(a.v), a.d / a.v}; }
+  friend __device__ __forceinline__ Dual atan2(const Dual& y, const Dual& x) {
+    const S r2 = x.v * x.v + y.v * y.v;
+    return {::atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / r2};
+  }
 };
+
+// Value part of a plain or dual scalar (for decisions taken on values).
+__device__ __forceinline__ double value_of(double x) { return x; }
+__device__ __forceinline__ float value_of(float x) { return x; }
+template <typename S>
+__device__ __forceinline__ S value_of(const Dual<S>& x) { return x.v; }
 
 template <typename S>
 struct ExpSeries<Dual<S>> {

@@ -1,0 +1,111 @@
+"""Sim(3) pose-graph optimisation on the GPU (dpvba_pgo_sim3 /
+dpvba_pgo_apply) against the float64 oracle (oracle/sim3_pgo.py).  Both
+sides compute in float64 with exact Jacobians (dual numbers on the GPU,
+autograd in the oracle); the similarities are compared by translation,
+rotation angle and scale at 1e-9, the costs at 1e-9 relative."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sim3_pgo as P
+from scenes.posegraph import loop_problem
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import paper_2408_01654_amd as dp
+    return dp
+
+
+@pytest.fixture(scope="module")
+def ctx(dp):
+    c = dp.Context(0)
+    yield c
+    c.close()
+
+
+def _compare(sims, want):
+    R1 = P.quat_to_rot(torch.as_tensor(sims[:, 3:7])).numpy()
+    R2 = P.quat_to_rot(torch.as_tensor(want[:, 3:7])).numpy()
+    dr = np.linalg.norm(P.so3_log(torch.as_tensor(np.swapaxes(R1, 1, 2) @ R2)).numpy(), axis=1).max()
+    dt = np.abs(sims[:, :3] - want[:, :3]).max()
+    ds = np.abs(sims[:, 7] - want[:, 7]).max()
+    return float(dt), float(dr), float(ds)
+
+
+CASES = [
+    ("loop40", dict(n=40, loops=((2, 30), (5, 36), (10, 38))), 6, 1e-4, False),
+    ("loop200", dict(n=200, seed=3, drift=0.08), 8, 1e-4, False),
+    ("levenberg", dict(n=60, seed=5), 5, 1e-3, True),
+    ("no_loops", dict(n=30, loops=()), 3, 1e-4, False),
+]
+
+
+@pytest.mark.parametrize("name,kw,iters,lam,lev", CASES, ids=[c[0] for c in CASES])
+def test_pgo_matches_oracle(dp, ctx, name, kw, iters, lam, lev):
+    p0, pg, lj, lk, lr = loop_problem(**kw)
+    print(f"pgo {name}: N={len(p0)} loops={len(lj)} iters={iters} lam={lam} levenberg={lev}", flush=True)
+    want, costs_o = (P.optimise(p0, lj, lk, lr, n_iters=iters, lam=lam) if not lev else
+                     _optimise_levenberg(p0, lj, lk, lr, iters, lam))
+    sims, costs = ctx.pgo_sim3(torch.as_tensor(p0).cuda(), lj, lk,
+                               torch.as_tensor(lr).cuda() if len(lj) else None, n_iters=iters, lam=lam,
+                               levenberg=lev)
+    got = sims.cpu().numpy()
+    dt, dr, ds = _compare(got, want)
+    rel = max(abs(a - b) / max(abs(b), 1e-300) for a, b in zip(costs, costs_o))
+    print(f"  dt {dt:.2e} dr {dr:.2e} ds {ds:.2e} cost rel {rel:.2e} costs {costs[0]:.3e} -> {costs[-1]:.3e}",
+          flush=True)
+    assert max(dt, dr, ds) < TOL
+    assert all(abs(a - b) <= TOL * max(abs(b), 1e-12) + 1e-25 for a, b in zip(costs, costs_o))
+
+
+def _optimise_levenberg(p0, lj, lk, lr, iters, lam):
+    """The oracle's iteration with H + lambda I (the flag's damping)."""
+    S = P.from_poses(p0)
+    n = len(p0)
+    a, b = P.edge_list(n, lj, lk)
+    C = P.edge_constants(S, lr)
+    costs = []
+    for _ in range(iters):
+        r, Ja, Jb = P.edge_jacobians(S, C, a, b)
+        costs.append(float((r * r).sum()))
+        H = np.zeros((7 * n, 7 * n))
+        g = np.zeros(7 * n)
+        for e in range(len(a)):
+            for p, Jp in ((a[e], Ja[e].numpy()), (b[e], Jb[e].numpy())):
+                g[7 * p:7 * p + 7] += Jp.T @ r[e].numpy()
+                for q, Jq in ((a[e], Ja[e].numpy()), (b[e], Jb[e].numpy())):
+                    H[7 * p:7 * p + 7, 7 * q:7 * q + 7] += Jp.T @ Jq
+        H, g = H[7:, 7:], g[7:]
+        step = -np.linalg.solve(H + lam * np.eye(H.shape[0]), g)
+        S = tuple(x.detach() for x in P.retract(S, torch.cat([torch.zeros(1, 7, dtype=torch.float64),
+                                                              torch.as_tensor(step.reshape(n - 1, 7))], 0)))
+    costs.append(P.cost(S, C, a, b))
+    return P.to_array(S), costs
+
+
+def test_pgo_apply(dp, ctx):
+    p0, pg, lj, lk, lr = loop_problem(n=25, seed=7)
+    sims, _ = ctx.pgo_sim3(torch.as_tensor(p0).cuda(), lj, lk, torch.as_tensor(lr).cuda(), n_iters=4)
+    rng = np.random.default_rng(2)
+    counts = rng.integers(0, 6, size=25)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    owner = np.repeat(np.arange(25), counts)
+    d = rng.uniform(0.2, 2.0, size=int(off[-1])).astype(np.float32)
+    poses = torch.as_tensor(p0.astype(np.float32)).cuda()
+    depth = torch.as_tensor(d).cuda()
+    ctx.pgo_apply(sims, torch.as_tensor(off).cuda(), poses, depth)
+    Pw, Dw = P.apply_to_ba(sims.cpu().numpy(), p0, d.astype(np.float64), owner)
+    assert np.array_equal(poses.cpu().numpy(), Pw.astype(np.float32))
+    np.testing.assert_allclose(depth.cpu().numpy(), Dw, rtol=1e-6)
+
+
+def test_pgo_rejects_bad_loops(dp, ctx):
+    p0, _, _, _, _ = loop_problem(n=10, loops=())
+    lr = torch.zeros((1, 8), dtype=torch.float64).cuda()
+    for j, k in ((3, 3), (-1, 4), (2, 10)):
+        with pytest.raises(dp.DpvbaError):
+            ctx.pgo_sim3(torch.as_tensor(p0).cuda(), [j], [k], lr, n_iters=1)
