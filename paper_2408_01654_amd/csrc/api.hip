@@ -176,6 +176,12 @@ namespace {
 // Shared-memory budget of one tile, and default patches per tile for the
 // float32 and float64 plans.
 constexpr int kLdsBudget = 150 * 1024;
+// Tiles of the multi-launch path (systems beyond the single-launch solver)
+// are planned to fit two float32 workgroups per CU (160 KiB of LDS): more
+// tiles, but two of them in flight per CU hide each other's dependent
+// phases.  The single-launch solver keeps one workgroup per CU anyway and
+// prefers fewer, larger tiles.
+constexpr int kLdsBudgetTwoPerCu = 80 * 1024;
 constexpr int kDefaultTilePatches32 = 96;
 constexpr int kDefaultTilePatches64 = 32;
 // Largest reduced system of one problem of a batch (its workgroup keeps the
@@ -612,7 +618,7 @@ static bool index_problem(int N, int P, int E, const int32_t* ii, const int32_t*
 // the gather lists.  Returns false if one patch alone does not fit.
 static bool plan_tiling(int N, int nf, const std::vector<int32_t>& jj, const std::vector<int32_t>& pcount,
                         const std::vector<int32_t>& pedges, const std::vector<std::vector<int32_t>>& frame_patches,
-                        int kcap, int tsize, HostTiling& H) {
+                        int kcap, int tsize, HostTiling& H, int lds_budget = kLdsBudget) {
   const int n_free = N - nf;
   auto patch_mult = [&](int k, std::map<int, int>& m) {
     for (int q = pcount[k]; q < pcount[k + 1]; ++q) m[jj[pedges[q]]]++;
@@ -695,7 +701,7 @@ static bool plan_tiling(int N, int nf, const std::vector<int32_t>& jj, const std
       int Tn, nb, mm;
       plan_of(merged, f, Tn, nb, mm);
       const bool fits = Tn <= kMaxSlots && (int)cur.size() + 1 <= kcap &&
-                        tile_lds_bytes((int)cur.size() + 1, Tn, nb, tsize) <= kLdsBudget;
+                        tile_lds_bytes((int)cur.size() + 1, Tn, nb, tsize) <= lds_budget;
       if (!fits) {
         if (cur.empty()) return false;
         emit(f, cur, cur_mult);
@@ -703,7 +709,7 @@ static bool plan_tiling(int N, int nf, const std::vector<int32_t>& jj, const std
         cur_mult.clear();
         merged = km;
         plan_of(merged, f, Tn, nb, mm);
-        if (!(Tn <= kMaxSlots && tile_lds_bytes(1, Tn, nb, tsize) <= kLdsBudget)) return false;
+        if (!(Tn <= kMaxSlots && tile_lds_bytes(1, Tn, nb, tsize) <= lds_budget)) return false;
       }
       cur.push_back(k);
       cur_mult = merged;
@@ -799,7 +805,10 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   const std::vector<int32_t>& pedges = X.pedges;
   const std::vector<std::vector<int32_t>>& frame_patches = X.frame_patches;
   HostTiling H32, H64;
-  if (!plan_tiling(N, nf, jj, pcount, pedges, frame_patches, kcap32, 4, H32)) return DPVBA_EINVAL;
+  const bool single_launch = 6 * (long long)n_free + 1 <= kSmallRows;
+  if (!plan_tiling(N, nf, jj, pcount, pedges, frame_patches, kcap32, 4, H32,
+                   single_launch ? kLdsBudget : kLdsBudgetTwoPerCu))
+    return DPVBA_EINVAL;
   if (!plan_tiling(N, nf, jj, pcount, pedges, frame_patches, kcap64, 8, H64)) return DPVBA_EINVAL;
   HIP_TRY(upload_tiling(c->tl[0], H32, st));
   HIP_TRY(upload_tiling(c->tl[1], H64, st));

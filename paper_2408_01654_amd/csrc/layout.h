@@ -64,7 +64,7 @@ __host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 // Schur-row matrix U (K_pad x W_pad, rows = patches, columns = 6 n_blk
 // block columns plus one column for w / sqrt(C~), padded for 16x16x4
 // matrix-core tiles; rows 16-byte aligned), which first holds the
-// per-thread partial sums.  Then a byte region of per-cell records (target,
+// wavefronts' per-slot partial sums.  Then a byte region of per-cell records (target,
 // weight) that each lane overwrites with its edge's results, later reused
 // for per-slot source blocks and their sums (and in phase 0 for the block
 // step).  Then the block -> slot range tables.
@@ -108,7 +108,7 @@ __host__ __device__ inline TileLds tile_lds_plan(int K, int Tn, int nb, int tsiz
   L.psum = L.hp + (tsize == 4 ? Tn * 24 + K * 4 : 0);
   L.m = L.psum + K * 8;
   L.u = round_up(L.m + Tn * kRedWidth, 4);
-  L.total_T = L.u + imax(L.K_pad * L.W_pad, nthreads * kRedWidth);
+  L.total_T = L.u + imax(L.K_pad * L.W_pad, (nthreads / 64) * Tn * kRedWidth);  // U, or the wavefronts' slot partials
   L.cell_bytes = imax(16, 8 * tsize);
   L.rec_bytes = imax(K * Tn * L.cell_bytes, imax(Tn * kSlotBlk + kSrcSums + tile_bterm_entries(nb), L.W_pad) * tsize);
   L.blk_s0 = 0;

@@ -307,16 +307,43 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
     }
   }
   if (n_invalid) atomicAdd(&sInvalid, n_invalid);
+  // per-slot partials within each wavefront: lanes l, l + Tn, l + 2 Tn, ...
+  // hold the same slot, so a tree over offsets Tn, 2 Tn, 4 Tn leaves the
+  // wavefront's total of each slot on its first Tn lanes (partners past the
+  // last thread group, or past the wavefront, add nothing)
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    const int valid_lanes = min(64, G * Tn - 64 * wv);  // lanes of this wavefront holding a thread group
+    for (int off = Tn; off < 64; off <<= 1) {
+      const bool take = lane + off < valid_lanes;
 #pragma unroll
-  for (int m = 0; m < kRedWidth; ++m) sWork[tid * kRedWidth + m] = acc[m];
+      for (int m = 0; m < kRedWidth; ++m) {
+        const T o = __shfl(acc[m], min(lane + off, 63));
+        acc[m] += take ? o : (T)0;
+      }
+    }
+    if (lane < Tn && lane < valid_lanes) {
+      const int ss = (64 * wv + lane) % Tn;
+#pragma unroll
+      for (int m = 0; m < kRedWidth; ++m) sWork[(wv * Tn + ss) * kRedWidth + m] = acc[m];
+    }
+  }
   __syncthreads();
 
-  // ---- phase 2a: per-slot totals, thread groups summed in order
-  for (int idx = tid; idx < Tn * kRedWidth; idx += blockDim.x) {
-    const int ss = idx / kRedWidth, m = idx % kRedWidth;
-    T v = (T)0;
-    for (int gg = 0; gg < G; ++gg) v += sWork[(gg * Tn + ss) * kRedWidth + m];
-    sM[ss * kRedWidth + m] = v;
+  // ---- phase 2a: per-slot totals, the wavefronts' partials summed in order
+  {
+    const int nwv = (G * Tn + 63) / 64;  // wavefronts holding thread groups
+    for (int idx = tid; idx < Tn * kRedWidth; idx += blockDim.x) {
+      const int ss = idx / kRedWidth, m = idx % kRedWidth;
+      T v = (T)0;
+      for (int w = 0; w < nwv; ++w) {
+        // slot ss appears among the first Tn lanes of wavefront w unless the
+        // wavefront holds fewer lanes than that
+        const int first = (ss - (64 * w) % Tn + Tn) % Tn;  // its first lane in wavefront w
+        if (first < min(64, G * Tn - 64 * w)) v += sWork[(w * Tn + ss) * kRedWidth + m];
+      }
+      sM[ss * kRedWidth + m] = v;
+    }
   }
   __syncthreads();
 
