@@ -123,137 +123,125 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
 
 // ------------------------------------------------------------------ large path
 
-// Factor the diagonal block at k0 (kb <= 64), write L back, and write
+// Factor the diagonal block at k0 (kb <= 64), write L back to S, and write
 // inv(L_kk) (lower, kb x kb, stride 64, zeros above the diagonal) to Linv.
 // The block is factored together with an identity appended below it: the
 // Cholesky factor of [[A, I], [I, .]] has L^-T in its lower-left block, so
-// one elimination gives both L and its inverse.  The 128 x 64 working matrix
-// lives in registers on a 16 x 16 thread grid (entry (16 bi + ty, 16 bk + tx)
-// on thread (ty, tx) = (tid mod 16, tid / 16); the panel loop is unrolled, so
-// every register index is a compile-time constant).  Columns go in panels
-// of 16: the threads publish the panel's column block in LDS (P0 / P1, 128 x
-// 17 each, alternating); one wavefront factors its 16 columns alone (rows on
-// lanes, pivots and column entries broadcast by v_readlane); after one
-// barrier every thread takes back its factored entries and applies the
-// rank-16 update to its blocks right of and below the panel.  Entries above
-// the diagonal of the A part are never read as results.
+// one elimination gives both L and its inverse.  The 128 x 64 working
+// matrix W (rows 0..63 the block, rows 64..127 the identity, row stride
+// kWld) lives in LDS, filled by the caller (fill_diag_w): the block's lower
+// triangle in rows and columns below kb, zeros elsewhere, and ones on the
+// diagonal of the padding (rows kb..63) and of the identity, so that every
+// panel takes all of its columns without a branch (the padding is never
+// stored).  Columns go in panels of 16 (p = 0..3, a
+// loop, not unrolled: the code is run once per launch and has to come into
+// the instruction cache every time):
+//   1. wavefront 0 factors the panel: lane l holds row l mod 16 of the
+//      16 x 16 diagonal block (ra: each 16-lane row of the wavefront a full
+//      copy) and one row of the panel below it (rb: lane row q takes row
+//      block q of the four that can be non-zero -- the A rows of the later
+//      blocks, the identity rows of the earlier panels and of this one; the
+//      identity rows of later panels are still zero in this column block).
+//      Column entries travel by the DPP row broadcast, a vector-register
+//      move within each 16-lane row, so the chain of 16 pivots takes no
+//      scalar registers and no barrier; the panel is written back;
+//   2. after one barrier, the four wavefronts apply the rank-16 update to
+//      the 16 x 16 blocks right of the panel whose rows can be non-zero,
+//      one matrix-core product per block, and all threads store the
+//      finished column block (its writes overlap the later panels); a
+//      second barrier closes the panel.
+// ddv: this thread's entry of the damped diagonal (thread t < kb: column
+// t), for the pivot report.  Entries above the diagonal of the A part are
+// never read as results.
+constexpr int kWld = kNB + 1;
+
 template <typename T>
-__device__ __forceinline__ void diag_factor(T* S, int n, int k0, int kb_in, T* Linv, const T* d0, int* status,
-                                            unsigned int* min_bits, T* P0, T* P1) {
-  constexpr int RB = 8, CB = 4;  // 128 rows, 64 columns
+__device__ __forceinline__ void diag_factor(T* W, T* S, int n, int k0, int kb_in, T* Linv, T ddv, int* status,
+                                            unsigned int* min_bits) {
   __shared__ T piv[kNB];
   __shared__ T dd[kNB];
   __shared__ int bad_s;
   __shared__ unsigned int minr_s;
   const int kb = __builtin_amdgcn_readfirstlane(kb_in);
   const int tid = threadIdx.x;
-  const int ty = tid & 15, tx = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
   if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }
-  if (tid < kb) dd[tid] = d0[k0 + tid];
-  T a[RB][CB];
-#pragma unroll
-  for (int bi = 0; bi < RB; ++bi)
-#pragma unroll
-    for (int bk = 0; bk < CB; ++bk) {
-      const int i = 16 * bi + ty, k = 16 * bk + tx;
-      T v = (T)0;
-      if (i < kNB) {
-        if (i < kb && k <= i) v = S[(size_t)(k0 + i) * n + k0 + k];
-      } else if (i - kNB == k && k < kb) {
-        v = (T)1;
-      }
-      a[bi][bk] = v;
-    }
+  if (tid < kb) dd[tid] = ddv;
   int bad = 0;
-#pragma unroll
-  for (int p = 0; p < CB; ++p) {
-    if (16 * p >= kb) continue;  // uniform
-    T* P = (p & 1) ? P1 : P0;
-#pragma unroll
-    for (int bi = p; bi < RB; ++bi) P[(16 * bi + ty) * 17 + tx] = a[bi][p];
-    __syncthreads();
-    if (wave == (p & 3)) {
-      // lane l holds rows 16 p + l and 16 p + l + 64 of the panel
-      const int rA = 16 * p + lane, rB = rA + 64;
+  for (int p = 0; 16 * p < kb; ++p) {
+    const int c0 = 16 * p;
+    // 1. the panel on wavefront 0
+    if (wave == 0) {
+      const int s = lane & 15, q = lane >> 4;
+      // row block of rb: the A blocks p + 1 .. 3, then the identity blocks 4 .. 4 + p
+      const int bq = q < 3 - p ? p + 1 + q : 4 + (q - (3 - p));
+      T* wa = W + (c0 + s) * kWld + c0;
+      T* wb = W + (16 * bq + s) * kWld + c0;
       T ra[16], rb[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        ra[c] = P[rA * 17 + c];
-        rb[c] = rB < 16 * RB ? P[rB * 17 + c] : (T)0;
+        ra[c] = wa[c];
+        rb[c] = wb[c];
       }
+      T dpiv = (T)0;  // lane c: the pivot of column c
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        const int j = 16 * p + c;
-        if (j >= kb) continue;  // uniform
-        T d;
-        if constexpr (sizeof(T) == 4) {
-          d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ra[c]), c));
-        } else {
-          const long long bits = __double_as_longlong(ra[c]);
-          const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), c);
-          const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), c);
-          d = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-        }
-        if (lane == 0) piv[j] = d;
-        if (!(d > (T)0) || !(d < (T)3.0e38)) {
-          bad = 1;
-          d = (T)1;
-        }
-        const T rs = pivot_rsqrt<T>(d);
+        const T d = row_bcast(ra[c], c);
+        dpiv = s == c ? d : dpiv;
+        const bool ok = d > (T)0 && d < (T)3.0e38;
+        bad |= !ok;
+        const T rs = ok ? pivot_rsqrt<T>(d) : (T)1;
         ra[c] *= rs;
         rb[c] *= rs;
 #pragma unroll
         for (int c2 = c + 1; c2 < 16; ++c2) {
-          T lk;  // entry (16 p + c2, j): lane c2's entry of column c
-          if constexpr (sizeof(T) == 4) {
-            lk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ra[c]), c2));
-          } else {
-            const long long bits = __double_as_longlong(ra[c]);
-            const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), c2);
-            const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), c2);
-            lk = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-          }
-          ra[c2] -= ra[c] * lk;
-          rb[c2] -= rb[c] * lk;
+          const T l = row_bcast(ra[c], c2);  // L(c0 + c2, c0 + c)
+          ra[c2] -= ra[c] * l;
+          rb[c2] -= rb[c] * l;
         }
       }
+      if (q == 0) {
+        piv[c0 + s] = dpiv;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        P[rA * 17 + c] = ra[c];
-        if (rB < 16 * RB) P[rB * 17 + c] = rb[c];
+        for (int c = 0; c < 16; ++c) wa[c] = ra[c];
       }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) wb[c] = rb[c];
     }
     __syncthreads();
+    // 2. rank-16 update right of the panel on the matrix cores: the 16 x 16
+    // blocks (bi, bk), bk = p + 1 .. 3, bi = bk .. 4 + p (bk-major), go to
+    // the wavefronts in turn; W_(bi,bk) -= W_(bi,p) W_(bk,p)^T
+    {
+      const int count = p == 0 ? 9 : p == 1 ? 7 : p == 2 ? 4 : 0;
+      for (int q = wave; q < count; q += 4) {
+        int bk = p + 1, rem = q;
+        while (rem >= 5 + p - bk) {
+          rem -= 5 + p - bk;
+          ++bk;
+        }
+        const int bi = bk + rem;
+        const T* xr = W + (16 * bi + (lane & 15)) * kWld + c0 + (lane >> 4);
+        const T* yr = W + (16 * bk + (lane & 15)) * kWld + c0 + (lane >> 4);
+        typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int bi = p; bi < RB; ++bi) a[bi][p] = P[(16 * bi + ty) * 17 + tx];
+        for (int k = 0; k < 16; k += 4) acc = Mfma<T>::step(xr[k], yr[k], acc);
 #pragma unroll
-    for (int bk = p + 1; bk < CB; ++bk) {
-      T lk[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) lk[c] = P[(16 * bk + tx) * 17 + c];
-#pragma unroll
-      for (int bi = bk; bi < RB; ++bi) {
-        T acc = (T)0;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) acc += P[(16 * bi + ty) * 17 + c] * lk[c];
-        a[bi][bk] -= acc;
+        for (int v = 0; v < 4; ++v) W[(16 * bi + Mfma<T>::row(lane, v)) * kWld + 16 * bk + (lane & 15)] -= acc[v];
       }
     }
+    // the column block is final: L rows c0 .. kb - 1, and columns c0 .. c0 + 15
+    // of L^-1 (rows of Linv), zeros above its diagonal
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u, r = e >> 4, c = c0 + (e & 15);
+      if (r < kb && c <= r) S[(size_t)(k0 + r) * n + k0 + c] = W[r * kWld + c];
+      const int kr = c0 + (e >> 6), rr = e & 63;  // Linv row kr, column rr
+      if (kr < kb && rr < kb) Linv[kr * kNB + rr] = kr >= rr ? W[(kNB + rr) * kWld + kr] : (T)0;
+    }
+    __syncthreads();
   }
-#pragma unroll
-  for (int bi = 0; bi < RB; ++bi)
-#pragma unroll
-    for (int bk = 0; bk < CB; ++bk) {
-      const int i = 16 * bi + ty, k = 16 * bk + tx;
-      if (i < kNB) {
-        if (i < kb && k <= i) S[(size_t)(k0 + i) * n + k0 + k] = a[bi][bk];
-      } else {
-        const int r = i - kNB;  // row r of L^-T = column r of L^-1
-        if (r < kb && k < kb) Linv[k * kNB + r] = (k >= r) ? a[bi][bk] : (T)0;
-      }
-    }
-  if (bad) atomicOr(&bad_s, 1);
+  if (wave == 0 && bad) atomicOr(&bad_s, 1);
   pivot_ratio_min<T>(piv, dd, kb, &minr_s);  // pivot report: smallest pivot / damped diagonal
   __syncthreads();
   if (tid == 0) {
@@ -262,11 +250,42 @@ __device__ __forceinline__ void diag_factor(T* S, int n, int k0, int kb_in, T* L
   }
 }
 
+// Entry (i, c), i < 64, of diag_factor's working matrix, given the block's
+// entry a (only read for i < kb, c <= i).
+template <typename T>
+__device__ __forceinline__ T diag_w_entry(int i, int c, int kb, T a) {
+  return (i < kb && c <= i) ? a : (T)(i == c && i >= kb ? 1 : 0);
+}
+
+// The identity half of W (rows 64..127); every thread of the workgroup.
+template <typename T>
+__device__ __forceinline__ void fill_diag_identity(T* W) {
+  const int r = threadIdx.x >> 2, c0 = 16 * (threadIdx.x & 3);
+  T* w = W + (kNB + r) * kWld + c0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) w[c] = (T)(c0 + c == r ? 1 : 0);
+}
+
+// W from the kb x kb block of S at (k0, k0) (its lower triangle).
+template <typename T>
+__device__ __forceinline__ void fill_diag_w(const T* S, int n, int k0, int kb, T* W) {
+  for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
+    const int i = e >> 6, c = e & 63;
+    T a = (T)0;
+    if (i < kb && c <= i) a = S[(size_t)(k0 + i) * n + k0 + c];
+    W[i * kWld + c] = diag_w_entry<T>(i, c, kb, a);
+  }
+  fill_diag_identity<T>(W);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, int kb, T* Linv, const T* d0,
                                                          int* status, unsigned int* min_bits) {
-  __shared__ T P[2][128 * 17];
-  diag_factor<T>(S, n, k0, kb, Linv, d0, status, min_bits, P[0], P[1]);
+  __shared__ T W[2 * kNB * kWld];
+  const T ddv = threadIdx.x < kb ? d0[k0 + threadIdx.x] : (T)0;
+  fill_diag_w<T>(S, n, k0, kb, W);
+  __syncthreads();
+  diag_factor<T>(W, S, n, k0, kb, Linv, ddv, status, min_bits);
 }
 
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
@@ -303,8 +322,9 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int nrows,
 template <typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
 syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* status, unsigned int* min_bits) {
-  __shared__ T Li[kNB][kNB + 1];
-  __shared__ T Lj[kNB][kNB + 1];
+  __shared__ T Lij[2][kNB][kNB + 1];  // contiguous: the look-ahead's W after the update
+  T (*Li)[kNB + 1] = Lij[0];
+  T (*Lj)[kNB + 1] = Lij[1];
   const int t0 = k0 + kb;
   const int blk = blockIdx.x;
   int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
@@ -334,7 +354,11 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
   if (blk == 0 && Linv_next) {
     __threadfence_block();
     __syncthreads();  // also frees Li and Lj for the factor's panels
-    diag_factor<T>(S, n, t0, ri, Linv_next, d0, status, min_bits, &Li[0][0], &Lj[0][0]);
+    const T ddv = tid < ri ? d0[t0 + tid] : (T)0;
+    T* W = &Lij[0][0][0];
+    fill_diag_w<T>(S, n, t0, ri, W);
+    __syncthreads();
+    diag_factor<T>(W, S, n, t0, ri, Linv_next, ddv, status, min_bits);
   }
 }
 
@@ -356,9 +380,13 @@ constexpr int kTB = 128;
 constexpr int kPanLd = 68;   // LDS row stride of the staged panel rows
 constexpr int kOutLd = 132;  // LDS row stride of the staged products
 constexpr int kSyrk128Lds = 2 * kTB * kPanLd * 4;
+static_assert(kTB * kPanLd >= 2 * kNB * kWld, "diagonal factor working matrix in the first panel region");
 
-__global__ void __launch_bounds__(256) syrk128_kernel(float* S, int n, int nrows, int k0, int kb, float* Linv_next,
-                                                      const float* d0, int* status, unsigned int* min_bits) {
+// Two wavefronts per SIMD (at most 256 registers), so two workgroups share a
+// CU although workgroup 0 also runs the register-heavy diagonal factor.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+syrk128_kernel(float* S, int n, int nrows, int k0, int kb, float* Linv_next, const float* d0, int* status,
+               unsigned int* min_bits) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   typedef float f2 __attribute__((ext_vector_type(2)));
   float* Pi = reinterpret_cast<float*>(dyn_lds);
@@ -367,9 +395,19 @@ __global__ void __launch_bounds__(256) syrk128_kernel(float* S, int n, int nrows
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const bool look = Linv_next != nullptr;
   if (look && blockIdx.x == 0) {
-    // next diagonal block: A_kk -= L_k L_k^T (64 x 64), then its factor
-    float (*Lk)[kNB + 1] = reinterpret_cast<float (*)[kNB + 1]>(Pi);
+    // next diagonal block: A_kk - L_k L_k^T (64 x 64) into W, then its factor
+    float* W = Pi;
+    float (*Lk)[kNB + 1] = reinterpret_cast<float (*)[kNB + 1]>(Pj);
     const int rb = min(kNB, n - t0);
+    const float ddv = tid < rb ? d0[t0 + tid] : 0.f;
+    float sv[4][4];  // the block's entries at this lane's product positions
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + Mfma<float>::row(lane, v), c = 16 * t + (lane & 15);
+        sv[t][v] = (r < rb && c <= r) ? S[(size_t)(t0 + r) * n + t0 + c] : 0.f;
+      }
     load_block64<float>(S + (size_t)t0 * n + k0, (size_t)n, rb, kb, Lk);
     __syncthreads();
     floatx4_t acc[4];
@@ -381,11 +419,11 @@ __global__ void __launch_bounds__(256) syrk128_kernel(float* S, int n, int nrows
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * w + Mfma<float>::row(lane, v), c = 16 * t + (lane & 15);
-        if (r < rb && c <= r) S[(size_t)(t0 + r) * n + t0 + c] -= acc[t][v];
+        W[r * kWld + c] = diag_w_entry<float>(r, c, rb, sv[t][v] - acc[t][v]);
       }
-    __threadfence_block();
+    fill_diag_identity<float>(W);
     __syncthreads();
-    diag_factor<float>(S, n, t0, rb, Linv_next, d0, status, min_bits, Pi, Pi + kTB * 17);
+    diag_factor<float>(W, S, n, t0, rb, Linv_next, ddv, status, min_bits);
     return;
   }
   const int Tc = (n - t0 + kTB - 1) / kTB;

@@ -593,6 +593,45 @@ __device__ __forceinline__ void panel_chol_solve(int n_in, const T* Sp_g, const 
 // Packed systems of up to 255 unknowns on one workgroup of 256 threads or
 // more: blocked factor and wavefront substitutions.
 
+// Value of v on lane c of each 16-lane row, for every lane of that row
+// (the DPP row broadcast of CDNA; c must fold to a constant).  The result
+// stays in a vector register: no scalar register, no readlane hazard.
+template <int C>
+__device__ __forceinline__ int row_bcast_bits(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + C, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int row_bcast_i(int v, int c) {
+  switch (c) {
+    case 0: return row_bcast_bits<0>(v);
+    case 1: return row_bcast_bits<1>(v);
+    case 2: return row_bcast_bits<2>(v);
+    case 3: return row_bcast_bits<3>(v);
+    case 4: return row_bcast_bits<4>(v);
+    case 5: return row_bcast_bits<5>(v);
+    case 6: return row_bcast_bits<6>(v);
+    case 7: return row_bcast_bits<7>(v);
+    case 8: return row_bcast_bits<8>(v);
+    case 9: return row_bcast_bits<9>(v);
+    case 10: return row_bcast_bits<10>(v);
+    case 11: return row_bcast_bits<11>(v);
+    case 12: return row_bcast_bits<12>(v);
+    case 13: return row_bcast_bits<13>(v);
+    case 14: return row_bcast_bits<14>(v);
+    default: return row_bcast_bits<15>(v);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T row_bcast(T v, int c) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(row_bcast_i(__float_as_int(v), c));
+  } else {
+    const long long bits = __double_as_longlong(v);
+    const int lo = row_bcast_i((int)(bits & 0xffffffffLL), c);
+    const int hi = row_bcast_i((int)(bits >> 32), c);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+
 // Value of v on lane l (uniform) of the wavefront.
 template <typename T>
 __device__ __forceinline__ T lane_bcast(T v, int l) {
