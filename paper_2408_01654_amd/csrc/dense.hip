@@ -552,7 +552,9 @@ __device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err,
   if (threadIdx.x == 0) {
     long long spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    // relaxed polls (an acquire per poll would invalidate this CU's caches
+    // every time), one acquire fence once the flag is seen
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kChainSpin ||
           (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrChain | kErrBarrier))) {
@@ -561,6 +563,7 @@ __device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err,
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok_s = ok;
   }
   __syncthreads();
