@@ -69,7 +69,8 @@ hipError_t launch_reproject(const float* poses, const float* inv_depth, const fl
                             float cx, float cy, float z_min, float* coords, uint8_t* valid, hipStream_t st);
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
-                             unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err, hipStream_t st, bool cooperative = false);
+                             unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err, hipStream_t st,
+                             bool cooperative = false, const int* reach = nullptr);
 hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st, int* err_clear = nullptr);
 template <typename TP, typename T>
 hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
@@ -77,7 +78,7 @@ hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_o
                             T lam_diag, int mirror, T* diag_out, hipStream_t st);
 template <typename T>
 hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
-                              hipStream_t st);
+                              hipStream_t st, const int* reach);
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
                              int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0,
@@ -295,6 +296,9 @@ struct dpvba_ctx {
   int* host_err_dev = nullptr;
   long long small_launches = 0;
   DevBuf chain_flags;  // per 64-row block: forward and backward publication epochs
+  // per 64-column panel of the reduced system: one past the last row that
+  // can be non-zero in the panel after the Cholesky fill (its envelope)
+  std::vector<int32_t> panel_reach;
   DevBuf one_inst;     // the analysed problem as a one-problem batch (small mixed solves)
   int chain_epoch = 0;
   DevBuf status, min_bits, devrep;
@@ -354,6 +358,12 @@ struct TraceScope {
 };
 
 // Epoch of the next chained triangular solve (never 0, the flags' initial value).
+// The panel reach of the analysed graph for a reduced system of n rows (null
+// when it was not computed for this n: the factor is then dense).
+static const int* reach_of(const dpvba_ctx* c, int n) {
+  return (int)c->panel_reach.size() == (n + 63) / 64 && n > 0 ? c->panel_reach.data() : nullptr;
+}
+
 static int next_epoch(dpvba_ctx* c) {
   c->chain_epoch = c->chain_epoch >= 0x3fffffff ? 1 : c->chain_epoch + 1;
   return c->chain_epoch;
@@ -813,6 +823,31 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(upload_tiling(c->tl[0], H32, st));
   HIP_TRY(upload_tiling(c->tl[1], H64, st));
   {
+    // envelope of the reduced system: block row P starts at its first
+    // coupled block column fq[P] (a tile contributes to (P, Q)); Cholesky
+    // fill stays between that column and the diagonal, so the rows that can
+    // be non-zero in block column Q end at the last P with fq[P] <= Q
+    std::vector<int32_t> fq(n_free), last(n_free, -1);
+    for (int Pp = 0; Pp < n_free; ++Pp) {
+      const long long base = (long long)Pp * (Pp + 1) / 2;
+      int q = Pp;
+      for (int Qq = 0; Qq < Pp; ++Qq)
+        if (H32.s_off[base + Qq + 1] > H32.s_off[base + Qq]) {
+          q = Qq;
+          break;
+        }
+      fq[Pp] = q;
+      last[q] = std::max(last[q], Pp);
+    }
+    for (int Qq = 1; Qq < n_free; ++Qq) last[Qq] = std::max(last[Qq], last[Qq - 1]);
+    const int n6 = 6 * n_free, np = (n6 + 63) / 64;
+    c->panel_reach.assign(np, n6);
+    for (int k = 0; k < np; ++k) {
+      const int qmax = std::min(64 * k + 63, n6 - 1) / 6;
+      c->panel_reach[k] = std::min(n6, 6 * (std::max(last[qmax], qmax) + 1));
+    }
+  }
+  {
     // both plans list the patches in the same order (frame, then patch id)
     if (H32.tile_patch != H64.tile_patch) return DPVBA_EINVAL;
     std::vector<int32_t> pos(P, -1), pose_off(N + 1, 0), pose_src(2 * (size_t)E);
@@ -1186,7 +1221,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
       e = launch_chol_solve<T>(ws.S, ws.rhs, n, dx, (T*)c->wy.p, (T*)c->Linv.p, ws.d0,
                                status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st,
-                               c->coop_launch);
+                               c->coop_launch, reach_of(c, n));
     }
     if (e != hipSuccess) return e;
     {
@@ -1321,7 +1356,9 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       if ((e = launch_lower_to_f32(S64, S32, n, st)) != hipSuccess) return e;
       if ((e = launch_convert<double, float>(d064, d032, n, st)) != hipSuccess) return e;
       if ((e = launch_convert<double, float>(s64, rhs32, n, st)) != hipSuccess) return e;
-      if ((e = launch_chol_factor<float>(S32, n, n, Linv32, d032, status + it, mb + it, st)) != hipSuccess) return e;
+      if ((e = launch_chol_factor<float>(S32, n, n, Linv32, d032, status + it, mb + it, st, reach_of(c, n))) !=
+          hipSuccess)
+        return e;
       if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
                                     next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch)) != hipSuccess)
         return e;
@@ -1522,7 +1559,8 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
     if ((e = gather()) != hipSuccess) return e;
     if ((e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, DX + (size_t)it * n, (T*)c->wy.p,
                                   (T*)c->Linv.p, (const T*)c->d0.p, status + it, mb + it, (int*)c->chain_flags.p,
-                                  next_epoch(c), err, c->host_err_dev, st, c->coop_launch)) != hipSuccess)
+                                  next_epoch(c), err, c->host_err_dev, st, c->coop_launch, reach_of(c, n))) !=
+        hipSuccess)
       return e;
     if ((e = launch_retract_copy<T>(xt, xt + np7, DX + (size_t)it * n, nf, N, status + it, st)) != hipSuccess)
       return e;
@@ -1550,7 +1588,8 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
       return e;
     if ((e = launch_chol_solve<T>((T*)c->S.p, urhs, n, up, (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p,
                                   status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it, (int*)c->chain_flags.p,
-                                  next_epoch(c), err, c->host_err_dev, st, c->coop_launch)) != hipSuccess)
+                                  next_epoch(c), err, c->host_err_dev, st, c->coop_launch, reach_of(c, n))) !=
+        hipSuccess)
       return e;
     if ((e = launch_adjoint_backsub<T>(tiles, tl.n_tiles, tl.max_w6, (const int*)tl.blk_pose.p,
                                        (const T*)c->U_s.p, (const T*)c->pscale_s.p, dbar, up, dx_t, stt, ud, dd,

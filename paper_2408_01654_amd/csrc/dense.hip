@@ -289,13 +289,19 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, in
 }
 
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
-// block per workgroup, on the matrix cores.
+// block per workgroup, on the matrix cores: the rows [k0 + kb, R) that can be
+// non-zero in the panel (R: the panel's reach, n for a dense matrix), then
+// the appended rows [n, nrows).
 template <typename T>
-__global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int nrows, int k0, int kb, const T* Linv) {
+__global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int nrows, int R, int k0, int kb,
+                                                         const T* Linv) {
   __shared__ T Ab[kNB][kNB + 1];
   __shared__ T Li[kNB][kNB + 1];
-  const int i0 = k0 + kb + blockIdx.x * kNB;
-  const int rows = min(kNB, nrows - i0);
+  const int t0 = k0 + kb;
+  const int n_main = R > t0 ? (R - t0 + kNB - 1) / kNB : 0;
+  const int b = blockIdx.x;
+  const int i0 = b < n_main ? t0 + b * kNB : n + (b - n_main) * kNB;
+  const int rows = min(kNB, (b < n_main ? R : nrows) - i0);
   const int tid = threadIdx.x;
   load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
   load_block64<T>(Linv, (size_t)kNB, kb, kb, Li);
@@ -363,14 +369,18 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
 }
 
 // Trailing update with 128 x 128 output tiles (float32): A_IJ -= L_Ik L_Jk^T
-// for the lower tiles of the trailing rows [t0, nrows) x columns [t0, n),
-// K = 64 (one panel).  Each of the four wavefronts takes one 64 x 64
-// quadrant as 4 x 4 matrix-core tiles accumulating L_I L_J^T; the quadrant
-// above the diagonal of a diagonal tile is skipped.  The products are then
-// staged in LDS and the tile is read and written row by row (contiguous
-// 512-byte rows): A - L_I L_J^T.  Four times the products per byte of panel
-// rows of a 64 x 64 update.  Rows beyond n (the right-hand side appended as
-// row n) are updated like any other row.
+// for the lower tiles of the trailing rows and columns [t0, R), K = 64 (one
+// panel).  R is the panel's reach: the rows below it have no entry in the
+// panel (the envelope of a sparse reduced system: fill stays between a row's
+// first non-zero and the diagonal), so their update is exactly zero and is
+// skipped; R = n for a dense matrix.  Each of the four wavefronts takes one
+// 64 x 64 quadrant as 4 x 4 matrix-core tiles accumulating L_I L_J^T; the
+// quadrant above the diagonal of a diagonal tile is skipped.  The products
+// are then staged in LDS and the tile is read and written row by row
+// (contiguous 512-byte rows): A - L_I L_J^T.  Four times the products per
+// byte of panel rows of a 64 x 64 update.  The right-hand side appended as
+// row n (nrows = n + 1) is updated by the diagonal tiles: s_J -= L_J l_n,
+// from the panel rows they hold anyway.
 //
 // Look-ahead: with Linv_next, workgroup 0 updates only the next diagonal
 // block (64 x 64; its quadrant of tile (0, 0) is left to it) and factors it
@@ -385,9 +395,10 @@ static_assert(kTB * kPanLd >= 2 * kNB * kWld, "diagonal factor working matrix in
 // Two wavefronts per SIMD (at most 256 registers), so two workgroups share a
 // CU although workgroup 0 also runs the register-heavy diagonal factor.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-syrk128_kernel(float* S, int n, int nrows, int k0, int kb, float* Linv_next, const float* d0, int* status,
+syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_next, const float* d0, int* status,
                unsigned int* min_bits) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
+  __shared__ float lrhs[kNB];  // l_n: the right-hand-side row's panel entries
   typedef float f2 __attribute__((ext_vector_type(2)));
   float* Pi = reinterpret_cast<float*>(dyn_lds);
   float* Pj = Pi + kTB * kPanLd;
@@ -426,21 +437,15 @@ syrk128_kernel(float* S, int n, int nrows, int k0, int kb, float* Linv_next, con
     diag_factor<float>(W, S, n, t0, rb, Linv_next, ddv, status, min_bits);
     return;
   }
-  const int Tc = (n - t0 + kTB - 1) / kTB;
-  const int ntri = Tc * (Tc + 1) / 2;
   const int blk = blockIdx.x - (look ? 1 : 0);
-  int I, J;
-  if (blk < ntri) {
-    I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > blk) --I;
-    while ((I + 1) * (I + 2) / 2 <= blk) ++I;
-    J = blk - I * (I + 1) / 2;
-  } else {  // the extra row tile below the last full one (rows up to nrows > n)
-    I = Tc;
-    J = blk - ntri;
-  }
+  int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > blk) --I;
+  while ((I + 1) * (I + 2) / 2 <= blk) ++I;
+  const int J = blk - I * (I + 1) / 2;
   const int i0 = t0 + I * kTB, j0 = t0 + J * kTB;
-  const int ri = min(kTB, nrows - i0), rj = min(kTB, n - j0);
+  const int ri = min(kTB, R - i0), rj = min(kTB, R - j0);
+  const bool rhs_row = I == J && nrows > n;
+  if (rhs_row && tid < kNB) lrhs[tid] = tid < kb ? S[(size_t)n * n + k0 + tid] : 0.f;
   const int wr = w >> 1, wc = w & 1;
   // the next diagonal block (rows and columns [t0, t0 + lb) of tile (0, 0)) is the look-ahead's
   const bool skip_lead = look && I == 0 && J == 0;
@@ -487,6 +492,16 @@ syrk128_kernel(float* S, int n, int nrows, int k0, int kb, float* Linv_next, con
 #pragma unroll
         for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
     }
+  }
+  if (rhs_row) {
+    // s_(j0 + c) -= sum_k L_(j0 + c, k) l_n(k): thread (c, half) takes 32 k
+    const int c = tid >> 1, h = tid & 1;
+    const float* pr = Pj + c * kPanLd + 32 * h;
+    float sum = 0.f;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) sum += pr[k] * lrhs[32 * h + k];
+    sum += __shfl_xor(sum, 1);
+    if (h == 0 && c < rj) S[(size_t)n * n + j0 + c] -= sum;
   }
   __syncthreads();  // the panel rows are dead: their LDS takes the products
   float* Out = Pi;  // [128][kOutLd]
@@ -787,10 +802,14 @@ int small_solve_max_n(int tsize) { return tsize == 4 ? 240 : 160; }
 // done by the factorisation's own panel solves and trailing updates.
 template <typename T>
 hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, int* status,
-                              unsigned int* min_bits, hipStream_t st) {
+                              unsigned int* min_bits, hipStream_t st, const int* reach) {
   const int nblk = (n + kNB - 1) / kNB;
   if (nblk == 0) return hipSuccess;
   if (sizeof(T) == 8 && nrows != n) return hipErrorInvalidValue;
+  if (nrows != n && nrows != n + 1) return hipErrorInvalidValue;  // at most the right-hand side appended
+  // float32: the trailing rows of panel k that can be non-zero end at
+  // reach[k] (host array, one entry per panel; null: dense)
+  auto reach_of = [&](int k) { return (sizeof(T) == 4 && reach) ? std::min(n, std::max(reach[k], 0)) : n; };
   hipLaunchKernelGGL((potrf_diag_kernel<T>), dim3(1), dim3(256), 0, st, S, n, 0, min(kNB, n), Linv_all, d0, status,
                      min_bits);
   if constexpr (sizeof(T) == 4) {
@@ -801,13 +820,16 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
     const int k0 = k * kNB, kb = min(kNB, n - k0);
     T* Linv = Linv_all + (size_t)k * kNB * kNB;
     const int t0 = k0 + kb;
-    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - t0 + kNB - 1) / kNB), dim3(256), 0, st, S, n, nrows,
-                       k0, kb, Linv);
+    const int R = reach_of(k);
+    const int n_main = R > t0 ? (R - t0 + kNB - 1) / kNB : 0;
+    if (n_main + nrows - n > 0)
+      hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(n_main + nrows - n), dim3(256), 0, st, S, n, nrows, R, k0, kb,
+                         Linv);
     // the trailing update also factors diagonal block k + 1 (its workgroup 0)
     if constexpr (sizeof(T) == 4) {
-      const int Tc = (n - t0 + kTB - 1) / kTB, Tr = (nrows - t0 + kTB - 1) / kTB;
-      const int tiles = Tc * (Tc + 1) / 2 + (Tr > Tc ? Tc : 0);
-      hipLaunchKernelGGL(syrk128_kernel, dim3(tiles + 1), dim3(256), kSyrk128Lds, st, S, n, nrows, k0, kb,
+      const int Tc = R > t0 ? (R - t0 + kTB - 1) / kTB : 0;
+      const int tiles = Tc * (Tc + 1) / 2;
+      hipLaunchKernelGGL(syrk128_kernel, dim3(tiles + 1), dim3(256), kSyrk128Lds, st, S, n, nrows, R, k0, kb,
                          Linv + kNB * kNB, d0, status, min_bits);
     } else {
       const int rest = nblk - k - 1;
@@ -817,8 +839,8 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
   }
   if (nrows > n) {  // the appended rows below the last diagonal block: their last panel solve
     const int k0 = (nblk - 1) * kNB;
-    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(256), 0, st, S, n, nrows, k0,
-                       n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB);
+    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(256), 0, st, S, n, nrows, n,
+                       k0, n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB);
   }
   return hipGetLastError();
 }
@@ -866,7 +888,7 @@ hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs,
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
                              unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err,
-                             hipStream_t st, bool cooperative) {
+                             hipStream_t st, bool cooperative, const int* reach) {
   if (n == 0) return hipSuccess;
   if (n <= small_solve_max_n(sizeof(T))) {
     const int lds = n + 1 <= kSmallRows
@@ -885,11 +907,11 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
     // leaves y = L^-1 s there and only the backward chain remains
     T* yrow = S + (size_t)n * n;
     hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, yrow, rhs, n);
-    e = launch_chol_factor<T>(S, n, n + 1, Linv_all, d0, status, min_bits, st);
+    e = launch_chol_factor<T>(S, n, n + 1, Linv_all, d0, status, min_bits, st, reach);
     if (e != hipSuccess) return e;
     e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1, cooperative);
   } else {
-    e = launch_chol_factor<T>(S, n, n, Linv_all, d0, status, min_bits, st);
+    e = launch_chol_factor<T>(S, n, n, Linv_all, d0, status, min_bits, st, nullptr);
     if (e != hipSuccess) return e;
     e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st, 0, cooperative);
   }
@@ -899,11 +921,12 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
 }
 
 template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, float*, float*, const float*, int*,
-                                             unsigned int*, int*, int, int*, int*, hipStream_t, bool);
+                                             unsigned int*, int*, int, int*, int*, hipStream_t, bool, const int*);
 template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, const double*,
-                                              int*, unsigned int*, int*, int, int*, int*, hipStream_t, bool);
+                                              int*, unsigned int*, int*, int, int*, int*, hipStream_t, bool,
+                                              const int*);
 template hipError_t launch_chol_factor<float>(float*, int, int, float*, const float*, int*, unsigned int*,
-                                              hipStream_t);
+                                              hipStream_t, const int*);
 template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, int*, int,
                                              int*, int*, hipStream_t, int, bool);
 
