@@ -600,6 +600,98 @@ def bench_pgo(n=1000, iters=10):
     return rec
 
 
+
+def bench_assembly_cold(scene, n_upper, steps=3):
+    """The edge assembly of the global BA with cold caches: before each
+    solve a 1 GiB buffer is written, which evicts the 256 MB last-level
+    cache (MALL) and the L2s, so the first assembly pass of the solve reads
+    its edge stream from HBM.  Reports that first pass's average launch time
+    and its fraction of the HBM peak with the same algorithmic bytes as the
+    headline roofline."""
+    import torch
+    import paper_2408_01654_amd as dp
+    s = scene
+    g = dp.GraphTensors.from_scene(s)
+    evict = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    times = []
+    with dp.Context(0) as ctx:
+        ctx.analyze(g)
+        poses0 = torch.as_tensor(s.poses).cuda().contiguous()
+        depth0 = torch.as_tensor(s.inv_depth).cuda().contiguous()
+        poses, depth = poses0.clone(), depth0.clone()
+        kw = dict(n_iters=1, lam=s.lam, z_min=s.z_min, precision=dp.FP32)
+        ctx.solve(g, poses, depth, report=False, **kw)
+        for _ in range(steps):
+            poses.copy_(poses0)
+            depth.copy_(depth0)
+            evict.fill_(1.0)
+            torch.cuda.synchronize()
+            ctx.trace_begin(sample_every=1, max_pairs=1024)
+            ctx.solve(g, poses, depth, report=False, **kw)
+            torch.cuda.synchronize()
+            ph = ctx.trace_end()
+            times.append(ph["assemble"][0] / ph["assemble"][1] * 1e3)
+    del evict
+    alg = assembly_alg_bytes(s, n_upper)
+    us = float(np.mean(times))
+    ach = alg / (us * 1e-6) / 1e9
+    log(f"[bench] cold-cache assembly: {us:.1f} us ({ach:.0f} GB/s, {ach / HBM_PEAK_GBS:.3f} of HBM peak)")
+    return {"workload": "first edge-assembly pass of the global BA after writing 1 GiB (caches evicted)",
+            "avg_launch_us": us, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "alg_bytes_per_launch": alg, "solves": steps}
+
+
+def bench_sweep(sizes=(100, 250, 500, 1000, 1500), steps=3):
+    """Keyframe-count sweep of the global BA (the synthetic analogue of the
+    paper's BA-size study, Appendix A): the total of 96k patches held
+    constant, N keyframes; per N the solve time, the per-iteration phases
+    (edge assembly, gather of the reduced system, camera solve) and the
+    device memory the solve holds.  There is no stored oracle result for
+    N != 1000: each point reports the cost before and after its 5 iterations
+    instead."""
+    import torch
+    import paper_2408_01654_amd as dp
+    from scenes import make_sweep
+    out = []
+    for N in sizes:
+        s = make_sweep(N)
+        g = dp.GraphTensors.from_scene(s)
+        torch.cuda.synchronize()
+        free0, _ = torch.cuda.mem_get_info()
+        with dp.Context(0) as ctx:
+            ctx.analyze(g)
+            poses0 = torch.as_tensor(s.poses).cuda().contiguous()
+            depth0 = torch.as_tensor(s.inv_depth).cuda().contiguous()
+            poses, depth = poses0.clone(), depth0.clone()
+            kw = dict(n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, precision=dp.FP32)
+            ctx.solve(g, poses, depth, report=False, **kw)
+            torch.cuda.synchronize()
+            ctx.trace_begin(sample_every=1, max_pairs=1 << 16)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                poses.copy_(poses0)
+                depth.copy_(depth0)
+                ctx.solve(g, poses, depth, report=False, **kw)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+            ph = ctx.trace_end()
+            free1, _ = torch.cuda.mem_get_info()
+            rep = ctx.solve(g, poses.copy_(poses0), depth.copy_(depth0), **kw)
+        avg = {k: (v[0] / v[1] * 1e3 if v[1] else 0.0) for k, v in ph.items()}
+        n = 6 * (s.n_frames - s.n_fixed)
+        rec = {"keyframes": N, "patches_per_frame": s.n_patches // N, "edges": s.n_edges, "n": n,
+               "ms_per_solve": 1e3 * sec, "us_per_iter": {"assembly": avg["assemble"], "gather": avg["gather"],
+                                                            "camera_solve": avg["factor"]},
+               "device_mem_mb": (free0 - free1) / 2 ** 20,
+               "camera_solve_flop_envelope": envelope_cholesky_flops(s), "camera_solve_flop_dense": cholesky_flops(n),
+               "cost_first_last": [rep["cost"][0], rep["cost"][-1]], "status": rep["status"]}
+        log(f"[bench] sweep N={N}: {rec['ms_per_solve']:.2f} ms/solve, assembly {avg['assemble']:.0f} us, "
+            f"gather {avg['gather']:.0f} us, camera solve {avg['factor']:.0f} us per iteration, "
+            f"{rec['device_mem_mb']:.0f} MB")
+        out.append(rec)
+    return {"workload": "global BA keyframe-count sweep, 96k patches held constant, +-6 temporal and proximity "
+                        "loop targets, 5 GN iterations, float32", "points": out}
+
 def bench_window(args):
     """Sliding-window local BA, 1000 calls (side record)."""
     import paper_2408_01654_amd as dp
@@ -736,10 +828,12 @@ def main():
     ap.add_argument("--trace-every", type=int, default=7, help="window record: event pair every n-th launch")
     ap.add_argument("--check", type=int, default=4, help="windows checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--side", default="window,mixed,batch,adjoint,correlation,proximity,pgo",
+    ap.add_argument("--side", default="window,mixed,batch,adjoint,correlation,proximity,pgo,sweep,cold",
                     help="comma list of side records: window (sliding-window BA), mixed (window and global BA in "
                          "DPVBA_MIXED), batch (256 uneven windows, every instance checked), adjoint (16 windows "
-                         "forward+adjoint); empty: none")
+                         "forward+adjoint), correlation, proximity, pgo (Sim(3) pose graph), sweep (keyframe-"
+                         "count sweep of the global BA), cold (edge assembly after evicting the caches); "
+                         "empty: none")
     ap.add_argument("--tile-patches", type=int, default=0,
                     help="patches per tile of the float32 plan of the window workload (0: library default)")
     ap.add_argument("--global-only", action="store_true",
@@ -800,6 +894,10 @@ def main():
         side["proximity"] = bench_proximity()
     if "pgo" in wanted:
         side["pgo"] = bench_pgo()
+    if "sweep" in wanted:
+        side["sweep"] = bench_sweep()
+    if "cold" in wanted:
+        side["assembly_cold"] = bench_assembly_cold(scene, n_upper)
 
     cpu = None
     if not args.no_cpu_baseline:

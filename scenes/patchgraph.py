@@ -341,13 +341,14 @@ def _loop_targets(c, min_gap=100, max_dist=2.0, n_loop=10):
 CFG2_DRIFT = 0.02   # linear scale drift reached at the last keyframe
 
 
-def _cfg2(noise_px=0.5, n_frames=1000, drift=CFG2_DRIFT):
+def _cfg2(noise_px=0.5, n_frames=1000, drift=CFG2_DRIFT, patches_per_frame=96, name=None):
     rng = _rng(2, 0, 0)
     R, c = circle_trajectory(n_frames)
     loops = _loop_targets(c)
     temporal = _window_targets(n_frames, 6)
     targets_of = lambda f: sorted(set(temporal(f)) | set(loops[f]))
-    u, v, d, ii, jj, kk, tgt, w = _render_graph(rng, R, c, [96] * n_frames, targets_of, noise_px)
+    K = patches_per_frame
+    u, v, d, ii, jj, kk, tgt, w = _render_graph(rng, R, c, [K] * n_frames, targets_of, noise_px)
     # initial estimate with scale drift: steps scaled by s_n, depths divided by s_n
     rng1 = _rng(2, 0, 1)
     s = 1.0 + drift * np.arange(n_frames) / (n_frames - 1)
@@ -358,9 +359,22 @@ def _cfg2(noise_px=0.5, n_frames=1000, drift=CFG2_DRIFT):
     phi = np.deg2rad(0.1) * rng1.normal(size=(n_frames, 3))
     phi[0] = 0.0
     R0 = R @ Rotation.from_rotvec(phi).as_matrix()
-    d0 = d / np.repeat(s, 96)
-    return _assemble_scene(CONFIG_NAMES[2], R, c, u, v, d, ii, jj, kk, tgt, w, 1, R0, c0, d0,
-                           n_iters=5, lam=1e-4, meta={"loop_pairs": int(sum(len(x) for x in loops))})
+    d0 = d / np.repeat(s, K)
+    return _assemble_scene(CONFIG_NAMES[2] if name is None else name, R, c, u, v, d, ii, jj, kk, tgt, w, 1, R0,
+                           c0, d0, n_iters=5, lam=1e-4, meta={"loop_pairs": int(sum(len(x) for x in loops))})
+
+
+def make_sweep(n_frames: int, total_patches: int = 96000, noise_px: float = 0.5) -> Scene:
+    """Keyframe-count sweep of the global BA (the synthetic analogue of the
+    paper's BA-size study, Appendix A): n_frames keyframes on the same circle
+    (1.58 laps), the total number of patches held at ``total_patches``
+    (total_patches / n_frames per frame), +-6 temporal targets and the same
+    proximity loop rule as the 1000-keyframe workload (about 12-16 edges per
+    patch), 2 % scale drift, the first pose fixed, 5 GN iterations.
+    make_sweep(1000) is the 1000-keyframe workload itself."""
+    K = total_patches // n_frames
+    return _cfg2(noise_px, n_frames=n_frames, patches_per_frame=K,
+                 name=CONFIG_NAMES[2] if (n_frames, K) == (1000, 96) else f"sweep_{n_frames}x{K}")
 
 
 def _cfg_window_instance(cfg, b, F, K, radius, n_fixed, noise_px=0.5):
