@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "dpvba.h"
+#include "factor_plan.h"
 #include "layout.h"
 #include "tileargs.h"
 
@@ -70,7 +71,7 @@ hipError_t launch_reproject(const float* poses, const float* inv_depth, const fl
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
                              unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err, hipStream_t st,
-                             bool cooperative = false, const int* reach = nullptr);
+                             bool cooperative = false, const PanelPlan* plan = nullptr);
 hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStream_t st, int* err_clear = nullptr);
 template <typename TP, typename T>
 hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
@@ -78,7 +79,7 @@ hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_o
                             T lam_diag, int mirror, T* diag_out, hipStream_t st);
 template <typename T>
 hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
-                              hipStream_t st, const int* reach);
+                              hipStream_t st, const PanelPlan* plan);
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
                              int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0,
@@ -296,9 +297,12 @@ struct dpvba_ctx {
   int* host_err_dev = nullptr;
   long long small_launches = 0;
   DevBuf chain_flags;  // per 64-row block: forward and backward publication epochs
-  // per 64-column panel of the reduced system: one past the last row that
-  // can be non-zero in the panel after the Cholesky fill (its envelope)
-  std::vector<int32_t> panel_reach;
+  // sparsity plan of the float32 factor (factor_plan.h): per 64-column panel
+  // its reach, and the 128-row tiles and 64-row blocks below its diagonal
+  // block that hold a row that can be non-zero in it
+  std::vector<int32_t> panel_reach, act_tiles_off, act_blocks_off;
+  DevBuf act_tiles, act_blocks;
+  PanelPlan plan{};
   DevBuf one_inst;     // the analysed problem as a one-problem batch (small mixed solves)
   int chain_epoch = 0;
   DevBuf status, min_bits, devrep;
@@ -358,10 +362,10 @@ struct TraceScope {
 };
 
 // Epoch of the next chained triangular solve (never 0, the flags' initial value).
-// The panel reach of the analysed graph for a reduced system of n rows (null
-// when it was not computed for this n: the factor is then dense).
-static const int* reach_of(const dpvba_ctx* c, int n) {
-  return (int)c->panel_reach.size() == (n + 63) / 64 && n > 0 ? c->panel_reach.data() : nullptr;
+// The factor plan of the analysed graph for a reduced system of n rows (null
+// when it was not built for this n: the factor is then dense).
+static const PanelPlan* reach_of(const dpvba_ctx* c, int n) {
+  return (int)c->panel_reach.size() == (n + 63) / 64 && n > 0 ? &c->plan : nullptr;
 }
 
 static int next_epoch(dpvba_ctx* c) {
@@ -522,7 +526,7 @@ void dpvba_destroy(dpvba_ctx* c) {
   DevBuf* bufs[] = {&c->part_S, &c->part_vec, &c->part_cost, &c->part_invalid, &c->U_s, &c->pscale_s,
                     &c->depth_s, &c->xh_s, &c->poses_a, &c->poses_b, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx,
                     &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
-                    &c->chain_flags, &c->one_inst,
+                    &c->chain_flags, &c->one_inst, &c->act_tiles, &c->act_blocks,
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
                     &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
                     &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
@@ -841,11 +845,33 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
     }
     for (int Qq = 1; Qq < n_free; ++Qq) last[Qq] = std::max(last[Qq], last[Qq - 1]);
     const int n6 = 6 * n_free, np = (n6 + 63) / 64;
-    c->panel_reach.assign(np, n6);
+    std::vector<int32_t> reach(np, n6), toff{0}, boff{0}, tl, bl;
     for (int k = 0; k < np; ++k) {
       const int qmax = std::min(64 * k + 63, n6 - 1) / 6;
-      c->panel_reach[k] = std::min(n6, 6 * (std::max(last[qmax], qmax) + 1));
+      reach[k] = std::min(n6, 6 * (std::max(last[qmax], qmax) + 1));
+      // rows of pose block P can be non-zero in panel k iff fq[P] <= qmax
+      const int t0 = 64 * (k + 1);
+      auto active = [&](int r0, int r1) {  // any row of [r0, r1) (clipped to n6)
+        for (int Pp = r0 / 6; Pp * 6 < std::min(r1, n6); ++Pp)
+          if (fq[Pp] <= qmax) return true;
+        return false;
+      };
+      for (int T = 0; t0 + 128 * T < n6; ++T)
+        if (active(t0 + 128 * T, t0 + 128 * T + 128)) tl.push_back(T);
+      for (int B = 0; t0 + 64 * B < n6; ++B)
+        if (active(t0 + 64 * B, t0 + 64 * B + 64)) bl.push_back(B);
+      toff.push_back((int32_t)tl.size());
+      boff.push_back((int32_t)bl.size());
     }
+    if (tl.empty()) tl.push_back(0);
+    if (bl.empty()) bl.push_back(0);
+    HIP_TRY(upload(c->act_tiles, tl, st));
+    HIP_TRY(upload(c->act_blocks, bl, st));
+    c->panel_reach = reach;
+    c->act_tiles_off = toff;
+    c->act_blocks_off = boff;
+    c->plan = PanelPlan{c->panel_reach.data(), c->act_tiles_off.data(), (const int*)c->act_tiles.p,
+                        c->act_blocks_off.data(), (const int*)c->act_blocks.p};
   }
   {
     // both plans list the patches in the same order (frame, then patch id)

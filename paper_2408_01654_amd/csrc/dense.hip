@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "factor_plan.h"
 #include "mfma.h"
 #include "packed.h"
 
@@ -289,18 +290,18 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, in
 }
 
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
-// block per workgroup, on the matrix cores: the rows [k0 + kb, R) that can be
-// non-zero in the panel (R: the panel's reach, n for a dense matrix), then
-// the appended rows [n, nrows).
+// block per workgroup, on the matrix cores: the blocks of rows [k0 + kb, R)
+// that can be non-zero in the panel (R: the panel's reach, n for a dense
+// matrix; with a list, only the listed blocks), then the appended rows
+// [n, nrows).
 template <typename T>
 __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int nrows, int R, int k0, int kb,
-                                                         const T* Linv) {
+                                                         const T* Linv, const int* blocks, int n_main) {
   __shared__ T Ab[kNB][kNB + 1];
   __shared__ T Li[kNB][kNB + 1];
   const int t0 = k0 + kb;
-  const int n_main = R > t0 ? (R - t0 + kNB - 1) / kNB : 0;
   const int b = blockIdx.x;
-  const int i0 = b < n_main ? t0 + b * kNB : n + (b - n_main) * kNB;
+  const int i0 = b < n_main ? t0 + (blocks ? blocks[b] : b) * kNB : n + (b - n_main) * kNB;
   const int rows = min(kNB, (b < n_main ? R : nrows) - i0);
   const int tid = threadIdx.x;
   load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
@@ -373,7 +374,9 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
 // panel).  R is the panel's reach: the rows below it have no entry in the
 // panel (the envelope of a sparse reduced system: fill stays between a row's
 // first non-zero and the diagonal), so their update is exactly zero and is
-// skipped; R = n for a dense matrix.  Each of the four wavefronts takes one
+// skipped; R = n for a dense matrix.  With a list of the active tiles (those
+// holding a row that is non-zero in the panel, factor_plan.h) only their
+// pairs are launched: a tile pair with an all-zero side has a zero update.  Each of the four wavefronts takes one
 // 64 x 64 quadrant as 4 x 4 matrix-core tiles accumulating L_I L_J^T; the
 // quadrant above the diagonal of a diagonal tile is skipped.  The products
 // are then staged in LDS and the tile is read and written row by row
@@ -396,7 +399,7 @@ static_assert(kTB * kPanLd >= 2 * kNB * kWld, "diagonal factor working matrix in
 // CU although workgroup 0 also runs the register-heavy diagonal factor.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_next, const float* d0, int* status,
-               unsigned int* min_bits) {
+               unsigned int* min_bits, const int* act) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   __shared__ float lrhs[kNB];  // l_n: the right-hand-side row's panel entries
   typedef float f2 __attribute__((ext_vector_type(2)));
@@ -438,10 +441,12 @@ syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_ne
     return;
   }
   const int blk = blockIdx.x - (look ? 1 : 0);
-  int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > blk) --I;
-  while ((I + 1) * (I + 2) / 2 <= blk) ++I;
-  const int J = blk - I * (I + 1) / 2;
+  int a = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+  while (a * (a + 1) / 2 > blk) --a;
+  while ((a + 1) * (a + 2) / 2 <= blk) ++a;
+  const int b = blk - a * (a + 1) / 2;
+  // pair (a, b), b <= a, of the active tiles (all tiles up to the reach without a list)
+  const int I = act ? act[a] : a, J = act ? act[b] : b;
   const int i0 = t0 + I * kTB, j0 = t0 + J * kTB;
   const int ri = min(kTB, R - i0), rj = min(kTB, R - j0);
   const bool rhs_row = I == J && nrows > n;
@@ -802,14 +807,15 @@ int small_solve_max_n(int tsize) { return tsize == 4 ? 240 : 160; }
 // done by the factorisation's own panel solves and trailing updates.
 template <typename T>
 hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, int* status,
-                              unsigned int* min_bits, hipStream_t st, const int* reach) {
+                              unsigned int* min_bits, hipStream_t st, const PanelPlan* plan) {
   const int nblk = (n + kNB - 1) / kNB;
   if (nblk == 0) return hipSuccess;
   if (sizeof(T) == 8 && nrows != n) return hipErrorInvalidValue;
   if (nrows != n && nrows != n + 1) return hipErrorInvalidValue;  // at most the right-hand side appended
   // float32: the trailing rows of panel k that can be non-zero end at
   // reach[k] (host array, one entry per panel; null: dense)
-  auto reach_of = [&](int k) { return (sizeof(T) == 4 && reach) ? std::min(n, std::max(reach[k], 0)) : n; };
+  const bool sparse = sizeof(T) == 4 && plan != nullptr;
+  auto reach_of = [&](int k) { return sparse ? std::min(n, std::max(plan->reach[k], 0)) : n; };
   hipLaunchKernelGGL((potrf_diag_kernel<T>), dim3(1), dim3(256), 0, st, S, n, 0, min(kNB, n), Linv_all, d0, status,
                      min_bits);
   if constexpr (sizeof(T) == 4) {
@@ -821,16 +827,18 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
     T* Linv = Linv_all + (size_t)k * kNB * kNB;
     const int t0 = k0 + kb;
     const int R = reach_of(k);
-    const int n_main = R > t0 ? (R - t0 + kNB - 1) / kNB : 0;
+    const int n_main = sparse ? plan->blocks_off[k + 1] - plan->blocks_off[k]
+                              : (R > t0 ? (R - t0 + kNB - 1) / kNB : 0);
     if (n_main + nrows - n > 0)
       hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(n_main + nrows - n), dim3(256), 0, st, S, n, nrows, R, k0, kb,
-                         Linv);
+                         Linv, sparse ? plan->blocks + plan->blocks_off[k] : (const int*)nullptr, n_main);
     // the trailing update also factors diagonal block k + 1 (its workgroup 0)
     if constexpr (sizeof(T) == 4) {
-      const int Tc = R > t0 ? (R - t0 + kTB - 1) / kTB : 0;
+      const int Tc = sparse ? plan->tiles_off[k + 1] - plan->tiles_off[k] : (R > t0 ? (R - t0 + kTB - 1) / kTB : 0);
       const int tiles = Tc * (Tc + 1) / 2;
       hipLaunchKernelGGL(syrk128_kernel, dim3(tiles + 1), dim3(256), kSyrk128Lds, st, S, n, nrows, R, k0, kb,
-                         Linv + kNB * kNB, d0, status, min_bits);
+                         Linv + kNB * kNB, d0, status, min_bits,
+                         sparse ? plan->tiles + plan->tiles_off[k] : (const int*)nullptr);
     } else {
       const int rest = nblk - k - 1;
       hipLaunchKernelGGL((syrk_update_kernel<T>), dim3(rest * (rest + 1) / 2), dim3(256), 0, st, S, n, k0, kb,
@@ -840,7 +848,7 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
   if (nrows > n) {  // the appended rows below the last diagonal block: their last panel solve
     const int k0 = (nblk - 1) * kNB;
     hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(256), 0, st, S, n, nrows, n,
-                       k0, n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB);
+                       k0, n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB, (const int*)nullptr, 0);
   }
   return hipGetLastError();
 }
@@ -888,7 +896,7 @@ hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs,
 template <typename T>
 hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Linv_all, const T* d0, int* status,
                              unsigned int* min_bits, int* flags, int epoch, int* err, int* host_err,
-                             hipStream_t st, bool cooperative, const int* reach) {
+                             hipStream_t st, bool cooperative, const PanelPlan* plan) {
   if (n == 0) return hipSuccess;
   if (n <= small_solve_max_n(sizeof(T))) {
     const int lds = n + 1 <= kSmallRows
@@ -907,7 +915,7 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
     // leaves y = L^-1 s there and only the backward chain remains
     T* yrow = S + (size_t)n * n;
     hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, yrow, rhs, n);
-    e = launch_chol_factor<T>(S, n, n + 1, Linv_all, d0, status, min_bits, st, reach);
+    e = launch_chol_factor<T>(S, n, n + 1, Linv_all, d0, status, min_bits, st, plan);
     if (e != hipSuccess) return e;
     e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1, cooperative);
   } else {
@@ -921,12 +929,13 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
 }
 
 template hipError_t launch_chol_solve<float>(float*, const float*, int, float*, float*, float*, const float*, int*,
-                                             unsigned int*, int*, int, int*, int*, hipStream_t, bool, const int*);
+                                             unsigned int*, int*, int, int*, int*, hipStream_t, bool,
+                                             const PanelPlan*);
 template hipError_t launch_chol_solve<double>(double*, const double*, int, double*, double*, double*, const double*,
                                               int*, unsigned int*, int*, int, int*, int*, hipStream_t, bool,
-                                              const int*);
+                                              const PanelPlan*);
 template hipError_t launch_chol_factor<float>(float*, int, int, float*, const float*, int*, unsigned int*,
-                                              hipStream_t, const int*);
+                                              hipStream_t, const PanelPlan*);
 template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, int*, int,
                                              int*, int*, hipStream_t, int, bool);
 

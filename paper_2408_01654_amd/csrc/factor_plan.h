@@ -1,0 +1,24 @@
+// Sparsity plan of the float32 blocked Cholesky of the reduced camera
+// system, built by the analysis from the structure of S (which 6 x 6 blocks
+// any tile contributes to).  Row r's envelope starts at the first column of
+// the first pose block its pose shares a patch with; Cholesky fill stays
+// between that column and the diagonal, so in panel k (columns 64 k ..
+// 64 k + 63) exactly the rows whose envelope starts inside or before the
+// panel can be non-zero.  The factor solves and updates only those: the
+// 64-row blocks and 128-row tiles below the panel's diagonal block that hold
+// such a row (block / tile indices count from t0 = 64 (k + 1)); every other
+// update is an exact zero.  Host arrays have one entry per panel (offsets one
+// more); the lists themselves are in device memory.
+#pragma once
+
+namespace dpvba {
+
+struct PanelPlan {
+  const int* reach;       // host [nblk]: one past the last such row (n if none beyond)
+  const int* tiles_off;   // host [nblk + 1]: panel k's active tiles are tiles[tiles_off[k] ..]
+  const int* tiles;       // device: 128-row tile indices, ascending
+  const int* blocks_off;  // host [nblk + 1]
+  const int* blocks;      // device: 64-row block indices, ascending
+};
+
+}  // namespace dpvba

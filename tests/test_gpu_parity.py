@@ -124,6 +124,22 @@ def test_large_reduced_system_uses_blocked_factorisation(dp, ctx, frames):
         _compare(s, P, D, Po, Do, TOL[prec], f"blocked {prec}")
 
 
+def test_envelope_limited_factor_on_a_loop(dp, ctx):
+    # 200 keyframes on the global-BA circle (1.58 laps) with 48 patches each:
+    # the proximity loops couple each pose with the same place one lap later,
+    # so the early panels of the factor reach only part of the n = 1194 rows
+    # and the trailing updates stop at their reach; the result must still
+    # match the float64 oracle
+    from scenes import make_sweep
+    s = make_sweep(200, total_patches=9600)
+    _log(f"envelope {s.name} E={s.n_edges}")
+    Po, Do, _ = ba64.solve_scene(s)
+    for prec in ("fp32", "mixed", "fp64"):
+        P, D, rep = _gpu_solve(dp, ctx, s, PREC[prec])
+        assert rep["status"] == 0
+        _compare(s, P, D, Po, Do, TOL[prec], f"envelope {prec}")
+
+
 def test_reproject_matches_oracle(dp, ctx):
     s = make_config(0)
     pb = ba64.Problem.from_scene(s)
