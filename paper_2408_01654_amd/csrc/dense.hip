@@ -152,23 +152,21 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
 //      finished column block (its writes overlap the later panels); a
 //      second barrier closes the panel.
 // ddv: this thread's entry of the damped diagonal (thread t < kb: column
-// t), for the pivot report.  Entries above the diagonal of the A part are
+// t), for the pivot report, which wavefront 0 forms panel by panel from the
+// pivots it holds and issues at the end (no closing barrier).  Entries above the diagonal of the A part are
 // never read as results.
 constexpr int kWld = kNB + 1;
 
 template <typename T>
 __device__ __forceinline__ void diag_factor(T* W, T* S, int n, int k0, int kb_in, T* Linv, T ddv, int* status,
                                             unsigned int* min_bits) {
-  __shared__ T piv[kNB];
   __shared__ T dd[kNB];
-  __shared__ int bad_s;
-  __shared__ unsigned int minr_s;
   const int kb = __builtin_amdgcn_readfirstlane(kb_in);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) { bad_s = 0; minr_s = __float_as_uint(3.0e38f); }
-  if (tid < kb) dd[tid] = ddv;
+  if (tid < kb) dd[tid] = ddv;  // wavefront 0, which alone reads it
   int bad = 0;
+  unsigned int minr = __float_as_uint(3.0e38f);  // wavefront 0: smallest pivot / damped diagonal
   for (int p = 0; 16 * p < kb; ++p) {
     const int c0 = 16 * p;
     // 1. the panel on wavefront 0
@@ -202,9 +200,16 @@ __device__ __forceinline__ void diag_factor(T* W, T* S, int n, int k0, int kb_in
         }
       }
       if (q == 0) {
-        piv[c0 + s] = dpiv;
 #pragma unroll
         for (int c = 0; c < 16; ++c) wa[c] = ra[c];
+      }
+      // pivot report of the panel: lane s takes column c0 + s (a NaN counts as 0)
+      {
+        const float ratio = c0 + s < kb ? (float)(dpiv / dd[c0 + s]) : 3.0e38f;
+        unsigned int m = __float_as_uint(ratio == ratio ? fmaxf(ratio, 0.f) : 0.f);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) m = min(m, (unsigned int)__shfl_xor((int)m, o));
+        minr = min(minr, m);
       }
 #pragma unroll
       for (int c = 0; c < 16; ++c) wb[c] = rb[c];
@@ -242,12 +247,9 @@ __device__ __forceinline__ void diag_factor(T* W, T* S, int n, int k0, int kb_in
     }
     __syncthreads();
   }
-  if (wave == 0 && bad) atomicOr(&bad_s, 1);
-  pivot_ratio_min<T>(piv, dd, kb, &minr_s);  // pivot report: smallest pivot / damped diagonal
-  __syncthreads();
-  if (tid == 0) {
-    if (bad_s) atomicOr(status, 1);
-    pivot_min(min_bits, __uint_as_float(minr_s));
+  if (tid == 0) {  // wavefront 0 holds the report; no barrier needed
+    if (bad) atomicOr(status, 1);
+    pivot_min(min_bits, __uint_as_float(minr));
   }
 }
 
