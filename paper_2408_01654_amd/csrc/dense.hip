@@ -467,6 +467,18 @@ syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_ne
   for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+  // the tile's own entries, read at once so that their latency overlaps the
+  // panel loads and the products: wavefront w takes rows w, w + 4, ...; lane
+  // l columns 2 l, 2 l + 1 (each access instruction covers one contiguous
+  // 512-byte row)
+  const int cc = 2 * lane;
+  f2 av[32];
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    const int r = w + 4 * u;
+    av[u] = (r < ri && cc < rj) ? *reinterpret_cast<const f2*>(S + (size_t)(i0 + r) * n + j0 + cc)
+                                : f2{0.f, 0.f};  // rj is even: n and j0 are
+  }
   // panel rows: 128 x kb of columns k0.. for the row tile and the column tile
   {
     f2 va[16], vb[16];
@@ -524,17 +536,8 @@ syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_ne
         }
   }
   __syncthreads();
-  // wavefront w takes rows w, w + 4, ...; lane l columns 2 l, 2 l + 1 (each
-  // access instruction covers one contiguous 512-byte row)
   {
-    const int c = 2 * lane;
-    f2 av[32];
-#pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const int r = w + 4 * u;
-      av[u] = (r < ri && c < rj) ? *reinterpret_cast<const f2*>(S + (size_t)(i0 + r) * n + j0 + c)
-                                 : f2{0.f, 0.f};  // rj is even: n and j0 are
-    }
+    const int c = cc;
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
       const int r = w + 4 * u;
