@@ -146,16 +146,60 @@ __global__ void __launch_bounds__(256) small_chol_solve_kernel(const T* S, const
 //      Column entries travel by the DPP row broadcast, a vector-register
 //      move within each 16-lane row, so the chain of 16 pivots takes no
 //      scalar registers and no barrier; the panel is written back;
-//   2. after one barrier, the four wavefronts apply the rank-16 update to
-//      the 16 x 16 blocks right of the panel whose rows can be non-zero,
-//      one matrix-core product per block, and all threads store the
-//      finished column block (its writes overlap the later panels); a
-//      second barrier closes the panel.
+//   2. after one barrier, the four wavefronts update the next column block
+//      by the panel (one matrix-core product per 16 x 16 block, one block
+//      each), which is all the next panel's chain needs; a second barrier
+//      closes the panel.  The rest of the panel's rank-16 update (the later
+//      column blocks, on the rows that can be non-zero) and the store of its
+//      finished column block are done by wavefronts 1..3 while wavefront 0
+//      factors the next panel, off the chain of dependent steps.
 // ddv: this thread's entry of the damped diagonal (thread t < kb: column
 // t), for the pivot report, which wavefront 0 forms panel by panel from the
 // pivots it holds and issues at the end (no closing barrier).  Entries above the diagonal of the A part are
 // never read as results.
 constexpr int kWld = kNB + 1;
+
+// Rank-16 update of diag_factor's working matrix by panel p on the matrix
+// cores: the 16 x 16 blocks (bi, bk), bk = bk_lo .. bk_hi (<= 3), bi = bk ..
+// 4 + p (the rows whose panel-p entries can be non-zero), bk-major, go to the
+// wavefronts first, first + nwav, ...: W_(bi,bk) -= W_(bi,p) W_(bk,p)^T.
+template <typename T>
+__device__ __forceinline__ void diag_update_blocks(T* W, int p, int bk_lo, int first, int nwav, int bk_hi = 3) {
+  const int lane = threadIdx.x & 63, c0 = 16 * p;
+  int count = 0;
+  for (int bk = bk_lo; bk <= bk_hi; ++bk) count += 5 + p - bk;
+  for (int q = first; q < count; q += nwav) {
+    int bk = bk_lo, rem = q;
+    while (rem >= 5 + p - bk) {
+      rem -= 5 + p - bk;
+      ++bk;
+    }
+    const int bi = bk + rem;
+    const T* xr = W + (16 * bi + (lane & 15)) * kWld + c0 + (lane >> 4);
+    const T* yr = W + (16 * bk + (lane & 15)) * kWld + c0 + (lane >> 4);
+    typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 16; k += 4) acc = Mfma<T>::step(xr[k], yr[k], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) W[(16 * bi + Mfma<T>::row(lane, v)) * kWld + 16 * bk + (lane & 15)] -= acc[v];
+  }
+}
+
+// Store of a finished column block (columns c0 .. c0 + 15) of diag_factor's
+// working matrix: L rows c0 .. kb - 1 into S, and rows c0 .. c0 + 15 of
+// L^-1 (zeros above its diagonal) into Linv; threads t0, t0 + nthr, ...
+template <typename T>
+__device__ __forceinline__ void diag_store_block(const T* W, T* S, int n, int k0, int kb, T* Linv, int c0, int t0,
+                                                 int nthr) {
+  if (t0 < 0) return;
+  for (int e = t0; e < 1024; e += nthr) {
+    const int r = e >> 4, c = c0 + (e & 15);
+    if (r < kb && c <= r) S[(size_t)(k0 + r) * n + k0 + c] = W[r * kWld + c];
+    const int kr = c0 + (e >> 6), rr = e & 63;  // Linv row kr, column rr
+    if (kr < kb && rr < kb) Linv[kr * kNB + rr] = kr >= rr ? W[(kNB + rr) * kWld + kr] : (T)0;
+  }
+}
+
 
 template <typename T>
 __device__ __forceinline__ void diag_factor(T* W, T* S, int n, int k0, int kb_in, T* Linv, T ddv, int* status,
@@ -165,7 +209,7 @@ __device__ __forceinline__ void diag_factor(T* W, T* S, int n, int k0, int kb_in
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   if (tid < kb) dd[tid] = ddv;  // wavefront 0, which alone reads it
-  int bad = 0;
+  int bad = 0, last = 0;
   unsigned int minr = __float_as_uint(3.0e38f);  // wavefront 0: smallest pivot / damped diagonal
   for (int p = 0; 16 * p < kb; ++p) {
     const int c0 = 16 * p;
@@ -213,40 +257,21 @@ __device__ __forceinline__ void diag_factor(T* W, T* S, int n, int k0, int kb_in
       }
 #pragma unroll
       for (int c = 0; c < 16; ++c) wb[c] = rb[c];
+    } else if (p > 0) {
+      // meanwhile wavefronts 1..3 finish panel p - 1: its update of the
+      // column blocks p + 1 .. 3 and the store of its column block
+      diag_update_blocks<T>(W, p - 1, p + 1, wave - 1, 3);
+      diag_store_block<T>(W, S, n, k0, kb, Linv, 16 * (p - 1), tid - 64, 192);
     }
     __syncthreads();
-    // 2. rank-16 update right of the panel on the matrix cores: the 16 x 16
-    // blocks (bi, bk), bk = p + 1 .. 3, bi = bk .. 4 + p (bk-major), go to
-    // the wavefronts in turn; W_(bi,bk) -= W_(bi,p) W_(bk,p)^T
-    {
-      const int count = p == 0 ? 9 : p == 1 ? 7 : p == 2 ? 4 : 0;
-      for (int q = wave; q < count; q += 4) {
-        int bk = p + 1, rem = q;
-        while (rem >= 5 + p - bk) {
-          rem -= 5 + p - bk;
-          ++bk;
-        }
-        const int bi = bk + rem;
-        const T* xr = W + (16 * bi + (lane & 15)) * kWld + c0 + (lane >> 4);
-        const T* yr = W + (16 * bk + (lane & 15)) * kWld + c0 + (lane >> 4);
-        typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < 16; k += 4) acc = Mfma<T>::step(xr[k], yr[k], acc);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) W[(16 * bi + Mfma<T>::row(lane, v)) * kWld + 16 * bk + (lane & 15)] -= acc[v];
-      }
-    }
-    // the column block is final: L rows c0 .. kb - 1, and columns c0 .. c0 + 15
-    // of L^-1 (rows of Linv), zeros above its diagonal
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + 256 * u, r = e >> 4, c = c0 + (e & 15);
-      if (r < kb && c <= r) S[(size_t)(k0 + r) * n + k0 + c] = W[r * kWld + c];
-      const int kr = c0 + (e >> 6), rr = e & 63;  // Linv row kr, column rr
-      if (kr < kb && rr < kb) Linv[kr * kNB + rr] = kr >= rr ? W[(kNB + rr) * kWld + kr] : (T)0;
-    }
+    // 2. what the next panel needs first: column block p + 1 updated by
+    // this panel (one 16 x 16 block per wavefront)
+    if (16 * (p + 1) < kb) diag_update_blocks<T>(W, p, p + 1, wave, 4, p + 1);
     __syncthreads();
+    last = p;
   }
+  // the last panel's column block (its later column blocks are padding)
+  diag_store_block<T>(W, S, n, k0, kb, Linv, 16 * last, tid, 256);
   if (tid == 0) {  // wavefront 0 holds the report; no barrier needed
     if (bad) atomicOr(status, 1);
     pivot_min(min_bits, __uint_as_float(minr));
