@@ -153,27 +153,33 @@ def cholesky_flops(n):
     return n ** 3 / 3.0 + 2.0 * n * n
 
 
-def envelope_cholesky_flops(s):
+def envelope_cholesky_flops(s, sys_order=None):
     """Algorithmic FLOP of the camera solve within the envelope of the
     reduced system, the work the factor has to do: Cholesky fill stays
     between a row's first coupled column and the diagonal, so column j of L
     has w_j = #{rows r > j whose envelope starts at or before j} entries
     below the diagonal; the factor costs sum_j w_j (w_j + 1) and the two
     triangular solves 4 sum_j (w_j + 1).  A row's envelope starts at the
-    first free pose that shares a patch with its pose (a patch couples its
+    first free pose (in the factored order: block row p is free pose
+    sys_order[p], the library's dpvba_get_system_order; None: the poses'
+    own order) that shares a patch with its pose (a patch couples its
     source frame and all of its targets)."""
     nf, N = s.n_fixed, s.n_frames
+    nfree = N - nf
+    pos = np.arange(nfree) if sys_order is None else np.argsort(np.asarray(sys_order))
     order = np.argsort(s.kk, kind="stable")
     kk, jj, owner = s.kk[order], s.jj[order], s.ii[order]
     starts = np.flatnonzero(np.r_[True, kk[1:] != kk[:-1]])
     ends = np.r_[starts[1:], len(kk)]
-    first = np.arange(N)
+    first = pos.copy()  # per free pose: first block row its row couples with
     for a, b in zip(starts, ends):
         fr = np.unique(np.r_[owner[a], jj[a:b]])
-        fr = fr[fr >= nf]
+        fr = fr[fr >= nf] - nf
         if len(fr):
-            first[fr] = np.minimum(first[fr], fr.min())
-    f_row = np.repeat(6 * (first[nf:] - nf), 6)  # first column of each scalar row
+            first[fr] = np.minimum(first[fr], pos[fr].min())
+    f_blk = np.empty(nfree, dtype=np.int64)
+    f_blk[pos] = first
+    f_row = np.repeat(6 * f_blk, 6)  # first column of each scalar row
     n = f_row.size
     # w_j = #{r > j : f_row[r] <= j}
     starts_at = np.bincount(f_row, minlength=n)
@@ -182,7 +188,7 @@ def envelope_cholesky_flops(s):
     return float(np.sum(w * (w + 1)) + 4.0 * np.sum(w + 1))
 
 
-def bench_global(steps, warmup=1, precision=None, scene=None, n_upper=None):
+def bench_global(steps, warmup=1, precision=None, scene=None, n_upper=None, keep_order=False):
     """Global BA after loop closure: 1000 keyframes x 96 patches, 1,505,568
     edges, 5 GN iterations (float32 or mixed).  Returns throughput, per-phase
     average launch durations, the edge-assembly and Cholesky rooflines and
@@ -195,8 +201,9 @@ def bench_global(steps, warmup=1, precision=None, scene=None, n_upper=None):
     g = dp.GraphTensors.from_scene(s)
     with dp.Context(0) as ctx:
         t0 = time.perf_counter()
-        ctx.analyze(g)
+        ctx.analyze(g, keep_order=keep_order)
         t_an = time.perf_counter() - t0
+        sys_order = ctx.system_order()
         poses0 = torch.as_tensor(s.poses).cuda().contiguous()
         depth0 = torch.as_tensor(s.inv_depth).cuda().contiguous()
         poses, depth = poses0.clone(), depth0.clone()
@@ -228,8 +235,9 @@ def bench_global(steps, warmup=1, precision=None, scene=None, n_upper=None):
     alg = assembly_alg_bytes(s, n_upper)
     ach = alg / (avg["assemble"] * 1e-6) / 1e9 if avg["assemble"] else 0.0
     n = 6 * (s.n_frames - s.n_fixed)
-    flops = envelope_cholesky_flops(s)
+    flops = envelope_cholesky_flops(s, sys_order)
     tf = flops / (avg["factor"] * 1e-6) / 1e12 if avg["factor"] else 0.0
+    permuted = bool(np.any(sys_order != np.arange(len(sys_order))))
     f32 = precision == dp.FP32
     name = "mixed (float64-refined camera solve)" if precision == dp.MIXED else "float32"
     out = {"workload": "global BA after loop closure: 1000 keyframes x 96 patches, 1,505,568 edges, "
@@ -250,8 +258,12 @@ def bench_global(steps, warmup=1, precision=None, scene=None, n_upper=None):
                                  "kernel": "blocked Cholesky and triangular solves of the 5994-wide camera system "
                                            "(factor phase: all of its launches)",
                                  "avg_launch_us": avg["factor"], "alg_flop_per_launch": flops,
-                                 "alg_flop_basis": "envelope of the reduced system (fill stays between a row's "
-                                                   "first coupled column and the diagonal)",
+                                 "alg_flop_basis": "envelope of the reduced system in its factored order "
+                                                   + ("(reverse Cuthill-McKee of the free poses)" if permuted
+                                                      else "(the poses' own order)")
+                                                   + ": fill stays between a row's first coupled column and "
+                                                     "the diagonal",
+                                 "natural_order_flop": envelope_cholesky_flops(s) if permuted else flops,
                                  "dense_flop": cholesky_flops(n), "n": n},
            "cost": rep["cost"], "status": rep["status"]}
     log(f"[bench] global BA {name}: {out['ms_per_solve']:.2f} ms/solve, {out['edges_per_s']:.4g} edge-iters/s, "
@@ -660,6 +672,7 @@ def bench_sweep(sizes=(100, 250, 500, 1000, 1500), steps=3):
         free0, _ = torch.cuda.mem_get_info()
         with dp.Context(0) as ctx:
             ctx.analyze(g)
+            sys_order = ctx.system_order()
             poses0 = torch.as_tensor(s.poses).cuda().contiguous()
             depth0 = torch.as_tensor(s.inv_depth).cuda().contiguous()
             poses, depth = poses0.clone(), depth0.clone()
@@ -683,7 +696,9 @@ def bench_sweep(sizes=(100, 250, 500, 1000, 1500), steps=3):
                "ms_per_solve": 1e3 * sec, "us_per_iter": {"assembly": avg["assemble"], "gather": avg["gather"],
                                                             "camera_solve": avg["factor"]},
                "device_mem_mb": (free0 - free1) / 2 ** 20,
-               "camera_solve_flop_envelope": envelope_cholesky_flops(s), "camera_solve_flop_dense": cholesky_flops(n),
+               "camera_solve_flop_envelope": envelope_cholesky_flops(s, sys_order),
+               "camera_solve_flop_envelope_natural_order": envelope_cholesky_flops(s),
+               "camera_solve_flop_dense": cholesky_flops(n),
                "cost_first_last": [rep["cost"][0], rep["cost"][-1]], "status": rep["status"]}
         log(f"[bench] sweep N={N}: {rec['ms_per_solve']:.2f} ms/solve, assembly {avg['assemble']:.0f} us, "
             f"gather {avg['gather']:.0f} us, camera solve {avg['factor']:.0f} us per iteration, "
@@ -828,9 +843,9 @@ def main():
     ap.add_argument("--trace-every", type=int, default=7, help="window record: event pair every n-th launch")
     ap.add_argument("--check", type=int, default=4, help="windows checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--side", default="window,mixed,batch,adjoint,correlation,proximity,pgo,sweep,cold",
+    ap.add_argument("--side", default="window,mixed,order,batch,adjoint,correlation,proximity,pgo,sweep,cold",
                     help="comma list of side records: window (sliding-window BA), mixed (window and global BA in "
-                         "DPVBA_MIXED), batch (256 uneven windows, every instance checked), adjoint (16 windows "
+                         "DPVBA_MIXED), order (global BA factored in the keyframes' own order), batch (256 uneven windows, every instance checked), adjoint (16 windows "
                          "forward+adjoint), correlation, proximity, pgo (Sim(3) pose graph), sweep (keyframe-"
                          "count sweep of the global BA), cold (edge assembly after evicting the caches); "
                          "empty: none")
@@ -882,6 +897,9 @@ def main():
             windows = build_windows(100)
         side["window_mixed"] = bench_window_mixed(windows, calls=100, steps=1)
         side["global_mixed"] = bench_global(3, 1, dp.MIXED, scene, n_upper)
+    if "order" in wanted:
+        # the same solve factored in the keyframes' own order (no reordering)
+        side["global_natural_order"] = bench_global(3, 1, dp.FP32, scene, n_upper, keep_order=True)
     if "batch" in wanted:
         ores = batch_oracle(256)
         side["batch_fp32"] = bench_batch(dp.FP32, graph=True, steps=5, oracle_res=ores)

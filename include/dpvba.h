@@ -189,14 +189,21 @@ dpvba_status dpvba_analyze(dpvba_ctx* ctx, const dpvba_graph* g, void* stream);
  * tile_patches_* patches of one source frame; 0 selects the default (96 for
  * the float32 plan, 32 for the float64 plan).  Larger tiles write smaller
  * partial systems; smaller tiles expose more workgroups.  Both plans are
- * built by every analysis.                                                */
+ * built by every analysis.
+ * keep_order: 0 lets the analysis factor a reduced system of more than 252
+ * unknowns in a reverse Cuthill-McKee order of the free poses (a symmetric
+ * permutation: the same solution, a smaller envelope of fill when loop
+ * closures couple distant keyframes; kept only if it shrinks the envelope),
+ * 1 keeps the poses' own order.  Results are reported in the poses' order
+ * either way.                                                             */
 typedef struct {
   int32_t tile_patches_fp32;
   int32_t tile_patches_fp64;
+  int32_t keep_order;
 } dpvba_tuning;
 
 /* dpvba_analyze with explicit tile shapes (tune may be NULL).  EINVAL for
- * negative entries.                                                       */
+ * negative entries or keep_order outside {0, 1}.                          */
 dpvba_status dpvba_analyze_ex(dpvba_ctx* ctx, const dpvba_graph* g, const dpvba_tuning* tune,
                               void* stream);
 
@@ -219,6 +226,15 @@ typedef struct {
 
 dpvba_status dpvba_get_analysis_info(const dpvba_ctx* ctx, int32_t precision,
                                      dpvba_analysis_info* info);
+
+/* Order of the free poses in the factored reduced system (host): block row
+ * p of the Cholesky factor is free pose order[p] (0-based among the free
+ * poses; pose n_fixed + order[p] of the graph).  The identity when the
+ * analysis kept the poses' own order.  Envelope fill (DPV-SLAM Appendix A:
+ * the Cholesky of the pose block is the solve's cost) follows this order.
+ *   order  [n] int32 (written), n = n_free of the analysis.
+ * EINVAL for a NULL order or a different n, ESTATE before an analysis.    */
+dpvba_status dpvba_get_system_order(const dpvba_ctx* ctx, int32_t* order, int32_t n);
 
 /* Reprojection of every edge's whole patch (eq. 2) with the patch's one
  * inverse depth.

@@ -54,7 +54,8 @@ class AnalysisInfo(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile_patches_fp32", ctypes.c_int32), ("tile_patches_fp64", ctypes.c_int32)]
+    _fields_ = [("tile_patches_fp32", ctypes.c_int32), ("tile_patches_fp64", ctypes.c_int32),
+                ("keep_order", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -128,6 +129,8 @@ def lib():
         L.dpvba_analyze_ex.restype = ctypes.c_int
         L.dpvba_get_analysis_info.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(AnalysisInfo)]
         L.dpvba_get_analysis_info.restype = ctypes.c_int
+        L.dpvba_get_system_order.argtypes = [vp, vp, ctypes.c_int32]
+        L.dpvba_get_system_order.restype = ctypes.c_int
         L.dpvba_last_error.argtypes = [vp]
         L.dpvba_last_error.restype = ctypes.c_char_p
         L.dpvba_status_string.argtypes = [ctypes.c_int]
@@ -279,9 +282,9 @@ class Context:
         except Exception:
             pass
 
-    def analyze(self, g: GraphTensors, stream=None, tile_patches_fp32=0, tile_patches_fp64=0):
+    def analyze(self, g: GraphTensors, stream=None, tile_patches_fp32=0, tile_patches_fp64=0, keep_order=False):
         gs = g.struct()
-        tune = Tuning(int(tile_patches_fp32), int(tile_patches_fp64))
+        tune = Tuning(int(tile_patches_fp32), int(tile_patches_fp64), int(bool(keep_order)))
         _check(lib().dpvba_analyze_ex(self._h, ctypes.byref(gs), ctypes.byref(tune), _stream(stream)),
                "dpvba_analyze", self._h)
         self._graph = g
@@ -290,6 +293,14 @@ class Context:
         info = AnalysisInfo()
         _check(lib().dpvba_get_analysis_info(self._h, int(precision), ctypes.byref(info)), "dpvba_get_analysis_info")
         return {f: getattr(info, f) for f, _ in AnalysisInfo._fields_}
+
+    def system_order(self) -> np.ndarray:
+        """dpvba_get_system_order: free pose at each block row of the factor."""
+        n = int(self.analysis_info()["n_free"])
+        out = np.zeros(max(n, 1), dtype=np.int32)
+        _check(lib().dpvba_get_system_order(self._h, out.ctypes.data_as(ctypes.c_void_p), n),
+               "dpvba_get_system_order", self._h)
+        return out[:n]
 
     def pgo_sim3(self, poses, loop_j, loop_k, loop_rel, n_fixed=1, n_iters=10, lam=1e-4, levenberg=False,
                  stream=None):

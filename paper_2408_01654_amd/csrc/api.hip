@@ -58,7 +58,9 @@ hipError_t launch_proximity_edges(const float* poses, int n, const int* patch_of
 template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
-                         T lam_diag, int mirror, T* diag_out, hipStream_t st);
+                         T lam_diag, int mirror, T* diag_out, hipStream_t st, const int* pos);
+template <typename T>
+hipError_t launch_permute6(const T* src, T* dst, const int* perm, int n_free, int to_system, hipStream_t st);
 template <typename T, typename P>
 hipError_t launch_edge_cost(const P* poses, const P* inv_depth, const float* patches, int p, const int* ii,
                             const int* jj, const int* kk, const float* target, const float* weight,
@@ -76,7 +78,7 @@ hipError_t launch_report_init(int* status, unsigned int* min_bits, int n, hipStr
 template <typename TP, typename T>
 hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
                             const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
-                            T lam_diag, int mirror, T* diag_out, hipStream_t st);
+                            T lam_diag, int mirror, T* diag_out, hipStream_t st, const int* pos);
 template <typename T>
 hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, int* status, unsigned int* min_bits,
                               hipStream_t st, const PanelPlan* plan);
@@ -276,6 +278,55 @@ static int writeback_lds_bytes(const Tiling& tl, int tsize) {
 
 }  // namespace
 
+// Host side of a factor plan (factor_plan.h) and its device lists.
+struct PlanStore {
+  std::vector<int32_t> reach, tiles_off, blocks_off;
+  DevBuf tiles, blocks;
+  PanelPlan plan{};
+  int n = 0;  // the system size the plan is for
+};
+
+// Factor plan of an n-row system of pose blocks of width bw whose block row
+// P couples first with block column fq[P] (<= P): per 64-column panel k the
+// reach, the 128-row tiles and the 64-row blocks below the panel's diagonal
+// block that hold a row whose envelope starts in or before the panel (block 0
+// always listed: the float64 trailing update runs its look-ahead there).
+static hipError_t build_plan(const std::vector<int32_t>& fq, int bw, int n, PlanStore& ps, hipStream_t st) {
+  const int nb = (int)fq.size(), np = (n + 63) / 64;
+  std::vector<int32_t> last(nb, -1);
+  for (int Pp = 0; Pp < nb; ++Pp) last[fq[Pp]] = std::max(last[fq[Pp]], Pp);
+  for (int Qq = 1; Qq < nb; ++Qq) last[Qq] = std::max(last[Qq], last[Qq - 1]);
+  std::vector<int32_t> reach(np, n), toff{0}, boff{0}, tl, bl;
+  for (int k = 0; k < np; ++k) {
+    const int qmax = std::min(64 * k + 63, n - 1) / bw;
+    reach[k] = std::min(n, bw * (std::max(last[qmax], qmax) + 1));
+    const int t0 = 64 * (k + 1);
+    auto active = [&](int r0, int r1) {  // any row of [r0, r1) (clipped to n)
+      for (int Pp = r0 / bw; Pp * bw < std::min(r1, n); ++Pp)
+        if (fq[Pp] <= qmax) return true;
+      return false;
+    };
+    for (int T = 0; t0 + 128 * T < n; ++T)
+      if (active(t0 + 128 * T, t0 + 128 * T + 128)) tl.push_back(T);
+    for (int B = 0; t0 + 64 * B < n; ++B)
+      if (B == 0 || active(t0 + 64 * B, t0 + 64 * B + 64)) bl.push_back(B);
+    toff.push_back((int32_t)tl.size());
+    boff.push_back((int32_t)bl.size());
+  }
+  if (tl.empty()) tl.push_back(0);
+  if (bl.empty()) bl.push_back(0);
+  hipError_t e;
+  if ((e = upload(ps.tiles, tl, st)) != hipSuccess) return e;
+  if ((e = upload(ps.blocks, bl, st)) != hipSuccess) return e;
+  ps.reach = reach;
+  ps.tiles_off = toff;
+  ps.blocks_off = boff;
+  ps.plan = PanelPlan{ps.reach.data(), ps.tiles_off.data(), (const int*)ps.tiles.p, ps.blocks_off.data(),
+                      (const int*)ps.blocks.p};
+  ps.n = n;
+  return hipSuccess;
+}
+
 struct dpvba_ctx {
   int device = 0;
   // analysed graph
@@ -300,9 +351,12 @@ struct dpvba_ctx {
   // sparsity plan of the float32 factor (factor_plan.h): per 64-column panel
   // its reach, and the 128-row tiles and 64-row blocks below its diagonal
   // block that hold a row that can be non-zero in it
-  std::vector<int32_t> panel_reach, act_tiles_off, act_blocks_off;
-  DevBuf act_tiles, act_blocks;
-  PanelPlan plan{};
+  PlanStore ba_plan;  // the analysed graph's reduced system
+  // system order of the large solves: block p of the factored system is free
+  // pose sys_perm[p] (sys_pos its inverse); empty: the poses' own order
+  std::vector<int32_t> sys_perm_h;
+  DevBuf sys_perm, sys_pos, sys_x, sys_b;
+  PlanStore pg_plan;  // the last pose graph's normal equations
   DevBuf one_inst;     // the analysed problem as a one-problem batch (small mixed solves)
   int chain_epoch = 0;
   DevBuf status, min_bits, devrep;
@@ -365,7 +419,103 @@ struct TraceScope {
 // The factor plan of the analysed graph for a reduced system of n rows (null
 // when it was not built for this n: the factor is then dense).
 static const PanelPlan* reach_of(const dpvba_ctx* c, int n) {
-  return (int)c->panel_reach.size() == (n + 63) / 64 && n > 0 ? &c->plan : nullptr;
+  return c->ba_plan.n == n && n > 0 ? &c->ba_plan.plan : nullptr;
+}
+
+// The large solves of a reduced system of more than this many unknowns run
+// in the system order (the smaller ones are gathered inside their kernels).
+constexpr int kPermuteMinUnknowns = kBatchMaxUnknowns;
+
+// System-order permutation (device, block p = free pose perm[p]) of the
+// analysed graph's large solves, or null for the poses' own order.
+static const int* sys_perm_of(const dpvba_ctx* c) {
+  return !c->sys_perm_h.empty() && 6 * c->n_free > kPermuteMinUnknowns ? (const int*)c->sys_perm.p : nullptr;
+}
+static const int* sys_pos_of(const dpvba_ctx* c) { return sys_perm_of(c) ? (const int*)c->sys_pos.p : nullptr; }
+
+// Block row P of a symmetric block pattern starts at block column fq[P]
+// (<= P): fill of a Cholesky factor stays between it and the diagonal.
+static double envelope_cost(const std::vector<int32_t>& fq) {
+  double s = 0.0;
+  for (size_t P = 0; P < fq.size(); ++P) {
+    const double w = (double)(P - fq[P] + 1);
+    s += w * w;
+  }
+  return s;
+}
+
+static std::vector<int32_t> first_coupled(const std::vector<std::vector<int32_t>>& adj,
+                                          const std::vector<int32_t>& pos) {
+  std::vector<int32_t> fq(adj.size());
+  for (size_t P = 0; P < adj.size(); ++P) {
+    int q = pos[P];
+    for (int Q : adj[P]) q = std::min(q, pos[Q]);
+    fq[pos[P]] = q;
+  }
+  return fq;
+}
+
+// Reverse Cuthill-McKee order of a graph (George and Liu's profile-reducing
+// ordering): per connected component, breadth-first from a pseudo-peripheral
+// vertex (the far end of repeated breadth-first sweeps), the unvisited
+// neighbours of each vertex queued by increasing degree; the whole order is
+// then reversed.  Returns order[p] = vertex at position p.
+static std::vector<int32_t> rcm_order(const std::vector<std::vector<int32_t>>& adj) {
+  const int nv = (int)adj.size();
+  std::vector<int32_t> order, level(nv, -1);
+  std::vector<char> done(nv, 0);
+  order.reserve(nv);
+  auto deg = [&](int v) { return (int)adj[v].size(); };
+  // breadth-first levels from r over the vertices not yet ordered; returns
+  // the last level's vertex of least degree and the eccentricity
+  auto sweep = [&](int r, int* far) {
+    std::vector<int32_t> q{r};
+    std::fill(level.begin(), level.end(), -1);
+    level[r] = 0;
+    for (size_t h = 0; h < q.size(); ++h)
+      for (int u : adj[q[h]])
+        if (!done[u] && level[u] < 0) {
+          level[u] = level[q[h]] + 1;
+          q.push_back(u);
+        }
+    const int ecc = level[q.back()];
+    int best = q.back();
+    for (int v : q)
+      if (level[v] == ecc && deg(v) < deg(best)) best = v;
+    *far = best;
+    return ecc;
+  };
+  for (;;) {
+    int r = -1;
+    for (int v = 0; v < nv; ++v)
+      if (!done[v] && (r < 0 || deg(v) < deg(r))) r = v;
+    if (r < 0) break;
+    int far = r, ecc = sweep(r, &far);
+    for (int t = 0; t < 8; ++t) {
+      int far2 = far;
+      const int e2 = sweep(far, &far2);
+      if (e2 <= ecc) break;
+      r = far;
+      ecc = e2;
+      far = far2;
+    }
+    const size_t first = order.size();
+    order.push_back(r);
+    done[r] = 1;
+    std::vector<int32_t> nb;
+    for (size_t h = first; h < order.size(); ++h) {
+      nb.clear();
+      for (int u : adj[order[h]])
+        if (!done[u]) {
+          done[u] = 1;
+          nb.push_back(u);
+        }
+      std::stable_sort(nb.begin(), nb.end(), [&](int a, int b) { return deg(a) < deg(b); });
+      order.insert(order.end(), nb.begin(), nb.end());
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
 }
 
 static int next_epoch(dpvba_ctx* c) {
@@ -407,6 +557,15 @@ dpvba_status dpvba_get_analysis_info(const dpvba_ctx* c, int32_t precision, dpvb
   info->grid_cells = t.grid_cells;
   info->u_elems = t.u_elems;
   info->lds_bytes = t.lds_bytes;
+  return DPVBA_OK;
+}
+
+dpvba_status dpvba_get_system_order(const dpvba_ctx* c, int32_t* order, int32_t n) {
+  if (!c || !order) return DPVBA_EINVAL;
+  if (!c->analysed) return DPVBA_ESTATE;
+  if (n != c->n_free) return DPVBA_EINVAL;
+  const bool perm = sys_perm_of(c) != nullptr;
+  for (int p = 0; p < n; ++p) order[p] = perm ? c->sys_perm_h[p] : p;
   return DPVBA_OK;
 }
 
@@ -526,7 +685,8 @@ void dpvba_destroy(dpvba_ctx* c) {
   DevBuf* bufs[] = {&c->part_S, &c->part_vec, &c->part_cost, &c->part_invalid, &c->U_s, &c->pscale_s,
                     &c->depth_s, &c->xh_s, &c->poses_a, &c->poses_b, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx,
                     &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
-                    &c->chain_flags, &c->one_inst, &c->act_tiles, &c->act_blocks,
+                    &c->chain_flags, &c->one_inst, &c->ba_plan.tiles, &c->ba_plan.blocks, &c->pg_plan.tiles,
+                    &c->pg_plan.blocks, &c->sys_perm, &c->sys_pos, &c->sys_x, &c->sys_b,
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
                     &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
                     &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
@@ -792,6 +952,7 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   int kcap32 = kDefaultTilePatches32, kcap64 = kDefaultTilePatches64;
   if (tune) {
     if (tune->tile_patches_fp32 < 0 || tune->tile_patches_fp64 < 0) return DPVBA_EINVAL;
+    if (tune->keep_order != 0 && tune->keep_order != 1) return DPVBA_EINVAL;
     if (tune->tile_patches_fp32 > 0) kcap32 = tune->tile_patches_fp32;
     if (tune->tile_patches_fp64 > 0) kcap64 = tune->tile_patches_fp64;
   }
@@ -831,47 +992,35 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
     // coupled block column fq[P] (a tile contributes to (P, Q)); Cholesky
     // fill stays between that column and the diagonal, so the rows that can
     // be non-zero in block column Q end at the last P with fq[P] <= Q
-    std::vector<int32_t> fq(n_free), last(n_free, -1);
+    std::vector<std::vector<int32_t>> adj(n_free);
     for (int Pp = 0; Pp < n_free; ++Pp) {
       const long long base = (long long)Pp * (Pp + 1) / 2;
-      int q = Pp;
       for (int Qq = 0; Qq < Pp; ++Qq)
         if (H32.s_off[base + Qq + 1] > H32.s_off[base + Qq]) {
-          q = Qq;
-          break;
+          adj[Pp].push_back(Qq);
+          adj[Qq].push_back(Pp);
         }
-      fq[Pp] = q;
-      last[q] = std::max(last[q], Pp);
     }
-    for (int Qq = 1; Qq < n_free; ++Qq) last[Qq] = std::max(last[Qq], last[Qq - 1]);
-    const int n6 = 6 * n_free, np = (n6 + 63) / 64;
-    std::vector<int32_t> reach(np, n6), toff{0}, boff{0}, tl, bl;
-    for (int k = 0; k < np; ++k) {
-      const int qmax = std::min(64 * k + 63, n6 - 1) / 6;
-      reach[k] = std::min(n6, 6 * (std::max(last[qmax], qmax) + 1));
-      // rows of pose block P can be non-zero in panel k iff fq[P] <= qmax
-      const int t0 = 64 * (k + 1);
-      auto active = [&](int r0, int r1) {  // any row of [r0, r1) (clipped to n6)
-        for (int Pp = r0 / 6; Pp * 6 < std::min(r1, n6); ++Pp)
-          if (fq[Pp] <= qmax) return true;
-        return false;
-      };
-      for (int T = 0; t0 + 128 * T < n6; ++T)
-        if (active(t0 + 128 * T, t0 + 128 * T + 128)) tl.push_back(T);
-      for (int B = 0; t0 + 64 * B < n6; ++B)
-        if (active(t0 + 64 * B, t0 + 64 * B + 64)) bl.push_back(B);
-      toff.push_back((int32_t)tl.size());
-      boff.push_back((int32_t)bl.size());
+    std::vector<int32_t> ident(n_free), pos(n_free);
+    for (int Pp = 0; Pp < n_free; ++Pp) ident[Pp] = Pp;
+    std::vector<int32_t> fq = first_coupled(adj, ident);
+    c->sys_perm_h.clear();
+    if (6 * n_free > kPermuteMinUnknowns && !(tune && tune->keep_order)) {
+      // a symmetric permutation leaves the solution unchanged and can shrink
+      // the envelope (and the factor's work) by orders of magnitude when
+      // loop closures couple distant keyframes
+      const std::vector<int32_t> order = rcm_order(adj);
+      for (int p = 0; p < n_free; ++p) pos[order[p]] = p;
+      std::vector<int32_t> fq_r = first_coupled(adj, pos);
+      if (envelope_cost(fq_r) < 0.9 * envelope_cost(fq)) {
+        c->sys_perm_h = order;
+        fq = fq_r;
+        HIP_TRY(upload(c->sys_perm, order, st));
+        HIP_TRY(upload(c->sys_pos, pos, st));
+      }
     }
-    if (tl.empty()) tl.push_back(0);
-    if (bl.empty()) bl.push_back(0);
-    HIP_TRY(upload(c->act_tiles, tl, st));
-    HIP_TRY(upload(c->act_blocks, bl, st));
-    c->panel_reach = reach;
-    c->act_tiles_off = toff;
-    c->act_blocks_off = boff;
-    c->plan = PanelPlan{c->panel_reach.data(), c->act_tiles_off.data(), (const int*)c->act_tiles.p,
-                        c->act_blocks_off.data(), (const int*)c->act_blocks.p};
+    c->ba_plan.n = 0;
+    HIP_TRY(build_plan(fq, 6, 6 * n_free, c->ba_plan, st));
   }
   {
     // both plans list the patches in the same order (frame, then patch id)
@@ -923,6 +1072,8 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(ensure(c->dx, n * 8));
   HIP_TRY(ensure(c->wb, n * 8));
   HIP_TRY(ensure(c->wy, n * 8));
+  HIP_TRY(ensure(c->sys_x, n * 8));
+  HIP_TRY(ensure(c->sys_b, n * 8));
   HIP_TRY(ensure(c->Linv, nblk64 * 64 * 64 * 8));
   if (c->chain_flags.bytes < 2 * nblk64 * 4 + 16) {
     HIP_TRY(ensure(c->chain_flags, 2 * nblk64 * 4 + 16));
@@ -1140,7 +1291,7 @@ static hipError_t reduced_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pose
   }
   return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
                           (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free, S,
-                          rhs, (T*)c->dB.p, lambda, lam_diag, 1, (T*)c->d0.p, st);
+                          rhs, (T*)c->dB.p, lambda, lam_diag, 1, (T*)c->d0.p, st, nullptr);
 }
 
 // Float32 tile assembly gathered in float64 (the DPVBA_MIXED system).
@@ -1164,7 +1315,7 @@ static hipError_t reduced_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, const f
   return launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
                                          (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
                                          (const int2*)tl.v_src.p, c->n_free, S, rhs, (double*)c->dB.p,
-                                         (double)lambda, (double)lam_diag, 1, (double*)c->d0.p, st);
+                                         (double)lambda, (double)lam_diag, 1, (double*)c->d0.p, st, nullptr);
 }
 
 template <typename T>
@@ -1181,6 +1332,9 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
   unsigned int* mb = ws.min_bits;
   T* pbuf[2] = {ws.pbuf0, ws.pbuf1};
   T* dx = ws.dx;
+  // the large iterations solve in the system order (workspaces of the
+  // context's own only)
+  const int* perm = ws_in ? nullptr : sys_perm_of(c);
   hipError_t e;
   // the call's failure word: that of the single launch's parity, else the large path's
   const int parity = (int)(c->small_launches & 1);
@@ -1240,14 +1394,15 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
       if (e == hipSuccess)
         e = launch_gather<T>(ws.part_S, ws.part_vec, (const int*)tl.s_off.p,
                              (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
-                             ws.S, ws.rhs, (T*)c->dB.p, lambda, lam_diag, 0, ws.d0, st);
+                             ws.S, ws.rhs, (T*)c->dB.p, lambda, lam_diag, 0, ws.d0, st, perm ? sys_pos_of(c) : nullptr);
     }
     if (e != hipSuccess) return e;
     {
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
-      e = launch_chol_solve<T>(ws.S, ws.rhs, n, dx, (T*)c->wy.p, (T*)c->Linv.p, ws.d0,
+      e = launch_chol_solve<T>(ws.S, ws.rhs, n, perm ? (T*)c->sys_x.p : dx, (T*)c->wy.p, (T*)c->Linv.p, ws.d0,
                                status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st,
                                c->coop_launch, reach_of(c, n));
+      if (e == hipSuccess && perm) e = launch_permute6<T>((const T*)c->sys_x.p, dx, perm, c->n_free, 0, st);
     }
     if (e != hipSuccess) return e;
     {
@@ -1340,7 +1495,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
         e = launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
                                             (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
                                             (const int2*)tl.v_src.p, c->n_free, S64, s64, (double*)c->dB.p,
-                                            (double)lambda, (double)lam_diag, 1, d064, st);
+                                            (double)lambda, (double)lam_diag, 1, d064, st, sys_pos_of(c));
       if (e != hipSuccess) return e;
     }
     if (n > 0 && n <= kBatchMaxUnknowns) {
@@ -1411,10 +1566,14 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       if (run64) {
         if ((e = launch_chol_solve<double>(S64, s64, n, x64, (double*)c->wy.p, (double*)c->Linv.p, d064, status64 + it,
                                            mb64 + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev,
-                                           st, c->coop_launch)) != hipSuccess)
+                                           st, c->coop_launch, reach_of(c, n))) != hipSuccess)
           return e;
       }
-      if ((e = launch_step_to_f32(x64, dx, n, fb + it, status64 + it, status + it, st)) != hipSuccess) return e;
+      // the step leaves the system order (perm: through c32, free by now)
+      const int* perm = sys_perm_of(c);
+      if ((e = launch_step_to_f32(x64, perm ? c32 : dx, n, fb + it, status64 + it, status + it, st)) != hipSuccess)
+        return e;
+      if (perm && (e = launch_permute6<float>(c32, dx, perm, c->n_free, 0, st)) != hipSuccess) return e;
     }
     {
       TraceScope ts(c, DPVBA_PHASE_RETRACT, st);
@@ -1571,8 +1730,12 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
   auto gather = [&]() {
     return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
                             (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
-                            (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, lam_diag, 0, (T*)c->d0.p, st);
+                            (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, lam_diag, 0, (T*)c->d0.p, st,
+                            sys_pos_of(c));
   };
+  const int* perm = sys_perm_of(c);
+  T* xs = (T*)c->sys_x.p;  // a solve's result in the system order
+  T* bs = (T*)c->sys_b.p;  // a right-hand side in the system order
   // replay: x_0 .. x_T, depths d_0 .. d_{T-1} in tile order, steps of the poses
   for (int it = 0; it < nit; ++it) {
     T* xt = Xp + it * np7;
@@ -1583,11 +1746,12 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
     if ((e = launch_tile_iterate<T>(A, tl.lds_bytes, st)) != hipSuccess) return e;
     if ((e = launch_copy<T>((const T*)c->depth_s.p, Xd + it * ntp, ntp, st)) != hipSuccess) return e;
     if ((e = gather()) != hipSuccess) return e;
-    if ((e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, DX + (size_t)it * n, (T*)c->wy.p,
+    if ((e = launch_chol_solve<T>((T*)c->S.p, (const T*)c->rhs.p, n, perm ? xs : DX + (size_t)it * n, (T*)c->wy.p,
                                   (T*)c->Linv.p, (const T*)c->d0.p, status + it, mb + it, (int*)c->chain_flags.p,
                                   next_epoch(c), err, c->host_err_dev, st, c->coop_launch, reach_of(c, n))) !=
         hipSuccess)
       return e;
+    if (perm && (e = launch_permute6<T>(xs, DX + (size_t)it * n, perm, c->n_free, 0, st)) != hipSuccess) return e;
     if ((e = launch_retract_copy<T>(xt, xt + np7, DX + (size_t)it * n, nf, N, status + it, st)) != hipSuccess)
       return e;
   }
@@ -1612,11 +1776,13 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
                                    (T*)c->part_vec.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
                                    dxbar, stt, urhs, st)) != hipSuccess)
       return e;
-    if ((e = launch_chol_solve<T>((T*)c->S.p, urhs, n, up, (T*)c->wy.p, (T*)c->Linv.p, (const T*)c->d0.p,
-                                  status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it, (int*)c->chain_flags.p,
-                                  next_epoch(c), err, c->host_err_dev, st, c->coop_launch, reach_of(c, n))) !=
-        hipSuccess)
+    if (perm && (e = launch_permute6<T>(urhs, bs, perm, c->n_free, 1, st)) != hipSuccess) return e;
+    if ((e = launch_chol_solve<T>((T*)c->S.p, perm ? bs : urhs, n, perm ? xs : up, (T*)c->wy.p, (T*)c->Linv.p,
+                                  (const T*)c->d0.p, status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it,
+                                  (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st, c->coop_launch,
+                                  reach_of(c, n))) != hipSuccess)
       return e;
+    if (perm && (e = launch_permute6<T>(xs, up, perm, c->n_free, 0, st)) != hipSuccess) return e;
     if ((e = launch_adjoint_backsub<T>(tiles, tl.n_tiles, tl.max_w6, (const int*)tl.blk_pose.p,
                                        (const T*)c->U_s.p, (const T*)c->pscale_s.p, dbar, up, dx_t, stt, ud, dd,
                                        st)) != hipSuccess)
@@ -1692,6 +1858,14 @@ dpvba_status dpvba_pgo_sim3(dpvba_ctx* c, int32_t n_frames, int32_t n_fixed, con
     pose_off.push_back((int32_t)pose_src.size());
   }
   const size_t n = 7 * (size_t)nf, nblk64 = (n + 63) / 64;
+  if (nf > 0) {
+    // envelope of the normal equations: each free pose's first coupled free pose
+    std::vector<int32_t> fq(nf);
+    for (int Pp = 0; Pp < nf; ++Pp) fq[Pp] = Pp;
+    for (auto& kv : blocks) fq[kv.first.first] = std::min(fq[kv.first.first], kv.first.second);
+    c->pg_plan.n = 0;
+    HIP_TRY(build_plan(fq, 7, (int)n, c->pg_plan, st));
+  }
   HIP_TRY(upload(c->pg_ea, ea, st));
   HIP_TRY(upload(c->pg_eb, eb, st));
   HIP_TRY(upload(c->pg_blk_pq, blk_pq, st));
@@ -1736,7 +1910,7 @@ dpvba_status dpvba_pgo_sim3(dpvba_ctx* c, int32_t n_frames, int32_t n_fixed, con
     HIP_TRY(launch_chol_solve<double>(H, (const double*)c->pg_rhs.p, (int)n, (double*)c->pg_dx.p,
                                       (double*)c->pg_wy.p, (double*)c->pg_Linv.p, (const double*)c->pg_d0.p,
                                       status + it, (unsigned int*)c->pg_mb.p + it, (int*)c->pg_flags.p, c->pg_epoch,
-                                      err, c->host_err_dev, st, c->coop_launch));
+                                      err, c->host_err_dev, st, c->coop_launch, &c->pg_plan.plan));
     HIP_TRY(launch_pgo_retract(sims, n_frames, n_fixed, (const double*)c->pg_dx.p, status + it, st));
   }
   HIP_TRY(launch_pgo_linearise(sims, (const double*)c->pg_C.p, (const int*)c->pg_ea.p, (const int*)c->pg_eb.p, E,

@@ -9,29 +9,34 @@ namespace dpvba {
 
 // Gather of the per-tile vectors into the right-hand side s and Diag(B).
 // The shares (type TP) are summed in the output type T, so float shares
-// gathered into double are combined without further rounding error.
+// gathered into double are combined without further rounding error.  With
+// pos, free pose P's rows go to block row pos[P] (a symmetric permutation
+// of the system; null: the poses' own order).
 template <typename TP, typename T>
 __global__ void gather_vec_kernel(const TP* part_vec, const int* off, const int2* src, int n, T* rhs,
-                                  T* dB) {
+                                  T* dB, const int* pos) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
   const int P_ = x / 6, m = x % 6;
+  const int xd = pos ? 6 * pos[P_] + m : x;
   T v = (T)0, d = (T)0;
   for (int q = off[P_]; q < off[P_ + 1]; ++q) {
     v += (T)part_vec[src[q].x + m];
     d += (T)part_vec[src[q].y + m];
   }
-  rhs[x] = v;
-  dB[x] = d;
+  rhs[xd] = v;
+  dB[xd] = d;
 }
 
 // Gather of every lower 6x6 block (P >= Q) of the damped reduced system from
 // the tile partials (zero where no tile contributes), with the damping
 // lam_diag Diag(B) + lambda added to the diagonal.  `mirror` also writes the
-// upper triangle.
+// upper triangle.  With pos, block (P, Q) goes to (pos[P], pos[Q]), as its
+// transpose into the lower triangle where pos[P] < pos[Q]; dB is then in
+// the permuted order (gather_vec_kernel with the same pos).
 template <typename TP, typename T>
 __global__ void gather_S_kernel(const TP* part_S, const int* off, const int* src, int n_free, T* S,
-                                const T* dB, T lambda, T lam_diag, int mirror, T* diag_out) {
+                                const T* dB, T lambda, T lam_diag, int mirror, T* diag_out, const int* pos) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nblk = (long long)n_free * (n_free + 1) / 2;
   if (g >= nblk * 36) return;
@@ -50,7 +55,12 @@ __global__ void gather_S_kernel(const TP* part_S, const int* off, const int* src
   }
   for (; q < hi; ++q) v += (T)part_S[src[q] + eo];
   const int n = 6 * n_free;
-  const int row = 6 * Pb + r, col = 6 * Qb + c;
+  int row = 6 * Pb + r, col = 6 * Qb + c;
+  if (pos) {
+    const int Pd = pos[Pb], Qd = pos[Qb];
+    row = Pd >= Qd ? 6 * Pd + r : 6 * Qd + c;
+    col = Pd >= Qd ? 6 * Qd + c : 6 * Pd + r;
+  }
   if (row == col) {
     v += lam_diag * dB[row] + lambda;
     if (diag_out) diag_out[row] = v;
@@ -201,23 +211,43 @@ hipError_t launch_report_finalize(dpvba_report* rep, const int* status, const un
 template <typename TP, typename T>
 hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
                             const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
-                            T lam_diag, int mirror, T* diag_out, hipStream_t st) {
+                            T lam_diag, int mirror, T* diag_out, hipStream_t st, const int* pos) {
   if (n_free == 0) return hipSuccess;
   const int n = 6 * n_free;
   hipLaunchKernelGGL((gather_vec_kernel<TP, T>), dim3((n + 255) / 256), dim3(256), 0, st, part_vec, v_off,
-                     v_src, n, rhs, dB);
+                     v_src, n, rhs, dB, pos);
   const long long tot = (long long)n_free * (n_free + 1) / 2 * 36;
   hipLaunchKernelGGL((gather_S_kernel<TP, T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,
-                     s_off, s_src, n_free, S, dB, lambda, lam_diag, mirror, diag_out);
+                     s_off, s_src, n_free, S, dB, lambda, lam_diag, mirror, diag_out, pos);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
-                         T lam_diag, int mirror, T* diag_out, hipStream_t st) {
+                         T lam_diag, int mirror, T* diag_out, hipStream_t st, const int* pos) {
   return launch_gather_as<T, T>(part_S, part_vec, s_off, s_src, v_off, v_src, n_free, S, rhs, dB, lambda, lam_diag,
-                                mirror, diag_out, st);
+                                mirror, diag_out, st, pos);
+}
+
+// Six-row blocks between the poses' order and a permuted system order:
+// block p of the system is free pose perm[p].  to_system: dst[p] = src[perm[p]];
+// else dst[perm[p]] = src[p].
+template <typename T>
+__global__ void permute6_kernel(const T* src, T* dst, const int* perm, int n_free, int to_system) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= 6 * n_free) return;
+  const int p = x / 6, m = x - 6 * p, q = 6 * perm[p] + m;
+  if (to_system) dst[x] = src[q];
+  else dst[q] = src[x];
+}
+
+template <typename T>
+hipError_t launch_permute6(const T* src, T* dst, const int* perm, int n_free, int to_system, hipStream_t st) {
+  if (n_free == 0) return hipSuccess;
+  hipLaunchKernelGGL((permute6_kernel<T>), dim3((6 * n_free + 255) / 256), dim3(256), 0, st, src, dst, perm, n_free,
+                     to_system);
+  return hipGetLastError();
 }
 
 template <typename T, typename P>
@@ -256,12 +286,14 @@ DPVBA_INSTANTIATE(float, float)
 DPVBA_INSTANTIATE(double, double)
 template hipError_t launch_gather<float>(const float*, const float*, const int*, const int*, const int*,
                                          const int2*, int, float*, float*, float*, float, float, int, float*,
-                                         hipStream_t);
+                                         hipStream_t, const int*);
 template hipError_t launch_gather<double>(const double*, const double*, const int*, const int*, const int*,
                                           const int2*, int, double*, double*, double*, double, double, int,
-                                          double*, hipStream_t);
+                                          double*, hipStream_t, const int*);
 template hipError_t launch_gather_as<float, double>(const float*, const float*, const int*, const int*,
                                                     const int*, const int2*, int, double*, double*, double*,
-                                                    double, double, int, double*, hipStream_t);
+                                                    double, double, int, double*, hipStream_t, const int*);
+template hipError_t launch_permute6<float>(const float*, float*, const int*, int, int, hipStream_t);
+template hipError_t launch_permute6<double>(const double*, double*, const int*, int, int, hipStream_t);
 
 }  // namespace dpvba

@@ -349,22 +349,27 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int nrows,
 }
 
 // Trailing update A_IJ -= L_Ik L_Jk^T for 64x64 blocks I >= J of the trailing
-// matrix, on the matrix cores; blockIdx.x enumerates the lower block pairs.
+// matrix, on the matrix cores; blockIdx.x enumerates the lower block pairs,
+// of all trailing blocks or, with act, of the listed ones (the blocks that
+// hold a row non-zero in the panel, ascending, block 0 first: a pair with an
+// all-zero side has a zero update).
 // float32: at least three wavefronts per SIMD (at most 170 registers), so
 // the trailing update keeps its occupancy although workgroup 0 also runs the
 // register-heavy diagonal factor (which still fits without spilling).
 template <typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
-syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* status, unsigned int* min_bits) {
+syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* status, unsigned int* min_bits,
+                   const int* act) {
   __shared__ T Lij[2][kNB][kNB + 1];  // contiguous: the look-ahead's W after the update
   T (*Li)[kNB + 1] = Lij[0];
   T (*Lj)[kNB + 1] = Lij[1];
   const int t0 = k0 + kb;
   const int blk = blockIdx.x;
-  int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > blk) --I;
-  while ((I + 1) * (I + 2) / 2 <= blk) ++I;
-  const int J = blk - I * (I + 1) / 2;
+  int a = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+  while (a * (a + 1) / 2 > blk) --a;
+  while ((a + 1) * (a + 2) / 2 <= blk) ++a;
+  const int b = blk - a * (a + 1) / 2;
+  const int I = act ? act[a] : a, J = act ? act[b] : b;
   const int i0 = t0 + I * kNB, j0 = t0 + J * kNB;
   const int ri = min(kNB, n - i0), rj = min(kNB, n - j0);
   const int tid = threadIdx.x;
@@ -842,10 +847,11 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
   if (nblk == 0) return hipSuccess;
   if (sizeof(T) == 8 && nrows != n) return hipErrorInvalidValue;
   if (nrows != n && nrows != n + 1) return hipErrorInvalidValue;  // at most the right-hand side appended
-  // float32: the trailing rows of panel k that can be non-zero end at
-  // reach[k] (host array, one entry per panel; null: dense)
-  const bool sparse = sizeof(T) == 4 && plan != nullptr;
-  auto reach_of = [&](int k) { return sparse ? std::min(n, std::max(plan->reach[k], 0)) : n; };
+  // with a plan only the blocks (and, float32, the 128-row tiles) that hold a
+  // row non-zero in the panel are solved and updated; float32 also stops at
+  // the panel's reach (the last row that can be non-zero in it)
+  const bool sparse = plan != nullptr;
+  auto reach_of = [&](int k) { return sparse && sizeof(T) == 4 ? std::min(n, std::max(plan->reach[k], 0)) : n; };
   hipLaunchKernelGGL((potrf_diag_kernel<T>), dim3(1), dim3(256), 0, st, S, n, 0, min(kNB, n), Linv_all, d0, status,
                      min_bits);
   if constexpr (sizeof(T) == 4) {
@@ -870,9 +876,10 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
                          Linv + kNB * kNB, d0, status, min_bits,
                          sparse ? plan->tiles + plan->tiles_off[k] : (const int*)nullptr);
     } else {
-      const int rest = nblk - k - 1;
+      const int rest = sparse ? n_main : nblk - k - 1;
       hipLaunchKernelGGL((syrk_update_kernel<T>), dim3(rest * (rest + 1) / 2), dim3(256), 0, st, S, n, k0, kb,
-                         Linv + kNB * kNB, d0, status, min_bits);
+                         Linv + kNB * kNB, d0, status, min_bits,
+                         sparse ? plan->blocks + plan->blocks_off[k] : (const int*)nullptr);
     }
   }
   if (nrows > n) {  // the appended rows below the last diagonal block: their last panel solve
@@ -949,7 +956,7 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
     if (e != hipSuccess) return e;
     e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1, cooperative);
   } else {
-    e = launch_chol_factor<T>(S, n, n, Linv_all, d0, status, min_bits, st, nullptr);
+    e = launch_chol_factor<T>(S, n, n, Linv_all, d0, status, min_bits, st, plan);
     if (e != hipSuccess) return e;
     e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st, 0, cooperative);
   }

@@ -9,6 +9,6 @@ mistake from the other through it.
 """
 from .patchgraph import (  # noqa: F401
     FX, FY, CX, CY, IMG_W, IMG_H, PATCH,
-    Scene, make_config, make_sweep, make_window, tiny_scene, window_sequence,
+    Scene, make_config, make_sweep, make_window, relabel_frames, tiny_scene, window_sequence,
     CONFIG_NAMES,
 )

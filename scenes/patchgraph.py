@@ -364,6 +364,26 @@ def _cfg2(noise_px=0.5, n_frames=1000, drift=CFG2_DRIFT, patches_per_frame=96, n
                            c0, d0, n_iters=5, lam=1e-4, meta={"loop_pairs": int(sum(len(x) for x in loops))})
 
 
+def relabel_frames(s: Scene, seed: int = 0) -> Scene:
+    """The same problem with its free frames numbered in a random order (the
+    fixed frames keep the first indices): frame f becomes new[f].  A banded
+    graph turns into one whose frame order couples distant indices, the case
+    a fill-reducing order of the reduced system has to undo."""
+    rng = np.random.default_rng(seed)
+    nf, N = s.n_fixed, s.n_frames
+    new = np.r_[np.arange(nf), nf + rng.permutation(N - nf)].astype(np.int32)
+    out = Scene(**{k: getattr(s, k) for k in s.__dataclass_fields__})
+    out.name = f"{s.name}_relabelled{seed}"
+    out.poses = np.empty_like(s.poses)
+    out.poses[new] = s.poses
+    out.poses_gt = np.empty_like(s.poses_gt)
+    out.poses_gt[new] = s.poses_gt
+    out.ii = new[s.ii]
+    out.jj = new[s.jj]
+    out.meta = dict(s.meta, relabel=new)
+    return out
+
+
 def make_sweep(n_frames: int, total_patches: int = 96000, noise_px: float = 0.5) -> Scene:
     """Keyframe-count sweep of the global BA (the synthetic analogue of the
     paper's BA-size study, Appendix A): n_frames keyframes on the same circle

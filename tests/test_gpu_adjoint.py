@@ -22,7 +22,7 @@ import pytest
 import torch
 
 from oracle import grad64
-from scenes import make_config, make_window, tiny_scene
+from scenes import make_config, make_window, relabel_frames, tiny_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -100,6 +100,10 @@ SCENES = [
     ("window", lambda: make_window(0), None),
     # 60 frames, 58 free: n = 348, the blocked factorisation of the large path
     ("blocked", lambda: tiny_scene(60, 12, seed=4, radius=5, trajectory="forward"), None),
+    # the same with its free frames numbered at random: the analysis factors
+    # the reduced system in a fill-reducing order, the adjoint solves included
+    ("relabelled", lambda: relabel_frames(tiny_scene(60, 12, seed=4, radius=5, trajectory="forward"), seed=5),
+     None),
 ]
 
 

@@ -36,9 +36,9 @@ def _log(msg):
     print(msg, flush=True)
 
 
-def _gpu_solve(dp, ctx, s: Scene, precision, n_iters=None, lam=None):
+def _gpu_solve(dp, ctx, s: Scene, precision, n_iters=None, lam=None, keep_order=False):
     g = dp.GraphTensors.from_scene(s)
-    ctx.analyze(g)
+    ctx.analyze(g, keep_order=keep_order)
     dt = torch.float64 if precision == dp.FP64 else torch.float32
     poses = torch.as_tensor(s.poses, dtype=dt).cuda().contiguous()
     depth = torch.as_tensor(s.inv_depth, dtype=dt).cuda().contiguous()
@@ -130,14 +130,56 @@ def test_envelope_limited_factor_on_a_loop(dp, ctx):
     # so the early panels of the factor reach only part of the n = 1194 rows
     # and the trailing updates stop at their reach; the result must still
     # match the float64 oracle
+    # (in the keyframes' own order and in the analysis' fill-reducing order)
     from scenes import make_sweep
     s = make_sweep(200, total_patches=9600)
     _log(f"envelope {s.name} E={s.n_edges}")
     Po, Do, _ = ba64.solve_scene(s)
-    for prec in ("fp32", "mixed", "fp64"):
-        P, D, rep = _gpu_solve(dp, ctx, s, PREC[prec])
-        assert rep["status"] == 0
-        _compare(s, P, D, Po, Do, TOL[prec], f"envelope {prec}")
+    for keep in (True, False):
+        for prec in ("fp32", "mixed", "fp64"):
+            P, D, rep = _gpu_solve(dp, ctx, s, PREC[prec], keep_order=keep)
+            assert rep["status"] == 0
+            _compare(s, P, D, Po, Do, TOL[prec], f"envelope {prec} keep_order={keep}")
+
+
+def _envelope_blocks(s, order):
+    """Sum over block rows of the squared envelope width (in pose blocks)
+    of the reduced system factored in `order` (block row p = free pose
+    order[p]); two free poses are coupled when a patch links them."""
+    nf = s.n_fixed
+    pos = np.argsort(order)
+    first = pos.copy()
+    for k in np.unique(s.kk):
+        fr = np.unique(np.r_[s.ii[s.kk == k], s.jj[s.kk == k]])
+        fr = fr[fr >= nf] - nf
+        if len(fr):
+            first[fr] = np.minimum(first[fr], pos[fr].min())
+    return float(np.sum((pos - first + 1.0) ** 2))
+
+
+def test_fill_reducing_order_on_relabelled_frames(dp, ctx):
+    # a banded problem (forward motion, targets within 5 frames) with its
+    # free frames numbered at random: in that numbering the envelope spans
+    # the whole system; the analysis must find an order with a far smaller
+    # one, report it, and every precision must still match the oracle
+    from scenes import relabel_frames
+    s = relabel_frames(tiny_scene(60, 12, seed=4, radius=5, trajectory="forward"), seed=5)
+    nfree = s.n_frames - s.n_fixed
+    Po, Do, _ = ba64.solve_scene(s)
+    g = dp.GraphTensors.from_scene(s)
+    ctx.analyze(g, keep_order=True)
+    assert np.array_equal(ctx.system_order(), np.arange(nfree))
+    ctx.analyze(g)
+    order = ctx.system_order()
+    assert np.array_equal(np.sort(order), np.arange(nfree))
+    e_nat, e_sys = _envelope_blocks(s, np.arange(nfree)), _envelope_blocks(s, order)
+    _log(f"relabelled: envelope (blocks^2) natural {e_nat:.0f}, system order {e_sys:.0f}")
+    assert e_sys < 0.25 * e_nat
+    for keep in (False, True):
+        for prec in ("fp32", "mixed", "fp64"):
+            P, D, rep = _gpu_solve(dp, ctx, s, PREC[prec], keep_order=keep)
+            assert rep["status"] == 0
+            _compare(s, P, D, Po, Do, TOL[prec], f"relabelled {prec} keep_order={keep}")
 
 
 def test_reproject_matches_oracle(dp, ctx):

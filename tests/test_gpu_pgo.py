@@ -39,6 +39,10 @@ def _compare(sims, want):
 CASES = [
     ("loop40", dict(n=40, loops=((2, 30), (5, 36), (10, 38))), 6, 1e-4, False),
     ("loop200", dict(n=200, seed=3, drift=0.08), 8, 1e-4, False),
+    # closures spread over the trajectory: an envelope with gaps, so the
+    # blocked factor skips blocks and block pairs that stay zero
+    ("loops_spread", dict(n=260, seed=11, loops=((3, 250), (40, 120), (100, 230), (150, 170), (20, 90))), 6, 1e-4,
+     False),
     ("levenberg", dict(n=60, seed=5), 5, 1e-3, True),
     ("no_loops", dict(n=30, loops=()), 3, 1e-4, False),
 ]

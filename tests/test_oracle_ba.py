@@ -420,3 +420,18 @@ def test_levenberg_damping_pins():
         np.testing.assert_allclose(delta, want, rtol=1e-8, atol=1e-12 * np.abs(want).max())
         if lam > 1e6:
             np.testing.assert_allclose(delta, -ne.g / lam, rtol=1e-4, atol=1e-4 * np.abs(ne.g / lam).max())
+
+
+def test_solution_independent_of_frame_numbering():
+    # renumbering the free frames permutes the reduced system symmetrically;
+    # Gauss-Newton steps (and so the solution) must not depend on it
+    from scenes import relabel_frames
+    s = tiny_scene(10, 6, seed=12)
+    r = relabel_frames(s, seed=3)
+    new = r.meta["relabel"]
+    P1, D1, _ = ba64.solve_scene(s)
+    P2, D2, _ = ba64.solve_scene(r)
+    dt, dr = ba64.pose_errors(P1, P2[new])
+    assert dt.max() < 1e-10 and dr.max() < 1e-10
+    np.testing.assert_allclose(D1, D2, rtol=1e-10)
+    assert not np.array_equal(new[s.n_fixed:], np.arange(s.n_fixed, s.n_frames))
