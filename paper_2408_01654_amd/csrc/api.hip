@@ -60,7 +60,8 @@ hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, c
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
                          T lam_diag, int mirror, T* diag_out, hipStream_t st, const int* pos);
 template <typename T>
-hipError_t launch_permute6(const T* src, T* dst, const int* perm, int n_free, int to_system, hipStream_t st);
+hipError_t launch_permute_blocks(const T* src, T* dst, const int* perm, int n_blk, int bw, int to_system,
+                                 hipStream_t st);
 template <typename T, typename P>
 hipError_t launch_edge_cost(const P* poses, const P* inv_depth, const float* patches, int p, const int* ii,
                             const int* jj, const int* kk, const float* target, const float* weight,
@@ -382,7 +383,7 @@ struct dpvba_ctx {
   // adjoint workspace
   // Sim(3) pose-graph optimisation workspace
   DevBuf pg_C, pg_ea, pg_eb, pg_r, pg_J, pg_H, pg_rhs, pg_dx, pg_d0, pg_wy, pg_Linv, pg_flags, pg_status, pg_mb,
-      pg_cost, pg_blk_pq, pg_blk_off, pg_blk_src, pg_pose_off, pg_pose_src;
+      pg_cost, pg_blk_pq, pg_blk_off, pg_blk_src, pg_pose_off, pg_pose_src, pg_perm, pg_xs;
   int pg_epoch = 0;
   DevBuf bw_poses, bw_depth, bw_dx, bw_pbar, bw_dbar, bw_dxbar, bw_rhs, bw_up, bw_ud, bw_dd, bw_edge, bw_status,
       bw_minbits;
@@ -693,7 +694,7 @@ void dpvba_destroy(dpvba_ctx* c) {
                     &c->d0_32, &c->mx_max, &c->mx_resid, &c->mx_fb, &c->mx_flag, &c->pg_C, &c->pg_ea, &c->pg_eb,
                     &c->pg_r, &c->pg_J, &c->pg_H, &c->pg_rhs, &c->pg_dx, &c->pg_d0, &c->pg_wy, &c->pg_Linv,
                     &c->pg_flags, &c->pg_status, &c->pg_mb, &c->pg_cost, &c->pg_blk_pq, &c->pg_blk_off,
-                    &c->pg_blk_src, &c->pg_pose_off, &c->pg_pose_src};
+                    &c->pg_blk_src, &c->pg_pose_off, &c->pg_pose_src, &c->pg_perm, &c->pg_xs};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (Tiling& t : c->tl)
@@ -1402,7 +1403,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
       e = launch_chol_solve<T>(ws.S, ws.rhs, n, perm ? (T*)c->sys_x.p : dx, (T*)c->wy.p, (T*)c->Linv.p, ws.d0,
                                status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st,
                                c->coop_launch, reach_of(c, n));
-      if (e == hipSuccess && perm) e = launch_permute6<T>((const T*)c->sys_x.p, dx, perm, c->n_free, 0, st);
+      if (e == hipSuccess && perm) e = launch_permute_blocks<T>((const T*)c->sys_x.p, dx, perm, c->n_free, 6, 0, st);
     }
     if (e != hipSuccess) return e;
     {
@@ -1573,7 +1574,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       const int* perm = sys_perm_of(c);
       if ((e = launch_step_to_f32(x64, perm ? c32 : dx, n, fb + it, status64 + it, status + it, st)) != hipSuccess)
         return e;
-      if (perm && (e = launch_permute6<float>(c32, dx, perm, c->n_free, 0, st)) != hipSuccess) return e;
+      if (perm && (e = launch_permute_blocks<float>(c32, dx, perm, c->n_free, 6, 0, st)) != hipSuccess) return e;
     }
     {
       TraceScope ts(c, DPVBA_PHASE_RETRACT, st);
@@ -1751,7 +1752,7 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
                                   next_epoch(c), err, c->host_err_dev, st, c->coop_launch, reach_of(c, n))) !=
         hipSuccess)
       return e;
-    if (perm && (e = launch_permute6<T>(xs, DX + (size_t)it * n, perm, c->n_free, 0, st)) != hipSuccess) return e;
+    if (perm && (e = launch_permute_blocks<T>(xs, DX + (size_t)it * n, perm, c->n_free, 6, 0, st)) != hipSuccess) return e;
     if ((e = launch_retract_copy<T>(xt, xt + np7, DX + (size_t)it * n, nf, N, status + it, st)) != hipSuccess)
       return e;
   }
@@ -1776,13 +1777,13 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
                                    (T*)c->part_vec.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
                                    dxbar, stt, urhs, st)) != hipSuccess)
       return e;
-    if (perm && (e = launch_permute6<T>(urhs, bs, perm, c->n_free, 1, st)) != hipSuccess) return e;
+    if (perm && (e = launch_permute_blocks<T>(urhs, bs, perm, c->n_free, 6, 1, st)) != hipSuccess) return e;
     if ((e = launch_chol_solve<T>((T*)c->S.p, perm ? bs : urhs, n, perm ? xs : up, (T*)c->wy.p, (T*)c->Linv.p,
                                   (const T*)c->d0.p, status + DPVBA_MAX_ITERS + it, mb + DPVBA_MAX_ITERS + it,
                                   (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st, c->coop_launch,
                                   reach_of(c, n))) != hipSuccess)
       return e;
-    if (perm && (e = launch_permute6<T>(xs, up, perm, c->n_free, 0, st)) != hipSuccess) return e;
+    if (perm && (e = launch_permute_blocks<T>(xs, up, perm, c->n_free, 6, 0, st)) != hipSuccess) return e;
     if ((e = launch_adjoint_backsub<T>(tiles, tl.n_tiles, tl.max_w6, (const int*)tl.blk_pose.p,
                                        (const T*)c->U_s.p, (const T*)c->pscale_s.p, dbar, up, dx_t, stt, ud, dd,
                                        st)) != hipSuccess)
@@ -1834,16 +1835,44 @@ dpvba_status dpvba_pgo_sim3(dpvba_ctx* c, int32_t n_frames, int32_t n_fixed, con
   std::vector<int32_t> ea(std::max(E, 1)), eb(std::max(E, 1));
   for (int e = 0; e < n_frames - 1; ++e) { ea[e] = e; eb[e] = e + 1; }
   for (int l = 0; l < n_loops; ++l) { ea[n_frames - 1 + l] = loop_j[l]; eb[n_frames - 1 + l] = loop_k[l]; }
-  // block lists of the free poses' normal equations, contributions in residual order
+  // order of the free poses in the normal equations: a reverse Cuthill-McKee
+  // order where it shrinks the envelope (loop closures couple poses far
+  // apart in time), else their own; pos[f] = block row of free pose f
+  std::vector<int32_t> pos(std::max(nf, 0)), order;
+  for (int f = 0; f < nf; ++f) pos[f] = f;
+  if (nf > 0) {
+    std::vector<std::vector<int32_t>> adj(nf);
+    for (int e = 0; e < E; ++e) {
+      const int fa = ea[e] - n_fixed, fb = eb[e] - n_fixed;
+      if (fa >= 0 && fb >= 0 && fa != fb) {
+        adj[fa].push_back(fb);
+        adj[fb].push_back(fa);
+      }
+    }
+    for (auto& a : adj) {
+      std::sort(a.begin(), a.end());
+      a.erase(std::unique(a.begin(), a.end()), a.end());
+    }
+    const std::vector<int32_t> cand = rcm_order(adj);
+    std::vector<int32_t> cpos(nf);
+    for (int p = 0; p < nf; ++p) cpos[cand[p]] = p;
+    if (envelope_cost(first_coupled(adj, cpos)) < 0.9 * envelope_cost(first_coupled(adj, pos))) {
+      order = cand;
+      pos = cpos;
+    }
+  }
+  // block lists of the free poses' normal equations (at their block rows),
+  // contributions in residual order
   std::map<std::pair<int, int>, std::vector<int32_t>> blocks;
   std::vector<std::vector<int32_t>> pose_list(std::max(nf, 0));
   for (int e = 0; e < E; ++e) {
     const int fa = ea[e] - n_fixed, fb = eb[e] - n_fixed;
-    if (fa >= 0) { blocks[{fa, fa}].push_back(4 * e + 0); pose_list[fa].push_back(2 * e); }
-    if (fb >= 0) { blocks[{fb, fb}].push_back(4 * e + 3); pose_list[fb].push_back(2 * e + 1); }
+    const int pa = fa >= 0 ? pos[fa] : -1, pb = fb >= 0 ? pos[fb] : -1;
+    if (fa >= 0) { blocks[{pa, pa}].push_back(4 * e + 0); pose_list[pa].push_back(2 * e); }
+    if (fb >= 0) { blocks[{pb, pb}].push_back(4 * e + 3); pose_list[pb].push_back(2 * e + 1); }
     if (fa >= 0 && fb >= 0) {
-      if (fa > fb) blocks[{fa, fb}].push_back(4 * e + 1);
-      else blocks[{fb, fa}].push_back(4 * e + 2);
+      if (pa > pb) blocks[{pa, pb}].push_back(4 * e + 1);
+      else blocks[{pb, pa}].push_back(4 * e + 2);
     }
   }
   std::vector<int32_t> blk_pq, blk_off{0}, blk_src, pose_off{0}, pose_src;
@@ -1866,6 +1895,7 @@ dpvba_status dpvba_pgo_sim3(dpvba_ctx* c, int32_t n_frames, int32_t n_fixed, con
     c->pg_plan.n = 0;
     HIP_TRY(build_plan(fq, 7, (int)n, c->pg_plan, st));
   }
+  if (!order.empty()) HIP_TRY(upload(c->pg_perm, order, st));
   HIP_TRY(upload(c->pg_ea, ea, st));
   HIP_TRY(upload(c->pg_eb, eb, st));
   HIP_TRY(upload(c->pg_blk_pq, blk_pq, st));
@@ -1879,6 +1909,7 @@ dpvba_status dpvba_pgo_sim3(dpvba_ctx* c, int32_t n_frames, int32_t n_fixed, con
   HIP_TRY(ensure(c->pg_H, std::max<size_t>(n * n, 1) * 8));
   HIP_TRY(ensure(c->pg_rhs, std::max<size_t>(n, 1) * 8));
   HIP_TRY(ensure(c->pg_dx, std::max<size_t>(n, 1) * 8));
+  HIP_TRY(ensure(c->pg_xs, std::max<size_t>(n, 1) * 8));
   HIP_TRY(ensure(c->pg_d0, std::max<size_t>(n, 1) * 8));
   HIP_TRY(ensure(c->pg_wy, std::max<size_t>(n, 1) * 8));
   HIP_TRY(ensure(c->pg_Linv, std::max<size_t>(nblk64, 1) * 64 * 64 * 8));
@@ -1907,10 +1938,14 @@ dpvba_status dpvba_pgo_sim3(dpvba_ctx* c, int32_t n_frames, int32_t n_fixed, con
                               (const int*)c->pg_pose_off.p, (const int*)c->pg_pose_src.p, nf, lambda, lam_diag, H,
                               (double*)c->pg_d0.p, (double*)c->pg_rhs.p, st));
     c->pg_epoch = c->pg_epoch >= 0x3fffffff ? 1 : c->pg_epoch + 1;
-    HIP_TRY(launch_chol_solve<double>(H, (const double*)c->pg_rhs.p, (int)n, (double*)c->pg_dx.p,
+    const bool perm = !order.empty();
+    HIP_TRY(launch_chol_solve<double>(H, (const double*)c->pg_rhs.p, (int)n, (double*)(perm ? c->pg_xs.p : c->pg_dx.p),
                                       (double*)c->pg_wy.p, (double*)c->pg_Linv.p, (const double*)c->pg_d0.p,
                                       status + it, (unsigned int*)c->pg_mb.p + it, (int*)c->pg_flags.p, c->pg_epoch,
                                       err, c->host_err_dev, st, c->coop_launch, &c->pg_plan.plan));
+    if (perm)
+      HIP_TRY(launch_permute_blocks<double>((const double*)c->pg_xs.p, (double*)c->pg_dx.p, (const int*)c->pg_perm.p,
+                                            nf, 7, 0, st));
     HIP_TRY(launch_pgo_retract(sims, n_frames, n_fixed, (const double*)c->pg_dx.p, status + it, st));
   }
   HIP_TRY(launch_pgo_linearise(sims, (const double*)c->pg_C.p, (const int*)c->pg_ea.p, (const int*)c->pg_eb.p, E,

@@ -230,23 +230,24 @@ hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, c
                                 mirror, diag_out, st, pos);
 }
 
-// Six-row blocks between the poses' order and a permuted system order:
-// block p of the system is free pose perm[p].  to_system: dst[p] = src[perm[p]];
-// else dst[perm[p]] = src[p].
+// Row blocks of width bw between the poses' order and a permuted system
+// order: block p of the system is pose perm[p].  to_system: dst block p =
+// src block perm[p]; else dst block perm[p] = src block p.
 template <typename T>
-__global__ void permute6_kernel(const T* src, T* dst, const int* perm, int n_free, int to_system) {
+__global__ void permute_blocks_kernel(const T* src, T* dst, const int* perm, int n_blk, int bw, int to_system) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= 6 * n_free) return;
-  const int p = x / 6, m = x - 6 * p, q = 6 * perm[p] + m;
+  if (x >= bw * n_blk) return;
+  const int p = x / bw, m = x - bw * p, q = bw * perm[p] + m;
   if (to_system) dst[x] = src[q];
   else dst[q] = src[x];
 }
 
 template <typename T>
-hipError_t launch_permute6(const T* src, T* dst, const int* perm, int n_free, int to_system, hipStream_t st) {
-  if (n_free == 0) return hipSuccess;
-  hipLaunchKernelGGL((permute6_kernel<T>), dim3((6 * n_free + 255) / 256), dim3(256), 0, st, src, dst, perm, n_free,
-                     to_system);
+hipError_t launch_permute_blocks(const T* src, T* dst, const int* perm, int n_blk, int bw, int to_system,
+                                 hipStream_t st) {
+  if (n_blk == 0) return hipSuccess;
+  hipLaunchKernelGGL((permute_blocks_kernel<T>), dim3((bw * n_blk + 255) / 256), dim3(256), 0, st, src, dst, perm,
+                     n_blk, bw, to_system);
   return hipGetLastError();
 }
 
@@ -293,7 +294,7 @@ template hipError_t launch_gather<double>(const double*, const double*, const in
 template hipError_t launch_gather_as<float, double>(const float*, const float*, const int*, const int*,
                                                     const int*, const int2*, int, double*, double*, double*,
                                                     double, double, int, double*, hipStream_t, const int*);
-template hipError_t launch_permute6<float>(const float*, float*, const int*, int, int, hipStream_t);
-template hipError_t launch_permute6<double>(const double*, double*, const int*, int, int, hipStream_t);
+template hipError_t launch_permute_blocks<float>(const float*, float*, const int*, int, int, int, hipStream_t);
+template hipError_t launch_permute_blocks<double>(const double*, double*, const int*, int, int, int, hipStream_t);
 
 }  // namespace dpvba

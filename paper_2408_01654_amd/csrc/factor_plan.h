@@ -1,4 +1,4 @@
-// Sparsity plan of the float32 blocked Cholesky of the reduced camera
+// Sparsity plan of the blocked Cholesky of the reduced camera
 // system, built by the analysis from the structure of S (which 6 x 6 blocks
 // any tile contributes to).  Row r's envelope starts at the first column of
 // the first pose block its pose shares a patch with; Cholesky fill stays
@@ -7,8 +7,9 @@
 // panel can be non-zero.  The factor solves and updates only those: the
 // 64-row blocks and 128-row tiles below the panel's diagonal block that hold
 // such a row (block / tile indices count from t0 = 64 (k + 1)); every other
-// update is an exact zero.  Host arrays have one entry per panel (offsets one
-// more); the lists themselves are in device memory.
+// update is an exact zero (float32 factors also stop each panel at its
+// reach).  Host arrays have one entry per panel (offsets one more); the
+// lists themselves are in device memory.
 #pragma once
 
 namespace dpvba {
