@@ -86,7 +86,7 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
                              int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0,
-                             bool cooperative = false);
+                             bool cooperative = false, const PanelPlan* plan = nullptr);
 // mixed-precision helpers (mixed.hip)
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st);
@@ -282,7 +282,7 @@ static int writeback_lds_bytes(const Tiling& tl, int tsize) {
 // Host side of a factor plan (factor_plan.h) and its device lists.
 struct PlanStore {
   std::vector<int32_t> reach, tiles_off, blocks_off;
-  DevBuf tiles, blocks;
+  DevBuf tiles, blocks, chain_lo, chain_hi;
   PanelPlan plan{};
   int n = 0;  // the system size the plan is for
 };
@@ -316,14 +316,33 @@ static hipError_t build_plan(const std::vector<int32_t>& fq, int bw, int n, Plan
   }
   if (tl.empty()) tl.push_back(0);
   if (bl.empty()) bl.push_back(0);
+  // triangular-solve ranges per pair of 64-row blocks: block I's rows start
+  // at column block fcb[I] (the envelope), and the rows that reach block
+  // k's columns end at reach[k] (non-decreasing in k)
+  std::vector<int32_t> fcb(np);
+  for (int I = 0; I < np; ++I) {
+    int lo = I;
+    for (int Pp = (64 * I) / bw; Pp * bw < std::min(64 * I + 64, n); ++Pp) lo = std::min(lo, (bw * fq[Pp]) / 64);
+    fcb[I] = lo;
+  }
+  const int npair = (np + 1) / 2;
+  std::vector<int32_t> plo(npair), phi(npair);
+  for (int Q = 0; Q < npair; ++Q) {
+    const int I0 = 2 * Q, I1 = std::min(2 * Q + 1, np - 1);
+    plo[Q] = std::min(fcb[I0], fcb[I1]) / 2;
+    phi[Q] = std::max(Q, std::min(npair - 1, (reach[I1] - 1) / 128));
+  }
   hipError_t e;
+  if ((e = upload(ps.chain_lo, plo, st)) != hipSuccess) return e;
+  if ((e = upload(ps.chain_hi, phi, st)) != hipSuccess) return e;
   if ((e = upload(ps.tiles, tl, st)) != hipSuccess) return e;
   if ((e = upload(ps.blocks, bl, st)) != hipSuccess) return e;
   ps.reach = reach;
   ps.tiles_off = toff;
   ps.blocks_off = boff;
-  ps.plan = PanelPlan{ps.reach.data(), ps.tiles_off.data(), (const int*)ps.tiles.p, ps.blocks_off.data(),
-                      (const int*)ps.blocks.p};
+  ps.plan = PanelPlan{ps.reach.data(),          ps.tiles_off.data(),         (const int*)ps.tiles.p,
+                      ps.blocks_off.data(),      (const int*)ps.blocks.p,     (const int*)ps.chain_lo.p,
+                      (const int*)ps.chain_hi.p};
   ps.n = n;
   return hipSuccess;
 }
@@ -687,7 +706,8 @@ void dpvba_destroy(dpvba_ctx* c) {
                     &c->depth_s, &c->xh_s, &c->poses_a, &c->poses_b, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx,
                     &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
                     &c->chain_flags, &c->one_inst, &c->ba_plan.tiles, &c->ba_plan.blocks, &c->pg_plan.tiles,
-                    &c->pg_plan.blocks, &c->sys_perm, &c->sys_pos, &c->sys_x, &c->sys_b,
+                    &c->pg_plan.blocks, &c->ba_plan.chain_lo, &c->ba_plan.chain_hi, &c->pg_plan.chain_lo,
+                    &c->pg_plan.chain_hi, &c->sys_perm, &c->sys_pos, &c->sys_x, &c->sys_b,
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
                     &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
                     &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
@@ -1542,14 +1562,16 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
           hipSuccess)
         return e;
       if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
-                                    next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch)) != hipSuccess)
+                                    next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch, reach_of(c, n))) !=
+          hipSuccess)
         return e;
       if ((e = launch_convert<float, double>(c32, x64, n, st)) != hipSuccess) return e;
       for (int k = 0; k < n_refine; ++k) {
         if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
         if ((e = launch_convert<double, float>(r64, rhs32, n, st)) != hipSuccess) return e;
         if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
-                                      next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch)) != hipSuccess)
+                                      next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch, reach_of(c, n))) !=
+            hipSuccess)
           return e;
         if ((e = launch_accumulate(x64, c32, n, st)) != hipSuccess) return e;
       }

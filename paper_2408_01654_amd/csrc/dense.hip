@@ -600,6 +600,9 @@ syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_ne
 // workgroup's wait (or a grid barrier of the call) has expired, but not for an
 // input-range report, which leaves the arithmetic valid.  The L blocks are loaded before the wait
 // for the vector they multiply, so the chain only carries the dependent part.
+// With pair_lo / pair_hi (a factor plan's envelope) a pair takes only the
+// earlier pairs from pair_lo[Q] (forward) and the later ones up to
+// pair_hi[Q] (backward): the other blocks of L it would multiply are zero.
 constexpr long long kChainSpin = 1LL << 22;
 
 __device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err, int* host_err) {
@@ -634,7 +637,8 @@ __device__ __forceinline__ void chain_publish(int* flag, int epoch) {
 template <typename T>
 __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, const T* Linv_all, const T* b, T* y,
                                                          T* x, int* flags, int epoch, int* err, int* host_err,
-                                                         int backward_only) {
+                                                         int backward_only, const int* pair_lo,
+                                                         const int* pair_hi) {
   __shared__ T Li[2][kNB][kNB + 1];  // inverses of the pair's diagonal blocks
   __shared__ T acc[2][kNB];
   __shared__ T vk[2][kNB];
@@ -664,7 +668,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
     T lc[16];  // L_{I1, I0}: the in-pair block
 #pragma unroll
     for (int m = 0; m < 16; ++m) lc[m] = r < rows1 ? L[(size_t)(i1 + r) * n + i0 + 16 * q + m] : (T)0;
-    for (int P = 0; P < Q; ++P) {
+    for (int P = pair_lo ? pair_lo[Q] : 0; P < Q; ++P) {
       const int k0 = 2 * P * kNB;  // both blocks of an earlier pair are full
       T la[32], lb[32];
 #pragma unroll
@@ -749,7 +753,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
       const int rr = 16 * q + m;
       lc[m] = (rr < rows1 && c < rows0) ? L[(size_t)(i1 + rr) * n + i0 + c] : (T)0;
     }
-    for (int P = npair - 1; P > Q; --P) {
+    for (int P = pair_hi ? pair_hi[Q] : npair - 1; P > Q; --P) {
       const int K0 = 2 * P, K1 = 2 * P + 1;
       const int k0 = K0 * kNB, kb0 = min(kNB, n - k0);
       const int k1 = K1 * kNB, kb1 = K1 < nblk ? min(kNB, n - k1) : 0;
@@ -916,17 +920,20 @@ int trsv_chain_grid(int nblk) {
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
                              int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0,
-                             bool cooperative = false) {
+                             bool cooperative = false, const PanelPlan* plan = nullptr) {
   const int nblk = (n + kNB - 1) / kNB;
   const int grid = trsv_chain_grid<T>(nblk);
   if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
+  const int* pair_lo = plan ? plan->chain_lo : nullptr;
+  const int* pair_hi = plan ? plan->chain_hi : nullptr;
   if (!cooperative) {
     hipLaunchKernelGGL((trsv_chain_kernel<T>), dim3(grid), dim3(256), 0, st, L, n, Linv_all, rhs, work_y, x, flags,
-                       epoch, err, host_err, backward_only);
+                       epoch, err, host_err, backward_only, pair_lo, pair_hi);
     return hipGetLastError();
   }
-  void* args[] = {(void*)&L, (void*)&n, (void*)&Linv_all, (void*)&rhs, (void*)&work_y, (void*)&x, (void*)&flags,
-                  (void*)&epoch, (void*)&err, (void*)&host_err, (void*)&backward_only};
+  void* args[] = {(void*)&L,     (void*)&n,   (void*)&Linv_all, (void*)&rhs,           (void*)&work_y,
+                  (void*)&x,     (void*)&flags, (void*)&epoch,  (void*)&err,           (void*)&host_err,
+                  (void*)&backward_only, (void*)&pair_lo, (void*)&pair_hi};
   return hipLaunchCooperativeKernel((const void*)trsv_chain_kernel<T>, dim3(grid), dim3(256), args, 0, st);
 }
 
@@ -954,11 +961,11 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
     hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, yrow, rhs, n);
     e = launch_chol_factor<T>(S, n, n + 1, Linv_all, d0, status, min_bits, st, plan);
     if (e != hipSuccess) return e;
-    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1, cooperative);
+    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1, cooperative, plan);
   } else {
     e = launch_chol_factor<T>(S, n, n, Linv_all, d0, status, min_bits, st, plan);
     if (e != hipSuccess) return e;
-    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st, 0, cooperative);
+    e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, work_y, flags, epoch, err, host_err, st, 0, cooperative, plan);
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((zero_on_status_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, dx, n, status);
@@ -974,6 +981,6 @@ template hipError_t launch_chol_solve<double>(double*, const double*, int, doubl
 template hipError_t launch_chol_factor<float>(float*, int, int, float*, const float*, int*, unsigned int*,
                                               hipStream_t, const PanelPlan*);
 template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, int*, int,
-                                             int*, int*, hipStream_t, int, bool);
+                                             int*, int*, hipStream_t, int, bool, const PanelPlan*);
 
 }  // namespace dpvba

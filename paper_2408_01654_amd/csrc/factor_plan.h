@@ -8,7 +8,7 @@
 // 64-row blocks and 128-row tiles below the panel's diagonal block that hold
 // such a row (block / tile indices count from t0 = 64 (k + 1)); every other
 // update is an exact zero (float32 factors also stop each panel at its
-// reach).  Host arrays have one entry per panel (offsets one more); the
+// reach).  The triangular solves skip the blocks of L outside the envelope.  Host arrays have one entry per panel (offsets one more); the
 // lists themselves are in device memory.
 #pragma once
 
@@ -20,6 +20,11 @@ struct PanelPlan {
   const int* tiles;       // device: 128-row tile indices, ascending
   const int* blocks_off;  // host [nblk + 1]
   const int* blocks;      // device: 64-row block indices, ascending
+  // device, one entry per pair of 64-row blocks (2P, 2P + 1): the first pair
+  // whose columns the pair's rows reach (forward substitution) and the last
+  // pair whose rows reach the pair's columns (backward substitution)
+  const int* chain_lo;
+  const int* chain_hi;
 };
 
 }  // namespace dpvba
