@@ -60,6 +60,10 @@ hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, c
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
                          T lam_diag, int mirror, T* diag_out, hipStream_t st, const int* pos);
 template <typename T>
+hipError_t launch_gather_env(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
+                             const int* v_off, const int2* v_src, int n_free, const int4* env, int n_env, T* S, T* rhs,
+                             T* dB, T lambda, T lam_diag, T* diag_out, hipStream_t st, const int* pos);
+template <typename T>
 hipError_t launch_permute_blocks(const T* src, T* dst, const int* perm, int n_blk, int bw, int to_system,
                                  hipStream_t st);
 template <typename T, typename P>
@@ -376,6 +380,11 @@ struct dpvba_ctx {
   // pose sys_perm[p] (sys_pos its inverse); empty: the poses' own order
   std::vector<int32_t> sys_perm_h;
   DevBuf sys_perm, sys_pos, sys_x, sys_b;
+  // blocks of the envelope in the system order (int4: block row, block
+  // column, the poses' lower block, transposed) and the element size S was
+  // last zeroed for outside the envelope (0: not zeroed)
+  DevBuf env_blk;
+  int n_env = 0, s_env_elem = 0;
   PlanStore pg_plan;  // the last pose graph's normal equations
   DevBuf one_inst;     // the analysed problem as a one-problem batch (small mixed solves)
   int chain_epoch = 0;
@@ -452,6 +461,29 @@ static const int* sys_perm_of(const dpvba_ctx* c) {
   return !c->sys_perm_h.empty() && 6 * c->n_free > kPermuteMinUnknowns ? (const int*)c->sys_perm.p : nullptr;
 }
 static const int* sys_pos_of(const dpvba_ctx* c) { return sys_perm_of(c) ? (const int*)c->sys_pos.p : nullptr; }
+
+// Gather of the large path's damped reduced system into the context's S in
+// the system order: only the envelope's blocks (the rest of S zeroed once
+// per analysis and element type), or every lower block for the smaller
+// systems.
+template <typename T>
+static hipError_t gather_system(dpvba_ctx* c, const Tiling& tl, const T* part_S, const T* part_vec, T* S, T* rhs,
+                                T lambda, T lam_diag, T* d0, hipStream_t st) {
+  const int n = 6 * c->n_free;
+  if (c->n_env > 0 && n > kPermuteMinUnknowns && S == (T*)c->S.p) {
+    if (c->s_env_elem != (int)sizeof(T)) {
+      hipError_t e = launch_fill<T>(S, (long long)n * n, (T)0, st);
+      if (e != hipSuccess) return e;
+      c->s_env_elem = (int)sizeof(T);
+    }
+    return launch_gather_env<T>(part_S, part_vec, (const int*)tl.s_off.p, (const int*)tl.s_src.p,
+                                (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free, (const int4*)c->env_blk.p,
+                                c->n_env, S, rhs, (T*)c->dB.p, lambda, lam_diag, d0, st, sys_pos_of(c));
+  }
+  return launch_gather<T>(part_S, part_vec, (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
+                          (const int2*)tl.v_src.p, c->n_free, S, rhs, (T*)c->dB.p, lambda, lam_diag, 0, d0, st,
+                          sys_pos_of(c));
+}
 
 // Block row P of a symmetric block pattern starts at block column fq[P]
 // (<= P): fill of a Cholesky factor stays between it and the diagonal.
@@ -707,7 +739,7 @@ void dpvba_destroy(dpvba_ctx* c) {
                     &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
                     &c->chain_flags, &c->one_inst, &c->ba_plan.tiles, &c->ba_plan.blocks, &c->pg_plan.tiles,
                     &c->pg_plan.blocks, &c->ba_plan.chain_lo, &c->ba_plan.chain_hi, &c->pg_plan.chain_lo,
-                    &c->pg_plan.chain_hi, &c->sys_perm, &c->sys_pos, &c->sys_x, &c->sys_b,
+                    &c->pg_plan.chain_hi, &c->sys_perm, &c->sys_pos, &c->sys_x, &c->sys_b, &c->env_blk,
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
                     &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
                     &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
@@ -1042,6 +1074,20 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
     }
     c->ba_plan.n = 0;
     HIP_TRY(build_plan(fq, 6, 6 * n_free, c->ba_plan, st));
+    c->n_env = 0;
+    c->s_env_elem = 0;
+    if (6 * n_free > kPermuteMinUnknowns) {
+      std::vector<int32_t> env;
+      const bool perm = !c->sys_perm_h.empty();
+      for (int Ps = 0; Ps < n_free; ++Ps)
+        for (int Qs = fq[Ps]; Qs <= Ps; ++Qs) {
+          const int Pp = perm ? c->sys_perm_h[Ps] : Ps, Qq = perm ? c->sys_perm_h[Qs] : Qs;
+          const int a = std::max(Pp, Qq), b = std::min(Pp, Qq);
+          env.insert(env.end(), {Ps, Qs, (int32_t)((long long)a * (a + 1) / 2 + b), Pp < Qq ? 1 : 0});
+        }
+      HIP_TRY(upload(c->env_blk, env, st));
+      c->n_env = (int)(env.size() / 4);
+    }
   }
   {
     // both plans list the patches in the same order (frame, then patch id)
@@ -1413,9 +1459,10 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
       TraceScope ts(c, DPVBA_PHASE_GATHER, st);
       e = launch_report_reduce(ws.part_cost, ws.part_invalid, tl.n_tiles, &dev->cost[it], &dev->n_invalid[it], st);
       if (e == hipSuccess)
-        e = launch_gather<T>(ws.part_S, ws.part_vec, (const int*)tl.s_off.p,
-                             (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
-                             ws.S, ws.rhs, (T*)c->dB.p, lambda, lam_diag, 0, ws.d0, st, perm ? sys_pos_of(c) : nullptr);
+        e = !ws_in ? gather_system<T>(c, tl, ws.part_S, ws.part_vec, ws.S, ws.rhs, lambda, lam_diag, ws.d0, st)
+                   : launch_gather<T>(ws.part_S, ws.part_vec, (const int*)tl.s_off.p, (const int*)tl.s_src.p,
+                                    (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free, ws.S, ws.rhs,
+                                    (T*)c->dB.p, lambda, lam_diag, 0, ws.d0, st, nullptr);
     }
     if (e != hipSuccess) return e;
     {
@@ -1517,6 +1564,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
                                             (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
                                             (const int2*)tl.v_src.p, c->n_free, S64, s64, (double*)c->dB.p,
                                             (double)lambda, (double)lam_diag, 1, d064, st, sys_pos_of(c));
+      c->s_env_elem = 0;  // S now holds the whole float64 system
       if (e != hipSuccess) return e;
     }
     if (n > 0 && n <= kBatchMaxUnknowns) {
@@ -1751,10 +1799,8 @@ static hipError_t backward_impl(dpvba_ctx* c, const dpvba_graph* g, const T* pos
   if ((e = launch_report_init(status, mb, 2 * DPVBA_MAX_ITERS, st, err)) != hipSuccess) return e;
   if ((e = launch_copy<T>(poses0, Xp, np7, st)) != hipSuccess) return e;
   auto gather = [&]() {
-    return launch_gather<T>((const T*)c->part_S.p, (const T*)c->part_vec.p, (const int*)tl.s_off.p,
-                            (const int*)tl.s_src.p, (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
-                            (T*)c->S.p, (T*)c->rhs.p, (T*)c->dB.p, lambda, lam_diag, 0, (T*)c->d0.p, st,
-                            sys_pos_of(c));
+    return gather_system<T>(c, tl, (const T*)c->part_S.p, (const T*)c->part_vec.p, (T*)c->S.p, (T*)c->rhs.p, lambda,
+                            lam_diag, (T*)c->d0.p, st);
   };
   const int* perm = sys_perm_of(c);
   T* xs = (T*)c->sys_x.p;  // a solve's result in the system order

@@ -69,6 +69,38 @@ __global__ void gather_S_kernel(const TP* part_S, const int* off, const int* src
   if (mirror && row != col) S[(size_t)col * n + row] = v;
 }
 
+// Gather of the blocks inside the envelope of the reduced system in its
+// system order only (env: per block its block row and column in that order,
+// the poses' lower block it comes from and whether it is that block's
+// transpose); the entries outside the envelope are zero and stay zero
+// through the factorisation, so the caller zeroes them once.  Same sums in
+// the same order as gather_S_kernel.
+template <typename TP, typename T>
+__global__ void gather_S_env_kernel(const TP* part_S, const int* off, const int* src, const int4* env, int n_env,
+                                    int n, T* S, const T* dB, T lambda, T lam_diag, T* diag_out) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long long)n_env * 36) return;
+  const int b = (int)(g / 36), e = (int)(g % 36), r = e / 6, c = e % 6;
+  const int4 E = env[b];
+  if (E.x == E.y && r < c) return;
+  const int eo = E.w ? r * 6 + c : c * 6 + r;  // the tiles store upper entries of their block pairs
+  const int lo = off[E.z], hi = off[E.z + 1];
+  T v = (T)0;
+  int q = lo;
+  for (; q + 4 <= hi; q += 4) {
+    const T v0 = (T)part_S[src[q] + eo], v1 = (T)part_S[src[q + 1] + eo];
+    const T v2 = (T)part_S[src[q + 2] + eo], v3 = (T)part_S[src[q + 3] + eo];
+    v += v0; v += v1; v += v2; v += v3;
+  }
+  for (; q < hi; ++q) v += (T)part_S[src[q] + eo];
+  const int row = 6 * E.x + r, col = 6 * E.y + c;
+  if (row == col) {
+    v += lam_diag * dB[row] + lambda;
+    if (diag_out) diag_out[row] = v;
+  }
+  S[(size_t)row * n + col] = v;
+}
+
 // Cost of every edge at an iterate, summed per block in a fixed order.
 template <typename T, typename P>
 __global__ void __launch_bounds__(256) edge_cost_kernel(const P* poses, const P* inv_depth,
@@ -223,6 +255,21 @@ hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_o
 }
 
 template <typename T>
+hipError_t launch_gather_env(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
+                             const int* v_off, const int2* v_src, int n_free, const int4* env, int n_env, T* S, T* rhs,
+                             T* dB, T lambda, T lam_diag, T* diag_out, hipStream_t st, const int* pos) {
+  if (n_free == 0) return hipSuccess;
+  const int n = 6 * n_free;
+  hipLaunchKernelGGL((gather_vec_kernel<T, T>), dim3((n + 255) / 256), dim3(256), 0, st, part_vec, v_off, v_src, n,
+                     rhs, dB, pos);
+  const long long tot = (long long)n_env * 36;
+  if (tot > 0)
+    hipLaunchKernelGGL((gather_S_env_kernel<T, T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,
+                       s_off, s_src, env, n_env, n, S, dB, lambda, lam_diag, diag_out);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_gather(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                          const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
                          T lam_diag, int mirror, T* diag_out, hipStream_t st, const int* pos) {
@@ -294,6 +341,12 @@ template hipError_t launch_gather<double>(const double*, const double*, const in
 template hipError_t launch_gather_as<float, double>(const float*, const float*, const int*, const int*,
                                                     const int*, const int2*, int, double*, double*, double*,
                                                     double, double, int, double*, hipStream_t, const int*);
+template hipError_t launch_gather_env<float>(const float*, const float*, const int*, const int*, const int*,
+                                             const int2*, int, const int4*, int, float*, float*, float*, float, float,
+                                             float*, hipStream_t, const int*);
+template hipError_t launch_gather_env<double>(const double*, const double*, const int*, const int*, const int*,
+                                              const int2*, int, const int4*, int, double*, double*, double*, double,
+                                              double, double*, hipStream_t, const int*);
 template hipError_t launch_permute_blocks<float>(const float*, float*, const int*, int, int, int, hipStream_t);
 template hipError_t launch_permute_blocks<double>(const double*, double*, const int*, int, int, int, hipStream_t);
 

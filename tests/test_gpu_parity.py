@@ -309,3 +309,23 @@ def test_global_ba_matches_oracle_golden(dp, ctx, prec):
          f"scale-aligned dt {dts.max():.3e} (scale {sc - 1:+.2e})")
     tol = TOL[prec]
     assert dr.max() < tol and dt.max() < tol and rel.max() < tol
+
+
+def test_precisions_in_turn_after_one_analysis(dp, ctx):
+    # one analysis, then float32, float64, mixed, float64, float32 solves on
+    # the same context: the large path's reduced system buffer is shared by
+    # the precisions (and only the envelope is gathered into it), so each
+    # solve must start from a clean system whatever the previous one left
+    from scenes import make_sweep
+    s = make_sweep(200, total_patches=9600)
+    Po, Do, _ = ba64.solve_scene(s)
+    g = dp.GraphTensors.from_scene(s)
+    ctx.analyze(g)
+    for prec in ("fp32", "fp64", "mixed", "fp64", "fp32"):
+        dt = torch.float64 if PREC[prec] == dp.FP64 else torch.float32
+        poses = torch.as_tensor(s.poses, dtype=dt).cuda().contiguous()
+        depth = torch.as_tensor(s.inv_depth, dtype=dt).cuda().contiguous()
+        rep = ctx.solve(g, poses, depth, n_iters=s.n_iters, lam=s.lam, z_min=s.z_min, precision=PREC[prec])
+        assert rep["status"] == 0
+        _compare(s, poses.double().cpu().numpy(), depth.double().cpu().numpy(), Po, Do, TOL[prec],
+                 f"in turn {prec}")
