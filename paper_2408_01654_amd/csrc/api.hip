@@ -30,8 +30,8 @@ hipError_t launch_tile_finalize(const TileInfo* tiles, int n_tiles, int lds_byte
                                 const T* dx, const int* status, int status_stride, T* depth_out,
                                 const T* poses_final, T* poses_out, int n_frames, hipStream_t st);
 template <typename T>
-hipError_t launch_retract_copy(const T* poses_cur, T* poses_next, const T* dx, int n_fixed, int n_frames,
-                               const int* status, hipStream_t st);
+hipError_t launch_retract_copy(const T* poses_cur, T* poses_next, T* dx, int n_fixed, int n_frames,
+                               const int* status, hipStream_t st, const T* dx_sys = nullptr, const int* pos = nullptr);
 template <typename T>
 int small_solve_grid(int lds_bytes);
 template <typename T>
@@ -1402,6 +1402,8 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
   // the large iterations solve in the system order (workspaces of the
   // context's own only)
   const int* perm = ws_in ? nullptr : sys_perm_of(c);
+  // the float32 blocked factor takes s as row n of S: gather it there
+  T* rhs_s = !ws_in && sizeof(T) == 4 && n > small_solve_max_n(4) ? ws.S + (size_t)n * n : ws.rhs;
   hipError_t e;
   // the call's failure word: that of the single launch's parity, else the large path's
   const int parity = (int)(c->small_launches & 1);
@@ -1459,7 +1461,7 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
       TraceScope ts(c, DPVBA_PHASE_GATHER, st);
       e = launch_report_reduce(ws.part_cost, ws.part_invalid, tl.n_tiles, &dev->cost[it], &dev->n_invalid[it], st);
       if (e == hipSuccess)
-        e = !ws_in ? gather_system<T>(c, tl, ws.part_S, ws.part_vec, ws.S, ws.rhs, lambda, lam_diag, ws.d0, st)
+        e = !ws_in ? gather_system<T>(c, tl, ws.part_S, ws.part_vec, ws.S, rhs_s, lambda, lam_diag, ws.d0, st)
                    : launch_gather<T>(ws.part_S, ws.part_vec, (const int*)tl.s_off.p, (const int*)tl.s_src.p,
                                     (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free, ws.S, ws.rhs,
                                     (T*)c->dB.p, lambda, lam_diag, 0, ws.d0, st, nullptr);
@@ -1467,15 +1469,16 @@ static hipError_t solve_impl(dpvba_ctx* c, const dpvba_graph* g, T* poses, T* de
     if (e != hipSuccess) return e;
     {
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
-      e = launch_chol_solve<T>(ws.S, ws.rhs, n, perm ? (T*)c->sys_x.p : dx, (T*)c->wy.p, (T*)c->Linv.p, ws.d0,
+      e = launch_chol_solve<T>(ws.S, rhs_s, n, perm ? (T*)c->sys_x.p : dx, (T*)c->wy.p, (T*)c->Linv.p, ws.d0,
                                status + it, mb + it, (int*)c->chain_flags.p, next_epoch(c), err, c->host_err_dev, st,
                                c->coop_launch, reach_of(c, n));
-      if (e == hipSuccess && perm) e = launch_permute_blocks<T>((const T*)c->sys_x.p, dx, perm, c->n_free, 6, 0, st);
     }
     if (e != hipSuccess) return e;
     {
       TraceScope ts(c, DPVBA_PHASE_RETRACT, st);
-      e = launch_retract_copy<T>(cur, next, dx, c->n_fixed, c->N, status + it, st);
+      // perm: the step leaves the system order here (stored into dx)
+      e = launch_retract_copy<T>(cur, next, dx, c->n_fixed, c->N, status + it, st, perm ? (const T*)c->sys_x.p : nullptr,
+                                 perm ? sys_pos_of(c) : nullptr);
     }
     if (e != hipSuccess) return e;
   }

@@ -7,25 +7,49 @@
 
 namespace dpvba {
 
-// Gather of the per-tile vectors into the right-hand side s and Diag(B).
-// The shares (type TP) are summed in the output type T, so float shares
-// gathered into double are combined without further rounding error.  With
-// pos, free pose P's rows go to block row pos[P] (a symmetric permutation
-// of the system; null: the poses' own order).
+// Gather of the per-tile vectors into the right-hand side s and Diag(B):
+// one wavefront per free pose P, lane l summing the pose's shares l, l + 64,
+// ... (six right-hand-side and six Diag(B) entries each), then a butterfly
+// over the lanes; fixed order, so the result is reproducible.  The shares
+// (type TP) are summed in the output type T, so float shares gathered into
+// double are combined without further rounding error.  With pos, free pose
+// P's rows go to block row pos[P] (a symmetric permutation of the system;
+// null: the poses' own order).
 template <typename TP, typename T>
-__global__ void gather_vec_kernel(const TP* part_vec, const int* off, const int2* src, int n, T* rhs,
-                                  T* dB, const int* pos) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n) return;
-  const int P_ = x / 6, m = x % 6;
-  const int xd = pos ? 6 * pos[P_] + m : x;
-  T v = (T)0, d = (T)0;
-  for (int q = off[P_]; q < off[P_ + 1]; ++q) {
-    v += (T)part_vec[src[q].x + m];
-    d += (T)part_vec[src[q].y + m];
+__global__ void __launch_bounds__(256) gather_vec_kernel(const TP* part_vec, const int* off, const int2* src,
+                                                         int n_free, T* rhs, T* dB, const int* pos) {
+  const int P_ = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (P_ >= n_free) return;
+  T v[6], d[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) v[m] = d[m] = (T)0;
+  for (int q = off[P_] + lane; q < off[P_ + 1]; q += 64) {
+    const int2 sq = src[q];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      v[m] += (T)part_vec[sq.x + m];
+      d[m] += (T)part_vec[sq.y + m];
+    }
   }
-  rhs[xd] = v;
-  dB[xd] = d;
+#pragma unroll
+  for (int h = 32; h >= 1; h >>= 1)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      v[m] += __shfl_xor(v[m], h);
+      d[m] += __shfl_xor(d[m], h);
+    }
+  if (lane < 6) {
+    T vv = v[0], dd = d[0];
+#pragma unroll
+    for (int m = 1; m < 6; ++m)
+      if (lane == m) {
+        vv = v[m];
+        dd = d[m];
+      }
+    const int xd = 6 * (pos ? pos[P_] : P_) + lane;
+    rhs[xd] = vv;
+    dB[xd] = dd;
+  }
 }
 
 // Gather of every lower 6x6 block (P >= Q) of the damped reduced system from
@@ -245,9 +269,8 @@ hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_o
                             const int* v_off, const int2* v_src, int n_free, T* S, T* rhs, T* dB, T lambda,
                             T lam_diag, int mirror, T* diag_out, hipStream_t st, const int* pos) {
   if (n_free == 0) return hipSuccess;
-  const int n = 6 * n_free;
-  hipLaunchKernelGGL((gather_vec_kernel<TP, T>), dim3((n + 255) / 256), dim3(256), 0, st, part_vec, v_off,
-                     v_src, n, rhs, dB, pos);
+  hipLaunchKernelGGL((gather_vec_kernel<TP, T>), dim3((n_free + 3) / 4), dim3(256), 0, st, part_vec, v_off,
+                     v_src, n_free, rhs, dB, pos);
   const long long tot = (long long)n_free * (n_free + 1) / 2 * 36;
   hipLaunchKernelGGL((gather_S_kernel<TP, T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,
                      s_off, s_src, n_free, S, dB, lambda, lam_diag, mirror, diag_out, pos);
@@ -260,8 +283,8 @@ hipError_t launch_gather_env(const T* part_S, const T* part_vec, const int* s_of
                              T* dB, T lambda, T lam_diag, T* diag_out, hipStream_t st, const int* pos) {
   if (n_free == 0) return hipSuccess;
   const int n = 6 * n_free;
-  hipLaunchKernelGGL((gather_vec_kernel<T, T>), dim3((n + 255) / 256), dim3(256), 0, st, part_vec, v_off, v_src, n,
-                     rhs, dB, pos);
+  hipLaunchKernelGGL((gather_vec_kernel<T, T>), dim3((n_free + 3) / 4), dim3(256), 0, st, part_vec, v_off, v_src,
+                     n_free, rhs, dB, pos);
   const long long tot = (long long)n_env * 36;
   if (tot > 0)
     hipLaunchKernelGGL((gather_S_env_kernel<T, T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,

@@ -958,7 +958,8 @@ hipError_t launch_chol_solve(T* S, const T* rhs, int n, T* dx, T* work_y, T* Lin
     // s appended as row n of S (which has room for n + 1 rows): the factor
     // leaves y = L^-1 s there and only the backward chain remains
     T* yrow = S + (size_t)n * n;
-    hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, yrow, rhs, n);
+    if (rhs != yrow)  // a caller may have gathered s straight into that row
+      hipLaunchKernelGGL((copy_vec_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, st, yrow, rhs, n);
     e = launch_chol_factor<T>(S, n, n + 1, Linv_all, d0, status, min_bits, st, plan);
     if (e != hipSuccess) return e;
     e = launch_chol_apply<T>(S, n, Linv_all, rhs, dx, yrow, flags, epoch, err, host_err, st, 1, cooperative, plan);

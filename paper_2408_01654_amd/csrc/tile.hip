@@ -866,18 +866,25 @@ __global__ void __launch_bounds__(kTileThreads) tile_finalize_kernel(
 
 // Pose update of the large path: x_{t+1} = x_t Exp(dxi) for free poses.
 template <typename T>
-__global__ void retract_copy_kernel(const T* poses_cur, T* poses_next, const T* dx, int n_fixed, int n_frames,
-                                    const int* status) {
+__global__ void retract_copy_kernel(const T* poses_cur, T* poses_next, T* dx, int n_fixed, int n_frames,
+                                    const int* status, const T* dx_sys, const int* pos) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_frames) return;
   const T* pc = poses_cur + 7 * (size_t)i;
   T* pn = poses_next + 7 * (size_t)i;
   for (int m = 0; m < 7; ++m) pn[m] = pc[m];
-  if (i >= n_fixed && !(status && *status)) {
-    T xi[6];
-    for (int m = 0; m < 6; ++m) xi[m] = dx[6 * (i - n_fixed) + m];
-    retract_pose<T, T>(pn, xi);
+  if (i < n_fixed) return;
+  const int f = i - n_fixed;
+  T xi[6];
+  if (dx_sys) {  // the step in the system order: free pose f's block is pos[f]; stored back in the poses' order
+    for (int m = 0; m < 6; ++m) {
+      xi[m] = dx_sys[6 * pos[f] + m];
+      dx[6 * f + m] = xi[m];
+    }
+  } else {
+    for (int m = 0; m < 6; ++m) xi[m] = dx[6 * f + m];
   }
+  if (!(status && *status)) retract_pose<T, T>(pn, xi);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -910,10 +917,10 @@ hipError_t launch_tile_finalize(const TileInfo* tiles, int n_tiles, int lds_byte
 }
 
 template <typename T>
-hipError_t launch_retract_copy(const T* poses_cur, T* poses_next, const T* dx, int n_fixed, int n_frames,
-                               const int* status, hipStream_t st) {
+hipError_t launch_retract_copy(const T* poses_cur, T* poses_next, T* dx, int n_fixed, int n_frames,
+                               const int* status, hipStream_t st, const T* dx_sys, const int* pos) {
   hipLaunchKernelGGL((retract_copy_kernel<T>), dim3((n_frames + 127) / 128), dim3(128), 0, st, poses_cur,
-                     poses_next, dx, n_fixed, n_frames, status);
+                     poses_next, dx, n_fixed, n_frames, status, dx_sys, pos);
   return hipGetLastError();
 }
 
@@ -954,7 +961,8 @@ hipError_t launch_small_solve(const SmallArgs<T>& S, int grid, int lds_bytes, bo
   template hipError_t launch_tile_finalize<T>(const TileInfo*, int, int, const int*, const int*, const T*, \
                                               const T*, const T*, const T*, const int*, int, T*, const T*, \
                                               T*, int, hipStream_t);                                       \
-  template hipError_t launch_retract_copy<T>(const T*, T*, const T*, int, int, const int*, hipStream_t);  \
+  template hipError_t launch_retract_copy<T>(const T*, T*, T*, int, int, const int*, hipStream_t, const T*,    \
+                                             const int*);                                                  \
   template int small_solve_grid<T>(int);                                                                  \
   template hipError_t launch_small_solve<T>(const SmallArgs<T>&, int, int, bool, hipStream_t);
 
