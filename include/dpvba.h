@@ -437,6 +437,31 @@ dpvba_status dpvba_solve_backward(dpvba_ctx* ctx, const dpvba_graph* g, const fl
                                   const float* grad_poses, const float* grad_inv_depth,
                                   float* grad_target, float* grad_weight, void* stream);
 
+/* dpvba_solve and dpvba_solve_backward over n independent problems at once
+ * (the batch of sliding windows whose adjoints the update operator's
+ * training needs, Sec. 2): problem i runs on context ctxs[i], analysed for
+ * graphs[i], with the i-th entry of every array (host arrays of n device
+ * pointers; grad_poses / grad_inv_depth may be NULL, or hold NULL entries,
+ * for zero; reports NULL or n host reports).  The problems run concurrently,
+ * each on a stream of its own context, ordered after the work already on
+ * `stream`; `stream` waits for all of them.  Launches whose workgroups
+ * wait for each other are cooperative here (dpvba_set_cooperative(1) for
+ * the duration of the call), so concurrent grids cannot starve them; the
+ * single-launch solver of small problems is then slower than alone, so
+ * dpvba_solve_many pays off for large problems, and the adjoint (whose
+ * small problems need no such launch) for any.  The contexts must be
+ * distinct and on one device.  Returns the first failure
+ * (every problem is still enqueued and joined); EINVAL for a bad n or
+ * context list.                                                           */
+dpvba_status dpvba_solve_many(int32_t n, dpvba_ctx* const* ctxs, const dpvba_graph* graphs,
+                              float* const* poses, float* const* inv_depth, const dpvba_opts* opts,
+                              dpvba_report* reports, void* stream);
+dpvba_status dpvba_solve_backward_many(int32_t n, dpvba_ctx* const* ctxs, const dpvba_graph* graphs,
+                                       const float* const* poses0, const float* const* inv_depth0,
+                                       const dpvba_opts* opts, const float* const* grad_poses,
+                                       const float* const* grad_inv_depth, float* const* grad_target,
+                                       float* const* grad_weight, void* stream);
+
 /* A batch of independent problems packed back to back (many uneven
  * sliding windows, Sec. 3.1, solved together).  Host struct; the offset and
  * n_fixed arrays are host memory, the data arrays device memory.

@@ -115,6 +115,11 @@ def lib():
         L.dpvba_solve_backward.argtypes = [vp, ctypes.POINTER(Graph), vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp,
                                            vp]
         L.dpvba_solve_backward.restype = ctypes.c_int
+        L.dpvba_solve_many.argtypes = [ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp, vp]
+        L.dpvba_solve_many.restype = ctypes.c_int
+        L.dpvba_solve_backward_many.argtypes = [ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp,
+                                                vp]
+        L.dpvba_solve_backward_many.restype = ctypes.c_int
         L.dpvba_analyze_batch.argtypes = [vp, ctypes.POINTER(Batch), vp, vp]
         L.dpvba_analyze_batch.restype = ctypes.c_int
         L.dpvba_solve_batch.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, ctypes.POINTER(Opts), vp, vp]
@@ -497,6 +502,55 @@ class Context:
         return {PHASES[p]: (ms[p], ns[p], nl[p]) for p in range(n)}
 
 
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[_ptr(t).value if t is not None else None for t in ts])
+
+
+def _many_args(contexts, graphs):
+    if len(contexts) != len(graphs) or not contexts:
+        raise ValueError("one graph per context, at least one")
+    hs = (ctypes.c_void_p * len(contexts))(*[c._h for c in contexts])
+    gs = (Graph * len(graphs))(*[g.struct() for g in graphs])
+    return hs, gs
+
+
+def solve_many(contexts, graphs, poses, inv_depth, n_iters=2, lam=1e-4, z_min=0.1, precision=FP32, stream=None,
+               flags=0):
+    """dpvba_solve_many: in-place solves of several analysed problems
+    (contexts[i] analysed for graphs[i]; poses[i], inv_depth[i] as for
+    Context.solve), run concurrently; no reports."""
+    want = torch.float64 if precision == FP64 else torch.float32
+    for t in list(poses) + list(inv_depth):
+        if t.dtype != want or not t.is_contiguous():
+            raise TypeError(f"poses and inv_depth must be contiguous {want} tensors")
+    hs, gs = _many_args(contexts, graphs)
+    o = Context._opts(n_iters, lam, z_min, precision, flags)
+    _check(lib().dpvba_solve_many(len(contexts), hs, gs, _ptrs(poses), _ptrs(inv_depth), ctypes.byref(o), None,
+                                  _stream(stream)), "dpvba_solve_many", contexts[0]._h)
+
+
+def solve_backward_many(contexts, graphs, poses0, inv_depth0, grad_poses=None, grad_inv_depth=None, n_iters=2,
+                        lam=1e-4, z_min=0.1, precision=FP32, stream=None, flags=0):
+    """dpvba_solve_backward_many: Context.solve_backward of several problems,
+    run concurrently.  grad_poses / grad_inv_depth: lists (entries may be
+    None) or None.  Returns the lists of (grad_target, grad_weight)."""
+    want = torch.float64 if precision == FP64 else torch.float32
+    n = len(contexts)
+    gp = [None] * n if grad_poses is None else list(grad_poses)
+    gd = [None] * n if grad_inv_depth is None else list(grad_inv_depth)
+    for t in list(poses0) + list(inv_depth0) + gp + gd:
+        if t is not None and (t.dtype != want or not t.is_contiguous()):
+            raise TypeError(f"all arrays must be contiguous {want} tensors")
+    hs, gs = _many_args(contexts, graphs)
+    gt = [torch.empty((g.ii.shape[0], 2), dtype=want, device=p.device) for g, p in zip(graphs, poses0)]
+    gw = [torch.empty_like(t) for t in gt]
+    o = Context._opts(n_iters, lam, z_min, precision, flags)
+    _check(lib().dpvba_solve_backward_many(n, hs, gs, _ptrs(poses0), _ptrs(inv_depth0), ctypes.byref(o), _ptrs(gp),
+                                           _ptrs(gd), _ptrs(gt), _ptrs(gw), _stream(stream)),
+           "dpvba_solve_backward_many", contexts[0]._h)
+    return gt, gw
+
+
 class _BundleAdjust(torch.autograd.Function):
     """(target, weight) -> (poses, inv_depth) after n_iters iterations, with
     the adjoint of the unrolled iterations as its backward."""
@@ -535,3 +589,54 @@ def bundle_adjust(context: Context, graph: GraphTensors, poses0, inv_depth0, tar
     analysed `graph` (its index arrays); the graph's own target and weight
     are not used.  Forward and backward run in libdpvba.so."""
     return _BundleAdjust.apply(target, weight, poses0, inv_depth0, context, graph, n_iters, lam, z_min, precision)
+
+
+class _BundleAdjustMany(torch.autograd.Function):
+    """bundle_adjust over several problems: the forwards run one after
+    another on the current stream (ordinary launches: a small problem's
+    single-launch solver is fastest alone), the adjoints concurrently
+    (dpvba_solve_backward_many).  Inputs: the per-problem targets and
+    weights, then the starting points; outputs: poses and inverse depths of
+    every problem."""
+
+    @staticmethod
+    def forward(ctx, meta, *tensors):
+        contexts, graphs, n_iters, lam, z_min, precision = meta
+        n = len(contexts)
+        dt = torch.float64 if precision == FP64 else torch.float32
+        tg, wg, p0, d0 = tensors[:n], tensors[n:2 * n], tensors[2 * n:3 * n], tensors[3 * n:]
+        gs = [GraphTensors(g.n_frames, g.n_fixed, g.patches, g.ii, g.jj, g.kk,
+                           t.detach().to(torch.float32).contiguous(), w.detach().to(torch.float32).contiguous(),
+                           g.intrinsics) for g, t, w in zip(graphs, tg, wg)]
+        p0 = [p.detach().to(dt).contiguous() for p in p0]
+        d0 = [d.detach().to(dt).contiguous() for d in d0]
+        poses, ds = [p.clone() for p in p0], [d.clone() for d in d0]
+        for c, g, p, d in zip(contexts, gs, poses, ds):
+            c.solve(g, p, d, n_iters, lam, z_min, precision, report=False)
+        ctx.save_for_backward(*p0, *d0)
+        ctx.gs, ctx.contexts, ctx.args = gs, contexts, (n_iters, lam, z_min, precision)
+        ctx.dtypes = [(t.dtype, w.dtype) for t, w in zip(tg, wg)]
+        return (*poses, *ds)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        n = len(ctx.contexts)
+        saved = ctx.saved_tensors
+        p0, d0 = list(saved[:n]), list(saved[n:])
+        gp = [None if g is None else g.to(p.dtype).contiguous() for g, p in zip(grads[:n], p0)]
+        gd = [None if g is None else g.to(d.dtype).contiguous() for g, d in zip(grads[n:], d0)]
+        gt, gw = solve_backward_many(ctx.contexts, ctx.gs, p0, d0, gp, gd, *ctx.args)
+        gt = [t.to(dt[0]) for t, dt in zip(gt, ctx.dtypes)]
+        gw = [w.to(dt[1]) for w, dt in zip(gw, ctx.dtypes)]
+        return (None, *gt, *gw, *([None] * (2 * n)))
+
+
+def bundle_adjust_many(contexts, graphs, poses0, inv_depth0, targets, weights, n_iters=2, lam=1e-4, z_min=0.1,
+                       precision=FP32):
+    """bundle_adjust for several problems at once (contexts[i] has analysed
+    graphs[i]): returns the lists of poses and inverse depths; the backward
+    runs the problems' adjoints concurrently."""
+    n = len(contexts)
+    out = _BundleAdjustMany.apply((list(contexts), list(graphs), n_iters, lam, z_min, precision), *targets, *weights,
+                                  *poses0, *inv_depth0)
+    return list(out[:n]), list(out[n:])

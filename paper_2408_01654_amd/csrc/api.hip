@@ -420,6 +420,10 @@ struct dpvba_ctx {
   bool tracing = false;
   int trace_every = 1;
   std::vector<hipEvent_t> ev;       // 2 per pair
+  // the context's own stream and events for the calls over many contexts
+  // (created on first use, default priority)
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_start = nullptr, aux_done = nullptr;
   std::vector<int> ev_phase;        // phase per pair
   int ev_used = 0;
   long long seen[DPVBA_N_PHASES] = {0};
@@ -753,6 +757,9 @@ void dpvba_destroy(dpvba_ctx* c) {
     for (DevBuf* b : t.bufs)
       if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->aux_start) (void)hipEventDestroy(c->aux_start);
+  if (c->aux_done) (void)hipEventDestroy(c->aux_done);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   if (c->host_flag) (void)hipHostFree(c->host_flag);
   if (c->host_err) (void)hipHostFree(c->host_err);
   {
@@ -2204,6 +2211,70 @@ dpvba_status dpvba_solve_backward(dpvba_ctx* c, const dpvba_graph* g, const floa
                                  st));
   }
   return DPVBA_OK;
+}
+
+}  // extern "C"
+
+// Runs fn(i, stream_i) for the n contexts concurrently: each on its own
+// stream, after the work already enqueued on `st`, and makes `st` wait for
+// all of them.  The contexts must be distinct (a context's workspace serves
+// one call at a time) and on one device.  Returns the first failure; the
+// joins are enqueued whatever happens.
+template <typename F>
+static dpvba_status fan_out(int32_t n, dpvba_ctx* const* ctxs, hipStream_t st, F&& fn) {
+  if (n < 1 || !ctxs) return DPVBA_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || ctxs[i]->device != ctxs[0]->device) return DPVBA_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return DPVBA_EINVAL;
+  }
+  dpvba_ctx* c = ctxs[0];  // failures of the shared steps are recorded here
+  HIP_TRY(hipSetDevice(c->device));
+  for (int i = 0; i < n; ++i) {
+    dpvba_ctx* ci = ctxs[i];
+    if (!ci->aux) HIP_TRY(hipStreamCreateWithFlags(&ci->aux, hipStreamNonBlocking));
+    if (!ci->aux_start) HIP_TRY(hipEventCreateWithFlags(&ci->aux_start, hipEventDisableTiming));
+    if (!ci->aux_done) HIP_TRY(hipEventCreateWithFlags(&ci->aux_done, hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventRecord(c->aux_start, st));
+  dpvba_status first = DPVBA_OK;
+  for (int i = 0; i < n; ++i) {
+    dpvba_ctx* ci = ctxs[i];
+    HIP_TRY(hipStreamWaitEvent(ci->aux, c->aux_start, 0));
+    // launches that wait for other workgroups of their grid go cooperative:
+    // concurrent grids could otherwise hold the slots a waiting grid needs
+    const bool coop = ci->coop_launch;
+    ci->coop_launch = true;
+    const dpvba_status rc = fn(i, (void*)ci->aux);
+    ci->coop_launch = coop;
+    if (rc != DPVBA_OK && first == DPVBA_OK) first = rc;
+    HIP_TRY(hipEventRecord(ci->aux_done, ci->aux));
+    HIP_TRY(hipStreamWaitEvent(st, ci->aux_done, 0));
+  }
+  return first;
+}
+
+extern "C" {
+
+dpvba_status dpvba_solve_many(int32_t n, dpvba_ctx* const* ctxs, const dpvba_graph* graphs, float* const* poses,
+                              float* const* inv_depth, const dpvba_opts* opts, dpvba_report* reports, void* stream) {
+  if (!graphs || !poses || !inv_depth) return DPVBA_EINVAL;
+  return fan_out(n, ctxs, (hipStream_t)stream, [&](int i, void* s) {
+    return dpvba_solve(ctxs[i], &graphs[i], poses[i], inv_depth[i], opts, reports ? &reports[i] : nullptr, s);
+  });
+}
+
+dpvba_status dpvba_solve_backward_many(int32_t n, dpvba_ctx* const* ctxs, const dpvba_graph* graphs,
+                                       const float* const* poses0, const float* const* inv_depth0,
+                                       const dpvba_opts* opts, const float* const* grad_poses,
+                                       const float* const* grad_inv_depth, float* const* grad_target,
+                                       float* const* grad_weight, void* stream) {
+  if (!graphs || !poses0 || !inv_depth0 || !grad_target || !grad_weight) return DPVBA_EINVAL;
+  return fan_out(n, ctxs, (hipStream_t)stream, [&](int i, void* s) {
+    return dpvba_solve_backward(ctxs[i], &graphs[i], poses0[i], inv_depth0[i], opts,
+                                grad_poses ? grad_poses[i] : nullptr, grad_inv_depth ? grad_inv_depth[i] : nullptr,
+                                grad_target[i], grad_weight[i], s);
+  });
 }
 
 }  // extern "C"

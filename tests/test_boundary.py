@@ -48,6 +48,15 @@ def test_null_arguments_rejected_on_host():
     assert L.dpvba_reduced_system(None, None, None, None, None, None, None, None, None) == binding.DPVBA_EINVAL
     assert L.dpvba_solve_backward(None, ctypes.byref(g), None, None, ctypes.byref(o), None, None, None, None,
                                   None) == binding.DPVBA_EINVAL
+    # calls over many contexts: an empty or missing context list is refused
+    # before anything touches a device
+    hs = (ctypes.c_void_p * 2)(None, None)
+    gs = (binding.Graph * 2)()
+    ps = (ctypes.c_void_p * 2)(None, None)
+    for n, h in ((0, hs), (2, hs), (1, None)):
+        assert L.dpvba_solve_many(n, h, gs, ps, ps, ctypes.byref(o), None, None) == binding.DPVBA_EINVAL
+        assert L.dpvba_solve_backward_many(n, h, gs, ps, ps, ctypes.byref(o), None, None, ps, ps, None) \
+            == binding.DPVBA_EINVAL
     b = binding.Batch()
     assert L.dpvba_analyze_batch(None, ctypes.byref(b), None, None) == binding.DPVBA_EINVAL
     assert L.dpvba_solve_batch(None, ctypes.byref(b), None, None, ctypes.byref(o), None, None) == binding.DPVBA_EINVAL
@@ -59,6 +68,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(binding.Graph) == 5 * 4 + 4 + 6 * 8 + 4 * 4
     assert binding.Graph.patches.offset == 24
     assert ctypes.sizeof(binding.Opts) == 32
+    assert ctypes.sizeof(binding.Tuning) == 12 and binding.Tuning.keep_order.offset == 8
     assert binding.Opts.lambda_.offset == 8
     assert binding.Report.cost.offset == 8
     assert ctypes.sizeof(binding.Report) == 8 + 33 * 8 + 32 * 4 + 32 * 8 + 32 * 8 + 32 * 4

@@ -195,3 +195,70 @@ def test_adjoint_levenberg_fp64(dp, ctx):
     et, ew = _rel(gt.cpu().numpy(), gt_o), _rel(gw.cpu().numpy(), gw_o)
     _log(f"adjoint levenberg: target rel {et:.3e} weight rel {ew:.3e}")
     assert et < TOL64 and ew < TOL64
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_many_problems_concurrently_match_one_by_one(dp, prec):
+    # dpvba_solve_many / dpvba_solve_backward_many run four windows on their
+    # contexts' own streams at once; each problem's results must be those of
+    # its own call, bit for bit (same kernels, fixed summation orders)
+    P = dp.FP64 if prec == "fp64" else dp.FP32
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    scenes = [make_config(3, i) for i in range(4)]
+    ctxs = [dp.Context(0) for _ in scenes]
+    try:
+        gs = [dp.GraphTensors.from_scene(s) for s in scenes]
+        for c, g in zip(ctxs, gs):
+            c.analyze(g)
+        p0 = [torch.as_tensor(s.poses, dtype=dt).cuda().contiguous() for s in scenes]
+        d0 = [torch.as_tensor(s.inv_depth, dtype=dt).cuda().contiguous() for s in scenes]
+        kw = dict(n_iters=2, lam=scenes[0].lam, z_min=scenes[0].z_min, precision=P)
+        pm, dm = [p.clone() for p in p0], [d.clone() for d in d0]
+        dp.solve_many(ctxs, gs, pm, dm, **kw)
+        gen = torch.Generator().manual_seed(7)
+        gp = [torch.randn(p.shape, generator=gen, dtype=dt).cuda() for p in p0]
+        gd = [None if i == 2 else torch.randn(d.shape, generator=gen, dtype=dt).cuda() for i, d in enumerate(d0)]
+        gt, gw = dp.solve_backward_many(ctxs, gs, p0, d0, gp, gd, **kw)
+        torch.cuda.synchronize()
+        for i, (c, g) in enumerate(zip(ctxs, gs)):
+            p1, d1 = p0[i].clone(), d0[i].clone()
+            c.solve(g, p1, d1, report=False, **kw)
+            t1, w1 = c.solve_backward(g, p0[i], d0[i], gp[i], gd[i], **kw)
+            torch.cuda.synchronize()
+            _log(f"many {prec} window {i}: E={g.ii.shape[0]}")
+            assert torch.equal(pm[i], p1) and torch.equal(dm[i], d1)
+            assert torch.equal(gt[i], t1) and torch.equal(gw[i], w1)
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_autograd_layer_many_fp32(dp):
+    # the layer over several windows (forwards and adjoints concurrent)
+    # against the float64 gradient oracle of each window
+    scenes = [make_config(3, i) for i in range(3)]
+    ctxs = [dp.Context(0) for _ in scenes]
+    try:
+        gs = [dp.GraphTensors.from_scene(s) for s in scenes]
+        for c, g in zip(ctxs, gs):
+            c.analyze(g)
+        tg = [g.target.clone().requires_grad_(True) for g in gs]
+        wg = [g.weight.clone().requires_grad_(True) for g in gs]
+        p0 = [torch.as_tensor(s.poses, dtype=torch.float32).cuda() for s in scenes]
+        d0 = [torch.as_tensor(s.inv_depth, dtype=torch.float32).cuda() for s in scenes]
+        s0 = scenes[0]
+        poses, ds = dp.bundle_adjust_many(ctxs, gs, p0, d0, tg, wg, n_iters=s0.n_iters, lam=s0.lam, z_min=s0.z_min)
+        loss = sum(grad64.pose_depth_loss(p, d, torch.as_tensor(s.poses_gt, dtype=torch.float32).cuda(),
+                                          torch.as_tensor(s.inv_depth_gt, dtype=torch.float32).cuda(), s.n_fixed)
+                   for p, d, s in zip(poses, ds, scenes))
+        loss.backward()
+        for i, s in enumerate(scenes):
+            L, gt_o, gw_o, _, _ = grad64.loss_and_grads(s)
+            et = _rel(tg[i].grad.double().cpu().numpy(), gt_o)
+            ew = _rel(wg[i].grad.double().cpu().numpy(), gw_o)
+            tol = _tol32(s)
+            _log(f"layer many, window {i}: target rel {et:.3e} weight rel {ew:.3e} (tol {tol:.3e})")
+            assert et < tol and ew < tol
+    finally:
+        for c in ctxs:
+            c.close()
