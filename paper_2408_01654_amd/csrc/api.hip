@@ -1158,7 +1158,7 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(ensure(c->edge_part, ((size_t)(E + 255) / 256) * 8));
   HIP_TRY(ensure(c->status, 2 * DPVBA_MAX_ITERS * 4));  // [MAX, 2 MAX): float64 fallback solves
   HIP_TRY(ensure(c->min_bits, 2 * DPVBA_MAX_ITERS * 4));
-  HIP_TRY(ensure(c->S32, n * n * 4));
+  HIP_TRY(ensure(c->S32, (n + 1) * n * 4));  // s appended as row n for the first solve
   HIP_TRY(ensure(c->x64, n * 8));
   HIP_TRY(ensure(c->r64, n * 8));
   HIP_TRY(ensure(c->rhs32, n * 4));
@@ -1615,13 +1615,15 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
       if ((e = launch_lower_to_f32(S64, S32, n, st)) != hipSuccess) return e;
       if ((e = launch_convert<double, float>(d064, d032, n, st)) != hipSuccess) return e;
-      if ((e = launch_convert<double, float>(s64, rhs32, n, st)) != hipSuccess) return e;
-      if ((e = launch_chol_factor<float>(S32, n, n, Linv32, d032, status + it, mb + it, st, reach_of(c, n))) !=
+      // s rides along as row n: the factor leaves y = L^-1 s there, so the
+      // first solve is the backward chain alone
+      float* y32 = S32 + (size_t)n * n;
+      if ((e = launch_convert<double, float>(s64, y32, n, st)) != hipSuccess) return e;
+      if ((e = launch_chol_factor<float>(S32, n, n + 1, Linv32, d032, status + it, mb + it, st, reach_of(c, n))) !=
           hipSuccess)
         return e;
-      if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
-                                    next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch, reach_of(c, n))) !=
-          hipSuccess)
+      if ((e = launch_chol_apply<float>(S32, n, Linv32, y32, c32, y32, (int*)c->chain_flags.p, next_epoch(c), err,
+                                    c->host_err_dev, st, 1, c->coop_launch, reach_of(c, n))) != hipSuccess)
         return e;
       if ((e = launch_convert<float, double>(c32, x64, n, st)) != hipSuccess) return e;
       for (int k = 0; k < n_refine; ++k) {
