@@ -63,6 +63,11 @@ template <typename T>
 hipError_t launch_gather_env(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                              const int* v_off, const int2* v_src, int n_free, const int4* env, int n_env, T* S, T* rhs,
                              T* dB, T lambda, T lam_diag, T* diag_out, hipStream_t st, const int* pos);
+template <typename TP, typename T>
+hipError_t launch_gather_env_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
+                                const int* v_off, const int2* v_src, int n_free, const int4* env, int n_env, T* S,
+                                T* rhs, T* dB, T lambda, T lam_diag, T* diag_out, hipStream_t st, const int* pos,
+                                int mirror);
 template <typename T>
 hipError_t launch_permute_blocks(const T* src, T* dst, const int* perm, int n_blk, int bw, int to_system,
                                  hipStream_t st);
@@ -94,9 +99,10 @@ hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs,
 // mixed-precision helpers (mixed.hip)
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st);
-hipError_t launch_lower_to_f32(const double* S64, float* S32, int n, hipStream_t st);
+hipError_t launch_lower_to_f32(const double* S64, float* S32, int n, hipStream_t st,
+                               const PanelPlan* env = nullptr);
 hipError_t launch_residual64(const double* S, const double* s, const double* x, int n, double* r,
-                             unsigned long long* maxes, hipStream_t st);
+                             unsigned long long* maxes, hipStream_t st, const PanelPlan* env = nullptr);
 hipError_t launch_accumulate(double* x, const float* c, int n, hipStream_t st);
 hipError_t launch_refine_decide(const unsigned long long* maxes, const int* status32, double tol, int force,
                                 double* resid_out, int* fallback_out, int* host_flag, hipStream_t st);
@@ -286,7 +292,7 @@ static int writeback_lds_bytes(const Tiling& tl, int tsize) {
 // Host side of a factor plan (factor_plan.h) and its device lists.
 struct PlanStore {
   std::vector<int32_t> reach, tiles_off, blocks_off;
-  DevBuf tiles, blocks, chain_lo, chain_hi;
+  DevBuf tiles, blocks, chain_lo, chain_hi, fq_dev, reach_dev;
   PanelPlan plan{};
   int n = 0;  // the system size the plan is for
 };
@@ -339,6 +345,8 @@ static hipError_t build_plan(const std::vector<int32_t>& fq, int bw, int n, Plan
   hipError_t e;
   if ((e = upload(ps.chain_lo, plo, st)) != hipSuccess) return e;
   if ((e = upload(ps.chain_hi, phi, st)) != hipSuccess) return e;
+  if ((e = upload(ps.fq_dev, fq, st)) != hipSuccess) return e;
+  if ((e = upload(ps.reach_dev, reach, st)) != hipSuccess) return e;
   if ((e = upload(ps.tiles, tl, st)) != hipSuccess) return e;
   if ((e = upload(ps.blocks, bl, st)) != hipSuccess) return e;
   ps.reach = reach;
@@ -346,7 +354,8 @@ static hipError_t build_plan(const std::vector<int32_t>& fq, int bw, int n, Plan
   ps.blocks_off = boff;
   ps.plan = PanelPlan{ps.reach.data(),          ps.tiles_off.data(),         (const int*)ps.tiles.p,
                       ps.blocks_off.data(),      (const int*)ps.blocks.p,     (const int*)ps.chain_lo.p,
-                      (const int*)ps.chain_hi.p};
+                      (const int*)ps.chain_hi.p, (const int*)ps.fq_dev.p,  (const int*)ps.reach_dev.p,
+                      bw};
   ps.n = n;
   return hipSuccess;
 }
@@ -385,6 +394,7 @@ struct dpvba_ctx {
   // last zeroed for outside the envelope (0: not zeroed)
   DevBuf env_blk;
   int n_env = 0, s_env_elem = 0;
+  bool s32_zeroed = false;  // S32 zero outside the envelope (mixed path)
   PlanStore pg_plan;  // the last pose graph's normal equations
   DevBuf one_inst;     // the analysed problem as a one-problem batch (small mixed solves)
   int chain_epoch = 0;
@@ -743,7 +753,8 @@ void dpvba_destroy(dpvba_ctx* c) {
                     &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
                     &c->chain_flags, &c->one_inst, &c->ba_plan.tiles, &c->ba_plan.blocks, &c->pg_plan.tiles,
                     &c->pg_plan.blocks, &c->ba_plan.chain_lo, &c->ba_plan.chain_hi, &c->pg_plan.chain_lo,
-                    &c->pg_plan.chain_hi, &c->sys_perm, &c->sys_pos, &c->sys_x, &c->sys_b, &c->env_blk,
+                    &c->pg_plan.chain_hi, &c->ba_plan.fq_dev, &c->ba_plan.reach_dev, &c->pg_plan.fq_dev,
+                    &c->pg_plan.reach_dev, &c->sys_perm, &c->sys_pos, &c->sys_x, &c->sys_b, &c->env_blk,
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,
                     &c->bw_dx, &c->bw_pbar, &c->bw_dbar, &c->bw_dxbar, &c->bw_rhs, &c->bw_up, &c->bw_ud, &c->bw_dd,
                     &c->bw_edge, &c->bw_status, &c->bw_minbits, &c->S32, &c->x64, &c->r64, &c->rhs32, &c->c32,
@@ -1083,6 +1094,7 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
     HIP_TRY(build_plan(fq, 6, 6 * n_free, c->ba_plan, st));
     c->n_env = 0;
     c->s_env_elem = 0;
+    c->s32_zeroed = false;
     if (6 * n_free > kPermuteMinUnknowns) {
       std::vector<int32_t> env;
       const bool perm = !c->sys_perm_h.empty();
@@ -1569,12 +1581,26 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
       TraceScope ts(c, DPVBA_PHASE_GATHER, st);
       e = launch_report_reduce((const double*)c->part_cost.p, (const int*)c->part_invalid.p, tl.n_tiles,
                                &dev->cost[it], &dev->n_invalid[it], st);
-      if (e == hipSuccess && n > kBatchMaxUnknowns)  // small systems are gathered by the one-problem batch
-        e = launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
-                                            (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
-                                            (const int2*)tl.v_src.p, c->n_free, S64, s64, (double*)c->dB.p,
-                                            (double)lambda, (double)lam_diag, 1, d064, st, sys_pos_of(c));
-      c->s_env_elem = 0;  // S now holds the whole float64 system
+      if (e == hipSuccess && n > kBatchMaxUnknowns) {  // small systems are gathered by the one-problem batch
+        if (c->n_env > 0) {
+          // the envelope's blocks and their mirror images; S64 zero elsewhere
+          if (c->s_env_elem != 8) {
+            if ((e = launch_fill<double>(S64, (long long)n * n, 0.0, st)) != hipSuccess) return e;
+            c->s_env_elem = 8;
+          }
+          e = launch_gather_env_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
+                                                  (const int*)tl.s_off.p, (const int*)tl.s_src.p,
+                                                  (const int*)tl.v_off.p, (const int2*)tl.v_src.p, c->n_free,
+                                                  (const int4*)c->env_blk.p, c->n_env, S64, s64, (double*)c->dB.p,
+                                                  (double)lambda, (double)lam_diag, d064, st, sys_pos_of(c), 1);
+        } else {
+          e = launch_gather_as<float, double>((const float*)c->part_S.p, (const float*)c->part_vec.p,
+                                              (const int*)tl.s_off.p, (const int*)tl.s_src.p, (const int*)tl.v_off.p,
+                                              (const int2*)tl.v_src.p, c->n_free, S64, s64, (double*)c->dB.p,
+                                              (double)lambda, (double)lam_diag, 1, d064, st, sys_pos_of(c));
+          c->s_env_elem = 0;  // S now holds the whole float64 system
+        }
+      }
       if (e != hipSuccess) return e;
     }
     if (n > 0 && n <= kBatchMaxUnknowns) {
@@ -1613,7 +1639,12 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
     }
     if (n > 0) {
       TraceScope ts(c, DPVBA_PHASE_FACTOR, st);
-      if ((e = launch_lower_to_f32(S64, S32, n, st)) != hipSuccess) return e;
+      const PanelPlan* env = c->n_env > 0 ? reach_of(c, n) : nullptr;  // envelope-limited conversion and residuals
+      if (env && !c->s32_zeroed) {
+        if ((e = launch_fill<float>(S32, (long long)n * n, 0.f, st)) != hipSuccess) return e;
+        c->s32_zeroed = true;
+      }
+      if ((e = launch_lower_to_f32(S64, S32, n, st, env)) != hipSuccess) return e;
       if ((e = launch_convert<double, float>(d064, d032, n, st)) != hipSuccess) return e;
       // s rides along as row n: the factor leaves y = L^-1 s there, so the
       // first solve is the backward chain alone
@@ -1627,7 +1658,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
         return e;
       if ((e = launch_convert<float, double>(c32, x64, n, st)) != hipSuccess) return e;
       for (int k = 0; k < n_refine; ++k) {
-        if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
+        if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st, env)) != hipSuccess) return e;
         if ((e = launch_convert<double, float>(r64, rhs32, n, st)) != hipSuccess) return e;
         if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
                                       next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch, reach_of(c, n))) !=
@@ -1635,7 +1666,7 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
           return e;
         if ((e = launch_accumulate(x64, c32, n, st)) != hipSuccess) return e;
       }
-      if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st)) != hipSuccess) return e;
+      if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st, env)) != hipSuccess) return e;
       if ((e = launch_refine_decide(maxes, status + it, kRefineTol, force_fb ? 1 : 0, resid + it, fb + it,
                                     (int*)c->mx_flag.p, st)) != hipSuccess)
         return e;

@@ -98,10 +98,11 @@ __global__ void gather_S_kernel(const TP* part_S, const int* off, const int* src
 // the poses' lower block it comes from and whether it is that block's
 // transpose); the entries outside the envelope are zero and stay zero
 // through the factorisation, so the caller zeroes them once.  Same sums in
-// the same order as gather_S_kernel.
+// the same order as gather_S_kernel.  `mirror` also writes the upper
+// triangle.
 template <typename TP, typename T>
 __global__ void gather_S_env_kernel(const TP* part_S, const int* off, const int* src, const int4* env, int n_env,
-                                    int n, T* S, const T* dB, T lambda, T lam_diag, T* diag_out) {
+                                    int n, T* S, const T* dB, T lambda, T lam_diag, T* diag_out, int mirror) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (long long)n_env * 36) return;
   const int b = (int)(g / 36), e = (int)(g % 36), r = e / 6, c = e % 6;
@@ -123,6 +124,7 @@ __global__ void gather_S_env_kernel(const TP* part_S, const int* off, const int*
     if (diag_out) diag_out[row] = v;
   }
   S[(size_t)row * n + col] = v;
+  if (mirror && row != col) S[(size_t)col * n + row] = v;
 }
 
 // Cost of every edge at an iterate, summed per block in a fixed order.
@@ -277,19 +279,28 @@ hipError_t launch_gather_as(const TP* part_S, const TP* part_vec, const int* s_o
   return hipGetLastError();
 }
 
+template <typename TP, typename T>
+hipError_t launch_gather_env_as(const TP* part_S, const TP* part_vec, const int* s_off, const int* s_src,
+                                const int* v_off, const int2* v_src, int n_free, const int4* env, int n_env, T* S,
+                                T* rhs, T* dB, T lambda, T lam_diag, T* diag_out, hipStream_t st, const int* pos,
+                                int mirror) {
+  if (n_free == 0) return hipSuccess;
+  const int n = 6 * n_free;
+  hipLaunchKernelGGL((gather_vec_kernel<TP, T>), dim3((n_free + 3) / 4), dim3(256), 0, st, part_vec, v_off, v_src,
+                     n_free, rhs, dB, pos);
+  const long long tot = (long long)n_env * 36;
+  if (tot > 0)
+    hipLaunchKernelGGL((gather_S_env_kernel<TP, T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,
+                       s_off, s_src, env, n_env, n, S, dB, lambda, lam_diag, diag_out, mirror);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gather_env(const T* part_S, const T* part_vec, const int* s_off, const int* s_src,
                              const int* v_off, const int2* v_src, int n_free, const int4* env, int n_env, T* S, T* rhs,
                              T* dB, T lambda, T lam_diag, T* diag_out, hipStream_t st, const int* pos) {
-  if (n_free == 0) return hipSuccess;
-  const int n = 6 * n_free;
-  hipLaunchKernelGGL((gather_vec_kernel<T, T>), dim3((n_free + 3) / 4), dim3(256), 0, st, part_vec, v_off, v_src,
-                     n_free, rhs, dB, pos);
-  const long long tot = (long long)n_env * 36;
-  if (tot > 0)
-    hipLaunchKernelGGL((gather_S_env_kernel<T, T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part_S,
-                       s_off, s_src, env, n_env, n, S, dB, lambda, lam_diag, diag_out);
-  return hipGetLastError();
+  return launch_gather_env_as<T, T>(part_S, part_vec, s_off, s_src, v_off, v_src, n_free, env, n_env, S, rhs, dB,
+                                    lambda, lam_diag, diag_out, st, pos, 0);
 }
 
 template <typename T>
@@ -370,6 +381,10 @@ template hipError_t launch_gather_env<float>(const float*, const float*, const i
 template hipError_t launch_gather_env<double>(const double*, const double*, const int*, const int*, const int*,
                                               const int2*, int, const int4*, int, double*, double*, double*, double,
                                               double, double*, hipStream_t, const int*);
+template hipError_t launch_gather_env_as<float, double>(const float*, const float*, const int*, const int*,
+                                                        const int*, const int2*, int, const int4*, int, double*,
+                                                        double*, double*, double, double, double*, hipStream_t,
+                                                        const int*, int);
 template hipError_t launch_permute_blocks<float>(const float*, float*, const int*, int, int, int, hipStream_t);
 template hipError_t launch_permute_blocks<double>(const double*, double*, const int*, int, int, int, hipStream_t);
 

@@ -25,6 +25,12 @@ struct PanelPlan {
   // pair whose rows reach the pair's columns (backward substitution)
   const int* chain_lo;
   const int* chain_hi;
+  // device: per block row of width bw, its first coupled block column (fq),
+  // and per 64-column panel the reach; row r's entries lie in columns
+  // [bw fq[r / bw], reach[r / 64]) of the symmetric matrix
+  const int* fq_dev;
+  const int* reach_dev;
+  int bw;
 };
 
 }  // namespace dpvba

@@ -10,6 +10,7 @@
 // float32 factorisation met a non-positive pivot) the caller re-solves with
 // a float64 Cholesky of S64.
 #include "common.h"
+#include "factor_plan.h"
 
 namespace dpvba {
 
@@ -19,26 +20,33 @@ __global__ void convert_kernel(const Ti* src, To* dst, long long n) {
   if (q < n) dst[q] = (To)src[q];
 }
 
-// Lower triangle (row-major, full storage) of S64 into S32.
-__global__ void lower_to_f32_kernel(const double* S64, float* S32, int n) {
+// Lower triangle (row-major, full storage) of S64 into S32; with an
+// envelope (fq, bw: row r starts at column bw fq[r / bw]) only the entries
+// from the row's first column on (the caller keeps S32 zero before it).
+__global__ void lower_to_f32_kernel(const double* S64, float* S32, int n, const int* fq, int bw) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (long long)n * n) return;
   const int r = (int)(q / n), c = (int)(q - (long long)r * n);
-  if (c <= r) S32[q] = (float)S64[q];
+  if (c <= r && (!fq || c >= bw * fq[r / bw])) S32[q] = (float)S64[q];
 }
 
 // r = s - S x, one wavefront per row, summed in a fixed order; the largest
 // |r_i| and |s_i| are kept as ordered bits of non-negative doubles (integer
 // maxima, independent of the order of the atomics).
+// With an envelope (fq, bw, reach) a row's non-zero entries lie in columns
+// [bw fq[row / bw], reach[row / 64]) of the symmetric S, and only those
+// are read.
 __global__ void __launch_bounds__(256) residual64_kernel(const double* S, const double* s, const double* x, int n,
                                                          double* r, unsigned long long* rmax,
-                                                         unsigned long long* smax) {
+                                                         unsigned long long* smax, const int* fq, int bw,
+                                                         const int* reach) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const double* Sr = S + (size_t)row * n;
+  const int c0 = fq ? bw * fq[row / bw] : 0, c1 = fq ? min(n, reach[row / 64]) : n;
   double v = 0.0;
-  for (int c = lane; c < n; c += 64) v += Sr[c] * x[c];
+  for (int c = c0 + lane; c < c1; c += 64) v += Sr[c] * x[c];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if (lane == 0) {
     const double rv = s[row] - v;
@@ -92,17 +100,20 @@ hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_lower_to_f32(const double* S64, float* S32, int n, hipStream_t st) {
+hipError_t launch_lower_to_f32(const double* S64, float* S32, int n, hipStream_t st, const PanelPlan* env) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(lower_to_f32_kernel, dim3(nblocks((long long)n * n, 256)), dim3(256), 0, st, S64, S32, n);
+  hipLaunchKernelGGL(lower_to_f32_kernel, dim3(nblocks((long long)n * n, 256)), dim3(256), 0, st, S64, S32, n,
+                     env ? env->fq_dev : (const int*)nullptr, env ? env->bw : 1);
   return hipGetLastError();
 }
 
 hipError_t launch_residual64(const double* S, const double* s, const double* x, int n, double* r,
-                             unsigned long long* maxes, hipStream_t st) {
+                             unsigned long long* maxes, hipStream_t st, const PanelPlan* env) {
   hipLaunchKernelGGL(clear_max_kernel, dim3(1), dim3(64), 0, st, maxes);
   if (n > 0)
-    hipLaunchKernelGGL(residual64_kernel, dim3(nblocks(n, 4)), dim3(256), 0, st, S, s, x, n, r, maxes, maxes + 1);
+    hipLaunchKernelGGL(residual64_kernel, dim3(nblocks(n, 4)), dim3(256), 0, st, S, s, x, n, r, maxes, maxes + 1,
+                       env ? env->fq_dev : (const int*)nullptr, env ? env->bw : 1,
+                       env ? env->reach_dev : (const int*)nullptr);
   return hipGetLastError();
 }
 
