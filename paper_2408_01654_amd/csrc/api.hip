@@ -95,7 +95,7 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
                              int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0,
-                             bool cooperative = false, const PanelPlan* plan = nullptr);
+                             bool cooperative = false, const PanelPlan* plan = nullptr, const int* skip = nullptr);
 // mixed-precision helpers (mixed.hip)
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti* src, To* dst, long long n, hipStream_t st);
@@ -103,7 +103,8 @@ hipError_t launch_lower_to_f32(const double* S64, float* S32, int n, hipStream_t
                                const PanelPlan* env = nullptr);
 hipError_t launch_residual64(const double* S, const double* s, const double* x, int n, double* r,
                              unsigned long long* maxes, hipStream_t st, const PanelPlan* env = nullptr);
-hipError_t launch_accumulate(double* x, const float* c, int n, hipStream_t st);
+hipError_t launch_accumulate(double* x, const float* c, int n, hipStream_t st, const int* skip = nullptr);
+hipError_t launch_refine_check(const unsigned long long* maxes, double tol, int* skip, hipStream_t st);
 hipError_t launch_refine_decide(const unsigned long long* maxes, const int* status32, double tol, int force,
                                 double* resid_out, int* fallback_out, int* host_flag, hipStream_t st);
 hipError_t launch_step_to_f32(const double* x, float* dx, int n, const int* fallback, const int* status64,
@@ -1657,14 +1658,17 @@ static hipError_t solve_mixed_impl(dpvba_ctx* c, const dpvba_graph* g, float* po
                                     c->host_err_dev, st, 1, c->coop_launch, reach_of(c, n))) != hipSuccess)
         return e;
       if ((e = launch_convert<float, double>(c32, x64, n, st)) != hipSuccess) return e;
+      int* skip = (int*)c->mx_flag.p + 1;  // set on the device once the residual meets the tolerance
       for (int k = 0; k < n_refine; ++k) {
         if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st, env)) != hipSuccess) return e;
+        // the first step is always taken; a later one only while needed
+        if (k > 0 && (e = launch_refine_check(maxes, kRefineTol, skip, st)) != hipSuccess) return e;
         if ((e = launch_convert<double, float>(r64, rhs32, n, st)) != hipSuccess) return e;
         if ((e = launch_chol_apply<float>(S32, n, Linv32, rhs32, c32, (float*)c->wy.p, (int*)c->chain_flags.p,
-                                      next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch, reach_of(c, n))) !=
-            hipSuccess)
+                                      next_epoch(c), err, c->host_err_dev, st, 0, c->coop_launch, reach_of(c, n),
+                                      k > 0 ? skip : nullptr)) != hipSuccess)
           return e;
-        if ((e = launch_accumulate(x64, c32, n, st)) != hipSuccess) return e;
+        if ((e = launch_accumulate(x64, c32, n, st, k > 0 ? skip : nullptr)) != hipSuccess) return e;
       }
       if ((e = launch_residual64(S64, s64, x64, n, r64, maxes, st, env)) != hipSuccess) return e;
       if ((e = launch_refine_decide(maxes, status + it, kRefineTol, force_fb ? 1 : 0, resid + it, fb + it,

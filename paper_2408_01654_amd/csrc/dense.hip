@@ -603,6 +603,8 @@ syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_ne
 // With pair_lo / pair_hi (a factor plan's envelope) a pair takes only the
 // earlier pairs from pair_lo[Q] (forward) and the later ones up to
 // pair_hi[Q] (backward): the other blocks of L it would multiply are zero.
+// With *skip set on the device the whole call is a no-op (every workgroup
+// returns before any wait).
 constexpr long long kChainSpin = 1LL << 22;
 
 __device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err, int* host_err) {
@@ -638,7 +640,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, const T* Linv_all, const T* b, T* y,
                                                          T* x, int* flags, int epoch, int* err, int* host_err,
                                                          int backward_only, const int* pair_lo,
-                                                         const int* pair_hi) {
+                                                         const int* pair_hi, const int* skip) {
+  if (skip && *skip) return;
   __shared__ T Li[2][kNB][kNB + 1];  // inverses of the pair's diagonal blocks
   __shared__ T acc[2][kNB];
   __shared__ T vk[2][kNB];
@@ -920,7 +923,7 @@ int trsv_chain_grid(int nblk) {
 template <typename T>
 hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs, T* x, T* work_y, int* flags,
                              int epoch, int* err, int* host_err, hipStream_t st, int backward_only = 0,
-                             bool cooperative = false, const PanelPlan* plan = nullptr) {
+                             bool cooperative = false, const PanelPlan* plan = nullptr, const int* skip = nullptr) {
   const int nblk = (n + kNB - 1) / kNB;
   const int grid = trsv_chain_grid<T>(nblk);
   if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
@@ -928,12 +931,12 @@ hipError_t launch_chol_apply(const T* L, int n, const T* Linv_all, const T* rhs,
   const int* pair_hi = plan ? plan->chain_hi : nullptr;
   if (!cooperative) {
     hipLaunchKernelGGL((trsv_chain_kernel<T>), dim3(grid), dim3(256), 0, st, L, n, Linv_all, rhs, work_y, x, flags,
-                       epoch, err, host_err, backward_only, pair_lo, pair_hi);
+                       epoch, err, host_err, backward_only, pair_lo, pair_hi, skip);
     return hipGetLastError();
   }
   void* args[] = {(void*)&L,     (void*)&n,   (void*)&Linv_all, (void*)&rhs,           (void*)&work_y,
                   (void*)&x,     (void*)&flags, (void*)&epoch,  (void*)&err,           (void*)&host_err,
-                  (void*)&backward_only, (void*)&pair_lo, (void*)&pair_hi};
+                  (void*)&backward_only, (void*)&pair_lo, (void*)&pair_hi, (void*)&skip};
   return hipLaunchCooperativeKernel((const void*)trsv_chain_kernel<T>, dim3(grid), dim3(256), args, 0, st);
 }
 
@@ -982,6 +985,6 @@ template hipError_t launch_chol_solve<double>(double*, const double*, int, doubl
 template hipError_t launch_chol_factor<float>(float*, int, int, float*, const float*, int*, unsigned int*,
                                               hipStream_t, const PanelPlan*);
 template hipError_t launch_chol_apply<float>(const float*, int, const float*, const float*, float*, float*, int*, int,
-                                             int*, int*, hipStream_t, int, bool, const PanelPlan*);
+                                             int*, int*, hipStream_t, int, bool, const PanelPlan*, const int*);
 
 }  // namespace dpvba

@@ -60,10 +60,19 @@ __global__ void clear_max_kernel(unsigned long long* m) {
   if (threadIdx.x < 2) m[threadIdx.x] = 0ull;
 }
 
-// x64 += c32
-__global__ void accumulate_kernel(double* x, const float* c, int n) {
+// x64 += c32 (nothing when *skip: that refinement step was not taken)
+__global__ void accumulate_kernel(double* x, const float* c, int n, const int* skip) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) x[q] += (double)c[q];
+  if (q < n && !(skip && *skip)) x[q] += (double)c[q];
+}
+
+// *skip = the relative residual (largest |r_i| / largest |s_i|) already
+// meets the tolerance: the remaining refinement steps are not taken.
+__global__ void refine_check_kernel(const unsigned long long* m, double tol, int* skip) {
+  if (threadIdx.x != 0) return;
+  const double rmax = __longlong_as_double((long long)m[0]);
+  const double smax = __longlong_as_double((long long)m[1]);
+  *skip = (smax > 0.0 ? rmax / smax : rmax) <= tol;
 }
 
 // Accept or fall back; records the relative residual and the decision.
@@ -117,9 +126,14 @@ hipError_t launch_residual64(const double* S, const double* s, const double* x, 
   return hipGetLastError();
 }
 
-hipError_t launch_accumulate(double* x, const float* c, int n, hipStream_t st) {
+hipError_t launch_refine_check(const unsigned long long* maxes, double tol, int* skip, hipStream_t st) {
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(64), 0, st, maxes, tol, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(double* x, const float* c, int n, hipStream_t st, const int* skip) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(accumulate_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, x, c, n);
+  hipLaunchKernelGGL(accumulate_kernel, dim3(nblocks(n, 256)), dim3(256), 0, st, x, c, n, skip);
   return hipGetLastError();
 }
 
