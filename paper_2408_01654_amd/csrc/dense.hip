@@ -31,23 +31,28 @@ template <typename T> struct Pair2 { typedef T type __attribute__((ext_vector_ty
 // rows x cols (<= 64 x 64, cols even) block at src (row stride ld) into
 // dst[64][65], zero outside: each thread issues its eight pair loads before
 // any store, so the block arrives in one memory round trip.
-template <typename T>
-__device__ __forceinline__ void load_block64(const T* src, size_t ld, int rows, int cols, T (*dst)[kNB + 1]) {
+template <typename T, int NT>
+__device__ __forceinline__ void load_block64_nt(const T* src, size_t ld, int rows, int cols, T (*dst)[kNB + 1]) {
   typedef typename Pair2<T>::type T2;
-  constexpr int PER = kNB * kNB / 2 / 256;
+  constexpr int PER = kNB * kNB / 2 / NT;
   const int tid = threadIdx.x;
   T2 v[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int q = tid + 256 * u, r = q / (kNB / 2), c = 2 * (q % (kNB / 2));
+    const int q = tid + NT * u, r = q / (kNB / 2), c = 2 * (q % (kNB / 2));
     v[u] = (r < rows && c < cols) ? *reinterpret_cast<const T2*>(src + (size_t)r * ld + c) : T2{0, 0};
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int q = tid + 256 * u, r = q / (kNB / 2), c = 2 * (q % (kNB / 2));
+    const int q = tid + NT * u, r = q / (kNB / 2), c = 2 * (q % (kNB / 2));
     dst[r][c] = v[u].x;
     dst[r][c + 1] = v[u].y;
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_block64(const T* src, size_t ld, int rows, int cols, T (*dst)[kNB + 1]) {
+  load_block64_nt<T, 256>(src, ld, rows, cols, dst);
 }
 
 __device__ __forceinline__ void pivot_min(unsigned int* min_bits, float ratio) {
@@ -317,12 +322,14 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, in
 }
 
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
-// block per workgroup, on the matrix cores: the blocks of rows [k0 + kb, R)
+// block per workgroup of eight wavefronts (two 16 x 16 output tiles each, so
+// the product's matrix-core chain is half that of four wavefronts; the
+// panel solves sit on the factor's serial path), on the matrix cores: the blocks of rows [k0 + kb, R)
 // that can be non-zero in the panel (R: the panel's reach, n for a dense
 // matrix; with a list, only the listed blocks), then the appended rows
 // [n, nrows).
 template <typename T>
-__global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int nrows, int R, int k0, int kb,
+__global__ void __launch_bounds__(512) trsm_panel_kernel(T* S, int n, int nrows, int R, int k0, int kb,
                                                          const T* Linv, const int* blocks, int n_main) {
   __shared__ T Ab[kNB][kNB + 1];
   __shared__ T Li[kNB][kNB + 1];
@@ -331,19 +338,28 @@ __global__ void __launch_bounds__(256) trsm_panel_kernel(T* S, int n, int nrows,
   const int i0 = b < n_main ? t0 + (blocks ? blocks[b] : b) * kNB : n + (b - n_main) * kNB;
   const int rows = min(kNB, (b < n_main ? R : nrows) - i0);
   const int tid = threadIdx.x;
-  load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
-  load_block64<T>(Linv, (size_t)kNB, kb, kb, Li);
+  load_block64_nt<T, 512>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
+  load_block64_nt<T, 512>(Linv, (size_t)kNB, kb, kb, Li);
   __syncthreads();
-  typename Mfma<T>::acc_t acc[4];
+  // eight wavefronts: rows 16 (w mod 4), column tiles 2 (w / 4) and 2 (w / 4) + 1
+  const int lane = tid & 63, w = tid >> 6, wr = w & 3, wc = w >> 2;
+  typename Mfma<T>::acc_t acc[2];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-  gemm_nt_64<T>(&Ab[0][0], &Li[0][0], kNB + 1, kNB, acc);
-  const int lane = tid & 63, w = tid >> 6;
+  for (int t = 0; t < 2; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  {
+    const T* xr = &Ab[0][0] + (16 * wr + (lane & 15)) * (kNB + 1) + (lane >> 4);
+    const T* yr = &Li[0][0] + (32 * wc + (lane & 15)) * (kNB + 1) + (lane >> 4);
+    for (int kk = 0; kk < kNB; kk += 4) {
+      const T a = xr[kk];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 2; ++t) acc[t] = Mfma<T>::step(a, yr[16 * t * (kNB + 1) + kk], acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = 16 * w + Mfma<T>::row(lane, v), c = 16 * t + (lane & 15);
+      const int r = 16 * wr + Mfma<T>::row(lane, v), c = 32 * wc + 16 * t + (lane & 15);
       if (r < rows && c < kb) S[(size_t)(i0 + r) * n + k0 + c] = acc[t][v];
     }
 }
@@ -873,7 +889,7 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
     const int n_main = sparse ? plan->blocks_off[k + 1] - plan->blocks_off[k]
                               : (R > t0 ? (R - t0 + kNB - 1) / kNB : 0);
     if (n_main + nrows - n > 0)
-      hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(n_main + nrows - n), dim3(256), 0, st, S, n, nrows, R, k0, kb,
+      hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(n_main + nrows - n), dim3(512), 0, st, S, n, nrows, R, k0, kb,
                          Linv, sparse ? plan->blocks + plan->blocks_off[k] : (const int*)nullptr, n_main);
     // the trailing update also factors diagonal block k + 1 (its workgroup 0)
     if constexpr (sizeof(T) == 4) {
@@ -891,7 +907,7 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
   }
   if (nrows > n) {  // the appended rows below the last diagonal block: their last panel solve
     const int k0 = (nblk - 1) * kNB;
-    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(256), 0, st, S, n, nrows, n,
+    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(512), 0, st, S, n, nrows, n,
                        k0, n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB, (const int*)nullptr, 0);
   }
   return hipGetLastError();
