@@ -442,7 +442,8 @@ dpvba_status dpvba_solve_backward(dpvba_ctx* ctx, const dpvba_graph* g, const fl
  * training needs, Sec. 2): problem i runs on context ctxs[i], analysed for
  * graphs[i], with the i-th entry of every array (host arrays of n device
  * pointers; grad_poses / grad_inv_depth may be NULL, or hold NULL entries,
- * for zero; reports NULL or n host reports).  The problems run concurrently,
+ * for zero; reports NULL or n host reports, complete once `stream` has
+ * completed).  The problems run concurrently,
  * each on a stream of its own context, ordered after the work already on
  * `stream`; `stream` waits for all of them.  Launches whose workgroups
  * wait for each other are cooperative here (dpvba_set_cooperative(1) for
