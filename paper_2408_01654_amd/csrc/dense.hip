@@ -389,14 +389,45 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
   const int i0 = t0 + I * kNB, j0 = t0 + J * kNB;
   const int ri = min(kNB, n - i0), rj = min(kNB, n - j0);
   const int tid = threadIdx.x;
-  load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, ri, kb, Li);
-  load_block64<T>(S + (size_t)j0 * n + k0, (size_t)n, rj, kb, Lj);
-  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
   typename Mfma<T>::acc_t acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  if (blk == 0 && Linv_next) {
+    // workgroup 0: the next diagonal block (pair (0, 0)), A - L_0 L_0^T formed
+    // straight into the factor's working matrix and factored at once, while
+    // the other workgroups finish the trailing update (look-ahead of one
+    // panel); the factor stores the block
+    T sv[4][4];  // the block's entries at this lane's product positions
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + Mfma<T>::row(lane, v), c = 16 * t + (lane & 15);
+        sv[t][v] = (r < ri && c <= r) ? S[(size_t)(i0 + r) * n + i0 + c] : (T)0;
+      }
+    const T ddv = tid < ri ? d0[t0 + tid] : (T)0;
+    load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, ri, kb, Li);
+    __syncthreads();
+    gemm_nt_64<T>(&Li[0][0], &Li[0][0], kNB + 1, kNB, acc);
+    __syncthreads();  // Li is overwritten by the working matrix
+    T* W = &Lij[0][0][0];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * w + Mfma<T>::row(lane, v), c = 16 * t + (lane & 15);
+        W[r * kWld + c] = diag_w_entry<T>(r, c, ri, sv[t][v] - acc[t][v]);
+      }
+    fill_diag_identity<T>(W);
+    __syncthreads();
+    diag_factor<T>(W, S, n, t0, ri, Linv_next, ddv, status, min_bits);
+    return;
+  }
+  load_block64<T>(S + (size_t)i0 * n + k0, (size_t)n, ri, kb, Li);
+  load_block64<T>(S + (size_t)j0 * n + k0, (size_t)n, rj, kb, Lj);
+  __syncthreads();
   gemm_nt_64<T>(&Li[0][0], &Lj[0][0], kNB + 1, kNB, acc);
-  const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -404,17 +435,6 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
       const int r = 16 * w + Mfma<T>::row(lane, v), c = 16 * t + (lane & 15);
       if (r < ri && c < rj && (I != J || c <= r)) S[(size_t)(i0 + r) * n + j0 + c] -= acc[t][v];
     }
-  // workgroup 0 holds the next diagonal block, now final: factor it while the
-  // other workgroups finish the trailing update (look-ahead of one panel)
-  if (blk == 0 && Linv_next) {
-    __threadfence_block();
-    __syncthreads();  // also frees Li and Lj for the factor's panels
-    const T ddv = tid < ri ? d0[t0 + tid] : (T)0;
-    T* W = &Lij[0][0][0];
-    fill_diag_w<T>(S, n, t0, ri, W);
-    __syncthreads();
-    diag_factor<T>(W, S, n, t0, ri, Linv_next, ddv, status, min_bits);
-  }
 }
 
 // Trailing update with 128 x 128 output tiles (float32): A_IJ -= L_Ik L_Jk^T
