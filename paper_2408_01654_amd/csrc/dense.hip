@@ -672,6 +672,50 @@ __device__ __forceinline__ void chain_publish(int* flag, int epoch) {
   if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// float32 backward pass: the solved x values travel with the call's epoch
+// in one 64-bit word each (value bits low, epoch high), stored and polled
+// as single-copy-atomic agent-scope words, so a value is its own flag: no
+// release of the producer's cache, no acquire on the consumer's, and the
+// data arrives with the signal.
+__device__ __forceinline__ void chain_put_x(unsigned long long* xw, int row, float v, int epoch) {
+  const unsigned long long word = ((unsigned long long)(unsigned)epoch << 32) | (unsigned long long)__float_as_uint(v);
+  __hip_atomic_store(xw + row, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// vk[h][t] = x of rows k0 + t (h = 0, t < kb0) and k1 + t (h = 1, t < kb1),
+// each polled until it carries `epoch` (bounded, like chain_wait).
+__device__ __forceinline__ bool chain_get_x(const unsigned long long* xw, int k0, int kb0, int k1, int kb1,
+                                            int epoch, int* err, int* host_err, float (*vk)[kNB]) {
+  __shared__ int fail_s;
+  const int tid = threadIdx.x;
+  if (tid == 0) fail_s = 0;
+  __syncthreads();
+  if (tid < 2 * kNB) {
+    const int h = tid >> 6, t = tid & 63;
+    const int rows = h ? kb1 : kb0;
+    float v = 0.f;
+    if (t < rows) {
+      const unsigned long long* w = xw + (h ? k1 : k0) + t;
+      unsigned long long word = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      long long spins = 0;
+      while ((int)(word >> 32) != epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kChainSpin ||
+            (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrChain | kErrBarrier))) {
+          report_device_error(err, host_err, kErrChain);
+          fail_s = 1;
+          break;
+        }
+        word = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      v = __uint_as_float((unsigned)(word & 0xffffffffull));
+    }
+    vk[h][t] = v;
+  }
+  __syncthreads();
+  return fail_s == 0;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, const T* Linv_all, const T* b, T* y,
                                                          T* x, int* flags, int epoch, int* err, int* host_err,
@@ -686,6 +730,9 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
   const int npair = (nblk + 1) / 2;
   const int tid = threadIdx.x;
   const int G = gridDim.x;
+  // float32: the backward pass's values-with-epoch words, after the flags
+  // (8-byte aligned; the caller sizes flags for them)
+  unsigned long long* xw = reinterpret_cast<unsigned long long*>(flags + ((2 * nblk + 1) & ~1));
   int* fwd = flags;
   int* bwd = flags + nblk;
   // ---- forward: thread (r, q) = (tid / 4, tid mod 4) takes row r, columns 16 q .. 16 q + 15
@@ -804,12 +851,16 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
         la[m] = (rr < kb && c < rows0) ? L[(size_t)(kr + rr) * n + i0 + c] : (T)0;
         lb[m] = (rr < kb && c < rows1) ? L[(size_t)(kr + rr) * n + i1 + c] : (T)0;
       }
-      if (!chain_wait(bwd + P, epoch, err, host_err)) return;
-      if (tid < kNB) {
-        vk[0][tid] = tid < kb0 ? x[k0 + tid] : (T)0;
-        vk[1][tid] = tid < kb1 ? x[k1 + tid] : (T)0;
+      if constexpr (sizeof(T) == 4) {
+        if (!chain_get_x(xw, k0, kb0, k1, kb1, epoch, err, host_err, vk)) return;
+      } else {
+        if (!chain_wait(bwd + P, epoch, err, host_err)) return;
+        if (tid < kNB) {
+          vk[0][tid] = tid < kb0 ? x[k0 + tid] : (T)0;
+          vk[1][tid] = tid < kb1 ? x[k1 + tid] : (T)0;
+        }
+        __syncthreads();
       }
-      __syncthreads();
       T va = (T)0, vb = (T)0;
 #pragma unroll
       for (int m = 0; m < 32; ++m) {
@@ -836,7 +887,10 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
       if (tid < kNB) {
         const T w = (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
         vk[1][tid] = tid < rows1 ? w : (T)0;
-        if (tid < rows1) x[i1 + tid] = w;
+        if (tid < rows1) {
+          x[i1 + tid] = w;
+          if constexpr (sizeof(T) == 4) chain_put_x(xw, i1 + tid, w, epoch);
+        }
       }
       __syncthreads();
       T u = (T)0;
@@ -853,9 +907,13 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
       for (int m = 0; m < 16; ++m) v += Li[0][16 * q + m][c] * acc[0][16 * q + m];
       part[1][q][c] = v;
       __syncthreads();
-      if (tid < rows0) x[i0 + tid] = (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
+      if (tid < rows0) {
+        const T v0 = (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
+        x[i0 + tid] = v0;
+        if constexpr (sizeof(T) == 4) chain_put_x(xw, i0 + tid, v0, epoch);
+      }
     }
-    chain_publish(bwd + Q, epoch);
+    if constexpr (sizeof(T) == 8) chain_publish(bwd + Q, epoch);
   }
 }
 
@@ -947,7 +1005,9 @@ int trsv_chain_grid(int nblk) {
 
 // x = (L L^T)^-1 rhs with a factor from launch_chol_factor: one cooperative
 // launch (trsv_chain_kernel).  flags holds 2 ceil(n / 64) ints that the
-// library never resets: each call passes a fresh epoch.
+// library never resets (each call passes a fresh epoch), followed for
+// float32 by 64 ceil(n / 64) 64-bit words at the next 8-byte boundary (the
+// backward pass's values with their epoch).
 // backward_only: work_y already holds y = L^-1 rhs (rhs unused).  The grid
 // never exceeds the workgroups the device holds at once (at most one per
 // pair of 64-row blocks).  cooperative = false (the default): an ordinary
