@@ -1162,9 +1162,9 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(ensure(c->sys_x, n * 8));
   HIP_TRY(ensure(c->sys_b, n * 8));
   HIP_TRY(ensure(c->Linv, nblk64 * 64 * 64 * 8));
-  // the triangular chain's flags, then (float32) one 64-bit value word per row
-  if (c->chain_flags.bytes < 2 * nblk64 * 4 + 16 + nblk64 * 64 * 8) {
-    HIP_TRY(ensure(c->chain_flags, 2 * nblk64 * 4 + 16 + nblk64 * 64 * 8));
+  // the triangular chain's flags, then (float32) two 64-bit value words per row
+  if (c->chain_flags.bytes < 2 * nblk64 * 4 + 16 + 2 * nblk64 * 64 * 8) {
+    HIP_TRY(ensure(c->chain_flags, 2 * nblk64 * 4 + 16 + 2 * nblk64 * 64 * 8));
     HIP_TRY(hipMemsetAsync(c->chain_flags.p, 0, c->chain_flags.bytes, st));
     HIP_TRY(hipStreamSynchronize(st));
     c->chain_epoch = 0;

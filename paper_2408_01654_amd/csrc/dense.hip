@@ -672,9 +672,10 @@ __device__ __forceinline__ void chain_publish(int* flag, int epoch) {
   if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// float32 backward pass: the solved x values travel with the call's epoch
-// in one 64-bit word each (value bits low, epoch high), stored and polled
-// as single-copy-atomic agent-scope words, so a value is its own flag: no
+// float32 passes: the solved values travel with the call's epoch in one
+// 64-bit word each (value bits low, epoch high; separate word arrays for
+// the forward and the backward pass), stored and polled as
+// single-copy-atomic agent-scope words, so a value is its own flag: no
 // release of the producer's cache, no acquire on the consumer's, and the
 // data arrives with the signal.
 __device__ __forceinline__ void chain_put_x(unsigned long long* xw, int row, float v, int epoch) {
@@ -730,9 +731,10 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
   const int npair = (nblk + 1) / 2;
   const int tid = threadIdx.x;
   const int G = gridDim.x;
-  // float32: the backward pass's values-with-epoch words, after the flags
-  // (8-byte aligned; the caller sizes flags for them)
+  // float32: the backward and forward passes' values-with-epoch words, after
+  // the flags (8-byte aligned; the caller sizes flags for them)
   unsigned long long* xw = reinterpret_cast<unsigned long long*>(flags + ((2 * nblk + 1) & ~1));
+  unsigned long long* yw = xw + (size_t)nblk * kNB;
   int* fwd = flags;
   int* bwd = flags + nblk;
   // ---- forward: thread (r, q) = (tid / 4, tid mod 4) takes row r, columns 16 q .. 16 q + 15
@@ -763,12 +765,16 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
         la[m] = r < rows0 ? L[(size_t)(i0 + r) * n + col] : (T)0;
         lb[m] = r < rows1 ? L[(size_t)(i1 + r) * n + col] : (T)0;
       }
-      if (!chain_wait(fwd + P, epoch, err, host_err)) return;
-      if (tid < kNB) {
-        vk[0][tid] = y[k0 + tid];
-        vk[1][tid] = y[k0 + kNB + tid];
+      if constexpr (sizeof(T) == 4) {
+        if (!chain_get_x(yw, k0, kNB, k0 + kNB, kNB, epoch, err, host_err, vk)) return;
+      } else {
+        if (!chain_wait(fwd + P, epoch, err, host_err)) return;
+        if (tid < kNB) {
+          vk[0][tid] = y[k0 + tid];
+          vk[1][tid] = y[k0 + kNB + tid];
+        }
+        __syncthreads();
       }
-      __syncthreads();
       T va = (T)0, vb = (T)0;
 #pragma unroll
       for (int m = 0; m < 32; ++m) {
@@ -795,7 +801,10 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
       if (tid < kNB) {
         const T w = (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
         vk[0][tid] = tid < rows0 ? w : (T)0;
-        if (tid < rows0) y[i0 + tid] = w;
+        if (tid < rows0) {
+          y[i0 + tid] = w;
+          if constexpr (sizeof(T) == 4) chain_put_x(yw, i0 + tid, w, epoch);
+        }
       }
       __syncthreads();
     }
@@ -812,9 +821,13 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
       for (int m = 0; m < 16; ++m) w += Li[1][r][16 * q + m] * acc[1][16 * q + m];
       part[0][q][r] = w;
       __syncthreads();
-      if (tid < rows1) y[i1 + tid] = (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
+      if (tid < rows1) {
+        const T v1 = (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
+        y[i1 + tid] = v1;
+        if constexpr (sizeof(T) == 4) chain_put_x(yw, i1 + tid, v1, epoch);
+      }
     }
-    chain_publish(fwd + Q, epoch);
+    if constexpr (sizeof(T) == 8) chain_publish(fwd + Q, epoch);
   }
   // ---- backward, pairs in decreasing order: thread (c, q) = (tid mod 64, tid / 64)
   // takes column c and rows 16 q .. 16 q + 15 of a block
@@ -1006,8 +1019,8 @@ int trsv_chain_grid(int nblk) {
 // x = (L L^T)^-1 rhs with a factor from launch_chol_factor: one cooperative
 // launch (trsv_chain_kernel).  flags holds 2 ceil(n / 64) ints that the
 // library never resets (each call passes a fresh epoch), followed for
-// float32 by 64 ceil(n / 64) 64-bit words at the next 8-byte boundary (the
-// backward pass's values with their epoch).
+// float32 by 2 x 64 ceil(n / 64) 64-bit words at the next 8-byte boundary
+// (the backward and the forward pass's values with their epoch).
 // backward_only: work_y already holds y = L^-1 rhs (rhs unused).  The grid
 // never exceeds the workgroups the device holds at once (at most one per
 // pair of 64-row blocks).  cooperative = false (the default): an ordinary
