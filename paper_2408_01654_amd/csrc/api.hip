@@ -381,7 +381,7 @@ struct dpvba_ctx {
   int* host_err = nullptr;
   int* host_err_dev = nullptr;
   long long small_launches = 0;
-  DevBuf chain_flags;  // per 64-row block: forward and backward publication epochs
+  DevBuf chain_flags;  // the triangular chain's value-and-epoch words (chain_words_bytes)
   // sparsity plan of the float32 factor (factor_plan.h): per 64-column panel
   // its reach, and the 128-row tiles and 64-row blocks below its diagonal
   // block that hold a row that can be non-zero in it
@@ -465,6 +465,10 @@ struct TraceScope {
 static const PanelPlan* reach_of(const dpvba_ctx* c, int n) {
   return c->ba_plan.n == n && n > 0 ? &c->ba_plan.plan : nullptr;
 }
+
+// Bytes of the triangular chain's value words for nblk 64-row blocks: two
+// passes, two 64-bit words per row (float64; float32 uses one).
+static size_t chain_words_bytes(size_t nblk) { return 2 * nblk * 64 * 2 * 8; }
 
 // The large solves of a reduced system of more than this many unknowns run
 // in the system order (the smaller ones are gathered inside their kernels).
@@ -1162,9 +1166,9 @@ dpvba_status dpvba_analyze_ex(dpvba_ctx* c, const dpvba_graph* g, const dpvba_tu
   HIP_TRY(ensure(c->sys_x, n * 8));
   HIP_TRY(ensure(c->sys_b, n * 8));
   HIP_TRY(ensure(c->Linv, nblk64 * 64 * 64 * 8));
-  // the triangular chain's flags, then (float32) two 64-bit value words per row
-  if (c->chain_flags.bytes < 2 * nblk64 * 4 + 16 + 2 * nblk64 * 64 * 8) {
-    HIP_TRY(ensure(c->chain_flags, 2 * nblk64 * 4 + 16 + 2 * nblk64 * 64 * 8));
+  // the triangular chain's value words: two passes, up to two words per row
+  if (c->chain_flags.bytes < chain_words_bytes(nblk64)) {
+    HIP_TRY(ensure(c->chain_flags, chain_words_bytes(nblk64)));
     HIP_TRY(hipMemsetAsync(c->chain_flags.p, 0, c->chain_flags.bytes, st));
     HIP_TRY(hipStreamSynchronize(st));
     c->chain_epoch = 0;
@@ -2029,8 +2033,8 @@ dpvba_status dpvba_pgo_sim3(dpvba_ctx* c, int32_t n_frames, int32_t n_fixed, con
   HIP_TRY(ensure(c->pg_d0, std::max<size_t>(n, 1) * 8));
   HIP_TRY(ensure(c->pg_wy, std::max<size_t>(n, 1) * 8));
   HIP_TRY(ensure(c->pg_Linv, std::max<size_t>(nblk64, 1) * 64 * 64 * 8));
-  if (c->pg_flags.bytes < 2 * nblk64 * 4 + 16) {
-    HIP_TRY(ensure(c->pg_flags, 2 * nblk64 * 4 + 16));
+  if (c->pg_flags.bytes < chain_words_bytes(nblk64)) {
+    HIP_TRY(ensure(c->pg_flags, chain_words_bytes(nblk64)));
     HIP_TRY(hipMemsetAsync(c->pg_flags.p, 0, c->pg_flags.bytes, st));
     c->pg_epoch = 0;
   }

@@ -629,64 +629,64 @@ syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_ne
 // inside the workgroup and solves the second; backward (L^T x = y) runs the
 // same chain from the last pair down with L_KI^T and inv(L_II)^T.  Pairing
 // halves the number of inter-workgroup hops on the dependent chain.  A pair
-// is published by storing the call's epoch into its flag (agent-scope
-// release after the data); a consumer reads the flag with an agent-scope
-// acquire.  Every wait is bounded: on timeout *err is set and the workgroup
-// returns, so every workgroup exits; a wait also gives up as soon as another
-// workgroup's wait (or a grid barrier of the call) has expired, but not for an
-// input-range report, which leaves the arithmetic valid.  The L blocks are loaded before the wait
-// for the vector they multiply, so the chain only carries the dependent part.
-// With pair_lo / pair_hi (a factor plan's envelope) a pair takes only the
-// earlier pairs from pair_lo[Q] (forward) and the later ones up to
-// pair_hi[Q] (backward): the other blocks of L it would multiply are zero.
-// With *skip set on the device the whole call is a no-op (every workgroup
-// returns before any wait).
+// is published through its solved values themselves (below).  Every wait is
+// bounded: on timeout *err is set and the workgroup returns, so every
+// workgroup exits; a wait also gives up as soon as another workgroup's wait
+// (or a grid barrier of the call) has expired, but not for an input-range
+// report, which leaves the arithmetic valid.  The L blocks are loaded before
+// the wait for the vector they multiply, so the chain only carries the
+// dependent part.  With pair_lo / pair_hi (a factor plan's envelope) a pair
+// takes only the earlier pairs from pair_lo[Q] (forward) and the later ones
+// up to pair_hi[Q] (backward): the other blocks of L it would multiply are
+// zero.  With *skip set on the device the whole call is a no-op (every
+// workgroup returns before any wait).
 constexpr long long kChainSpin = 1LL << 22;
 
-__device__ __forceinline__ bool chain_wait(const int* flag, int epoch, int* err, int* host_err) {
-  __shared__ int ok_s;
-  if (threadIdx.x == 0) {
-    long long spins = 0;
-    int ok = 1;
-    // relaxed polls (an acquire per poll would invalidate this CU's caches
-    // every time), one acquire fence once the flag is seen
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kChainSpin ||
-          (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrChain | kErrBarrier))) {
-        report_device_error(err, host_err, kErrChain);
-        ok = 0;
-        break;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    ok_s = ok;
+// The solved values of both passes travel with the call's epoch in 64-bit
+// words (32 value bits low, the epoch high: one word per float32 value, two
+// per float64 value, low half first; separate word arrays for the forward
+// and the backward pass), stored and polled as single-copy-atomic
+// agent-scope words, so a value is its own flag: no release of the
+// producer's cache, no acquire on the consumer's, and the data arrives with
+// the signal.
+template <typename T>
+__device__ __forceinline__ void chain_put_x(unsigned long long* xw, int row, T v, int epoch) {
+  const unsigned long long tag = (unsigned long long)(unsigned)epoch << 32;
+  if constexpr (sizeof(T) == 4) {
+    __hip_atomic_store(xw + row, tag | (unsigned long long)__float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    __hip_atomic_store(xw + 2 * (size_t)row, tag | (bits & 0xffffffffull), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(xw + 2 * (size_t)row + 1, tag | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __syncthreads();
-  return ok_s != 0;
 }
 
-__device__ __forceinline__ void chain_publish(int* flag, int epoch) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// One word polled until it carries `epoch` (bounded); false on a timeout or
+// another wait's failure (reported).
+__device__ __forceinline__ bool chain_poll_word(const unsigned long long* w, int epoch, int* err, int* host_err,
+                                                unsigned long long* out) {
+  unsigned long long word = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  long long spins = 0;
+  while ((int)(word >> 32) != epoch) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kChainSpin ||
+        (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrChain | kErrBarrier))) {
+      report_device_error(err, host_err, kErrChain);
+      return false;
+    }
+    word = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  *out = word;
+  return true;
 }
 
-// float32 passes: the solved values travel with the call's epoch in one
-// 64-bit word each (value bits low, epoch high; separate word arrays for
-// the forward and the backward pass), stored and polled as
-// single-copy-atomic agent-scope words, so a value is its own flag: no
-// release of the producer's cache, no acquire on the consumer's, and the
-// data arrives with the signal.
-__device__ __forceinline__ void chain_put_x(unsigned long long* xw, int row, float v, int epoch) {
-  const unsigned long long word = ((unsigned long long)(unsigned)epoch << 32) | (unsigned long long)__float_as_uint(v);
-  __hip_atomic_store(xw + row, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// vk[h][t] = x of rows k0 + t (h = 0, t < kb0) and k1 + t (h = 1, t < kb1),
-// each polled until it carries `epoch` (bounded, like chain_wait).
+// vk[h][t] = the values of rows k0 + t (h = 0, t < kb0) and k1 + t (h = 1,
+// t < kb1), each polled until it carries `epoch`.
+template <typename T>
 __device__ __forceinline__ bool chain_get_x(const unsigned long long* xw, int k0, int kb0, int k1, int kb1,
-                                            int epoch, int* err, int* host_err, float (*vk)[kNB]) {
+                                            int epoch, int* err, int* host_err, T (*vk)[kNB]) {
   __shared__ int fail_s;
   const int tid = threadIdx.x;
   if (tid == 0) fail_s = 0;
@@ -694,22 +694,20 @@ __device__ __forceinline__ bool chain_get_x(const unsigned long long* xw, int k0
   if (tid < 2 * kNB) {
     const int h = tid >> 6, t = tid & 63;
     const int rows = h ? kb1 : kb0;
-    float v = 0.f;
+    T v = (T)0;
     if (t < rows) {
-      const unsigned long long* w = xw + (h ? k1 : k0) + t;
-      unsigned long long word = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      long long spins = 0;
-      while ((int)(word >> 32) != epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kChainSpin ||
-            (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrChain | kErrBarrier))) {
-          report_device_error(err, host_err, kErrChain);
+      const int row = (h ? k1 : k0) + t;
+      unsigned long long lo = 0, hi = 0;
+      if constexpr (sizeof(T) == 4) {
+        if (chain_poll_word(xw + row, epoch, err, host_err, &lo)) v = __uint_as_float((unsigned)(lo & 0xffffffffull));
+        else fail_s = 1;
+      } else {
+        if (chain_poll_word(xw + 2 * (size_t)row, epoch, err, host_err, &lo) &&
+            chain_poll_word(xw + 2 * (size_t)row + 1, epoch, err, host_err, &hi))
+          v = __longlong_as_double((long long)(((hi & 0xffffffffull) << 32) | (lo & 0xffffffffull)));
+        else
           fail_s = 1;
-          break;
-        }
-        word = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      v = __uint_as_float((unsigned)(word & 0xffffffffull));
     }
     vk[h][t] = v;
   }
@@ -731,12 +729,11 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
   const int npair = (nblk + 1) / 2;
   const int tid = threadIdx.x;
   const int G = gridDim.x;
-  // float32: the backward and forward passes' values-with-epoch words, after
-  // the flags (8-byte aligned; the caller sizes flags for them)
-  unsigned long long* xw = reinterpret_cast<unsigned long long*>(flags + ((2 * nblk + 1) & ~1));
-  unsigned long long* yw = xw + (size_t)nblk * kNB;
-  int* fwd = flags;
-  int* bwd = flags + nblk;
+  // the backward and forward passes' value words (flags is 8-byte aligned;
+  // the caller sizes it for them)
+  constexpr int kWords = sizeof(T) == 4 ? 1 : 2;
+  unsigned long long* xw = reinterpret_cast<unsigned long long*>(flags);
+  unsigned long long* yw = xw + (size_t)nblk * kNB * kWords;
   // ---- forward: thread (r, q) = (tid / 4, tid mod 4) takes row r, columns 16 q .. 16 q + 15
   // (skipped when the factor already produced y = L^-1 b in y)
   for (int Q = backward_only ? npair : blockIdx.x; Q < npair; Q += G) {
@@ -765,16 +762,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
         la[m] = r < rows0 ? L[(size_t)(i0 + r) * n + col] : (T)0;
         lb[m] = r < rows1 ? L[(size_t)(i1 + r) * n + col] : (T)0;
       }
-      if constexpr (sizeof(T) == 4) {
-        if (!chain_get_x(yw, k0, kNB, k0 + kNB, kNB, epoch, err, host_err, vk)) return;
-      } else {
-        if (!chain_wait(fwd + P, epoch, err, host_err)) return;
-        if (tid < kNB) {
-          vk[0][tid] = y[k0 + tid];
-          vk[1][tid] = y[k0 + kNB + tid];
-        }
-        __syncthreads();
-      }
+      if (!chain_get_x<T>(yw, k0, kNB, k0 + kNB, kNB, epoch, err, host_err, vk)) return;
       T va = (T)0, vb = (T)0;
 #pragma unroll
       for (int m = 0; m < 32; ++m) {
@@ -803,7 +791,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
         vk[0][tid] = tid < rows0 ? w : (T)0;
         if (tid < rows0) {
           y[i0 + tid] = w;
-          if constexpr (sizeof(T) == 4) chain_put_x(yw, i0 + tid, w, epoch);
+          chain_put_x<T>(yw, i0 + tid, w, epoch);
         }
       }
       __syncthreads();
@@ -824,10 +812,10 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
       if (tid < rows1) {
         const T v1 = (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
         y[i1 + tid] = v1;
-        if constexpr (sizeof(T) == 4) chain_put_x(yw, i1 + tid, v1, epoch);
+        chain_put_x<T>(yw, i1 + tid, v1, epoch);
       }
     }
-    if constexpr (sizeof(T) == 8) chain_publish(fwd + Q, epoch);
+
   }
   // ---- backward, pairs in decreasing order: thread (c, q) = (tid mod 64, tid / 64)
   // takes column c and rows 16 q .. 16 q + 15 of a block
@@ -864,16 +852,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
         la[m] = (rr < kb && c < rows0) ? L[(size_t)(kr + rr) * n + i0 + c] : (T)0;
         lb[m] = (rr < kb && c < rows1) ? L[(size_t)(kr + rr) * n + i1 + c] : (T)0;
       }
-      if constexpr (sizeof(T) == 4) {
-        if (!chain_get_x(xw, k0, kb0, k1, kb1, epoch, err, host_err, vk)) return;
-      } else {
-        if (!chain_wait(bwd + P, epoch, err, host_err)) return;
-        if (tid < kNB) {
-          vk[0][tid] = tid < kb0 ? x[k0 + tid] : (T)0;
-          vk[1][tid] = tid < kb1 ? x[k1 + tid] : (T)0;
-        }
-        __syncthreads();
-      }
+      if (!chain_get_x<T>(xw, k0, kb0, k1, kb1, epoch, err, host_err, vk)) return;
       T va = (T)0, vb = (T)0;
 #pragma unroll
       for (int m = 0; m < 32; ++m) {
@@ -902,7 +881,7 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
         vk[1][tid] = tid < rows1 ? w : (T)0;
         if (tid < rows1) {
           x[i1 + tid] = w;
-          if constexpr (sizeof(T) == 4) chain_put_x(xw, i1 + tid, w, epoch);
+          chain_put_x<T>(xw, i1 + tid, w, epoch);
         }
       }
       __syncthreads();
@@ -923,10 +902,10 @@ __global__ void __launch_bounds__(256) trsv_chain_kernel(const T* L, int n, cons
       if (tid < rows0) {
         const T v0 = (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
         x[i0 + tid] = v0;
-        if constexpr (sizeof(T) == 4) chain_put_x(xw, i0 + tid, v0, epoch);
+        chain_put_x<T>(xw, i0 + tid, v0, epoch);
       }
     }
-    if constexpr (sizeof(T) == 8) chain_publish(bwd + Q, epoch);
+
   }
 }
 
@@ -1017,10 +996,9 @@ int trsv_chain_grid(int nblk) {
 }
 
 // x = (L L^T)^-1 rhs with a factor from launch_chol_factor: one cooperative
-// launch (trsv_chain_kernel).  flags holds 2 ceil(n / 64) ints that the
-// library never resets (each call passes a fresh epoch), followed for
-// float32 by 2 x 64 ceil(n / 64) 64-bit words at the next 8-byte boundary
-// (the backward and the forward pass's values with their epoch).
+// launch (trsv_chain_kernel).  flags (8-byte aligned) holds the two passes'
+// value words, 2 x 64 ceil(n / 64) x (1 for float32, 2 for float64) 64-bit
+// words that the library never resets: each call passes a fresh epoch.
 // backward_only: work_y already holds y = L^-1 rhs (rhs unused).  The grid
 // never exceeds the workgroups the device holds at once (at most one per
 // pair of 64-row blocks).  cooperative = false (the default): an ordinary
