@@ -322,14 +322,15 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, in
 }
 
 // Panel solve below the diagonal block: L_ik = A_ik inv(L_kk)^T, one 64-row
-// block per workgroup of eight wavefronts (two 16 x 16 output tiles each, so
-// the product's matrix-core chain is half that of four wavefronts; the
-// panel solves sit on the factor's serial path), on the matrix cores: the blocks of rows [k0 + kb, R)
+// block per workgroup of sixteen wavefronts (one 16 x 16 output tile each,
+// so the product's matrix-core chain is a quarter of that of four
+// wavefronts; the panel solves sit on the factor's serial path), on the
+// matrix cores: the blocks of rows [k0 + kb, R)
 // that can be non-zero in the panel (R: the panel's reach, n for a dense
 // matrix; with a list, only the listed blocks), then the appended rows
 // [n, nrows).
 template <typename T>
-__global__ void __launch_bounds__(512) trsm_panel_kernel(T* S, int n, int nrows, int R, int k0, int kb,
+__global__ void __launch_bounds__(1024) trsm_panel_kernel(T* S, int n, int nrows, int R, int k0, int kb,
                                                          const T* Linv, const int* blocks, int n_main) {
   __shared__ T Ab[kNB][kNB + 1];
   __shared__ T Li[kNB][kNB + 1];
@@ -338,30 +339,22 @@ __global__ void __launch_bounds__(512) trsm_panel_kernel(T* S, int n, int nrows,
   const int i0 = b < n_main ? t0 + (blocks ? blocks[b] : b) * kNB : n + (b - n_main) * kNB;
   const int rows = min(kNB, (b < n_main ? R : nrows) - i0);
   const int tid = threadIdx.x;
-  load_block64_nt<T, 512>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
-  load_block64_nt<T, 512>(Linv, (size_t)kNB, kb, kb, Li);
+  load_block64_nt<T, 1024>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
+  load_block64_nt<T, 1024>(Linv, (size_t)kNB, kb, kb, Li);
   __syncthreads();
   // eight wavefronts: rows 16 (w mod 4), column tiles 2 (w / 4) and 2 (w / 4) + 1
   const int lane = tid & 63, w = tid >> 6, wr = w & 3, wc = w >> 2;
-  typename Mfma<T>::acc_t acc[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  typename Mfma<T>::acc_t acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
   {
     const T* xr = &Ab[0][0] + (16 * wr + (lane & 15)) * (kNB + 1) + (lane >> 4);
-    const T* yr = &Li[0][0] + (32 * wc + (lane & 15)) * (kNB + 1) + (lane >> 4);
-    for (int kk = 0; kk < kNB; kk += 4) {
-      const T a = xr[kk];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) acc[t] = Mfma<T>::step(a, yr[16 * t * (kNB + 1) + kk], acc[t]);
-    }
+    const T* yr = &Li[0][0] + (16 * wc + (lane & 15)) * (kNB + 1) + (lane >> 4);
+    for (int kk = 0; kk < kNB; kk += 4) acc = Mfma<T>::step(xr[kk], yr[kk], acc);
   }
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * wr + Mfma<T>::row(lane, v), c = 32 * wc + 16 * t + (lane & 15);
-      if (r < rows && c < kb) S[(size_t)(i0 + r) * n + k0 + c] = acc[t][v];
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int r = 16 * wr + Mfma<T>::row(lane, v), c = 16 * wc + (lane & 15);
+    if (r < rows && c < kb) S[(size_t)(i0 + r) * n + k0 + c] = acc[v];
+  }
 }
 
 // Trailing update A_IJ -= L_Ik L_Jk^T for 64x64 blocks I >= J of the trailing
@@ -959,7 +952,7 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
     const int n_main = sparse ? plan->blocks_off[k + 1] - plan->blocks_off[k]
                               : (R > t0 ? (R - t0 + kNB - 1) / kNB : 0);
     if (n_main + nrows - n > 0)
-      hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(n_main + nrows - n), dim3(512), 0, st, S, n, nrows, R, k0, kb,
+      hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(n_main + nrows - n), dim3(1024), 0, st, S, n, nrows, R, k0, kb,
                          Linv, sparse ? plan->blocks + plan->blocks_off[k] : (const int*)nullptr, n_main);
     // the trailing update also factors diagonal block k + 1 (its workgroup 0)
     if constexpr (sizeof(T) == 4) {
@@ -977,7 +970,7 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
   }
   if (nrows > n) {  // the appended rows below the last diagonal block: their last panel solve
     const int k0 = (nblk - 1) * kNB;
-    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(512), 0, st, S, n, nrows, n,
+    hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(1024), 0, st, S, n, nrows, n,
                        k0, n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB, (const int*)nullptr, 0);
   }
   return hipGetLastError();
