@@ -292,23 +292,23 @@ static int writeback_lds_bytes(const Tiling& tl, int tsize) {
 
 // Host side of a factor plan (factor_plan.h) and its device lists.
 struct PlanStore {
-  std::vector<int32_t> reach, tiles_off, blocks_off;
-  DevBuf tiles, blocks, chain_lo, chain_hi, fq_dev, reach_dev;
+  std::vector<int32_t> reach, blocks_off;
+  DevBuf blocks, chain_lo, chain_hi, fq_dev, reach_dev;
   PanelPlan plan{};
   int n = 0;  // the system size the plan is for
 };
 
 // Factor plan of an n-row system of pose blocks of width bw whose block row
 // P couples first with block column fq[P] (<= P): per 64-column panel k the
-// reach, the 128-row tiles and the 64-row blocks below the panel's diagonal
-// block that hold a row whose envelope starts in or before the panel (block 0
-// always listed: the float64 trailing update runs its look-ahead there).
+// reach and the 64-row blocks below the panel's diagonal block that hold a
+// row whose envelope starts in or before the panel (block 0 always listed:
+// the trailing update runs its look-ahead there).
 static hipError_t build_plan(const std::vector<int32_t>& fq, int bw, int n, PlanStore& ps, hipStream_t st) {
   const int nb = (int)fq.size(), np = (n + 63) / 64;
   std::vector<int32_t> last(nb, -1);
   for (int Pp = 0; Pp < nb; ++Pp) last[fq[Pp]] = std::max(last[fq[Pp]], Pp);
   for (int Qq = 1; Qq < nb; ++Qq) last[Qq] = std::max(last[Qq], last[Qq - 1]);
-  std::vector<int32_t> reach(np, n), toff{0}, boff{0}, tl, bl;
+  std::vector<int32_t> reach(np, n), boff{0}, bl;
   for (int k = 0; k < np; ++k) {
     const int qmax = std::min(64 * k + 63, n - 1) / bw;
     reach[k] = std::min(n, bw * (std::max(last[qmax], qmax) + 1));
@@ -318,14 +318,10 @@ static hipError_t build_plan(const std::vector<int32_t>& fq, int bw, int n, Plan
         if (fq[Pp] <= qmax) return true;
       return false;
     };
-    for (int T = 0; t0 + 128 * T < n; ++T)
-      if (active(t0 + 128 * T, t0 + 128 * T + 128)) tl.push_back(T);
     for (int B = 0; t0 + 64 * B < n; ++B)
       if (B == 0 || active(t0 + 64 * B, t0 + 64 * B + 64)) bl.push_back(B);
-    toff.push_back((int32_t)tl.size());
     boff.push_back((int32_t)bl.size());
   }
-  if (tl.empty()) tl.push_back(0);
   if (bl.empty()) bl.push_back(0);
   // triangular-solve ranges per pair of 64-row blocks: block I's rows start
   // at column block fcb[I] (the envelope), and the rows that reach block
@@ -348,15 +344,12 @@ static hipError_t build_plan(const std::vector<int32_t>& fq, int bw, int n, Plan
   if ((e = upload(ps.chain_hi, phi, st)) != hipSuccess) return e;
   if ((e = upload(ps.fq_dev, fq, st)) != hipSuccess) return e;
   if ((e = upload(ps.reach_dev, reach, st)) != hipSuccess) return e;
-  if ((e = upload(ps.tiles, tl, st)) != hipSuccess) return e;
   if ((e = upload(ps.blocks, bl, st)) != hipSuccess) return e;
   ps.reach = reach;
-  ps.tiles_off = toff;
   ps.blocks_off = boff;
-  ps.plan = PanelPlan{ps.reach.data(),          ps.tiles_off.data(),         (const int*)ps.tiles.p,
-                      ps.blocks_off.data(),      (const int*)ps.blocks.p,     (const int*)ps.chain_lo.p,
-                      (const int*)ps.chain_hi.p, (const int*)ps.fq_dev.p,  (const int*)ps.reach_dev.p,
-                      bw};
+  ps.plan = PanelPlan{ps.reach.data(),          ps.blocks_off.data(),     (const int*)ps.blocks.p,
+                      (const int*)ps.chain_lo.p, (const int*)ps.chain_hi.p, (const int*)ps.fq_dev.p,
+                      (const int*)ps.reach_dev.p, bw};
   ps.n = n;
   return hipSuccess;
 }
@@ -383,8 +376,8 @@ struct dpvba_ctx {
   long long small_launches = 0;
   DevBuf chain_flags;  // the triangular chain's value-and-epoch words (chain_words_bytes)
   // sparsity plan of the float32 factor (factor_plan.h): per 64-column panel
-  // its reach, and the 128-row tiles and 64-row blocks below its diagonal
-  // block that hold a row that can be non-zero in it
+  // its reach and the 64-row blocks below its diagonal block that hold a row
+  // that can be non-zero in it
   PlanStore ba_plan;  // the analysed graph's reduced system
   // system order of the large solves: block p of the factored system is free
   // pose sys_perm[p] (sys_pos its inverse); empty: the poses' own order
@@ -756,8 +749,8 @@ void dpvba_destroy(dpvba_ctx* c) {
   DevBuf* bufs[] = {&c->part_S, &c->part_vec, &c->part_cost, &c->part_invalid, &c->U_s, &c->pscale_s,
                     &c->depth_s, &c->xh_s, &c->poses_a, &c->poses_b, &c->S, &c->rhs, &c->dB, &c->d0, &c->dx,
                     &c->wb, &c->wy, &c->Linv, &c->edge_part, &c->ticket, &c->dev_err, &c->status, &c->min_bits, &c->devrep,
-                    &c->chain_flags, &c->one_inst, &c->ba_plan.tiles, &c->ba_plan.blocks, &c->pg_plan.tiles,
-                    &c->pg_plan.blocks, &c->ba_plan.chain_lo, &c->ba_plan.chain_hi, &c->pg_plan.chain_lo,
+                    &c->chain_flags, &c->one_inst, &c->ba_plan.blocks, &c->pg_plan.blocks,
+                    &c->ba_plan.chain_lo, &c->ba_plan.chain_hi, &c->pg_plan.chain_lo,
                     &c->pg_plan.chain_hi, &c->ba_plan.fq_dev, &c->ba_plan.reach_dev, &c->pg_plan.fq_dev,
                     &c->pg_plan.reach_dev, &c->sys_perm, &c->sys_pos, &c->sys_x, &c->sys_b, &c->env_blk,
                     &c->pcount, &c->pedges, &c->pose_off, &c->pose_src, &c->patch_pos, &c->bw_poses, &c->bw_depth,

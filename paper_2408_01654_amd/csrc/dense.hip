@@ -430,42 +430,46 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
     }
 }
 
-// Trailing update with 128 x 128 output tiles (float32): A_IJ -= L_Ik L_Jk^T
-// for the lower tiles of the trailing rows and columns [t0, R), K = 64 (one
-// panel).  R is the panel's reach: the rows below it have no entry in the
-// panel (the envelope of a sparse reduced system: fill stays between a row's
-// first non-zero and the diagonal), so their update is exactly zero and is
-// skipped; R = n for a dense matrix.  With a list of the active tiles (those
-// holding a row that is non-zero in the panel, factor_plan.h) only their
-// pairs are launched: a tile pair with an all-zero side has a zero update.  Each of the four wavefronts takes one
-// 64 x 64 quadrant as 4 x 4 matrix-core tiles accumulating L_I L_J^T; the
-// quadrant above the diagonal of a diagonal tile is skipped.  The products
-// are then staged in LDS and the tile is read and written row by row
-// (contiguous 512-byte rows): A - L_I L_J^T.  Four times the products per
-// byte of panel rows of a 64 x 64 update.  The right-hand side appended as
-// row n (nrows = n + 1) is updated by the diagonal tiles: s_J -= L_J l_n,
-// from the panel rows they hold anyway.
+// Trailing update of the float32 factor: A_IJ -= L_Ik L_Jk^T for the lower
+// pairs (I, J) of 64-row blocks of the trailing rows and columns [t0, R),
+// K = 64 (one panel), one workgroup per pair.  R is the panel's reach: the
+// rows below it have no entry in the panel (the envelope of a sparse reduced
+// system: fill stays between a row's first non-zero and the diagonal), so
+// their update is exactly zero and is skipped; R = n for a dense matrix.
+// With a list of the active blocks (those holding a row that is non-zero in
+// the panel, factor_plan.h) only their pairs are launched: a pair with an
+// all-zero side has a zero update.  Each of the four wavefronts takes one
+// 32 x 32 quadrant as 2 x 2 matrix-core tiles accumulating L_I L_J^T; the
+// quadrant above the diagonal of a diagonal pair is skipped.  The products
+// are then staged in LDS and A is read and written as contiguous 256-byte
+// rows: A - L_I L_J^T.  The pairs are 64 rows high, not 128: a trailing
+// update of the sparse system has only a few active rows per panel, so a
+// launch holds far fewer workgroups than the chip has CUs and each
+// workgroup's latency (its loads and its products on one CU) is what counts.
+// The right-hand side appended as row n (nrows = n + 1) is updated by the
+// diagonal pairs: s_J -= L_J l_n, from the panel rows they hold anyway.
 //
 // Look-ahead: with Linv_next, workgroup 0 updates only the next diagonal
-// block (64 x 64; its quadrant of tile (0, 0) is left to it) and factors it
-// at once, so the factor of the next panel starts with the launch instead of
-// after a whole tile.
-constexpr int kTB = 128;
-constexpr int kPanLd = 68;   // LDS row stride of the staged panel rows
-constexpr int kOutLd = 132;  // LDS row stride of the staged products
-constexpr int kSyrk128Lds = 2 * kTB * kPanLd * 4;
-static_assert(kTB * kPanLd >= 2 * kNB * kWld, "diagonal factor working matrix in the first panel region");
+// block (pair (0, 0), whose workgroup only updates the right-hand side) and
+// factors it at once, so the factor of the next panel starts with the launch
+// instead of after the update.
+constexpr int kTB = 64;     // trailing-update tile: one pair of 64-row blocks
+constexpr int kPanLd = 68;  // LDS row stride of the staged panel rows and products
+constexpr int kPiFloats = 2 * kNB * kWld;  // the look-ahead's working matrix, or a tile's row-block panel rows
+constexpr int kPjFloats = kTB * kPanLd;
+constexpr int kSyrk64Lds = (kPiFloats + kPjFloats) * 4;
+static_assert(kPiFloats >= kTB * kPanLd && kPjFloats >= kNB * (kNB + 1), "LDS regions");
 
 // Two wavefronts per SIMD (at most 256 registers), so two workgroups share a
 // CU although workgroup 0 also runs the register-heavy diagonal factor.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_next, const float* d0, int* status,
+syrk64_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_next, const float* d0, int* status,
                unsigned int* min_bits, const int* act) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   __shared__ float lrhs[kNB];  // l_n: the right-hand-side row's panel entries
   typedef float f2 __attribute__((ext_vector_type(2)));
   float* Pi = reinterpret_cast<float*>(dyn_lds);
-  float* Pj = Pi + kTB * kPanLd;
+  float* Pj = Pi + kPiFloats;
   const int t0 = k0 + kb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const bool look = Linv_next != nullptr;
@@ -506,110 +510,111 @@ syrk128_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_ne
   while (a * (a + 1) / 2 > blk) --a;
   while ((a + 1) * (a + 2) / 2 <= blk) ++a;
   const int b = blk - a * (a + 1) / 2;
-  // pair (a, b), b <= a, of the active tiles (all tiles up to the reach without a list)
+  // pair (a, b), b <= a, of the active blocks (all blocks up to the reach without a list)
   const int I = act ? act[a] : a, J = act ? act[b] : b;
   const int i0 = t0 + I * kTB, j0 = t0 + J * kTB;
   const int ri = min(kTB, R - i0), rj = min(kTB, R - j0);
   const bool rhs_row = I == J && nrows > n;
   if (rhs_row && tid < kNB) lrhs[tid] = tid < kb ? S[(size_t)n * n + k0 + tid] : 0.f;
+  // the next diagonal block (pair (0, 0)) is the look-ahead's: here only its
+  // share of the right-hand-side row
+  const bool lead = look && I == 0 && J == 0;
   const int wr = w >> 1, wc = w & 1;
-  // the next diagonal block (rows and columns [t0, t0 + lb) of tile (0, 0)) is the look-ahead's
-  const bool skip_lead = look && I == 0 && J == 0;
-  const int lb = min(kNB, n - t0);
-  const bool active = !(I == J && wr < wc);
+  const bool active = !lead && !(I == J && wr < wc);
+  const float* PJ = I == J ? Pi : Pj;  // a diagonal pair stages its panel rows once
   // accumulators (lane: column 16 tj + (lane & 15), rows 4 (lane >> 4) + v of
-  // tile ti) collect L_I L_J^T from zero and are subtracted from A once:
-  // starting them from A would round every step at the size of A, which the
-  // update nearly cancels on the ill-conditioned directions
-  floatx4_t acc[4][4];
+  // tile ti of the wavefront's 32 x 32 quadrant) collect L_I L_J^T from zero
+  // and are subtracted from A once: starting them from A would round every
+  // step at the size of A, which the update nearly cancels on the
+  // ill-conditioned directions
+  floatx4_t acc[2][2];
 #pragma unroll
-  for (int ti = 0; ti < 4; ++ti)
+  for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = floatx4_t{0.f, 0.f, 0.f, 0.f};
   // the tile's own entries, read at once so that their latency overlaps the
-  // panel loads and the products: wavefront w takes rows w, w + 4, ...; lane
-  // l columns 2 l, 2 l + 1 (each access instruction covers one contiguous
-  // 512-byte row)
-  const int cc = 2 * lane;
-  f2 av[32];
+  // panel loads and the products: thread t takes rows (t >> 5) + 8 u,
+  // columns 2 (t & 31) and 2 (t & 31) + 1 (each access instruction covers
+  // two contiguous 256-byte rows)
+  const int cc = 2 * (tid & 31), rr = tid >> 5;
+  f2 av[8];
 #pragma unroll
-  for (int u = 0; u < 32; ++u) {
-    const int r = w + 4 * u;
-    av[u] = (r < ri && cc < rj) ? *reinterpret_cast<const f2*>(S + (size_t)(i0 + r) * n + j0 + cc)
-                                : f2{0.f, 0.f};  // rj is even: n and j0 are
+  for (int u = 0; u < 8; ++u) {
+    const int r = rr + 8 * u;
+    av[u] = (!lead && r < ri && cc < rj) ? *reinterpret_cast<const f2*>(S + (size_t)(i0 + r) * n + j0 + cc)
+                                         : f2{0.f, 0.f};  // rj is even: n and j0 are
   }
-  // panel rows: 128 x kb of columns k0.. for the row tile and the column tile
+  // panel rows: 64 x kb of columns k0.. for the row block and the column block
   {
-    f2 va[16], vb[16];
+    f2 va[8], vb[8];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int q = tid + 256 * u, r = q >> 5, c = 2 * (q & 31);
       va[u] = (r < ri && c < kb) ? *reinterpret_cast<const f2*>(S + (size_t)(i0 + r) * n + k0 + c) : f2{0.f, 0.f};
-      vb[u] = (r < rj && c < kb) ? *reinterpret_cast<const f2*>(S + (size_t)(j0 + r) * n + k0 + c) : f2{0.f, 0.f};
+      vb[u] = (I != J && r < rj && c < kb) ? *reinterpret_cast<const f2*>(S + (size_t)(j0 + r) * n + k0 + c)
+                                           : f2{0.f, 0.f};
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int q = tid + 256 * u, r = q >> 5, c = 2 * (q & 31);
       *reinterpret_cast<f2*>(Pi + r * kPanLd + c) = va[u];
-      *reinterpret_cast<f2*>(Pj + r * kPanLd + c) = vb[u];
+      if (I != J) *reinterpret_cast<f2*>(Pj + r * kPanLd + c) = vb[u];
     }
   }
   __syncthreads();
   if (active) {
-    const float* pa = Pi + (64 * wr + (lane & 15)) * kPanLd + (lane >> 4);
-    const float* pb = Pj + (64 * wc + (lane & 15)) * kPanLd + (lane >> 4);
+    const float* pa = Pi + (32 * wr + (lane & 15)) * kPanLd + (lane >> 4);
+    const float* pb = PJ + (32 * wc + (lane & 15)) * kPanLd + (lane >> 4);
     for (int k = 0; k < kNB; k += 4) {
-      float a[4], b[4];
+      float x[2], y[2];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        a[t] = pa[16 * t * kPanLd + k];
-        b[t] = pb[16 * t * kPanLd + k];
+      for (int t = 0; t < 2; ++t) {
+        x[t] = pa[16 * t * kPanLd + k];
+        y[t] = pb[16 * t * kPanLd + k];
       }
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti)
+      for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[ti], y[tj], acc[ti][tj], 0, 0, 0);
     }
   }
   if (rhs_row) {
-    // s_(j0 + c) -= sum_k L_(j0 + c, k) l_n(k): thread (c, half) takes 32 k
-    const int c = tid >> 1, h = tid & 1;
-    const float* pr = Pj + c * kPanLd + 32 * h;
+    // s_(j0 + c) -= sum_k L_(j0 + c, k) l_n(k): thread (c, q) takes 16 k
+    const int c = tid >> 2, h = tid & 3;
+    const float* pr = PJ + c * kPanLd + 16 * h;
     float sum = 0.f;
 #pragma unroll
-    for (int k = 0; k < 32; ++k) sum += pr[k] * lrhs[32 * h + k];
+    for (int k = 0; k < 16; ++k) sum += pr[k] * lrhs[16 * h + k];
     sum += __shfl_xor(sum, 1);
+    sum += __shfl_xor(sum, 2);
     if (h == 0 && c < rj) S[(size_t)n * n + j0 + c] -= sum;
   }
+  if (lead) return;
   __syncthreads();  // the panel rows are dead: their LDS takes the products
-  float* Out = Pi;  // [128][kOutLd]
+  float* Out = Pi;  // [64][kPanLd]
   if (active) {
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti)
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < 4; ++tj)
+      for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = 64 * wr + 16 * ti + 4 * (lane >> 4) + v, c = 64 * wc + 16 * tj + (lane & 15);
-          Out[r * kOutLd + c] = acc[ti][tj][v];
+          const int r = 32 * wr + 16 * ti + 4 * (lane >> 4) + v, c = 32 * wc + 16 * tj + (lane & 15);
+          Out[r * kPanLd + c] = acc[ti][tj][v];
         }
   }
   __syncthreads();
-  {
-    const int c = cc;
 #pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const int r = w + 4 * u;
-      if (r >= ri || c >= rj) continue;
-      if (skip_lead && r < lb && c < lb) continue;
-      const float* o = Out + r * kOutLd + c;
-      const f2 nv = av[u] - f2{o[0], o[1]};
-      float* dst = S + (size_t)(i0 + r) * n + j0 + c;
-      if (I != J || c + 1 <= r) {
-        *reinterpret_cast<f2*>(dst) = nv;
-      } else if (c == r) {
-        dst[0] = nv.x;
-      }
+  for (int u = 0; u < 8; ++u) {
+    const int r = rr + 8 * u;
+    if (r >= ri || cc >= rj) continue;
+    const float* o = Out + r * kPanLd + cc;
+    const f2 nv = av[u] - f2{o[0], o[1]};
+    float* dst = S + (size_t)(i0 + r) * n + j0 + cc;
+    if (I != J || cc + 1 <= r) {
+      *reinterpret_cast<f2*>(dst) = nv;
+    } else if (cc == r) {
+      dst[0] = nv.x;
     }
   }
 }
@@ -933,15 +938,15 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
   if (nblk == 0) return hipSuccess;
   if (sizeof(T) == 8 && nrows != n) return hipErrorInvalidValue;
   if (nrows != n && nrows != n + 1) return hipErrorInvalidValue;  // at most the right-hand side appended
-  // with a plan only the blocks (and, float32, the 128-row tiles) that hold a
-  // row non-zero in the panel are solved and updated; float32 also stops at
-  // the panel's reach (the last row that can be non-zero in it)
+  // with a plan only the 64-row blocks that hold a row non-zero in the panel
+  // are solved and updated; float32 also stops at the panel's reach (the last
+  // row that can be non-zero in it)
   const bool sparse = plan != nullptr;
   auto reach_of = [&](int k) { return sparse && sizeof(T) == 4 ? std::min(n, std::max(plan->reach[k], 0)) : n; };
   hipLaunchKernelGGL((potrf_diag_kernel<T>), dim3(1), dim3(256), 0, st, S, n, 0, min(kNB, n), Linv_all, d0, status,
                      min_bits);
   if constexpr (sizeof(T) == 4) {
-    hipError_t e = opt_in_lds((const void*)syrk128_kernel, kSyrk128Lds);
+    hipError_t e = opt_in_lds((const void*)syrk64_kernel, kSyrk64Lds);
     if (e != hipSuccess) return e;
   }
   for (int k = 0; k + 1 < nblk; ++k) {
@@ -956,11 +961,10 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
                          Linv, sparse ? plan->blocks + plan->blocks_off[k] : (const int*)nullptr, n_main);
     // the trailing update also factors diagonal block k + 1 (its workgroup 0)
     if constexpr (sizeof(T) == 4) {
-      const int Tc = sparse ? plan->tiles_off[k + 1] - plan->tiles_off[k] : (R > t0 ? (R - t0 + kTB - 1) / kTB : 0);
-      const int tiles = Tc * (Tc + 1) / 2;
-      hipLaunchKernelGGL(syrk128_kernel, dim3(tiles + 1), dim3(256), kSyrk128Lds, st, S, n, nrows, R, k0, kb,
+      const int pairs = n_main * (n_main + 1) / 2;
+      hipLaunchKernelGGL(syrk64_kernel, dim3(pairs + 1), dim3(256), kSyrk64Lds, st, S, n, nrows, R, k0, kb,
                          Linv + kNB * kNB, d0, status, min_bits,
-                         sparse ? plan->tiles + plan->tiles_off[k] : (const int*)nullptr);
+                         sparse ? plan->blocks + plan->blocks_off[k] : (const int*)nullptr);
     } else {
       const int rest = sparse ? n_main : nblk - k - 1;
       hipLaunchKernelGGL((syrk_update_kernel<T>), dim3(rest * (rest + 1) / 2), dim3(256), 0, st, S, n, k0, kb,

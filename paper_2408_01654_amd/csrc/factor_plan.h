@@ -5,8 +5,8 @@
 // between that column and the diagonal, so in panel k (columns 64 k ..
 // 64 k + 63) exactly the rows whose envelope starts inside or before the
 // panel can be non-zero.  The factor solves and updates only those: the
-// 64-row blocks and 128-row tiles below the panel's diagonal block that hold
-// such a row (block / tile indices count from t0 = 64 (k + 1)); every other
+// 64-row blocks below the panel's diagonal block that hold such a row
+// (block indices count from t0 = 64 (k + 1)); every other
 // update is an exact zero (float32 factors also stop each panel at its
 // reach).  The triangular solves skip the blocks of L outside the envelope.  Host arrays have one entry per panel (offsets one more); the
 // lists themselves are in device memory.
@@ -16,9 +16,7 @@ namespace dpvba {
 
 struct PanelPlan {
   const int* reach;       // host [nblk]: one past the last such row (n if none beyond)
-  const int* tiles_off;   // host [nblk + 1]: panel k's active tiles are tiles[tiles_off[k] ..]
-  const int* tiles;       // device: 128-row tile indices, ascending
-  const int* blocks_off;  // host [nblk + 1]
+  const int* blocks_off;  // host [nblk + 1]: panel k's active blocks are blocks[blocks_off[k] ..]
   const int* blocks;      // device: 64-row block indices, ascending
   // device, one entry per pair of 64-row blocks (2P, 2P + 1): the first pair
   // whose columns the pair's rows reach (forward substitution) and the last
