@@ -328,10 +328,14 @@ __global__ void __launch_bounds__(256) potrf_diag_kernel(T* S, int n, int k0, in
 // matrix cores: the blocks of rows [k0 + kb, R)
 // that can be non-zero in the panel (R: the panel's reach, n for a dense
 // matrix; with a list, only the listed blocks), then the appended rows
-// [n, nrows).
+// [n, nrows).  With lead set, the workgroup of the first block below the
+// diagonal block (rows t0 = k0 + kb ..) also updates the next diagonal block
+// by the panel, A_t0t0 -= L_t0k L_t0k^T (its lower triangle), from the L
+// block it has just formed: the next diagonal factor then starts from S
+// alone.
 template <typename T>
 __global__ void __launch_bounds__(1024) trsm_panel_kernel(T* S, int n, int nrows, int R, int k0, int kb,
-                                                         const T* Linv, const int* blocks, int n_main) {
+                                                         const T* Linv, const int* blocks, int n_main, int lead) {
   __shared__ T Ab[kNB][kNB + 1];
   __shared__ T Li[kNB][kNB + 1];
   const int t0 = k0 + kb;
@@ -339,11 +343,26 @@ __global__ void __launch_bounds__(1024) trsm_panel_kernel(T* S, int n, int nrows
   const int i0 = b < n_main ? t0 + (blocks ? blocks[b] : b) * kNB : n + (b - n_main) * kNB;
   const int rows = min(kNB, (b < n_main ? R : nrows) - i0);
   const int tid = threadIdx.x;
+  // sixteen wavefronts: output tile (w mod 4, w / 4)
+  const int lane = tid & 63, w = tid >> 6, wr = w & 3, wc = w >> 2;
+  const bool lead_blk = lead && b < n_main && i0 == t0;
+  const int rb = min(kNB, n - t0);
+  // lower 16 x 16 tile w (< 10) of the next diagonal block, (di, dj): the ten
+  // go to wavefronts 0..9, i.e. at most three per SIMD
+  int di = 0;
+  while ((di + 1) * (di + 2) / 2 <= w) ++di;
+  const int dj = w - di * (di + 1) / 2;
+  T dv[4];  // the next diagonal block's entries at that tile's product positions
+  if (lead_blk) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * di + Mfma<T>::row(lane, v), c = 16 * dj + (lane & 15);
+      dv[v] = (w < 10 && r < rb && c <= r) ? S[(size_t)(t0 + r) * n + t0 + c] : (T)0;
+    }
+  }
   load_block64_nt<T, 1024>(S + (size_t)i0 * n + k0, (size_t)n, rows, kb, Ab);
   load_block64_nt<T, 1024>(Linv, (size_t)kNB, kb, kb, Li);
   __syncthreads();
-  // eight wavefronts: rows 16 (w mod 4), column tiles 2 (w / 4) and 2 (w / 4) + 1
-  const int lane = tid & 63, w = tid >> 6, wr = w & 3, wc = w >> 2;
   typename Mfma<T>::acc_t acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
   {
     const T* xr = &Ab[0][0] + (16 * wr + (lane & 15)) * (kNB + 1) + (lane >> 4);
@@ -354,6 +373,26 @@ __global__ void __launch_bounds__(1024) trsm_panel_kernel(T* S, int n, int nrows
   for (int v = 0; v < 4; ++v) {
     const int r = 16 * wr + Mfma<T>::row(lane, v), c = 16 * wc + (lane & 15);
     if (r < rows && c < kb) S[(size_t)(i0 + r) * n + k0 + c] = acc[v];
+  }
+  if (!lead_blk) return;
+  // the L block (zero outside rows < rows, columns < kb) replaces A in LDS,
+  // then the lower 16 x 16 tiles of L L^T, summed from zero and subtracted
+  // once
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Ab[16 * wr + Mfma<T>::row(lane, v)][16 * wc + (lane & 15)] = acc[v];
+  __syncthreads();
+  if (w >= 10) return;
+  typename Mfma<T>::acc_t p = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  {
+    const T* xr = &Ab[0][0] + (16 * di + (lane & 15)) * (kNB + 1) + (lane >> 4);
+    const T* yr = &Ab[0][0] + (16 * dj + (lane & 15)) * (kNB + 1) + (lane >> 4);
+    for (int kk = 0; kk < kNB; kk += 4) p = Mfma<T>::step(xr[kk], yr[kk], p);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = 16 * di + Mfma<T>::row(lane, v), c = 16 * dj + (lane & 15);
+    if (r < rb && c <= r) S[(size_t)(t0 + r) * n + t0 + c] = dv[v] - p[v];
   }
 }
 
@@ -449,16 +488,17 @@ syrk_update_kernel(T* S, int n, int k0, int kb, T* Linv_next, const T* d0, int* 
 // The right-hand side appended as row n (nrows = n + 1) is updated by the
 // diagonal pairs: s_J -= L_J l_n, from the panel rows they hold anyway.
 //
-// Look-ahead: with Linv_next, workgroup 0 updates only the next diagonal
-// block (pair (0, 0), whose workgroup only updates the right-hand side) and
-// factors it at once, so the factor of the next panel starts with the launch
-// instead of after the update.
+// Look-ahead: with Linv_next, workgroup 0 factors the next diagonal block at
+// once (pair (0, 0), whose workgroup only updates the right-hand side here),
+// so the factor of the next panel starts with the launch instead of after the
+// update.  The panel solve before this launch (its lead workgroup) has
+// already subtracted the panel's share from that block.
 constexpr int kTB = 64;     // trailing-update tile: one pair of 64-row blocks
 constexpr int kPanLd = 68;  // LDS row stride of the staged panel rows and products
 constexpr int kPiFloats = 2 * kNB * kWld;  // the look-ahead's working matrix, or a tile's row-block panel rows
 constexpr int kPjFloats = kTB * kPanLd;
 constexpr int kSyrk64Lds = (kPiFloats + kPjFloats) * 4;
-static_assert(kPiFloats >= kTB * kPanLd && kPjFloats >= kNB * (kNB + 1), "LDS regions");
+static_assert(kPiFloats >= kTB * kPanLd, "LDS regions");
 
 // Two wavefronts per SIMD (at most 256 registers), so two workgroups share a
 // CU although workgroup 0 also runs the register-heavy diagonal factor.
@@ -474,32 +514,22 @@ syrk64_kernel(float* S, int n, int nrows, int R, int k0, int kb, float* Linv_nex
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const bool look = Linv_next != nullptr;
   if (look && blockIdx.x == 0) {
-    // next diagonal block: A_kk - L_k L_k^T (64 x 64) into W, then its factor
+    // next diagonal block, already updated by the panel (the panel solve's
+    // lead workgroup): its lower triangle into W, then its factor
     float* W = Pi;
-    float (*Lk)[kNB + 1] = reinterpret_cast<float (*)[kNB + 1]>(Pj);
     const int rb = min(kNB, n - t0);
     const float ddv = tid < rb ? d0[t0 + tid] : 0.f;
-    float sv[4][4];  // the block's entries at this lane's product positions
+    float av[16];  // rows w + 4 u, column lane: one 256-byte row per access
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int u = 0; u < 16; ++u) {
+      const int r = w + 4 * u;
+      av[u] = (r < rb && lane <= r) ? S[(size_t)(t0 + r) * n + t0 + lane] : 0.f;
+    }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * w + Mfma<float>::row(lane, v), c = 16 * t + (lane & 15);
-        sv[t][v] = (r < rb && c <= r) ? S[(size_t)(t0 + r) * n + t0 + c] : 0.f;
-      }
-    load_block64<float>(S + (size_t)t0 * n + k0, (size_t)n, rb, kb, Lk);
-    __syncthreads();
-    floatx4_t acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    gemm_nt_64<float>(&Lk[0][0], &Lk[0][0], kNB + 1, kNB, acc);
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * w + Mfma<float>::row(lane, v), c = 16 * t + (lane & 15);
-        W[r * kWld + c] = diag_w_entry<float>(r, c, rb, sv[t][v] - acc[t][v]);
-      }
+    for (int u = 0; u < 16; ++u) {
+      const int r = w + 4 * u;
+      W[r * kWld + lane] = diag_w_entry<float>(r, lane, rb, av[u]);
+    }
     fill_diag_identity<float>(W);
     __syncthreads();
     diag_factor<float>(W, S, n, t0, rb, Linv_next, ddv, status, min_bits);
@@ -958,7 +988,8 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
                               : (R > t0 ? (R - t0 + kNB - 1) / kNB : 0);
     if (n_main + nrows - n > 0)
       hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3(n_main + nrows - n), dim3(1024), 0, st, S, n, nrows, R, k0, kb,
-                         Linv, sparse ? plan->blocks + plan->blocks_off[k] : (const int*)nullptr, n_main);
+                         Linv, sparse ? plan->blocks + plan->blocks_off[k] : (const int*)nullptr, n_main,
+                         sizeof(T) == 4 ? 1 : 0);
     // the trailing update also factors diagonal block k + 1 (its workgroup 0)
     if constexpr (sizeof(T) == 4) {
       const int pairs = n_main * (n_main + 1) / 2;
@@ -975,7 +1006,7 @@ hipError_t launch_chol_factor(T* S, int n, int nrows, T* Linv_all, const T* d0, 
   if (nrows > n) {  // the appended rows below the last diagonal block: their last panel solve
     const int k0 = (nblk - 1) * kNB;
     hipLaunchKernelGGL((trsm_panel_kernel<T>), dim3((nrows - n + kNB - 1) / kNB), dim3(1024), 0, st, S, n, nrows, n,
-                       k0, n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB, (const int*)nullptr, 0);
+                       k0, n - k0, Linv_all + (size_t)(nblk - 1) * kNB * kNB, (const int*)nullptr, 0, 0);
   }
   return hipGetLastError();
 }
