@@ -278,8 +278,9 @@ struct Tiling {
   int n_tiles = 0, lds_bytes = 0, max_w6 = 0, max_k = 0;
   long long part_S = 0, part_vec = 0, u_elems = 0, u_alloc = 0, grid_cells = 0, n_tp = 0;
   DevBuf tiles, tile_patch, slot_frame, slot_blk, edge_grid, blk_pose, s_off, s_src, v_off, v_src;
-  DevBuf* bufs[10] = {&tiles, &tile_patch, &slot_frame, &slot_blk, &edge_grid, &blk_pose, &s_off, &s_src, &v_off,
-                      &v_src};
+  DevBuf order;  // launch order of the tiles: the heaviest first
+  DevBuf* bufs[11] = {&tiles, &tile_patch, &slot_frame, &slot_blk, &edge_grid, &blk_pose, &s_off, &s_src, &v_off,
+                      &v_src, &order};
 };
 
 // Shared memory of the depth write-back (tile_writeback): the block step
@@ -1003,6 +1004,20 @@ static hipError_t upload_tiling(Tiling& T_, const HostTiling& H, hipStream_t st)
   if ((e = upload(T_.s_src, H.s_src, st)) != hipSuccess) return e;
   if ((e = upload(T_.v_off, H.v_off, st)) != hipSuccess) return e;
   if ((e = upload(T_.v_src, H.v_src, st)) != hipSuccess) return e;
+  {
+    // one workgroup per tile: the heaviest tiles go first, so the last ones
+    // to start are short (work ~ edge cells + Schur rows + the U^T U product)
+    std::vector<int32_t> ord(H.tiles.size());
+    std::vector<long long> cost(H.tiles.size());
+    for (size_t t = 0; t < H.tiles.size(); ++t) {
+      const TileInfo& ti = H.tiles[t];
+      ord[t] = (int32_t)t;
+      cost[t] = (long long)ti.n_patch * (ti.n_slot + 6 * ti.n_blk) + 18LL * ti.n_blk * (ti.n_blk + 1);
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    if (ord.empty()) ord.push_back(0);
+    if ((e = upload(T_.order, ord, st)) != hipSuccess) return e;
+  }
   T_.n_tiles = (int)H.tiles.size();
   T_.lds_bytes = H.lds;
   T_.max_w6 = H.max_w6;
@@ -1334,6 +1349,7 @@ static IterArgs<T> make_iter_args(dpvba_ctx* c, const SolveWs<T>& w, const dpvba
   A.s_src = (const int*)tl.s_src.p;
   A.v_off = (const int*)tl.v_off.p;
   A.v_src = (const int2*)tl.v_src.p;
+  A.order = (const int*)tl.order.p;
   A.dx = w.dx;
   A.first = 1;
   return A;

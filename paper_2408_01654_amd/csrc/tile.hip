@@ -605,7 +605,7 @@ __device__ __forceinline__ void tile_assemble(const IterArgs<T>& A, int tile, un
 template <typename T>
 __global__ void __launch_bounds__(tile_threads(sizeof(T))) tile_iterate_kernel(IterArgs<T> A) {
   extern __shared__ __align__(16) unsigned char lds[];
-  tile_assemble<T, tile_threads(sizeof(T))>(A, blockIdx.x, lds);
+  tile_assemble<T, tile_threads(sizeof(T))>(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x, lds);
 }
 
 // Damped reduced system of a small problem (packed lower triangle, row i at

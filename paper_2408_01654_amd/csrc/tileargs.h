@@ -50,6 +50,7 @@ struct IterArgs {
   int* invalid_out;
   int* dev_err;            // device failure word of the call (bit 4: invalid target / weight)
   int* host_err;           // host-visible sticky copy of the failure bits
+  const int* order;        // one launch per pass: workgroup g runs tile order[g] (heaviest first), or g if null
 };
 
 // Arguments of the single-launch solver of small problems.
